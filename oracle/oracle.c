@@ -1,0 +1,237 @@
+/*
+ * CPU oracle for the pairwise genotype statistics of Chang et al.,
+ * "Second-generation PLINK: rising to the challenge of larger and richer
+ * datasets" (GigaScience 2015; arXiv 1410.4803).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow definition that the
+ * GPU library is checked against.  Only the tests, the smoke check and the
+ * benchmark's CPU-baseline leg load it; the library never does, and this file
+ * shares no code, header or table with it.
+ *
+ * Everything works on unpacked genotype codes (one int8 per call), never on
+ * packed words or bit tricks:
+ *   code 0 = homozygous A1, 1 = missing, 2 = heterozygous, 3 = homozygous A2
+ * (PLINK 1 binary .bed code table; the paper states only that calls are packed
+ * 2-bit elements, section "Bitwise parallelism").
+ *
+ * OpenMP parallelises the outer loop over pairs only; each pair's sum is the
+ * textbook loop in index order.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define MISSING 1
+
+/*
+ * Unpack a .bed payload.  Row v of `bed` starts at v*bytes_per_variant; the
+ * call of sample k is (byte[k/4] >> 2*(k%4)) & 3.  Bits past sample n-1 are
+ * ignored.  If `mask` is non-NULL (V rows of ceil(n/64) uint64, bit k%64 of
+ * word k/64), a set bit marks the call missing as well.
+ * Output: sample_major ? codes[k*V + v] : codes[v*n + k].
+ */
+void oracle_unpack(const uint8_t* bed, int64_t n, int64_t V, int64_t bytes_per_variant,
+                   const uint64_t* mask, int sample_major, int8_t* codes) {
+  const int64_t wpv = (n + 63) / 64;
+#pragma omp parallel for schedule(static)
+  for (int64_t v = 0; v < V; ++v) {
+    const uint8_t* row = bed + v * bytes_per_variant;
+    for (int64_t k = 0; k < n; ++k) {
+      int code = (row[k / 4] >> (2 * (k % 4))) & 3;
+      if (mask && ((mask[v * wpv + k / 64] >> (k % 64)) & 1ULL)) code = MISSING;
+      if (sample_major)
+        codes[k * V + v] = (int8_t)code;
+      else
+        codes[v * n + k] = (int8_t)code;
+    }
+  }
+}
+
+/* Number of A2 alleles carried by a non-missing call. */
+static int dosage(int code) {
+  if (code == 0) return 0; /* homozygous A1 */
+  if (code == 2) return 1; /* heterozygous */
+  return 2;                /* code 3, homozygous A2 */
+}
+
+/*
+ * Identity-by-state counts of one sample pair (section "Bitwise parallelism",
+ * the per-marker loop PLINK 1.07 used): markers where either call is missing
+ * are skipped; at the others the two samples share 2, 1 or 0 alleles
+ * identical by state.  The number of shared alleles is 2 - |dosage_i -
+ * dosage_j|.  out = {IBS0, IBS1, IBS2, jointly non-missing}.
+ * a and b point at the two samples' V codes (sample-major rows).
+ */
+static void ibs_pair(const int8_t* a, const int8_t* b, int64_t V, uint32_t out[4]) {
+  uint32_t ibs[3] = {0, 0, 0}, nonmiss = 0;
+  for (int64_t v = 0; v < V; ++v) {
+    if (a[v] == MISSING || b[v] == MISSING) continue;
+    nonmiss += 1;
+    const int d = abs(dosage(a[v]) - dosage(b[v]));
+    ibs[2 - d] += 1;
+  }
+  out[0] = ibs[0];
+  out[1] = ibs[1];
+  out[2] = ibs[2];
+  out[3] = nonmiss;
+}
+
+/*
+ * IBS counts for a list of pairs.  codes_sm: sample-major codes (n rows of V).
+ * out: npairs x 4 (IBS0, IBS1, IBS2, N).
+ */
+void oracle_ibs_pairs(const int8_t* codes_sm, int64_t n, int64_t V, const int64_t* pi,
+                      const int64_t* pj, int64_t npairs, uint32_t* out) {
+  (void)n;
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t p = 0; p < npairs; ++p)
+    ibs_pair(codes_sm + pi[p] * V, codes_sm + pj[p] * V, V, out + 4 * p);
+}
+
+/*
+ * The whole IBS matrix.  full != 0: n x n row-major, diagonal included.
+ * full == 0: strict upper triangle, row-major, entry (i,j), i<j, at
+ * i*n - i*(i+1)/2 + (j-i-1).  Four separate arrays.
+ */
+void oracle_ibs_matrix(const int8_t* codes_sm, int64_t n, int64_t V, int full, uint32_t* ibs0,
+                       uint32_t* ibs1, uint32_t* ibs2, uint32_t* nonmiss) {
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t j = full ? 0 : i + 1; j < n; ++j) {
+      uint32_t c[4];
+      ibs_pair(codes_sm + i * V, codes_sm + j * V, V, c);
+      const int64_t idx = full ? i * n + j : i * n - i * (i + 1) / 2 + (j - i - 1);
+      ibs0[idx] = c[0];
+      ibs1[idx] = c[1];
+      ibs2[idx] = c[2];
+      nonmiss[idx] = c[3];
+    }
+  }
+}
+
+/* x value of a non-missing call (section "Bit population count"): -1 for one
+ * homozygote, 0 for the heterozygote, +1 for the other homozygote.  The paper
+ * names the homozygotes minor/major; with fixed A1/A2 labels this uses
+ * -1 = homozygous A1 and +1 = homozygous A2 (r^2 does not depend on it). */
+static int xval(int code) {
+  if (code == 0) return -1;
+  if (code == 2) return 0;
+  return 1;
+}
+
+/*
+ * The six sums behind r for one variant pair (section "Bit population
+ * count"): over S_xy, the samples where neither call is missing,
+ * n = |S_xy|, Sx = sum x, Sy = sum y, Sxx = sum x^2, Syy = sum y^2,
+ * Sxy = sum x*y.  xa, xb: the two variants' n codes (variant-major rows).
+ */
+static void ld_sums(const int8_t* xa, const int8_t* xb, int64_t n, int64_t s[6]) {
+  int64_t cnt = 0, sx = 0, sy = 0, sxx = 0, syy = 0, sxy = 0;
+  for (int64_t k = 0; k < n; ++k) {
+    if (xa[k] == MISSING || xb[k] == MISSING) continue;
+    const int64_t x = xval(xa[k]), y = xval(xb[k]);
+    cnt += 1;
+    sx += x;
+    sy += y;
+    sxx += x * x;
+    syy += y * y;
+    sxy += x * y;
+  }
+  s[0] = cnt; s[1] = sx; s[2] = sy; s[3] = sxx; s[4] = syy; s[5] = sxy;
+}
+
+/*
+ * r^2 from the six sums, in double precision, following the paper's
+ * expression for r with missing data: with means over S_xy,
+ *   r = (Sxy/|S_xy| - xbar*ybar) / sqrt((x2bar - xbar^2)(y2bar - ybar^2)),
+ * then r^2 = r*r.  Undefined (NaN) when |S_xy| = 0 or a variance is 0.
+ */
+double oracle_r2(const int64_t s[6]) {
+  if (s[0] == 0) return NAN;
+  const double cnt = (double)s[0];
+  const double xbar = (double)s[1] / cnt, ybar = (double)s[2] / cnt;
+  const double x2bar = (double)s[3] / cnt, y2bar = (double)s[4] / cnt;
+  const double varx = x2bar - xbar * xbar, vary = y2bar - ybar * ybar;
+  if (varx == 0.0 || vary == 0.0) return NAN;
+  const double r = ((double)s[5] / cnt - xbar * ybar) / sqrt(varx * vary);
+  return r * r;
+}
+
+/* Sums and r^2 for a list of variant pairs.  codes_vm: variant-major codes
+ * (V rows of n).  sums: npairs x 6; r2: npairs. */
+void oracle_ld_pairs(const int8_t* codes_vm, int64_t n, int64_t V, const int64_t* pa,
+                     const int64_t* pb, int64_t npairs, int64_t* sums, double* r2) {
+  (void)V;
+#pragma omp parallel for schedule(dynamic, 256)
+  for (int64_t p = 0; p < npairs; ++p) {
+    ld_sums(codes_vm + pa[p] * n, codes_vm + pb[p] * n, n, sums + 6 * p);
+    r2[p] = oracle_r2(sums + 6 * p);
+  }
+}
+
+/* One emitted LD record: 64 bytes. */
+typedef struct {
+  int32_t a, b;
+  int64_t n, sx, sy, sxx, syy, sxy;
+  double r2;
+} oracle_ld_record;
+
+/*
+ * All variant pairs a < b <= a + window with first index a in [a_begin, a_end)
+ * and b < V, in (a, b) order; a pair is kept when its r^2 >= r2_min (an
+ * undefined r^2 is never kept).  Writes at most `capacity` records and returns
+ * the number of kept pairs.
+ */
+int64_t oracle_ld_window(const int8_t* codes_vm, int64_t n, int64_t V, int64_t a_begin,
+                         int64_t a_end, int64_t window, double r2_min, oracle_ld_record* out,
+                         int64_t capacity) {
+  const int64_t rows = a_end - a_begin;
+  if (rows <= 0) return 0;
+  int64_t* per_row = (int64_t*)calloc((size_t)rows + 1, sizeof(int64_t));
+  if (!per_row) return -1;
+  /* pass 1: how many pairs each row keeps */
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t r = 0; r < rows; ++r) {
+    const int64_t a = a_begin + r;
+    int64_t kept = 0;
+    for (int64_t b = a + 1; b <= a + window && b < V; ++b) {
+      int64_t s[6];
+      ld_sums(codes_vm + a * n, codes_vm + b * n, n, s);
+      const double r2 = oracle_r2(s);
+      if (r2 >= r2_min) ++kept;
+    }
+    per_row[r + 1] = kept;
+  }
+  for (int64_t r = 0; r < rows; ++r) per_row[r + 1] += per_row[r];
+  const int64_t total = per_row[rows];
+  /* pass 2: write the records in order */
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t r = 0; r < rows; ++r) {
+    const int64_t a = a_begin + r;
+    int64_t pos = per_row[r];
+    if (pos >= capacity) continue;
+    for (int64_t b = a + 1; b <= a + window && b < V && pos < capacity; ++b) {
+      int64_t s[6];
+      ld_sums(codes_vm + a * n, codes_vm + b * n, n, s);
+      const double r2 = oracle_r2(s);
+      if (!(r2 >= r2_min)) continue;
+      oracle_ld_record* o = out + pos++;
+      o->a = (int32_t)a;
+      o->b = (int32_t)b;
+      o->n = s[0]; o->sx = s[1]; o->sy = s[2]; o->sxx = s[3]; o->syy = s[4]; o->sxy = s[5];
+      o->r2 = r2;
+    }
+  }
+  free(per_row);
+  return total;
+}
+
+int oracle_threads(void) {
+#ifdef _OPENMP
+  extern int omp_get_max_threads(void);
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
