@@ -1,0 +1,161 @@
+/*
+ * pg -- pairwise genotype statistics on AMD MI355X (gfx950).
+ *
+ * C ABI of libpg.so.  The library computes, on the GPU, the two pairwise
+ * kernels that PLINK 1.9 accelerates with word-level bit operations (Chang et
+ * al., "Second-generation PLINK", GigaScience 2015, arXiv 1410.4803):
+ *
+ *  - identity-by-state: for every sample pair, the number of markers where
+ *    the two samples share 2, 1 or 0 alleles identical by state, and the
+ *    number of markers where neither call is missing (section "Bitwise
+ *    parallelism", the per-marker IBS loop and its XOR / mask / popcount
+ *    replacement);
+ *  - linkage disequilibrium: for every variant pair within a window, the six
+ *    sums n, Sx, Sy, Sxx, Syy, Sxy over the samples where neither call is
+ *    missing, and r^2 (section "Bit population count", the expression for r
+ *    with missing data).
+ *
+ * Input is the PLINK 1 binary genotype payload (.bed without its 3-byte
+ * header): variant-major rows of 2-bit codes, four calls per byte, sample k of
+ * a row at bits 2*(k%4) of byte k/4:
+ *     0 = homozygous A1, 1 = missing, 2 = heterozygous, 3 = homozygous A2.
+ * Bits past the last sample of a row are ignored.
+ *
+ * Conventions for every entry point:
+ *  - All array arguments are DEVICE pointers, allocated and owned by the
+ *    caller.  The library keeps no pointer after a call returns and never
+ *    allocates device memory: scratch space is the caller's `workspace`, of
+ *    at least the size the matching *_workspace_bytes call reports.
+ *  - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL means
+ *    the default stream).  Outputs are valid after the stream synchronises.
+ *  - Argument errors are detected on the host before anything is enqueued and
+ *    return PG_EINVAL (or PG_ENOMEM for a short workspace); a failed launch
+ *    returns PG_EDEVICE.  The library never aborts and never prints;
+ *    pg_last_error() describes the last failure of the calling thread.
+ *  - Calls on different streams may run concurrently; they share no state.
+ */
+#ifndef PG_H
+#define PG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PG_VERSION 1
+
+enum pg_status {
+  PG_OK = 0,
+  PG_EINVAL = -1,       /* invalid argument */
+  PG_ENOMEM = -2,       /* workspace smaller than required */
+  PG_EDEVICE = -3,      /* HIP runtime or launch failure */
+  PG_EUNSUPPORTED = -4  /* valid request this build cannot serve */
+};
+
+/* Static text for a status code. */
+const char* pg_status_str(int status);
+/* Detail of the calling thread's last failure ("" if none). */
+const char* pg_last_error(void);
+/* PG_VERSION of the built library. */
+int pg_version(void);
+
+/* A genotype matrix resident in device memory. */
+typedef struct pg_genotypes {
+  const uint8_t* bed;          /* variant-major .bed payload (device) */
+  int64_t n_samples;           /* samples per variant row, >= 1 */
+  int64_t n_variants;          /* rows, >= 1, < 2^31 */
+  int64_t bytes_per_variant;   /* row stride in bytes, >= ceil(n_samples/4);
+                                  0 means ceil(n_samples/4) */
+  const uint64_t* missing_mask;/* optional (NULL = none), device: n_variants
+                                  rows of ceil(n_samples/64) uint64; bit k%64 of
+                                  word k/64 set => call of sample k is treated
+                                  as missing, in addition to code 1 */
+} pg_genotypes;
+
+/* IBS output layouts. */
+enum pg_layout {
+  PG_TRI_UPPER = 0, /* strict upper triangle, row-major: pair (i,j), i<j, at
+                       index i*m - i*(i+1)/2 + (j-i-1); m(m-1)/2 entries */
+  PG_FULL = 1       /* m x m row-major, both halves and the diagonal */
+};
+
+/* Kernel path. */
+enum pg_path {
+  PG_PATH_AUTO = 0, /* library picks per shape */
+  PG_PATH_POPC = 1, /* bit planes + popcount on the vector ALUs */
+  PG_PATH_MFMA = 2  /* 2-bit codes expanded to int8 indicator features and
+                       contracted on the int8 matrix cores */
+};
+
+/*
+ * Sample selection and variant range (shared by the IBS and LD calls):
+ *   sample_idx  optional device int32 array of n_sel indices into
+ *               [0, n_samples); output rows/columns follow its order and
+ *               duplicates are allowed.  NULL selects all samples in order,
+ *               and n_sel must then be 0 or n_samples.
+ *   v_begin, v_end  variant range [v_begin, v_end); 0, 0 selects all.
+ */
+
+/* Workspace bytes pg_ibs_matrix needs for this shape and path. */
+int pg_ibs_workspace_bytes(const pg_genotypes* g, int64_t n_sel, int64_t v_begin, int64_t v_end,
+                           int path, size_t* bytes);
+
+/*
+ * Identity-by-state matrix over the selected samples (m of them) and
+ * variants.  For each output pair (i, j), over the selected variants where
+ * neither call is missing:
+ *   nonmiss = number of such variants,
+ *   ibs2 = same genotype, ibs0 = opposite homozygotes, ibs1 = the rest
+ * (ibs0 + ibs1 + ibs2 == nonmiss).  The diagonal of PG_FULL holds
+ * ibs2 = nonmiss = the sample's non-missing count, ibs0 = ibs1 = 0.
+ * Outputs are four caller-owned uint32 device arrays of m*m (PG_FULL) or
+ * m(m-1)/2 (PG_TRI_UPPER) entries; counts are exact.  With zero entries
+ * (one sample, PG_TRI_UPPER) the call validates its arguments, enqueues
+ * nothing and the output pointers may be NULL.
+ * Section "Bitwise parallelism".
+ */
+int pg_ibs_matrix(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_sel,
+                  int64_t v_begin, int64_t v_end, int out_layout, int path, uint32_t* ibs0,
+                  uint32_t* ibs1, uint32_t* ibs2, uint32_t* nonmiss, void* workspace,
+                  size_t workspace_bytes, void* stream);
+
+/* One emitted LD pair: 64 bytes. a < b are absolute variant indices. */
+typedef struct pg_ld_pair {
+  int32_t a, b;
+  int64_t n, sx, sy, sxx, syy, sxy;
+  double r2;
+} pg_ld_pair;
+
+/* Workspace bytes pg_ld_window needs for this shape, window and path. */
+int pg_ld_workspace_bytes(const pg_genotypes* g, int64_t n_sel, int64_t v_begin, int64_t v_end,
+                          int32_t window, int path, size_t* bytes);
+
+/*
+ * LD within a window over the selected samples and variants.  For every
+ * variant pair a < b <= a + window inside [v_begin, v_end), with x = -1 / 0 /
+ * +1 for homozygous A1 / heterozygous / homozygous A2 and S the samples where
+ * neither call is missing: n = |S|, sx = sum x_a, sy = sum x_b, sxx = sum x_a^2,
+ * syy = sum x_b^2, sxy = sum x_a x_b (exact), and
+ *   r2 = c*c / (va*vb),  c = n*sxy - sx*sy, va = n*sxx - sx^2, vb = n*syy - sy^2,
+ * evaluated in IEEE double from the exact integers (products, then one
+ * division, no contraction), clamped to <= 1; r2 is NaN when n == 0 or
+ * va*vb == 0.  This equals the square of r in section "Bit population count"
+ * (numerator and denominator multiplied by n^2).
+ * A pair is emitted iff r2 >= r2_min (NaN never).  Emitted pairs are written
+ * to `out` in increasing (a, b) order; *n_out (device int64) receives the total
+ * number of emitted pairs.  If that exceeds `capacity`, only the first
+ * `capacity` pairs (in the same order) are written; the call still succeeds,
+ * and the caller may retry with a larger buffer.
+ */
+int pg_ld_window(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_sel,
+                 int64_t v_begin, int64_t v_end, int32_t window, double r2_min, pg_ld_pair* out,
+                 int64_t capacity, int64_t* n_out, int path, void* workspace,
+                 size_t workspace_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PG_H */

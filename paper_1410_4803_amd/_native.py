@@ -1,0 +1,89 @@
+"""ctypes binding of libpg.so: argument marshalling only.
+
+Every statistic is computed by the library's HIP kernels; this module
+allocates device buffers with PyTorch, passes raw pointers and the current
+HIP stream, and turns status codes into exceptions.  There is no fallback: if
+libpg.so is missing or cannot be loaded, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpg.so")
+
+PG_OK, PG_EINVAL, PG_ENOMEM, PG_EDEVICE, PG_EUNSUPPORTED = 0, -1, -2, -3, -4
+PG_TRI_UPPER, PG_FULL = 0, 1
+PG_PATH_AUTO, PG_PATH_POPC, PG_PATH_MFMA = 0, 1, 2
+
+LAYOUTS = {"tri": PG_TRI_UPPER, "full": PG_FULL}
+PATHS = {"auto": PG_PATH_AUTO, "popc": PG_PATH_POPC, "mfma": PG_PATH_MFMA}
+
+# ABI symbols (include/pg.h)
+SYMBOLS = ("pg_status_str", "pg_last_error", "pg_version", "pg_ibs_workspace_bytes",
+           "pg_ibs_matrix", "pg_ld_workspace_bytes", "pg_ld_window")
+
+LD_PAIR = np.dtype([("a", "<i4"), ("b", "<i4"), ("n", "<i8"), ("sx", "<i8"), ("sy", "<i8"),
+                    ("sxx", "<i8"), ("syy", "<i8"), ("sxy", "<i8"), ("r2", "<f8")])
+assert LD_PAIR.itemsize == 64
+
+
+class PgError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: {status_str(status)} ({status}): {detail}")
+        self.status = status
+
+
+class Genotypes(ctypes.Structure):
+    """Mirror of pg_genotypes."""
+    _fields_ = [("bed", ctypes.c_void_p), ("n_samples", ctypes.c_int64),
+                ("n_variants", ctypes.c_int64), ("bytes_per_variant", ctypes.c_int64),
+                ("missing_mask", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load():
+    """Load libpg.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_1410_4803_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    i64, i32, dbl, p, sz = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
+    gp = ctypes.POINTER(Genotypes)
+    lib.pg_status_str.argtypes = [ctypes.c_int]
+    lib.pg_status_str.restype = ctypes.c_char_p
+    lib.pg_last_error.argtypes = []
+    lib.pg_last_error.restype = ctypes.c_char_p
+    lib.pg_version.argtypes = []
+    lib.pg_version.restype = ctypes.c_int
+    lib.pg_ibs_workspace_bytes.argtypes = [gp, i64, i64, i64, ctypes.c_int, ctypes.POINTER(sz)]
+    lib.pg_ibs_workspace_bytes.restype = ctypes.c_int
+    lib.pg_ibs_matrix.argtypes = [gp, p, i64, i64, i64, ctypes.c_int, ctypes.c_int, p, p, p, p, p,
+                                  sz, p]
+    lib.pg_ibs_matrix.restype = ctypes.c_int
+    lib.pg_ld_workspace_bytes.argtypes = [gp, i64, i64, i64, i32, ctypes.c_int, ctypes.POINTER(sz)]
+    lib.pg_ld_workspace_bytes.restype = ctypes.c_int
+    lib.pg_ld_window.argtypes = [gp, p, i64, i64, i64, i32, dbl, p, i64, p, ctypes.c_int, p, sz, p]
+    lib.pg_ld_window.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def status_str(status: int) -> str:
+    return load().pg_status_str(status).decode()
+
+
+def last_error() -> str:
+    return load().pg_last_error().decode()
+
+
+def check(status: int, where: str) -> None:
+    if status != PG_OK:
+        raise PgError(status, where, last_error())

@@ -1,0 +1,195 @@
+"""Python API over libpg.so: device buffers and streams come from PyTorch,
+every computation runs in the library's HIP kernels.
+
+    cohort = Cohort.from_numpy(bed, n_samples)          # resident in HBM
+    ibs0, ibs1, ibs2, n = ibs_matrix(cohort, layout="full")
+    recs = ld_records(cohort, window=1000, r2_min=0.2)  # numpy LD_PAIR array
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _native as N
+
+
+def _require_cuda(t: torch.Tensor, name: str, dtype) -> None:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else int(t.data_ptr())
+
+
+@dataclass
+class Cohort:
+    """A .bed genotype matrix resident in device memory.
+
+    bed: CUDA uint8 tensor holding n_variants rows of bytes_per_variant bytes
+    (variant-major PLINK 1 binary payload, no header).  missing_mask: optional
+    CUDA int64/uint64 tensor of n_variants x ceil(n_samples/64) words, bit set =
+    call missing."""
+    bed: torch.Tensor
+    n_samples: int
+    n_variants: int
+    bytes_per_variant: int = 0
+    missing_mask: torch.Tensor | None = None
+
+    def __post_init__(self):
+        _require_cuda(self.bed, "bed", torch.uint8)
+        bpv = self.bytes_per_variant or (self.n_samples + 3) // 4
+        if self.bed.numel() < self.n_variants * bpv:
+            raise ValueError("bed holds fewer than n_variants * bytes_per_variant bytes")
+        if self.missing_mask is not None:
+            if self.missing_mask.dtype not in (torch.int64, torch.uint64):
+                raise TypeError("missing_mask must be a 64-bit integer tensor")
+            if not self.missing_mask.is_cuda or not self.missing_mask.is_contiguous():
+                raise ValueError("missing_mask must be a contiguous CUDA tensor")
+            if self.missing_mask.numel() < self.n_variants * ((self.n_samples + 63) // 64):
+                raise ValueError("missing_mask is too small")
+
+    @classmethod
+    def from_numpy(cls, bed: np.ndarray, n_samples: int, missing_mask: np.ndarray | None = None,
+                   device="cuda") -> "Cohort":
+        bed = np.ascontiguousarray(bed, dtype=np.uint8)
+        t = torch.from_numpy(bed).to(device)
+        m = None
+        if missing_mask is not None:
+            m = torch.from_numpy(np.ascontiguousarray(missing_mask).view(np.int64)).to(device)
+        return cls(t, n_samples, bed.shape[0], bed.shape[1] if bed.ndim == 2 else 0, m)
+
+    def struct(self) -> N.Genotypes:
+        return N.Genotypes(self.bed.data_ptr(), self.n_samples, self.n_variants,
+                           self.bytes_per_variant, _ptr(self.missing_mask))
+
+    @property
+    def nbytes(self) -> int:
+        n = self.bed.numel()
+        if self.missing_mask is not None:
+            n += self.missing_mask.numel() * 8
+        return n
+
+
+def _sel(cohort: Cohort, sample_idx, v_range):
+    if sample_idx is not None:
+        _require_cuda(sample_idx, "sample_idx", torch.int32)
+        n_sel = sample_idx.numel()
+    else:
+        n_sel = 0
+    vb, ve = (0, 0) if v_range is None else (int(v_range[0]), int(v_range[1]))
+    return n_sel, vb, ve
+
+
+def _path(path) -> int:
+    return N.PATHS[path] if isinstance(path, str) else int(path)
+
+
+def ibs_workspace_bytes(cohort: Cohort, n_sel: int = 0, v_range=None, path="auto") -> int:
+    vb, ve = (0, 0) if v_range is None else v_range
+    out = ctypes.c_size_t(0)
+    g = cohort.struct()
+    N.check(N.load().pg_ibs_workspace_bytes(ctypes.byref(g), n_sel, vb, ve, _path(path),
+                                            ctypes.byref(out)), "pg_ibs_workspace_bytes")
+    return out.value
+
+
+def ibs_output_size(m: int, layout: str) -> int:
+    return m * m if layout == "full" else m * (m - 1) // 2
+
+
+def ibs_matrix(cohort: Cohort, *, sample_idx: torch.Tensor | None = None, v_range=None,
+               layout: str = "full", path="auto", out=None, workspace: torch.Tensor | None = None,
+               stream=None):
+    """IBS0, IBS1, IBS2, N as four CUDA int32 tensors (uint32 counts, all
+    < 2^31): (m, m) for layout "full", m(m-1)/2 packed upper triangle for
+    "tri".  Asynchronous on `stream` (default: the current stream)."""
+    lib = N.load()
+    n_sel, vb, ve = _sel(cohort, sample_idx, v_range)
+    m = n_sel or cohort.n_samples
+    size = ibs_output_size(m, layout)
+    if out is None:
+        shape = (m, m) if layout == "full" else (size,)
+        out = tuple(torch.empty(shape, dtype=torch.int32, device=cohort.bed.device)
+                    for _ in range(4))
+    else:
+        for k, t in enumerate(out):
+            _require_cuda(t, f"out[{k}]", torch.int32)
+            if t.numel() < size:
+                raise ValueError("output tensor too small")
+    need = ibs_workspace_bytes(cohort, n_sel, (vb, ve), path)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=cohort.bed.device)
+    g = cohort.struct()
+    st = lib.pg_ibs_matrix(ctypes.byref(g), _ptr(sample_idx), n_sel, vb, ve, N.LAYOUTS[layout],
+                           _path(path), *[_ptr(t) for t in out], _ptr(workspace),
+                           workspace.numel(), _stream_handle(stream))
+    N.check(st, "pg_ibs_matrix")
+    return out
+
+
+def ld_workspace_bytes(cohort: Cohort, window: int, n_sel: int = 0, v_range=None,
+                       path="auto") -> int:
+    vb, ve = (0, 0) if v_range is None else v_range
+    out = ctypes.c_size_t(0)
+    g = cohort.struct()
+    N.check(N.load().pg_ld_workspace_bytes(ctypes.byref(g), n_sel, vb, ve, window, _path(path),
+                                           ctypes.byref(out)), "pg_ld_workspace_bytes")
+    return out.value
+
+
+def ld_window(cohort: Cohort, window: int, r2_min: float, *, capacity: int,
+              sample_idx: torch.Tensor | None = None, v_range=None, path="auto", out=None,
+              n_out=None, workspace: torch.Tensor | None = None, stream=None):
+    """Asynchronous LD window call.  Returns (out, n_out): out is a CUDA
+    uint8 tensor of capacity x 64 bytes (pg_ld_pair records in (a, b) order),
+    n_out a CUDA int64 tensor holding the total number of emitted pairs."""
+    lib = N.load()
+    n_sel, vb, ve = _sel(cohort, sample_idx, v_range)
+    dev = cohort.bed.device
+    if out is None:
+        out = torch.empty((max(capacity, 1), 64), dtype=torch.uint8, device=dev)
+    if n_out is None:
+        n_out = torch.empty(1, dtype=torch.int64, device=dev)
+    need = ld_workspace_bytes(cohort, window, n_sel, (vb, ve), path)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    g = cohort.struct()
+    st = lib.pg_ld_window(ctypes.byref(g), _ptr(sample_idx), n_sel, vb, ve, int(window),
+                          float(r2_min), _ptr(out), int(capacity), _ptr(n_out), _path(path),
+                          _ptr(workspace), workspace.numel(), _stream_handle(stream))
+    N.check(st, "pg_ld_window")
+    return out, n_out
+
+
+def records_to_numpy(out: torch.Tensor, count: int) -> np.ndarray:
+    """First `count` records of an LD output buffer as a numpy LD_PAIR array."""
+    raw = out[:count].contiguous().cpu().numpy()
+    return raw.reshape(-1).view(N.LD_PAIR)[:count].copy()
+
+
+def ld_records(cohort: Cohort, window: int, r2_min: float, *, capacity: int | None = None,
+               **kw) -> np.ndarray:
+    """Synchronous LD window: all emitted pairs as a numpy LD_PAIR array.
+    Re-issues the call once with a larger buffer if the first one overflows."""
+    if capacity is None:
+        capacity = max(1024, 4 * cohort.n_variants)
+    out, n_out = ld_window(cohort, window, r2_min, capacity=capacity, **kw)
+    total = int(n_out.item())
+    if total > capacity:
+        out, n_out = ld_window(cohort, window, r2_min, capacity=total, **kw)
+        total = int(n_out.item())
+    return records_to_numpy(out, total)

@@ -1,0 +1,239 @@
+// C ABI of libpg.so: argument validation, workspace carving and dispatch.
+// Every check runs on the host before any launch; see include/pg.h for the
+// contract of each entry point.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "pg_internal.h"
+
+namespace pg {
+
+static thread_local char g_last_error[512] = "";
+
+int fail(int status, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+  va_end(ap);
+  return status;
+}
+
+int check_launch(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(PG_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+  return PG_OK;
+}
+
+namespace {
+
+constexpr int64_t kAlign = 256;
+constexpr int64_t kMaxIndex = (int64_t)1 << 31;
+
+struct Carve {
+  int64_t off = 0;
+  int64_t take(int64_t bytes) {
+    const int64_t o = off;
+    off = round_up(off + bytes, kAlign);
+    return o;
+  }
+};
+
+// Validates the matrix, the selection and the range; fills `s`.
+// `list` says whether a sample list is given (the workspace queries pass no
+// pointer, only its length).
+int make_sel(const pg_genotypes* g, bool list, const int32_t* idx, int64_t n_sel,
+             int64_t v_begin, int64_t v_end, Sel& s) {
+  if (!g) return fail(PG_EINVAL, "genotypes is NULL");
+  if (!g->bed) return fail(PG_EINVAL, "bed is NULL");
+  if (g->n_samples < 1 || g->n_samples >= kMaxIndex)
+    return fail(PG_EINVAL, "n_samples %lld outside [1, 2^31)", (long long)g->n_samples);
+  if (g->n_variants < 1 || g->n_variants >= kMaxIndex)
+    return fail(PG_EINVAL, "n_variants %lld outside [1, 2^31)", (long long)g->n_variants);
+  const int64_t min_bpv = ceil_div(g->n_samples, 4);
+  const int64_t bpv = g->bytes_per_variant == 0 ? min_bpv : g->bytes_per_variant;
+  if (bpv < min_bpv)
+    return fail(PG_EINVAL, "bytes_per_variant %lld < ceil(n_samples/4) = %lld",
+                (long long)bpv, (long long)min_bpv);
+  int64_t m = g->n_samples;
+  if (list) {
+    if (n_sel < 1 || n_sel >= kMaxIndex)
+      return fail(PG_EINVAL, "n_sel %lld outside [1, 2^31) with a sample list", (long long)n_sel);
+    m = n_sel;
+  } else if (n_sel != 0 && n_sel != g->n_samples) {
+    return fail(PG_EINVAL, "n_sel must be 0 or n_samples without a sample list");
+  }
+  int64_t vb = v_begin, ve = v_end;
+  if (vb == 0 && ve == 0) ve = g->n_variants;
+  if (vb < 0 || ve > g->n_variants || vb >= ve)
+    return fail(PG_EINVAL, "variant range [%lld, %lld) invalid for %lld variants", (long long)vb,
+                (long long)ve, (long long)g->n_variants);
+  s.bed = g->bed;
+  s.bpv = bpv;
+  s.mask = g->missing_mask;
+  s.wpm = ceil_div(g->n_samples, 64);
+  s.idx = idx;
+  s.n = g->n_samples;
+  s.m = m;
+  s.v0 = vb;
+  s.nv = ve - vb;
+  return PG_OK;
+}
+
+struct IbsPlan {
+  int path;
+  int64_t rows_pad, words;  // operand rows and K words
+  int64_t bytes;
+};
+
+int plan_ibs(const Sel& s, int path, IbsPlan& p) {
+  if (path == PG_PATH_AUTO) path = PG_PATH_MFMA;
+  if (path != PG_PATH_MFMA && path != PG_PATH_POPC)
+    return fail(PG_EINVAL, "unknown path %d", path);
+  p.path = path;
+  if (path == PG_PATH_MFMA) {
+    p.rows_pad = round_up(s.m, kIbsMfmaTile);
+    p.words = round_up(ceil_div(s.nv, 16), kIbsMfmaKWords);
+    p.bytes = p.rows_pad * p.words * 4;
+  } else {
+    p.rows_pad = round_up(s.m, kIbsPopcTile);
+    p.words = round_up(ceil_div(s.nv, 32), kIbsPopcKWords);
+    p.bytes = 3 * p.rows_pad * p.words * 4;
+  }
+  const int64_t nt = p.rows_pad / (path == PG_PATH_MFMA ? kIbsMfmaTile : kIbsPopcTile);
+  if (nt * (nt + 1) / 2 >= kMaxIndex) return fail(PG_EUNSUPPORTED, "too many samples for one call");
+  return PG_OK;
+}
+
+struct LdPlan {
+  int64_t rows_pad, wn, bm_words;
+  int64_t off_D, off_bm, off_cnt, off_off, bytes;
+};
+
+int plan_ld(const Sel& s, int32_t window, int path, LdPlan& p) {
+  if (window < 1) return fail(PG_EINVAL, "window %d < 1", (int)window);
+  if (path != PG_PATH_AUTO && path != PG_PATH_MFMA)
+    return fail(path == PG_PATH_POPC ? PG_EUNSUPPORTED : PG_EINVAL,
+                "LD path %d not available (use PG_PATH_AUTO or PG_PATH_MFMA)", path);
+  p.rows_pad = round_up(s.nv, kLdTile);
+  p.wn = round_up(ceil_div(s.m, 16), kLdKWords);
+  p.bm_words = ceil_div(window, 32);
+  Carve c;
+  p.off_D = c.take(p.rows_pad * p.wn * 4);
+  p.off_bm = c.take(p.rows_pad * p.bm_words * 4);
+  p.off_cnt = c.take(p.rows_pad * 4);
+  p.off_off = c.take((p.rows_pad + 1) * 8);
+  p.bytes = c.off;
+  return PG_OK;
+}
+
+}  // namespace
+}  // namespace pg
+
+using namespace pg;
+
+extern "C" {
+
+const char* pg_status_str(int status) {
+  switch (status) {
+    case PG_OK: return "ok";
+    case PG_EINVAL: return "invalid argument";
+    case PG_ENOMEM: return "workspace too small";
+    case PG_EDEVICE: return "device error";
+    case PG_EUNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+const char* pg_last_error(void) { return g_last_error; }
+
+int pg_version(void) { return PG_VERSION; }
+
+int pg_ibs_workspace_bytes(const pg_genotypes* g, int64_t n_sel, int64_t v_begin, int64_t v_end,
+                           int path, size_t* bytes) {
+  if (!bytes) return fail(PG_EINVAL, "bytes is NULL");
+  Sel s;
+  int rc = make_sel(g, n_sel > 0, nullptr, n_sel, v_begin, v_end, s);
+  if (rc != PG_OK) return rc;
+  IbsPlan p;
+  rc = plan_ibs(s, path, p);
+  if (rc != PG_OK) return rc;
+  *bytes = (size_t)p.bytes;
+  return PG_OK;
+}
+
+int pg_ibs_matrix(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_sel,
+                  int64_t v_begin, int64_t v_end, int out_layout, int path, uint32_t* ibs0,
+                  uint32_t* ibs1, uint32_t* ibs2, uint32_t* nonmiss, void* workspace,
+                  size_t workspace_bytes, void* stream) {
+  g_last_error[0] = 0;
+  Sel s;
+  int rc = make_sel(g, sample_idx != nullptr, sample_idx, n_sel, v_begin, v_end, s);
+  if (rc != PG_OK) return rc;
+  if (out_layout != PG_FULL && out_layout != PG_TRI_UPPER)
+    return fail(PG_EINVAL, "unknown layout %d", out_layout);
+  const int64_t entries = out_layout == PG_FULL ? s.m * s.m : s.m * (s.m - 1) / 2;
+  if (entries == 0) return PG_OK;  // one sample, triangle layout: nothing to write
+  if (!ibs0 || !ibs1 || !ibs2 || !nonmiss) return fail(PG_EINVAL, "an output pointer is NULL");
+  IbsPlan p;
+  rc = plan_ibs(s, path, p);
+  if (rc != PG_OK) return rc;
+  if ((int64_t)workspace_bytes < p.bytes || (!workspace && p.bytes > 0))
+    return fail(PG_ENOMEM, "workspace of %llu bytes < %lld required",
+                (unsigned long long)workspace_bytes, (long long)p.bytes);
+  hipStream_t st = (hipStream_t)stream;
+  IbsOut o{ibs0, ibs1, ibs2, nonmiss, s.m, out_layout == PG_FULL};
+  uint32_t* ws = (uint32_t*)workspace;
+  if (p.path == PG_PATH_MFMA) {
+    rc = launch_sample_major_2bit(s, ws, p.rows_pad, p.words, st);
+    if (rc == PG_OK) rc = launch_ibs_mfma(ws, p.words, o, st);
+  } else {
+    rc = launch_ibs_planes(s, ws, p.rows_pad, p.words, st);
+    if (rc == PG_OK) rc = launch_ibs_popc(ws, p.rows_pad, p.words, o, st);
+  }
+  return rc;
+}
+
+int pg_ld_workspace_bytes(const pg_genotypes* g, int64_t n_sel, int64_t v_begin, int64_t v_end,
+                          int32_t window, int path, size_t* bytes) {
+  if (!bytes) return fail(PG_EINVAL, "bytes is NULL");
+  Sel s;
+  int rc = make_sel(g, n_sel > 0, nullptr, n_sel, v_begin, v_end, s);
+  if (rc != PG_OK) return rc;
+  LdPlan p;
+  rc = plan_ld(s, window, path, p);
+  if (rc != PG_OK) return rc;
+  *bytes = (size_t)p.bytes;
+  return PG_OK;
+}
+
+int pg_ld_window(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_sel,
+                 int64_t v_begin, int64_t v_end, int32_t window, double r2_min, pg_ld_pair* out,
+                 int64_t capacity, int64_t* n_out, int path, void* workspace,
+                 size_t workspace_bytes, void* stream) {
+  g_last_error[0] = 0;
+  Sel s;
+  int rc = make_sel(g, sample_idx != nullptr, sample_idx, n_sel, v_begin, v_end, s);
+  if (rc != PG_OK) return rc;
+  if (!n_out) return fail(PG_EINVAL, "n_out is NULL");
+  if (capacity < 0) return fail(PG_EINVAL, "capacity < 0");
+  if (capacity > 0 && !out) return fail(PG_EINVAL, "out is NULL with capacity > 0");
+  LdPlan p;
+  rc = plan_ld(s, window, path, p);
+  if (rc != PG_OK) return rc;
+  if ((int64_t)workspace_bytes < p.bytes || !workspace)
+    return fail(PG_ENOMEM, "workspace of %llu bytes < %lld required",
+                (unsigned long long)workspace_bytes, (long long)p.bytes);
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  uint32_t* D = (uint32_t*)(ws + p.off_D);
+  LdScratch sc{(uint32_t*)(ws + p.off_bm), p.bm_words, (uint32_t*)(ws + p.off_cnt),
+               (int64_t*)(ws + p.off_off)};
+  rc = launch_variant_major_2bit(s, D, p.rows_pad, p.wn, st);
+  if (rc == PG_OK) rc = launch_ld_mfma(D, p.wn, s.nv, p.rows_pad, window, r2_min, sc, st);
+  if (rc == PG_OK)
+    rc = launch_ld_finish(D, p.wn, s.nv, s.v0, window, sc, out, capacity, n_out, st);
+  return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,114 @@
+// Internal declarations shared by the libpg sources (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/pg.h"
+
+namespace pg {
+
+// Records a failure message for pg_last_error() and returns `status`.
+int fail(int status, const char* fmt, ...);
+// Checks the last HIP launch error; returns PG_OK or PG_EDEVICE.
+int check_launch(const char* what);
+
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+
+// The caller's selection of a genotype matrix: which rows (variants) and
+// which samples, with the optional missing mask folded into the codes.
+struct Sel {
+  const uint8_t* bed;      // variant-major .bed payload
+  int64_t bpv;             // row stride in bytes
+  const uint64_t* mask;    // optional missing mask, wpm words per row
+  int64_t wpm;
+  const int32_t* idx;      // optional sample list
+  int64_t n;               // samples per row of the matrix
+  int64_t m;               // selected samples
+  int64_t v0;              // first selected variant
+  int64_t nv;              // selected variants
+};
+
+// 2-bit .bed code of selected sample k at selected variant v (both local);
+// positions past the selection, and list entries outside [0, n), read as 1
+// (missing).
+__device__ __forceinline__ uint32_t code_at(const Sel& s, int64_t v, int64_t k) {
+  if (v >= s.nv || k >= s.m) return 1u;
+  const int64_t row = s.v0 + v;
+  const int64_t smp = s.idx ? (int64_t)s.idx[k] : k;
+  if (smp < 0 || smp >= s.n) return 1u;
+  uint32_t c = (s.bed[row * s.bpv + (smp >> 2)] >> (2 * (smp & 3))) & 3u;
+  if (s.mask && ((s.mask[row * s.wpm + (smp >> 6)] >> (smp & 63)) & 1ull)) c = 1u;
+  return c;
+}
+
+// Sixteen codes of one word, all positions "missing".
+constexpr uint32_t kAllMissing16 = 0x55555555u;
+
+// ---- layout kernels (layout.hip) -------------------------------------------
+// Sample-major 2-bit words: T[i*wp + w] holds codes of variants 16w..16w+15
+// of selected sample i (code of variant 16w+t at bits 2t); rows_pad x wp.
+int launch_sample_major_2bit(const Sel& s, uint32_t* T, int64_t rows_pad, int64_t wp,
+                             hipStream_t st);
+// Sample-major bit planes for the popcount IBS path: for 32-variant word w,
+// plane p (0 = high code bit, 1 = low code bit, 2 = non-missing) of sample i
+// at P[(w*3 + p)*rows_pad + i]; words_pad words.
+int launch_ibs_planes(const Sel& s, uint32_t* P, int64_t rows_pad, int64_t words_pad,
+                      hipStream_t st);
+// Variant-major 2-bit words over the selected samples: D[v*wn + w] holds
+// codes of samples 16w..16w+15 of selected variant v; rows_pad x wn.
+int launch_variant_major_2bit(const Sel& s, uint32_t* D, int64_t rows_pad, int64_t wn,
+                              hipStream_t st);
+
+// ---- IBS ------------------------------------------------------------------
+struct IbsOut {
+  uint32_t* ibs0;
+  uint32_t* ibs1;
+  uint32_t* ibs2;
+  uint32_t* nonmiss;
+  int64_t m;     // matrix order
+  int full;      // PG_FULL or PG_TRI_UPPER
+};
+
+constexpr int kIbsMfmaTile = 128;     // samples per tile side
+constexpr int kIbsMfmaKWords = 16;    // 2-bit words per K chunk (256 variants)
+constexpr int kIbsPopcTile = 64;
+constexpr int kIbsPopcKWords = 16;    // 32-bit plane words per K chunk
+
+int launch_ibs_mfma(const uint32_t* T, int64_t wp, const IbsOut& o, hipStream_t st);
+int launch_ibs_popc(const uint32_t* P, int64_t rows_pad, int64_t words_pad, const IbsOut& o,
+                    hipStream_t st);
+
+// ---- LD -------------------------------------------------------------------
+constexpr int kLdTile = 64;           // variants per tile side
+constexpr int kLdKWords = 16;         // 2-bit words per K chunk (256 samples)
+
+struct LdScratch {
+  uint32_t* bitmap;    // rows_pad x bm_words, bit (b-a-1) of row a
+  int64_t bm_words;
+  uint32_t* rowcnt;    // rows_pad
+  int64_t* rowoff;     // rows_pad + 1
+};
+
+int launch_ld_mfma(const uint32_t* D, int64_t wn, int64_t nv, int64_t rows_pad, int32_t window,
+                   double r2_min, const LdScratch& sc, hipStream_t st);
+int launch_ld_finish(const uint32_t* D, int64_t wn, int64_t nv, int64_t v0, int32_t window,
+                     const LdScratch& sc, pg_ld_pair* out, int64_t capacity, int64_t* n_out,
+                     hipStream_t st);
+
+// r^2 from exact sums, as documented in pg.h; shared by every LD path so that
+// the emission decision and the emitted value are the same double.
+__device__ __forceinline__ double ld_r2(int64_t n, int64_t sx, int64_t sy, int64_t sxx,
+                                        int64_t syy, int64_t sxy) {
+  const int64_t c = n * sxy - sx * sy;
+  const int64_t va = n * sxx - sx * sx;
+  const int64_t vb = n * syy - sy * sy;
+  if (n == 0 || va == 0 || vb == 0) return __longlong_as_double(0x7ff8000000000000ll);
+  const double num = __dmul_rn((double)c, (double)c);
+  const double den = __dmul_rn((double)va, (double)vb);
+  const double r2 = __ddiv_rn(num, den);
+  return r2 > 1.0 ? 1.0 : r2;
+}
+
+}  // namespace pg

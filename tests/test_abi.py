@@ -1,0 +1,116 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects bad arguments with the documented status codes
+before touching the device (no compute calls here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1410_4803_amd import _native as N
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    text = open(os.path.join(ROOT, "include", "pg.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pg_\w+)\s*\(", text)))
+
+
+def test_every_header_symbol_is_exported():
+    lib = N.load()
+    names = _header_functions()
+    assert set(names) == set(N.SYMBOLS)
+    for name in names:
+        assert hasattr(lib, name), name
+    assert lib.pg_version() == 1
+
+
+def test_status_strings():
+    assert N.status_str(0) == "ok"
+    assert N.status_str(-2) == "workspace too small"
+    assert N.status_str(99) == "unknown status"
+
+
+def _g(n=100, V=50, bpv=0, bed=0x1000):
+    return N.Genotypes(bed, n, V, bpv, None)
+
+
+def _ibs_ws(g, n_sel=0, vb=0, ve=0, path=0):
+    b = ctypes.c_size_t(0)
+    rc = N.load().pg_ibs_workspace_bytes(ctypes.byref(g), n_sel, vb, ve, path, ctypes.byref(b))
+    return rc, b.value
+
+
+def _ld_ws(g, W, n_sel=0, vb=0, ve=0, path=0):
+    b = ctypes.c_size_t(0)
+    rc = N.load().pg_ld_workspace_bytes(ctypes.byref(g), n_sel, vb, ve, W, path, ctypes.byref(b))
+    return rc, b.value
+
+
+def test_workspace_sizes():
+    rc, b = _ibs_ws(_g(10000, 100000), path=N.PG_PATH_MFMA)
+    assert rc == 0 and b == 10112 * 6256 * 4
+    rc, b = _ibs_ws(_g(10000, 100000), path=N.PG_PATH_POPC)
+    assert rc == 0 and b == 3 * 10048 * 3136 * 4
+    rc, b = _ibs_ws(_g(100, 50), n_sel=7)
+    assert rc == 0 and b == 128 * 16 * 4
+    rc, b = _ld_ws(_g(5000, 500000), 1000)
+    assert rc == 0 and b > 500000 * 320 * 4
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n=0), N.PG_EINVAL), (dict(V=0), N.PG_EINVAL), (dict(n=1 << 31), N.PG_EINVAL),
+    (dict(bpv=3, n=100), N.PG_EINVAL), (dict(bed=0), N.PG_EINVAL)])
+def test_bad_matrix(kw, code):
+    rc, _ = _ibs_ws(_g(**kw))
+    assert rc == code
+    assert N.last_error() != ""
+
+
+def test_bad_selection_and_range():
+    g = _g(100, 50)
+    assert _ibs_ws(g, vb=10, ve=5)[0] == N.PG_EINVAL
+    assert _ibs_ws(g, vb=0, ve=51)[0] == N.PG_EINVAL
+    assert _ibs_ws(g, vb=-1, ve=5)[0] == N.PG_EINVAL
+    assert _ibs_ws(g, path=7)[0] == N.PG_EINVAL
+    assert _ld_ws(g, 0)[0] == N.PG_EINVAL
+    assert _ld_ws(g, 10, path=N.PG_PATH_POPC)[0] == N.PG_EUNSUPPORTED
+    assert _ibs_ws(g, vb=10, ve=20)[0] == 0
+
+
+def test_calls_reject_before_launch():
+    lib = N.load()
+    g = _g(100, 50)
+    fake = 0x2000
+    # short workspace
+    rc = lib.pg_ibs_matrix(ctypes.byref(g), None, 0, 0, 0, N.PG_FULL, 0, fake, fake, fake, fake,
+                           fake, 16, None)
+    assert rc == N.PG_ENOMEM
+    # NULL output
+    rc = lib.pg_ibs_matrix(ctypes.byref(g), None, 0, 0, 0, N.PG_FULL, 0, None, fake, fake, fake,
+                           fake, 1 << 30, None)
+    assert rc == N.PG_EINVAL
+    # bad layout
+    rc = lib.pg_ibs_matrix(ctypes.byref(g), None, 0, 0, 0, 5, 0, fake, fake, fake, fake,
+                           fake, 1 << 30, None)
+    assert rc == N.PG_EINVAL
+    # one sample, triangle layout: nothing to do, NULL outputs accepted
+    g1 = _g(1, 50)
+    rc = lib.pg_ibs_matrix(ctypes.byref(g1), None, 0, 0, 0, N.PG_TRI_UPPER, 0, None, None, None,
+                           None, None, 0, None)
+    assert rc == N.PG_OK
+    # LD: NULL n_out, negative capacity, NULL out with capacity
+    rc = lib.pg_ld_window(ctypes.byref(g), None, 0, 0, 0, 10, 0.2, fake, 10, None, 0, fake,
+                          1 << 30, None)
+    assert rc == N.PG_EINVAL
+    rc = lib.pg_ld_window(ctypes.byref(g), None, 0, 0, 0, 10, 0.2, fake, -1, fake, 0, fake,
+                          1 << 30, None)
+    assert rc == N.PG_EINVAL
+    rc = lib.pg_ld_window(ctypes.byref(g), None, 0, 0, 0, 10, 0.2, None, 5, fake, 0, fake,
+                          1 << 30, None)
+    assert rc == N.PG_EINVAL
+    rc = lib.pg_ld_window(ctypes.byref(g), None, 0, 0, 0, 10, 0.2, fake, 5, fake, 0, fake,
+                          8, None)
+    assert rc == N.PG_ENOMEM

@@ -1,0 +1,137 @@
+"""GPU parity for LD windows: counts bit-exact, r^2 within 1e-12 of the
+oracle, the emitted set equal up to pairs whose oracle r^2 lies within 1e-12
+of the threshold (the two sides evaluate r^2 by different double
+expressions), order (a, b), capacity protocol, determinism."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+pg = pytest.importorskip("paper_1410_4803_amd")
+
+TOL = 1e-12
+FIELDS = ("n", "sx", "sy", "sxx", "syy", "sxy")
+
+
+def _compare(got, ref, r2_min):
+    kg = got["a"].astype(np.int64) * (1 << 32) + got["b"]
+    kr = ref["a"].astype(np.int64) * (1 << 32) + ref["b"]
+    assert (np.diff(kg) > 0).all(), "GPU records not in (a, b) order"
+    common, ig, ir = np.intersect1d(kg, kr, return_indices=True)
+    only_g = np.setdiff1d(np.arange(len(kg)), ig)
+    only_r = np.setdiff1d(np.arange(len(kr)), ir)
+    # pairs on one side only must sit on the threshold
+    assert all(abs(got["r2"][k] - r2_min) <= TOL for k in only_g), got[only_g][:5]
+    assert all(abs(ref["r2"][k] - r2_min) <= TOL for k in only_r), ref[only_r][:5]
+    for f in FIELDS:
+        assert np.array_equal(got[f][ig], ref[f][ir]), f
+    d = np.abs(got["r2"][ig] - ref["r2"][ir])
+    assert np.nanmax(d, initial=0.0) <= TOL
+    return len(common)
+
+
+def _run(bed, n, W, r2_min, mask=None, **kw):
+    c = pg.Cohort.from_numpy(bed, n, mask)
+    return pg.ld_records(c, W, r2_min, **kw)
+
+
+@pytest.mark.parametrize("n,V,W", [(1, 5, 3), (2, 40, 7), (17, 65, 64), (63, 130, 65),
+                                   (64, 300, 1), (129, 257, 100), (300, 700, 257),
+                                   (1000, 400, 1000)])
+def test_ld_all_pairs_small(n, V, W):
+    """Every in-window pair with a defined r^2 (threshold -inf)."""
+    bed = synth.mosaic(n, V, switch=0.02, miss=0.05, seed=n + V + W, garbage_pad=True)
+    codes = oracle.unpack(bed, n, V)
+    ref = oracle.ld_window(codes, W, -np.inf)
+    got = _run(bed, n, W, -np.inf)
+    assert len(got) == len(ref)
+    _compare(got, ref, -np.inf)
+
+
+@pytest.mark.parametrize("r2_min", [0.2, 0.5, 0.9])
+def test_ld_threshold(r2_min):
+    n, V, W = 500, 3000, 300
+    bed = synth.mosaic(n, V, switch=0.005, miss=0.01, seed=3)
+    codes = oracle.unpack(bed, n, V)
+    ref = oracle.ld_window(codes, W, r2_min)
+    got = _run(bed, n, W, r2_min)
+    assert _compare(got, ref, r2_min) > 0
+
+
+def test_ld_mask_selection_range():
+    n, V, W = 400, 2000, 150
+    bed = synth.mosaic(n, V, switch=0.01, miss=0.01, seed=8, garbage_pad=True)
+    mask = synth.missing_mask(n, V, 0.05, seed=9)
+    rng = np.random.default_rng(1)
+    idx = rng.integers(0, n, 333).astype(np.int32)
+    vb, ve = 77, 1911
+    codes = oracle.select(oracle.unpack(bed, n, V, mask), idx, vb, ve)
+    ref = oracle.ld_window(codes, W, 0.2)
+    ref["a"] += vb
+    ref["b"] += vb
+    got = _run(bed, n, W, 0.2, mask, sample_idx=torch.from_numpy(idx).cuda(), v_range=(vb, ve))
+    assert _compare(got, ref, 0.2) > 0
+
+
+def test_ld_special_variants():
+    n, V = 200, 60
+    bed = synth.mosaic(n, V, switch=0.05, miss=0.02, seed=12)
+    codes = oracle.unpack(bed, n, V)
+    codes[10] = codes[9]                          # duplicate -> r2 = 1 exactly
+    codes[20] = np.where(codes[19] == 0, 3, np.where(codes[19] == 3, 0, codes[19]))
+    codes[30] = 3                                 # monomorphic -> undefined, never emitted
+    codes[40] = 1                                 # all missing
+    packed = np.zeros((V, (n + 3) // 4), dtype=np.uint8)
+    for k in range(n):
+        packed[:, k // 4] |= (codes[:, k].astype(np.uint8) << (2 * (k % 4)))
+    got = _run(packed, n, 20, -np.inf)
+    ref = oracle.ld_window(codes, 20, -np.inf)
+    _compare(got, ref, -np.inf)
+    dup = got[(got["a"] == 9) & (got["b"] == 10)]
+    assert len(dup) == 1 and dup["r2"][0] == 1.0 and dup["sxy"][0] == dup["sxx"][0]
+    neg = got[(got["a"] == 19) & (got["b"] == 20)]
+    assert neg["r2"][0] == 1.0 and neg["sxy"][0] == -neg["sxx"][0]
+    assert not np.isin(got["a"], [30, 40]).any() and not np.isin(got["b"], [30, 40]).any()
+    assert ((got["r2"] >= 0) & (got["r2"] <= 1)).all()
+
+
+def test_ld_capacity_protocol_and_determinism():
+    n, V, W = 300, 1500, 200
+    bed = synth.mosaic(n, V, switch=0.005, miss=0.01, seed=5)
+    c = pg.Cohort.from_numpy(bed, n)
+    full = pg.ld_records(c, W, 0.2)
+    assert len(full) > 50
+    out, n_out = pg.ld_window(c, W, 0.2, capacity=50)
+    assert int(n_out.item()) == len(full)
+    part = pg.records_to_numpy(out, 50)
+    assert part.tobytes() == full[:50].tobytes()
+    out0, n0 = pg.ld_window(c, W, 0.2, capacity=0)
+    assert int(n0.item()) == len(full)
+    again = pg.ld_records(c, W, 0.2)
+    assert again.tobytes() == full.tobytes()
+
+
+@pytest.fixture(scope="module")
+def ld_large():
+    w = synth.ld_large()
+    return w, pg.Cohort.from_numpy(w["bed"], w["n"])
+
+
+def test_ld_large_workload_sampled(ld_large):
+    """5,000 samples x 500,000 variants, window 1,000, r^2 >= 0.2, in the
+    benchmark's launch configuration; the oracle recomputes every pair of
+    three row ranges (including the first and last rows)."""
+    w, c = ld_large
+    n, V, W = w["n"], w["V"], w["window"]
+    got = pg.ld_records(c, W, w["r2_min"])
+    assert len(got) > 0
+    assert (np.diff(got["a"].astype(np.int64) * (1 << 32) + got["b"]) > 0).all()
+    codes = oracle.unpack(w["bed"], n, V)
+    for a0, a1 in [(0, 120), (250_000, 250_120), (V - 150, V)]:
+        ref = oracle.ld_window(codes, W, w["r2_min"], a_begin=a0, a_end=a1)
+        sel = got[(got["a"] >= a0) & (got["a"] < a1)]
+        assert _compare(sel, ref, w["r2_min"]) > 0
