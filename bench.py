@@ -1,0 +1,307 @@
+"""Benchmark: genotype-pair comparisons per second on one MI355X.
+
+Default workload: the 10,000-sample x 100,000-variant identity-by-state
+matrix (founder-mosaic genotypes, 2% missing, full 10k x 10k output), one
+pg_ibs_matrix call per step (operand layout + pair kernel), inputs resident in
+HBM.  Prints ONE JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--path auto|mfma|popc]
+                    [--no-cpu] [--quick] [--copy-calibration]
+
+Extras in the same line: the LD window workload (5,000 x 500,000, window
+1,000, r^2 >= 0.2), the 500 x 5,000 matrix latency, and the other IBS path at
+the default workload.  `roofline` comes from per-launch HIP-event timings of
+the pair kernel recorded by the library on the launch stream
+(pg_profile_events); `cpu_baseline` times the CPU oracle on a bounded sample
+of the same workload on this host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_INT8_TOPS = 5000.0        # MI355X dense int8 MFMA, 5.0 POP/s
+PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12   # 32-bit integer VALU lane-ops/s, 39.3 T
+PEAK_HBM_GBS = 8000.0
+# algorithmic work per unique genotype-pair comparison (one pair, one variant)
+IBS_MFMA_OPS = 4 * 2          # four int8 contractions: 4 MACs = 8 ops
+IBS_POPC_OPS = 10 / 32        # 10 VALU ops per 32-variant word
+LD_MFMA_OPS = 6 * 2           # six int8 contractions
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+class HipEvents:
+    """hipEvent_t handles through the HIP runtime (libpg links it)."""
+
+    def __init__(self):
+        self.rt = ctypes.CDLL("libamdhip64.so")
+        self.rt.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.rt.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p,
+                                                ctypes.c_void_p]
+        self.rt.hipEventDestroy.argtypes = [ctypes.c_void_p]
+
+    def create(self, n: int):
+        evs = []
+        for _ in range(n):
+            e = ctypes.c_void_p()
+            if self.rt.hipEventCreate(ctypes.byref(e)) != 0:
+                raise RuntimeError("hipEventCreate failed")
+            evs.append(e.value)
+        return evs
+
+    def ms(self, a, b) -> float:
+        out = ctypes.c_float()
+        if self.rt.hipEventElapsedTime(ctypes.byref(out), ctypes.c_void_p(a), ctypes.c_void_p(b)) != 0:
+            raise RuntimeError("hipEventElapsedTime failed")
+        return float(out.value)
+
+    def destroy(self, evs):
+        for e in evs:
+            self.rt.hipEventDestroy(ctypes.c_void_p(e))
+
+
+def set_stage_events(lib, evs):
+    if evs is None:
+        lib.pg_profile_events(None, 0)
+    else:
+        arr = (ctypes.c_void_p * len(evs))(*evs)
+        if lib.pg_profile_events(arr, len(evs)) != 0:
+            raise RuntimeError("pg_profile_events failed")
+
+
+def timed_steps(torch, lib, hip, call, steps, warmup, n_events):
+    """Runs warmup + timed steps of `call`; returns (ms_per_step, per-stage
+    per-launch durations in ms)."""
+    for _ in range(warmup):
+        call()
+    torch.cuda.synchronize()
+    evs = [hip.create(n_events) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        set_stage_events(lib, evs[k])
+        call()
+    set_stage_events(lib, None)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages = [[hip.ms(e[s], e[s + 1]) for e in evs] for s in range(n_events - 1)]
+    for e in evs:
+        hip.destroy(e)
+    return (t1 - t0) * 1e3 / steps, stages
+
+
+def mean(xs):
+    return sum(xs) / len(xs)
+
+
+def traffic_from_profile(kernel_src: str, kernel: str):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f).get(kernel)
+    if not rec:
+        return None
+    with open(kernel_src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if rec.get("source_sha256") != sha:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline_ibs(bed, n, V, budget_s: float):
+    """Times the CPU oracle on the first s samples (all variants, strict upper
+    triangle), s chosen for about `budget_s` seconds of host work."""
+    import numpy as np
+    import oracle
+    codes = oracle.unpack(bed, n, V)          # variant-major int8 (V, n)
+
+    def run(s):
+        sub = np.ascontiguousarray(codes[:, :s])
+        t = time.perf_counter()
+        oracle.ibs_matrix(sub, full=False)
+        return time.perf_counter() - t
+
+    s0 = 160
+    t0 = run(s0)
+    rate = s0 * (s0 - 1) / 2 * V / max(t0, 1e-6)
+    s = int(math.sqrt(2 * budget_s * rate / V))
+    s = max(s0, min(s, n))
+    t = run(s)
+    comps = s * (s - 1) / 2 * V
+    return {"value": round(comps / t / 1e9, 3), "unit": "G/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"first {s} samples x all {V} variants of the workload, strict upper "
+                      f"triangle ({comps:.3e} comparisons, {t:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--path", default="mfma", choices=["auto", "mfma", "popc"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--quick", action="store_true", help="default workload only, no extras")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (HBM counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    import paper_1410_4803_amd as pg
+    from paper_1410_4803_amd import _native as N
+
+    torch.cuda.set_device(0)
+    lib = N.load()
+    hip = HipEvents()
+    dev = torch.device("cuda:0")
+
+    # ---- default workload: IBS 10,000 x 100,000, full matrix ----
+    log("generating the 10000 x 100000 mosaic panel")
+    w = synth.ibs_large()
+    n, V = w["n"], w["V"]
+    cohort = pg.Cohort.from_numpy(w["bed"], n, device=dev)
+    comps = n * (n - 1) / 2 * V
+
+    def ibs_runner(path):
+        out = tuple(torch.empty((n, n), dtype=torch.int32, device=dev) for _ in range(4))
+        ws = torch.empty(pg.ibs_workspace_bytes(cohort, path=path), dtype=torch.uint8, device=dev)
+        return lambda: pg.ibs_matrix(cohort, layout="full", path=path, out=out, workspace=ws), out
+
+    path = "mfma" if args.path == "auto" else args.path
+    call, out = ibs_runner(path)
+    log(f"timing {args.steps} steps ({args.warmup} warmup), path {path}")
+    ms, stages = timed_steps(torch, lib, hip, call, args.steps, args.warmup, 3)
+    layout_ms, pair_ms = mean(stages[0]), mean(stages[1])
+    if path == "mfma":
+        ops = comps * IBS_MFMA_OPS
+        roof = {"bound": "mfma", "achieved": ops / (pair_ms * 1e-3) / 1e12, "peak": PEAK_INT8_TOPS,
+                "unit": "TOP/s", "kernel": "k_ibs_mfma"}
+    else:
+        ops = comps * IBS_POPC_OPS
+        roof = {"bound": "alu", "achieved": ops / (pair_ms * 1e-3) / 1e12, "peak": PEAK_VALU_TOPS,
+                "unit": "TOP/s", "kernel": "k_ibs_popc"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = traffic_from_profile(
+        os.path.join(ROOT, "paper_1410_4803_amd", "csrc", "ibs.hip"), roof["kernel"])
+    roof["achieved"] = round(roof["achieved"], 2)
+    roof["frac"] = round(roof["frac"], 4)
+    roof["launch_ms"] = round(pair_ms, 4)
+
+    result = {
+        "metric": "genotype-pair comparisons/sec (G/s)",
+        "value": round(comps / (ms * 1e-3) / 1e9, 1),
+        "unit": "G/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8" if path == "mfma" else "u32",
+        "data": "synthetic",
+        "config": {"workload": w["name"], "n_samples": n, "n_variants": V, "layout": "full",
+                   "path": path, "comparisons_per_step": comps},
+        "roofline": roof,
+        "stages_ms": {"layout": round(layout_ms, 4), "pair_kernel": round(pair_ms, 4)},
+    }
+    # sanity: the timed output is the IBS matrix (symmetric, sums agree)
+    torch.cuda.synchronize()
+    i0, i1, i2, nm = out
+    assert torch.equal(i0 + i1 + i2, nm) and torch.equal(nm, nm.T)
+    del out, call
+
+    extras = {}
+    if not args.quick:
+        other = "popc" if path == "mfma" else "mfma"
+        call2, out2 = ibs_runner(other)
+        log(f"timing the {other} path")
+        ms2, st2 = timed_steps(torch, lib, hip, call2, max(3, args.steps // 2), 1, 3)
+        extras[f"ibs_large_{other}"] = {"value": round(comps / (ms2 * 1e-3) / 1e9, 1), "unit": "G/s",
+                                        "ms_per_step": round(ms2, 3),
+                                        "pair_kernel_ms": round(mean(st2[1]), 3)}
+        del call2, out2
+        torch.cuda.empty_cache()
+
+        # IBS 500 x 5,000 (strict upper triangle): latency-bound
+        ws_ = synth.ibs_small()
+        c1 = pg.Cohort.from_numpy(ws_["bed"], ws_["n"], device=dev)
+        comps1 = ws_["n"] * (ws_["n"] - 1) / 2 * ws_["V"]
+        for p1 in ("mfma", "popc"):
+            o1 = tuple(torch.empty(124750, dtype=torch.int32, device=dev) for _ in range(4))
+            wk1 = torch.empty(pg.ibs_workspace_bytes(c1, path=p1), dtype=torch.uint8, device=dev)
+            ms1, st1 = timed_steps(torch, lib, hip, lambda: pg.ibs_matrix(
+                c1, layout="tri", path=p1, out=o1, workspace=wk1), 20, 5, 3)
+            extras[f"ibs_small_{p1}"] = {"value": round(comps1 / (ms1 * 1e-3) / 1e9, 1),
+                                         "unit": "G/s", "us_per_call": round(ms1 * 1e3, 1),
+                                         "pair_kernel_us": round(mean(st1[1]) * 1e3, 1)}
+
+        # LD 5,000 x 500,000, window 1,000, r^2 >= 0.2
+        log("generating the 5000 x 500000 LD panel")
+        wl = synth.ld_large()
+        cl = pg.Cohort.from_numpy(wl["bed"], wl["n"], device=dev)
+        W = wl["window"]
+        Vl = wl["V"]
+        pairs = sum(min(W, Vl - 1 - a) for a in range(Vl))
+        compsl = pairs * wl["n"]
+        cap = 4_000_000
+        ol = torch.empty((cap, 64), dtype=torch.uint8, device=dev)
+        nl = torch.empty(1, dtype=torch.int64, device=dev)
+        wkl = torch.empty(pg.ld_workspace_bytes(cl, W), dtype=torch.uint8, device=dev)
+        msl, stl = timed_steps(torch, lib, hip, lambda: pg.ld_window(
+            cl, W, wl["r2_min"], capacity=cap, out=ol, n_out=nl, workspace=wkl), args.steps, 2, 5)
+        band_ms = mean(stl[1])
+        extras["ld_large"] = {
+            "workload": wl["name"], "value": round(compsl / (msl * 1e-3) / 1e9, 1), "unit": "G/s",
+            "ms_per_step": round(msl, 3), "pairs": pairs, "emitted": int(nl.item()),
+            "stages_ms": {"layout": round(mean(stl[0]), 3), "band_kernel": round(band_ms, 3),
+                          "scan": round(mean(stl[2]), 3), "emit": round(mean(stl[3]), 3)},
+            "roofline": {"bound": "mfma", "kernel": "k_ld_mfma", "unit": "TOP/s",
+                         "achieved": round(compsl * LD_MFMA_OPS / (band_ms * 1e-3) / 1e12, 2),
+                         "peak": PEAK_INT8_TOPS,
+                         "frac": round(compsl * LD_MFMA_OPS / (band_ms * 1e-3) / 1e12
+                                       / PEAK_INT8_TOPS, 4)}}
+        del ol, wkl, cl
+
+    if args.copy_calibration:
+        # plain device copy of exactly 1 GiB, for the HBM byte counters
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    if extras:
+        result["extras"] = extras
+    if not args.no_cpu:
+        log("timing the CPU oracle on a bounded sample")
+        result["cpu_baseline"] = cpu_baseline_ibs(w["bed"], n, V, args.cpu_budget)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -61,6 +61,19 @@ const char* pg_last_error(void);
 /* PG_VERSION of the built library. */
 int pg_version(void);
 
+/*
+ * Stage timing, for measurement.  After this call, every pg_* compute call
+ * made by the calling thread records events[0] on its stream before its first
+ * kernel and events[k] after its k-th stage, for k < n_events:
+ *   pg_ibs_matrix: stage 1 = operand layout, stage 2 = pair kernel;
+ *   pg_ld_window:  stage 1 = operand layout and scratch clearing,
+ *                  stage 2 = banded pair kernel, 3 = scan, 4 = emit.
+ * events are hipEvent_t handles created and owned by the caller; they must
+ * stay valid while set.  NULL (or n_events = 0) turns recording off.
+ * Returns PG_EINVAL for n_events < 0 or > 16.
+ */
+int pg_profile_events(void* const* events, int n_events);
+
 /* A genotype matrix resident in device memory. */
 typedef struct pg_genotypes {
   const uint8_t* bed;          /* variant-major .bed payload (device) */

@@ -23,7 +23,8 @@ LAYOUTS = {"tri": PG_TRI_UPPER, "full": PG_FULL}
 PATHS = {"auto": PG_PATH_AUTO, "popc": PG_PATH_POPC, "mfma": PG_PATH_MFMA}
 
 # ABI symbols (include/pg.h)
-SYMBOLS = ("pg_status_str", "pg_last_error", "pg_version", "pg_ibs_workspace_bytes",
+SYMBOLS = ("pg_status_str", "pg_last_error", "pg_version", "pg_profile_events",
+           "pg_ibs_workspace_bytes",
            "pg_ibs_matrix", "pg_ld_workspace_bytes", "pg_ld_window")
 
 LD_PAIR = np.dtype([("a", "<i4"), ("b", "<i4"), ("n", "<i8"), ("sx", "<i8"), ("sy", "<i8"),
@@ -63,6 +64,8 @@ def load():
     lib.pg_last_error.restype = ctypes.c_char_p
     lib.pg_version.argtypes = []
     lib.pg_version.restype = ctypes.c_int
+    lib.pg_profile_events.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int]
+    lib.pg_profile_events.restype = ctypes.c_int
     lib.pg_ibs_workspace_bytes.argtypes = [gp, i64, i64, i64, ctypes.c_int, ctypes.POINTER(sz)]
     lib.pg_ibs_workspace_bytes.restype = ctypes.c_int
     lib.pg_ibs_matrix.argtypes = [gp, p, i64, i64, i64, ctypes.c_int, ctypes.c_int, p, p, p, p, p,

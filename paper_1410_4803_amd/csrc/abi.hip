@@ -19,6 +19,13 @@ int fail(int status, const char* fmt, ...) {
   return status;
 }
 
+static thread_local hipEvent_t g_events[16];
+static thread_local int g_n_events = 0;
+
+void mark_stage(int k, hipStream_t st) {
+  if (k < g_n_events && g_events[k]) (void)hipEventRecord(g_events[k], st);
+}
+
 int check_launch(const char* what) {
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(PG_EDEVICE, "%s: %s", what, hipGetErrorString(e));
@@ -149,6 +156,13 @@ const char* pg_last_error(void) { return g_last_error; }
 
 int pg_version(void) { return PG_VERSION; }
 
+int pg_profile_events(void* const* events, int n_events) {
+  if (n_events < 0 || n_events > 16) return fail(PG_EINVAL, "n_events %d outside [0, 16]", n_events);
+  g_n_events = events ? n_events : 0;
+  for (int k = 0; k < g_n_events; ++k) g_events[k] = (hipEvent_t)events[k];
+  return PG_OK;
+}
+
 int pg_ibs_workspace_bytes(const pg_genotypes* g, int64_t n_sel, int64_t v_begin, int64_t v_end,
                            int path, size_t* bytes) {
   if (!bytes) return fail(PG_EINVAL, "bytes is NULL");
@@ -184,13 +198,17 @@ int pg_ibs_matrix(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_se
   hipStream_t st = (hipStream_t)stream;
   IbsOut o{ibs0, ibs1, ibs2, nonmiss, s.m, out_layout == PG_FULL};
   uint32_t* ws = (uint32_t*)workspace;
+  mark_stage(0, st);
   if (p.path == PG_PATH_MFMA) {
     rc = launch_sample_major_2bit(s, ws, p.rows_pad, p.words, st);
+    mark_stage(1, st);
     if (rc == PG_OK) rc = launch_ibs_mfma(ws, p.words, o, st);
   } else {
     rc = launch_ibs_planes(s, ws, p.rows_pad, p.words, st);
+    mark_stage(1, st);
     if (rc == PG_OK) rc = launch_ibs_popc(ws, p.rows_pad, p.words, o, st);
   }
+  mark_stage(2, st);
   return rc;
 }
 
@@ -229,6 +247,7 @@ int pg_ld_window(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_sel
   uint32_t* D = (uint32_t*)(ws + p.off_D);
   LdScratch sc{(uint32_t*)(ws + p.off_bm), p.bm_words, (uint32_t*)(ws + p.off_cnt),
                (int64_t*)(ws + p.off_off)};
+  mark_stage(0, st);
   rc = launch_variant_major_2bit(s, D, p.rows_pad, p.wn, st);
   if (rc == PG_OK) rc = launch_ld_mfma(D, p.wn, s.nv, p.rows_pad, window, r2_min, sc, st);
   if (rc == PG_OK)

@@ -125,12 +125,15 @@ int launch_ld_mfma(const uint32_t* D, int64_t wn, int64_t nv, int64_t rows_pad, 
   int rc = fill_u32(sc.bitmap, rows_pad * sc.bm_words, 0u, st);
   if (rc == PG_OK) rc = fill_u32(sc.rowcnt, rows_pad, 0u, st);
   if (rc != PG_OK) return rc;
+  mark_stage(1, st);
   const int64_t n_row_tiles = rows_pad / kL;
   const int64_t n_band = ((int64_t)window + kL - 1) / kL + 1;
   const int64_t blocks = n_row_tiles * n_band;
   hipLaunchKernelGGL(k_ld_mfma, dim3((unsigned)blocks), dim3(256), 0, st, D, wn, nv, n_row_tiles,
                      n_band, window, r2_min, sc);
-  return check_launch("ld_mfma");
+  rc = check_launch("ld_mfma");
+  mark_stage(2, st);
+  return rc;
 }
 
 // ---- scan: row counts -> row offsets, total -> *n_out ----------------------------
@@ -223,10 +226,14 @@ int launch_ld_finish(const uint32_t* D, int64_t wn, int64_t nv, int64_t v0, int3
   (void)window;
   hipLaunchKernelGGL(k_ld_scan, dim3(1), dim3(1024), 0, st, sc.rowcnt, nv, sc.rowoff, n_out);
   int rc = check_launch("ld_scan");
-  if (rc != PG_OK || capacity <= 0) return rc;
-  hipLaunchKernelGGL(k_ld_emit, dim3((unsigned)ceil_div(nv, 4)), dim3(256), 0, st, D, wn, nv, v0,
-                     sc, out, capacity);
-  return check_launch("ld_emit");
+  mark_stage(3, st);
+  if (rc == PG_OK && capacity > 0) {
+    hipLaunchKernelGGL(k_ld_emit, dim3((unsigned)ceil_div(nv, 4)), dim3(256), 0, st, D, wn, nv,
+                       v0, sc, out, capacity);
+    rc = check_launch("ld_emit");
+  }
+  mark_stage(4, st);
+  return rc;
 }
 
 }  // namespace pg

@@ -12,6 +12,8 @@ namespace pg {
 int fail(int status, const char* fmt, ...);
 // Checks the last HIP launch error; returns PG_OK or PG_EDEVICE.
 int check_launch(const char* what);
+// Records the caller's stage event k (pg_profile_events) on `st`, if set.
+void mark_stage(int k, hipStream_t st);
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
