@@ -94,7 +94,9 @@ enum pg_layout {
   PG_FULL = 1       /* m x m row-major, both halves and the diagonal */
 };
 
-/* Kernel path. */
+/* Kernel path.  The low 8 bits of a `path` argument select the path; bits
+ * 8-15 select a kernel variant of that path (0 = the library's default; the
+ * tuner tries the others).  Unknown variants fall back to the default. */
 enum pg_path {
   PG_PATH_AUTO = 0, /* library picks per shape */
   PG_PATH_POPC = 1, /* bit planes + popcount on the vector ALUs */

@@ -89,11 +89,15 @@ int make_sel(const pg_genotypes* g, bool list, const int32_t* idx, int64_t n_sel
 
 struct IbsPlan {
   int path;
+  int variant;
   int64_t rows_pad, words;  // operand rows and K words
   int64_t bytes;
 };
 
-int plan_ibs(const Sel& s, int path, IbsPlan& p) {
+int plan_ibs(const Sel& s, int path_arg, IbsPlan& p) {
+  int path = path_arg & 0xFF;
+  p.variant = (path_arg >> 8) & 0xFF;
+  if (path_arg < 0 || (path_arg >> 16) != 0) return fail(PG_EINVAL, "bad path argument %d", path_arg);
   if (path == PG_PATH_AUTO) path = PG_PATH_MFMA;
   if (path != PG_PATH_MFMA && path != PG_PATH_POPC)
     return fail(PG_EINVAL, "unknown path %d", path);
@@ -114,7 +118,7 @@ int plan_ibs(const Sel& s, int path, IbsPlan& p) {
 
 struct LdPlan {
   int64_t rows_pad, wn, bm_words;
-  int64_t off_D, off_bm, off_cnt, off_off, bytes;
+  int64_t off_D, off_bm, off_cnt, off_off, off_bsum, bytes;
 };
 
 int plan_ld(const Sel& s, int32_t window, int path, LdPlan& p) {
@@ -130,6 +134,7 @@ int plan_ld(const Sel& s, int32_t window, int path, LdPlan& p) {
   p.off_bm = c.take(p.rows_pad * p.bm_words * 4);
   p.off_cnt = c.take(p.rows_pad * 4);
   p.off_off = c.take((p.rows_pad + 1) * 8);
+  p.off_bsum = c.take((int64_t)ld_scan_blocks(p.rows_pad) * 8);
   p.bytes = c.off;
   return PG_OK;
 }
@@ -202,7 +207,7 @@ int pg_ibs_matrix(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_se
   if (p.path == PG_PATH_MFMA) {
     rc = launch_sample_major_2bit(s, ws, p.rows_pad, p.words, st);
     mark_stage(1, st);
-    if (rc == PG_OK) rc = launch_ibs_mfma(ws, p.words, o, st);
+    if (rc == PG_OK) rc = launch_ibs_mfma(ws, p.words, o, p.variant, st);
   } else {
     rc = launch_ibs_planes(s, ws, p.rows_pad, p.words, st);
     mark_stage(1, st);
@@ -246,7 +251,7 @@ int pg_ld_window(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_sel
   char* ws = (char*)workspace;
   uint32_t* D = (uint32_t*)(ws + p.off_D);
   LdScratch sc{(uint32_t*)(ws + p.off_bm), p.bm_words, (uint32_t*)(ws + p.off_cnt),
-               (int64_t*)(ws + p.off_off)};
+               (int64_t*)(ws + p.off_off), (int64_t*)(ws + p.off_bsum)};
   mark_stage(0, st);
   rc = launch_variant_major_2bit(s, D, p.rows_pad, p.wn, st);
   if (rc == PG_OK) rc = launch_ld_mfma(D, p.wn, s.nv, p.rows_pad, window, r2_min, sc, st);

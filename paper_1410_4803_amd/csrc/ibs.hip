@@ -87,16 +87,177 @@ __device__ __forceinline__ void store_counts(const IbsOut& o, int64_t i, int64_t
 
 // ---- matrix-core path ---------------------------------------------------------
 // Block: 256 threads = 4 waves in a 2x2 grid over a 128x128 tile; each wave
-// owns 64x64 = 2x2 blocks of v_mfma_i32_32x32x32_i8.  K runs over variants in
-// chunks of 16 words (256 variants) staged through LDS.  Within a chunk, lane
-// group g = lane/32 of a 32x32x32 step s reads word 8g + s of its row, i.e.
-// the 16 K values of one MFMA lane are the 16 codes of one 2-bit word.
+// owns 64x64 = 2x2 blocks of v_mfma_i32_32x32x32_i8 and three accumulator sets
+// (G_m, G_w, G_h - G_c).  K runs over variants in chunks of 16 words (256
+// variants).  Lane group g = lane/32 of MFMA step s (0..7) holds the 16 codes
+// of word 8g + s of its row, i.e. one MFMA lane's 16 K values are one 2-bit
+// word.
+//
+// Variant 0 (default) pipelines three things: the next chunk is fetched from
+// global memory into registers while the current one is consumed from one of
+// two LDS buffers; each lane reads its 8 words per row with two 128-bit LDS
+// reads; and the features of step s+1 are expanded while the MFMAs of step s
+// run.  Variant 1 adds explicit interleaving hints (one MFMA, then a few
+// VALU instructions).  Variant 2 is the unpipelined form (single LDS buffer,
+// no prefetch), kept as a reference point for the tuner.
 constexpr int kT = kIbsMfmaTile;
 constexpr int kKW = kIbsMfmaKWords;
 constexpr int kLdsStride = kKW + 4;   // words per LDS row (padding vs. bank conflicts)
 
+struct Feat4 {
+  v4i m, w, h, c;
+};
+
+__device__ __forceinline__ Feat4 expand_a(uint32_t word) {
+  uint32_t c[4];
+  spread_codes(word, c);
+  return Feat4{lookup(kLutM, c), lookup(kLutW, c), lookup(kLutH, c), lookup(kLutC, c)};
+}
+
+__device__ __forceinline__ Feat4 expand_b(uint32_t word) {
+  uint32_t c[4];
+  spread_codes(word, c);
+  return Feat4{lookup(kLutM, c), lookup(kLutW, c), lookup(kLutH, c), lookup(kLutCn, c)};
+}
+
+struct IbsAcc {
+  v16i m[2][2], w[2][2], hc[2][2];
+};
+
+__device__ __forceinline__ void mfma_step(IbsAcc& acc, const Feat4 (&fa)[2], const Feat4 (&fb)[2]) {
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      acc.m[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a].m, fb[b].m, acc.m[a][b], 0, 0, 0);
+      acc.w[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a].w, fb[b].w, acc.w[a][b], 0, 0, 0);
+      acc.hc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a].h, fb[b].h, acc.hc[a][b], 0, 0, 0);
+      acc.hc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a].c, fb[b].c, acc.hc[a][b], 0, 0, 0);
+    }
+}
+
+// 32x32 accumulator layout: register v of lane l holds row
+// 8*(v/4) + 4*(l/32) + v%4 and column l%32 of the block.
+__device__ __forceinline__ void ibs_epilogue(const IbsAcc& acc, const IbsOut& o, int64_t I,
+                                             int64_t J, int wr, int wc, int lane) {
+  const bool mirror = (I != J);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t i = I * kT + wr * 64 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int64_t j = J * kT + wc * 64 + b * 32 + (lane & 31);
+        const uint32_t n = (uint32_t)acc.m[a][b][v];
+        const uint32_t z = (uint32_t)acc.hc[a][b][v] >> 1;
+        const uint32_t one = (n - (uint32_t)acc.w[a][b][v]) >> 1;
+        store_counts(o, i, j, mirror, n, z, one);
+      }
+}
+
+__device__ __forceinline__ void zero_acc(IbsAcc& acc) {
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      acc.m[a][b] = (v16i){0};
+      acc.w[a][b] = (v16i){0};
+      acc.hc[a][b] = (v16i){0};
+    }
+}
+
+template <bool kHints>
 __global__ __launch_bounds__(256, 1) void k_ibs_mfma(const uint32_t* __restrict__ T, int64_t wp,
                                                      int64_t nt, IbsOut o) {
+  __shared__ __attribute__((aligned(16))) uint32_t sA[2][kT * kLdsStride];
+  __shared__ __attribute__((aligned(16))) uint32_t sB[2][kT * kLdsStride];
+  int64_t I, J;
+  tri_tile(blockIdx.x, nt, I, J);
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int wid = t >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  const int g = lane >> 5;
+  const int rl = lane & 31;
+
+  // this thread's share of a chunk: rows t/4 and t/4 + 64, words 4*(t%4)..+3
+  const int lrow = t >> 2;
+  const int lq = (t & 3) * 4;
+  const uint32_t* pa = T + (I * kT + lrow) * wp + lq;
+  const uint32_t* pb = T + (J * kT + lrow) * wp + lq;
+  const int64_t half = 64 * wp;
+  uint4 ga0, ga1, gb0, gb1;
+  auto gload = [&](int64_t kc) {
+    ga0 = *reinterpret_cast<const uint4*>(pa + kc);
+    ga1 = *reinterpret_cast<const uint4*>(pa + half + kc);
+    gb0 = *reinterpret_cast<const uint4*>(pb + kc);
+    gb1 = *reinterpret_cast<const uint4*>(pb + half + kc);
+  };
+  auto lstore = [&](int buf) {
+    *reinterpret_cast<uint4*>(&sA[buf][lrow * kLdsStride + lq]) = ga0;
+    *reinterpret_cast<uint4*>(&sA[buf][(lrow + 64) * kLdsStride + lq]) = ga1;
+    *reinterpret_cast<uint4*>(&sB[buf][lrow * kLdsStride + lq]) = gb0;
+    *reinterpret_cast<uint4*>(&sB[buf][(lrow + 64) * kLdsStride + lq]) = gb1;
+  };
+
+  IbsAcc acc;
+  zero_acc(acc);
+  const int64_t nchunks = wp / kKW;
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int64_t k = 0; k < nchunks; ++k) {
+    const int buf = (int)(k & 1);
+    if (k + 1 < nchunks) gload((k + 1) * kKW);
+    // this lane's 8 words of each of its two A rows and two B rows
+    uint32_t wa[2][8], wb[2][8];
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      const uint32_t* ra = &sA[buf][(wr * 64 + x * 32 + rl) * kLdsStride + g * 8];
+      const uint32_t* rb = &sB[buf][(wc * 64 + x * 32 + rl) * kLdsStride + g * 8];
+      const uint4 a0 = *reinterpret_cast<const uint4*>(ra);
+      const uint4 a1 = *reinterpret_cast<const uint4*>(ra + 4);
+      const uint4 b0 = *reinterpret_cast<const uint4*>(rb);
+      const uint4 b1 = *reinterpret_cast<const uint4*>(rb + 4);
+      wa[x][0] = a0.x; wa[x][1] = a0.y; wa[x][2] = a0.z; wa[x][3] = a0.w;
+      wa[x][4] = a1.x; wa[x][5] = a1.y; wa[x][6] = a1.z; wa[x][7] = a1.w;
+      wb[x][0] = b0.x; wb[x][1] = b0.y; wb[x][2] = b0.z; wb[x][3] = b0.w;
+      wb[x][4] = b1.x; wb[x][5] = b1.y; wb[x][6] = b1.z; wb[x][7] = b1.w;
+    }
+    Feat4 fa[2], fb[2];
+    fa[0] = expand_a(wa[0][0]); fa[1] = expand_a(wa[1][0]);
+    fb[0] = expand_b(wb[0][0]); fb[1] = expand_b(wb[1][0]);
+#pragma unroll
+    for (int s = 0; s < kKW / 2; ++s) {
+      Feat4 na[2], nb[2];
+      if (s + 1 < kKW / 2) {
+        na[0] = expand_a(wa[0][s + 1]); na[1] = expand_a(wa[1][s + 1]);
+        nb[0] = expand_b(wb[0][s + 1]); nb[1] = expand_b(wb[1][s + 1]);
+      }
+      mfma_step(acc, fa, fb);
+      if constexpr (kHints) {
+        // interleave: 1 MFMA, then up to 6 VALU instructions, 16 times
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);
+        }
+      }
+      if (s + 1 < kKW / 2) {
+        fa[0] = na[0]; fa[1] = na[1];
+        fb[0] = nb[0]; fb[1] = nb[1];
+      }
+    }
+    if (k + 1 < nchunks) lstore(buf ^ 1);
+    __syncthreads();
+  }
+  ibs_epilogue(acc, o, I, J, wr, wc, lane);
+}
+
+// Unpipelined reference form (variant 2).
+__global__ __launch_bounds__(256, 1) void k_ibs_mfma_simple(const uint32_t* __restrict__ T,
+                                                            int64_t wp, int64_t nt, IbsOut o) {
   __shared__ __attribute__((aligned(16))) uint32_t sA[kT * kLdsStride];
   __shared__ __attribute__((aligned(16))) uint32_t sB[kT * kLdsStride];
   int64_t I, J;
@@ -107,15 +268,8 @@ __global__ __launch_bounds__(256, 1) void k_ibs_mfma(const uint32_t* __restrict_
   const int wr = wid >> 1, wc = wid & 1;
   const uint32_t* gA = T + I * kT * wp;
   const uint32_t* gB = T + J * kT * wp;
-
-  v16i acc_m[2][2], acc_w[2][2], acc_hc[2][2];
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) {
-      acc_m[a][b] = (v16i){0};
-      acc_w[a][b] = (v16i){0};
-      acc_hc[a][b] = (v16i){0};
-    }
-
+  IbsAcc acc;
+  zero_acc(acc);
   for (int64_t kc = 0; kc < wp; kc += kKW) {
     for (int h = 0; h < 2; ++h) {
       const int r = (t >> 2) + 64 * h;
@@ -131,51 +285,27 @@ __global__ __launch_bounds__(256, 1) void k_ibs_mfma(const uint32_t* __restrict_
 #pragma unroll 2
     for (int s = 0; s < kKW / 2; ++s) {
       const int kw = g * (kKW / 2) + s;
-      v4i fm_a[2], fw_a[2], fh_a[2], fc_a[2];
-      v4i fm_b[2], fw_b[2], fh_b[2], fc_b[2];
+      Feat4 fa[2], fb[2];
       for (int x = 0; x < 2; ++x) {
-        uint32_t c[4];
-        spread_codes(sA[(wr * 64 + x * 32 + rl) * kLdsStride + kw], c);
-        fm_a[x] = lookup(kLutM, c);
-        fw_a[x] = lookup(kLutW, c);
-        fh_a[x] = lookup(kLutH, c);
-        fc_a[x] = lookup(kLutC, c);
-        spread_codes(sB[(wc * 64 + x * 32 + rl) * kLdsStride + kw], c);
-        fm_b[x] = lookup(kLutM, c);
-        fw_b[x] = lookup(kLutW, c);
-        fh_b[x] = lookup(kLutH, c);
-        fc_b[x] = lookup(kLutCn, c);
+        fa[x] = expand_a(sA[(wr * 64 + x * 32 + rl) * kLdsStride + kw]);
+        fb[x] = expand_b(sB[(wc * 64 + x * 32 + rl) * kLdsStride + kw]);
       }
-      for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) {
-          acc_m[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fm_a[a], fm_b[b], acc_m[a][b], 0, 0, 0);
-          acc_w[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fw_a[a], fw_b[b], acc_w[a][b], 0, 0, 0);
-          acc_hc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fh_a[a], fh_b[b], acc_hc[a][b], 0, 0, 0);
-          acc_hc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fc_a[a], fc_b[b], acc_hc[a][b], 0, 0, 0);
-        }
+      mfma_step(acc, fa, fb);
     }
     __syncthreads();
   }
-
-  // 32x32 accumulator layout: register v of lane l holds row
-  // 8*(v/4) + 4*(l/32) + v%4 and column l%32 of the block.
-  const bool mirror = (I != J);
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b)
-      for (int v = 0; v < 16; ++v) {
-        const int64_t i = I * kT + wr * 64 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-        const int64_t j = J * kT + wc * 64 + b * 32 + (lane & 31);
-        const uint32_t n = (uint32_t)acc_m[a][b][v];
-        const uint32_t z = (uint32_t)acc_hc[a][b][v] >> 1;
-        const uint32_t one = (n - (uint32_t)acc_w[a][b][v]) >> 1;
-        store_counts(o, i, j, mirror, n, z, one);
-      }
+  ibs_epilogue(acc, o, I, J, wr, wc, lane);
 }
 
-int launch_ibs_mfma(const uint32_t* T, int64_t wp, const IbsOut& o, hipStream_t st) {
+int launch_ibs_mfma(const uint32_t* T, int64_t wp, const IbsOut& o, int variant, hipStream_t st) {
   const int64_t nt = ceil_div(o.m, kT);
   const int64_t blocks = nt * (nt + 1) / 2;
-  hipLaunchKernelGGL(k_ibs_mfma, dim3((unsigned)blocks), dim3(256), 0, st, T, wp, nt, o);
+  if (variant == 1)
+    hipLaunchKernelGGL(k_ibs_mfma<true>, dim3((unsigned)blocks), dim3(256), 0, st, T, wp, nt, o);
+  else if (variant == 2)
+    hipLaunchKernelGGL(k_ibs_mfma_simple, dim3((unsigned)blocks), dim3(256), 0, st, T, wp, nt, o);
+  else
+    hipLaunchKernelGGL(k_ibs_mfma<false>, dim3((unsigned)blocks), dim3(256), 0, st, T, wp, nt, o);
   return check_launch("ibs_mfma");
 }
 

@@ -6,6 +6,181 @@
 
 namespace pg {
 
+// ---- helpers for whole-matrix selections (no sample list) -------------------
+// Sixteen consecutive samples of one variant row as a 2-bit word (sample
+// 16g + k at bits 2k), with the missing mask applied and samples >= m forced
+// to missing.  Reads one dword when the row layout allows it, else bytes.
+__device__ __forceinline__ uint32_t spread16(uint32_t x) {
+  // bit k -> bit 2k, for the low 16 bits
+  x &= 0xFFFFu;
+  x = (x | (x << 8)) & 0x00FF00FFu;
+  x = (x | (x << 4)) & 0x0F0F0F0Fu;
+  x = (x | (x << 2)) & 0x33333333u;
+  x = (x | (x << 1)) & 0x55555555u;
+  return x;
+}
+
+__device__ __forceinline__ uint32_t row_word16(const Sel& s, int64_t v, int64_t g, bool aligned) {
+  if (v >= s.nv) return kAllMissing16;
+  const int64_t row = s.v0 + v;
+  const uint8_t* p = s.bed + row * s.bpv + 4 * g;
+  const int64_t avail = s.bpv - 4 * g;          // bytes of this row from byte 4g on
+  uint32_t w;
+  if (aligned && avail >= 4) {
+    w = *reinterpret_cast<const uint32_t*>(p);
+  } else {
+    w = 0;
+    for (int b = 0; b < 4; ++b)
+      if (b < avail) w |= (uint32_t)p[b] << (8 * b);
+  }
+  const int64_t valid = s.m - 16 * g;           // samples of this group inside the matrix
+  if (valid < 16) {
+    const uint32_t keep = valid <= 0 ? 0u : ((1u << (2 * valid)) - 1u);
+    w = (w & keep) | (kAllMissing16 & ~keep);
+  }
+  if (s.mask) {
+    const uint64_t mw = s.mask[row * s.wpm + ((16 * g) >> 6)];
+    const uint32_t lanes = spread16((uint32_t)(mw >> ((16 * g) & 63)));
+    w = (w & ~(lanes | (lanes << 1))) | lanes;  // masked calls -> code 01
+  }
+  return w;
+}
+
+// In-place transpose of a 16x16 matrix of 2-bit elements: element (r, c) at
+// bits 2c of x[r] moves to bits 2r of x[c].  Recursive block swap: exchange
+// the off-diagonal halves, then transpose each half-size block.
+__device__ __forceinline__ void transpose16_2bit(uint32_t x[16]) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const uint32_t t = ((x[r] >> 16) ^ x[r + 8]) & 0x0000FFFFu;
+    x[r] ^= t << 16;
+    x[r + 8] ^= t;
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r)
+    if ((r & 4) == 0) {
+      const uint32_t t = ((x[r] >> 8) ^ x[r + 4]) & 0x00FF00FFu;
+      x[r] ^= t << 8;
+      x[r + 4] ^= t;
+    }
+#pragma unroll
+  for (int r = 0; r < 16; ++r)
+    if ((r & 2) == 0) {
+      const uint32_t t = ((x[r] >> 4) ^ x[r + 2]) & 0x0F0F0F0Fu;
+      x[r] ^= t << 4;
+      x[r + 2] ^= t;
+    }
+#pragma unroll
+  for (int r = 0; r < 16; r += 2) {
+    const uint32_t t = ((x[r] >> 2) ^ x[r + 1]) & 0x33333333u;
+    x[r] ^= t << 2;
+    x[r + 1] ^= t;
+  }
+}
+
+// Sample-major 2-bit words without a sample list: a thread owns 16 samples x
+// 64 variants (four 16x16 transposes) and writes four consecutive words per
+// sample row.  Lanes take consecutive sample groups, so the row reads
+// coalesce.
+__global__ __launch_bounds__(256) void k_sample_major_fast(Sel s, uint32_t* __restrict__ T,
+                                                           int64_t rows_pad, int64_t wp,
+                                                           int aligned) {
+  const int64_t groups = rows_pad / 16;
+  const int64_t quads = wp / 4;
+  const int64_t total = groups * quads;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t g = e % groups;
+    const int64_t q = e / groups;
+    uint32_t out[4][16];
+#pragma unroll
+    for (int ww = 0; ww < 4; ++ww) {
+      const int64_t w = 4 * q + ww;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) out[ww][r] = row_word16(s, 16 * w + r, g, aligned != 0);
+      transpose16_2bit(out[ww]);
+    }
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+      *reinterpret_cast<uint4*>(T + (16 * g + c) * wp + 4 * q) =
+          make_uint4(out[0][c], out[1][c], out[2][c], out[3][c]);
+  }
+}
+
+// Every other bit (bits 0, 2, 4, ... of x) packed into the low 16 bits.
+__device__ __forceinline__ uint32_t compact_even_bits(uint32_t x) {
+  x &= 0x55555555u;
+  x = (x | (x >> 1)) & 0x33333333u;
+  x = (x | (x >> 2)) & 0x0F0F0F0Fu;
+  x = (x | (x >> 4)) & 0x00FF00FFu;
+  x = (x | (x >> 8)) & 0x0000FFFFu;
+  return x;
+}
+
+// Bit planes without a sample list: a thread owns 16 samples x 32 variants
+// (two 16x16 transposes), then splits each sample's 32 codes into the high
+// bit, low bit and non-missing planes; it writes 16 consecutive samples of
+// each plane word.
+__global__ __launch_bounds__(256) void k_ibs_planes_fast(Sel s, uint32_t* __restrict__ P,
+                                                         int64_t rows_pad, int64_t words_pad,
+                                                         int aligned) {
+  const int64_t groups = rows_pad / 16;
+  const int64_t total = groups * words_pad;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t g = e % groups;
+    const int64_t w = e / groups;
+    uint32_t lo16[16], hi16[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) lo16[r] = row_word16(s, 32 * w + r, g, aligned != 0);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) hi16[r] = row_word16(s, 32 * w + 16 + r, g, aligned != 0);
+    transpose16_2bit(lo16);
+    transpose16_2bit(hi16);
+    uint32_t H[16], L[16], M[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      const uint32_t a = lo16[c], b = hi16[c];   // variants 0-15 and 16-31 of sample c
+      const uint32_t miss_a = a & ~(a >> 1) & 0x55555555u;   // code 01
+      const uint32_t miss_b = b & ~(b >> 1) & 0x55555555u;
+      H[c] = compact_even_bits(a >> 1) | (compact_even_bits(b >> 1) << 16);
+      L[c] = compact_even_bits(a) | (compact_even_bits(b) << 16);
+      M[c] = ~(compact_even_bits(miss_a) | (compact_even_bits(miss_b) << 16));
+    }
+    uint32_t* dst = P + (w * 3) * rows_pad + 16 * g;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      *reinterpret_cast<uint4*>(dst + 4 * q) = make_uint4(H[4 * q], H[4 * q + 1], H[4 * q + 2], H[4 * q + 3]);
+      *reinterpret_cast<uint4*>(dst + rows_pad + 4 * q) =
+          make_uint4(L[4 * q], L[4 * q + 1], L[4 * q + 2], L[4 * q + 3]);
+      *reinterpret_cast<uint4*>(dst + 2 * rows_pad + 4 * q) =
+          make_uint4(M[4 * q], M[4 * q + 1], M[4 * q + 2], M[4 * q + 3]);
+    }
+  }
+}
+
+// Variant-major 2-bit words without a sample list: one word per thread.
+__global__ __launch_bounds__(256) void k_variant_major_fast(Sel s, uint32_t* __restrict__ D,
+                                                            int64_t rows_pad, int64_t wn,
+                                                            int aligned) {
+  const int64_t total = rows_pad * wn;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t w = e % wn;
+    const int64_t v = e / wn;
+    D[e] = row_word16(s, v, w, aligned != 0);
+  }
+}
+
+static bool rows_dword_aligned(const Sel& s) {
+  return (s.bpv % 4) == 0 && (reinterpret_cast<uintptr_t>(s.bed) % 4) == 0;
+}
+
+static unsigned stride_grid(int64_t items) {
+  const int64_t b = ceil_div(items, 256);
+  return (unsigned)(b < 65536 ? b : 65536);
+}
+
 // ---- sample-major 2-bit words (IBS, matrix-core path) -----------------------
 // A block owns 64 samples x 64 words (1024 variants).  Each thread packs 16
 // words of one sample from byte reads (a wave reads 16 consecutive bytes per
@@ -48,6 +223,11 @@ __global__ __launch_bounds__(256) void k_sample_major_2bit(Sel s, uint32_t* __re
 
 int launch_sample_major_2bit(const Sel& s, uint32_t* T, int64_t rows_pad, int64_t wp,
                              hipStream_t st) {
+  if (!s.idx && (wp % 4) == 0) {
+    hipLaunchKernelGGL(k_sample_major_fast, dim3(stride_grid(rows_pad / 16 * (wp / 4))), dim3(256),
+                       0, st, s, T, rows_pad, wp, (int)rows_dword_aligned(s));
+    return check_launch("sample_major_fast");
+  }
   dim3 grid((unsigned)(ceil_div(rows_pad, kSmSamples) * ceil_div(wp, kSmWords)));
   hipLaunchKernelGGL(k_sample_major_2bit, grid, dim3(256), 0, st, s, T, rows_pad, wp);
   return check_launch("sample_major_2bit");
@@ -74,6 +254,11 @@ __global__ __launch_bounds__(256) void k_ibs_planes(Sel s, uint32_t* __restrict_
 
 int launch_ibs_planes(const Sel& s, uint32_t* P, int64_t rows_pad, int64_t words_pad,
                       hipStream_t st) {
+  if (!s.idx) {
+    hipLaunchKernelGGL(k_ibs_planes_fast, dim3(stride_grid(rows_pad / 16 * words_pad)), dim3(256),
+                       0, st, s, P, rows_pad, words_pad, (int)rows_dword_aligned(s));
+    return check_launch("ibs_planes_fast");
+  }
   dim3 grid((unsigned)ceil_div(rows_pad * words_pad, 256));
   hipLaunchKernelGGL(k_ibs_planes, grid, dim3(256), 0, st, s, P, rows_pad, words_pad);
   return check_launch("ibs_planes");
@@ -93,6 +278,11 @@ __global__ __launch_bounds__(256) void k_variant_major_2bit(Sel s, uint32_t* __r
 
 int launch_variant_major_2bit(const Sel& s, uint32_t* D, int64_t rows_pad, int64_t wn,
                               hipStream_t st) {
+  if (!s.idx) {
+    hipLaunchKernelGGL(k_variant_major_fast, dim3(stride_grid(rows_pad * wn)), dim3(256), 0, st, s,
+                       D, rows_pad, wn, (int)rows_dword_aligned(s));
+    return check_launch("variant_major_fast");
+  }
   dim3 grid((unsigned)ceil_div(rows_pad * wn, 256));
   hipLaunchKernelGGL(k_variant_major_2bit, grid, dim3(256), 0, st, s, D, rows_pad, wn);
   return check_launch("variant_major_2bit");

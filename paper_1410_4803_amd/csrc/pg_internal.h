@@ -78,7 +78,7 @@ constexpr int kIbsMfmaKWords = 16;    // 2-bit words per K chunk (256 variants)
 constexpr int kIbsPopcTile = 64;
 constexpr int kIbsPopcKWords = 16;    // 32-bit plane words per K chunk
 
-int launch_ibs_mfma(const uint32_t* T, int64_t wp, const IbsOut& o, hipStream_t st);
+int launch_ibs_mfma(const uint32_t* T, int64_t wp, const IbsOut& o, int variant, hipStream_t st);
 int launch_ibs_popc(const uint32_t* P, int64_t rows_pad, int64_t words_pad, const IbsOut& o,
                     hipStream_t st);
 
@@ -91,7 +91,10 @@ struct LdScratch {
   int64_t bm_words;
   uint32_t* rowcnt;    // rows_pad
   int64_t* rowoff;     // rows_pad + 1
+  int64_t* bsum;       // ld_scan_blocks(rows) per-block sums
 };
+// Number of per-block partial sums the row-offset scan needs.
+int ld_scan_blocks(int64_t nv);
 
 int launch_ld_mfma(const uint32_t* D, int64_t wn, int64_t nv, int64_t rows_pad, int32_t window,
                    double r2_min, const LdScratch& sc, hipStream_t st);

@@ -143,3 +143,24 @@ def test_ibs_large_workload_sampled(large, path):
     nonmiss = (codes_sm != 1).sum(1)
     assert np.array_equal(torch.diagonal(nm).cpu().numpy(), nonmiss)
     assert np.array_equal(torch.diagonal(i2).cpu().numpy(), nonmiss)
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("n,extra", [(97, 0), (97, 5), (160, 3), (1000, 0)])
+def test_ibs_mask_and_row_stride(path, n, extra):
+    """Missing mask with all samples (the transposing layout path), rows
+    padded to a stride larger than ceil(n/4) with garbage bytes."""
+    V = 777
+    bed = synth.hwe(n, V, (0.05, 0.5), 0.02, seed=n + extra, garbage_pad=True)
+    mask = synth.missing_mask(n, V, 0.04, seed=n + 1)
+    if extra:
+        junk = np.random.default_rng(n).integers(0, 256, (V, extra), dtype=np.uint8)
+        bed = np.concatenate([bed, junk], axis=1)
+    codes = oracle.unpack(bed, n, V, mask)
+    ref = oracle.ibs_matrix(codes, full=True)
+    got = pg.ibs_matrix(_cohort(bed, n, mask), layout="full", path=path)
+    _check_full(got, ref)
+    for variant in (1, 2):
+        if path == "mfma":
+            got = pg.ibs_matrix(_cohort(bed, n, mask), layout="full", path=2 | (variant << 8))
+            _check_full(got, ref)

@@ -135,3 +135,18 @@ def test_ld_large_workload_sampled(ld_large):
         ref = oracle.ld_window(codes, W, w["r2_min"], a_begin=a0, a_end=a1)
         sel = got[(got["a"] >= a0) & (got["a"] < a1)]
         assert _compare(sel, ref, w["r2_min"]) > 0
+
+
+@pytest.mark.parametrize("n,extra", [(97, 0), (160, 5), (1000, 2)])
+def test_ld_mask_and_row_stride(n, extra):
+    V, W = 900, 120
+    bed = synth.mosaic(n, V, switch=0.01, miss=0.01, seed=n + extra, garbage_pad=True)
+    mask = synth.missing_mask(n, V, 0.03, seed=n + 7)
+    if extra:
+        junk = np.random.default_rng(n).integers(0, 256, (V, extra), dtype=np.uint8)
+        bed = np.concatenate([bed, junk], axis=1)
+    codes = oracle.unpack(bed, n, V, mask)
+    ref = oracle.ld_window(codes, W, -np.inf)
+    got = _run(bed, n, W, -np.inf, mask)
+    assert len(got) == len(ref)
+    _compare(got, ref, -np.inf)
