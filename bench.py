@@ -36,6 +36,7 @@ PEAK_HBM_GBS = 8000.0
 IBS_MFMA_OPS = 4 * 2          # four int8 contractions: 4 MACs = 8 ops
 IBS_POPC_OPS = 10 / 32        # 10 VALU ops per 32-variant word
 LD_MFMA_OPS = 6 * 2           # six int8 contractions
+LD_POPC_OPS = 16 / 32         # 16 VALU ops per 32-sample word
 
 
 def log(msg: str) -> None:
@@ -155,6 +156,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--path", default="mfma", choices=["auto", "mfma", "popc"])
+    ap.add_argument("--variant", type=int, default=0, help="kernel variant of the path (tuning)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--quick", action="store_true", help="default workload only, no extras")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
@@ -185,13 +187,14 @@ def main():
     cohort = pg.Cohort.from_numpy(w["bed"], n, device=dev)
     comps = n * (n - 1) / 2 * V
 
-    def ibs_runner(path):
+    def ibs_runner(path, variant=0):
         out = tuple(torch.empty((n, n), dtype=torch.int32, device=dev) for _ in range(4))
         ws = torch.empty(pg.ibs_workspace_bytes(cohort, path=path), dtype=torch.uint8, device=dev)
-        return lambda: pg.ibs_matrix(cohort, layout="full", path=path, out=out, workspace=ws), out
+        code = pg.PATHS[path] | (variant << 8)
+        return lambda: pg.ibs_matrix(cohort, layout="full", path=code, out=out, workspace=ws), out
 
     path = "mfma" if args.path == "auto" else args.path
-    call, out = ibs_runner(path)
+    call, out = ibs_runner(path, args.variant)
     log(f"timing {args.steps} steps ({args.warmup} warmup), path {path}")
     ms, stages = timed_steps(torch, lib, hip, call, args.steps, args.warmup, 3)
     layout_ms, pair_ms = mean(stages[0]), mean(stages[1])
@@ -224,7 +227,7 @@ def main():
         "dtype": "int8" if path == "mfma" else "u32",
         "data": "synthetic",
         "config": {"workload": w["name"], "n_samples": n, "n_variants": V, "layout": "full",
-                   "path": path, "comparisons_per_step": comps},
+                   "path": path, "variant": args.variant, "comparisons_per_step": comps},
         "roofline": roof,
         "stages_ms": {"layout": round(layout_ms, 4), "pair_kernel": round(pair_ms, 4)},
     }
@@ -270,21 +273,32 @@ def main():
         cap = 4_000_000
         ol = torch.empty((cap, 64), dtype=torch.uint8, device=dev)
         nl = torch.empty(1, dtype=torch.int64, device=dev)
-        wkl = torch.empty(pg.ld_workspace_bytes(cl, W), dtype=torch.uint8, device=dev)
-        msl, stl = timed_steps(torch, lib, hip, lambda: pg.ld_window(
-            cl, W, wl["r2_min"], capacity=cap, out=ol, n_out=nl, workspace=wkl), args.steps, 2, 5)
-        band_ms = mean(stl[1])
-        extras["ld_large"] = {
-            "workload": wl["name"], "value": round(compsl / (msl * 1e-3) / 1e9, 1), "unit": "G/s",
-            "ms_per_step": round(msl, 3), "pairs": pairs, "emitted": int(nl.item()),
-            "stages_ms": {"layout": round(mean(stl[0]), 3), "band_kernel": round(band_ms, 3),
-                          "scan": round(mean(stl[2]), 3), "emit": round(mean(stl[3]), 3)},
-            "roofline": {"bound": "mfma", "kernel": "k_ld_mfma", "unit": "TOP/s",
-                         "achieved": round(compsl * LD_MFMA_OPS / (band_ms * 1e-3) / 1e12, 2),
-                         "peak": PEAK_INT8_TOPS,
-                         "frac": round(compsl * LD_MFMA_OPS / (band_ms * 1e-3) / 1e12
-                                       / PEAK_INT8_TOPS, 4)}}
-        del ol, wkl, cl
+        for lpath in ("mfma", "popc"):
+            wkl = torch.empty(pg.ld_workspace_bytes(cl, W, path=lpath), dtype=torch.uint8,
+                              device=dev)
+            msl, stl = timed_steps(torch, lib, hip, lambda: pg.ld_window(
+                cl, W, wl["r2_min"], capacity=cap, out=ol, n_out=nl, workspace=wkl, path=lpath),
+                args.steps if lpath == "mfma" else 3, 2 if lpath == "mfma" else 1, 5)
+            band_ms = mean(stl[1])
+            rec = {"workload": wl["name"], "path": lpath,
+                   "value": round(compsl / (msl * 1e-3) / 1e9, 1), "unit": "G/s",
+                   "ms_per_step": round(msl, 3), "pairs": pairs, "emitted": int(nl.item()),
+                   "stages_ms": {"layout": round(mean(stl[0]), 3),
+                                 "band_kernel": round(band_ms, 3),
+                                 "scan": round(mean(stl[2]), 3), "emit": round(mean(stl[3]), 3)}}
+            if lpath == "mfma":
+                ach = compsl * LD_MFMA_OPS / (band_ms * 1e-3) / 1e12
+                rec["roofline"] = {"bound": "mfma", "kernel": "k_ld_mfma", "unit": "TOP/s",
+                                   "achieved": round(ach, 2), "peak": PEAK_INT8_TOPS,
+                                   "frac": round(ach / PEAK_INT8_TOPS, 4)}
+            else:
+                ach = compsl * LD_POPC_OPS / (band_ms * 1e-3) / 1e12
+                rec["roofline"] = {"bound": "alu", "kernel": "k_ld_popc", "unit": "TOP/s",
+                                   "achieved": round(ach, 2), "peak": round(PEAK_VALU_TOPS, 2),
+                                   "frac": round(ach / PEAK_VALU_TOPS, 4)}
+            extras[f"ld_large_{lpath}"] = rec
+            del wkl
+        del ol, cl
 
     if args.copy_calibration:
         # plain device copy of exactly 1 GiB, for the HBM byte counters

@@ -117,20 +117,31 @@ int plan_ibs(const Sel& s, int path_arg, IbsPlan& p) {
 }
 
 struct LdPlan {
-  int64_t rows_pad, wn, bm_words;
+  int path, variant;
+  int64_t rows_pad, words, bm_words;
   int64_t off_D, off_bm, off_cnt, off_off, off_bsum, bytes;
 };
 
-int plan_ld(const Sel& s, int32_t window, int path, LdPlan& p) {
+int plan_ld(const Sel& s, int32_t window, int path_arg, LdPlan& p) {
   if (window < 1) return fail(PG_EINVAL, "window %d < 1", (int)window);
-  if (path != PG_PATH_AUTO && path != PG_PATH_MFMA)
-    return fail(path == PG_PATH_POPC ? PG_EUNSUPPORTED : PG_EINVAL,
-                "LD path %d not available (use PG_PATH_AUTO or PG_PATH_MFMA)", path);
+  if (path_arg < 0 || (path_arg >> 16) != 0) return fail(PG_EINVAL, "bad path argument %d", path_arg);
+  int path = path_arg & 0xFF;
+  p.variant = (path_arg >> 8) & 0xFF;
+  if (path == PG_PATH_AUTO) path = PG_PATH_MFMA;
+  if (path != PG_PATH_MFMA && path != PG_PATH_POPC) return fail(PG_EINVAL, "unknown path %d", path);
+  p.path = path;
   p.rows_pad = round_up(s.nv, kLdTile);
-  p.wn = round_up(ceil_div(s.m, 16), kLdKWords);
   p.bm_words = ceil_div(window, 32);
+  int64_t operand_bytes;
+  if (path == PG_PATH_MFMA) {
+    p.words = round_up(ceil_div(s.m, 16), kLdKWords);
+    operand_bytes = p.rows_pad * p.words * 4;
+  } else {
+    p.words = round_up(ceil_div(s.m, 32), kLdPopcKWords);
+    operand_bytes = 3 * p.words * p.rows_pad * 4;
+  }
   Carve c;
-  p.off_D = c.take(p.rows_pad * p.wn * 4);
+  p.off_D = c.take(operand_bytes);
   p.off_bm = c.take(p.rows_pad * p.bm_words * 4);
   p.off_cnt = c.take(p.rows_pad * 4);
   p.off_off = c.take((p.rows_pad + 1) * 8);
@@ -252,11 +263,17 @@ int pg_ld_window(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_sel
   uint32_t* D = (uint32_t*)(ws + p.off_D);
   LdScratch sc{(uint32_t*)(ws + p.off_bm), p.bm_words, (uint32_t*)(ws + p.off_cnt),
                (int64_t*)(ws + p.off_off), (int64_t*)(ws + p.off_bsum)};
+  const bool planes = p.path == PG_PATH_POPC;
   mark_stage(0, st);
-  rc = launch_variant_major_2bit(s, D, p.rows_pad, p.wn, st);
-  if (rc == PG_OK) rc = launch_ld_mfma(D, p.wn, s.nv, p.rows_pad, window, r2_min, sc, st);
+  rc = planes ? launch_ld_planes(s, D, p.rows_pad, p.words, st)
+              : launch_variant_major_2bit(s, D, p.rows_pad, p.words, st);
+  if (rc == PG_OK) rc = ld_clear(sc, p.rows_pad, st);
+  mark_stage(1, st);
   if (rc == PG_OK)
-    rc = launch_ld_finish(D, p.wn, s.nv, s.v0, window, sc, out, capacity, n_out, st);
+    rc = planes ? launch_ld_popc(D, p.words, s.nv, p.rows_pad, window, r2_min, sc, st)
+                : launch_ld_mfma(D, p.words, s.nv, p.rows_pad, window, r2_min, sc, st);
+  if (rc == PG_OK)
+    rc = launch_ld_finish(D, planes, p.words, p.rows_pad, s.nv, s.v0, sc, out, capacity, n_out, st);
   return rc;
 }
 

@@ -93,13 +93,14 @@ __device__ __forceinline__ void store_counts(const IbsOut& o, int64_t i, int64_t
 // of word 8g + s of its row, i.e. one MFMA lane's 16 K values are one 2-bit
 // word.
 //
-// Variant 0 (default) pipelines three things: the next chunk is fetched from
+// The pipelined kernel overlaps three things: the next chunk is fetched from
 // global memory into registers while the current one is consumed from one of
 // two LDS buffers; each lane reads its 8 words per row with two 128-bit LDS
 // reads; and the features of step s+1 are expanded while the MFMAs of step s
-// run.  Variant 1 adds explicit interleaving hints (one MFMA, then a few
-// VALU instructions).  Variant 2 is the unpipelined form (single LDS buffer,
-// no prefetch), kept as a reference point for the tuner.
+// run.  Variant 0 (default) adds scheduling hints that interleave one MFMA
+// with a few VALU instructions; variant 1 leaves the order to the compiler;
+// variant 2 is the unpipelined form (single LDS buffer, no prefetch), kept as
+// a reference point for the tuner.
 constexpr int kT = kIbsMfmaTile;
 constexpr int kKW = kIbsMfmaKWords;
 constexpr int kLdsStride = kKW + 4;   // words per LDS row (padding vs. bank conflicts)
@@ -301,11 +302,11 @@ int launch_ibs_mfma(const uint32_t* T, int64_t wp, const IbsOut& o, int variant,
   const int64_t nt = ceil_div(o.m, kT);
   const int64_t blocks = nt * (nt + 1) / 2;
   if (variant == 1)
-    hipLaunchKernelGGL(k_ibs_mfma<true>, dim3((unsigned)blocks), dim3(256), 0, st, T, wp, nt, o);
+    hipLaunchKernelGGL(k_ibs_mfma<false>, dim3((unsigned)blocks), dim3(256), 0, st, T, wp, nt, o);
   else if (variant == 2)
     hipLaunchKernelGGL(k_ibs_mfma_simple, dim3((unsigned)blocks), dim3(256), 0, st, T, wp, nt, o);
   else
-    hipLaunchKernelGGL(k_ibs_mfma<false>, dim3((unsigned)blocks), dim3(256), 0, st, T, wp, nt, o);
+    hipLaunchKernelGGL(k_ibs_mfma<true>, dim3((unsigned)blocks), dim3(256), 0, st, T, wp, nt, o);
   return check_launch("ibs_mfma");
 }
 

@@ -159,6 +159,44 @@ __global__ __launch_bounds__(256) void k_ibs_planes_fast(Sel s, uint32_t* __rest
   }
 }
 
+// Variant-major bit planes for the popcount LD path: for 32-sample word w,
+// plane p (0 = homozygous A2, 1 = homozygous A1, 2 = non-missing) of selected
+// variant v at P[(w*3 + p)*rows_pad + v].  One plane word per thread.
+__device__ __forceinline__ void ld_planes_of(uint32_t x, uint32_t& hom2, uint32_t& hom1,
+                                             uint32_t& nonmiss) {
+  const uint32_t lo = x & 0x55555555u, hi = (x >> 1) & 0x55555555u;
+  hom2 = compact_even_bits(lo & hi);
+  hom1 = compact_even_bits(~(lo | hi) & 0x55555555u);
+  nonmiss = compact_even_bits(~(lo & ~hi) & 0x55555555u);
+}
+
+__global__ __launch_bounds__(256) void k_ld_planes(Sel s, uint32_t* __restrict__ P, int64_t rows_pad,
+                                                   int64_t words_pad, int aligned) {
+  const int64_t total = rows_pad * words_pad;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t v = e % rows_pad;
+    const int64_t w = e / rows_pad;
+    uint32_t x0, x1;
+    if (!s.idx) {
+      x0 = row_word16(s, v, 2 * w, aligned != 0);
+      x1 = row_word16(s, v, 2 * w + 1, aligned != 0);
+    } else {
+      x0 = 0; x1 = 0;
+      for (int b = 0; b < 16; ++b) {
+        x0 |= code_at(s, v, 32 * w + b) << (2 * b);
+        x1 |= code_at(s, v, 32 * w + 16 + b) << (2 * b);
+      }
+    }
+    uint32_t p0, q0, m0, p1, q1, m1;
+    ld_planes_of(x0, p0, q0, m0);
+    ld_planes_of(x1, p1, q1, m1);
+    P[(w * 3 + 0) * rows_pad + v] = p0 | (p1 << 16);
+    P[(w * 3 + 1) * rows_pad + v] = q0 | (q1 << 16);
+    P[(w * 3 + 2) * rows_pad + v] = m0 | (m1 << 16);
+  }
+}
+
 // Variant-major 2-bit words without a sample list: one word per thread.
 __global__ __launch_bounds__(256) void k_variant_major_fast(Sel s, uint32_t* __restrict__ D,
                                                             int64_t rows_pad, int64_t wn,
@@ -286,6 +324,13 @@ int launch_variant_major_2bit(const Sel& s, uint32_t* D, int64_t rows_pad, int64
   dim3 grid((unsigned)ceil_div(rows_pad * wn, 256));
   hipLaunchKernelGGL(k_variant_major_2bit, grid, dim3(256), 0, st, s, D, rows_pad, wn);
   return check_launch("variant_major_2bit");
+}
+
+int launch_ld_planes(const Sel& s, uint32_t* P, int64_t rows_pad, int64_t words_pad,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_ld_planes, dim3(stride_grid(rows_pad * words_pad)), dim3(256), 0, st, s, P,
+                     rows_pad, words_pad, (int)rows_dword_aligned(s));
+  return check_launch("ld_planes");
 }
 
 }  // namespace pg

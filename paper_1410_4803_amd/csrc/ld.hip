@@ -52,6 +52,110 @@ static int fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st) {
   return check_launch("fill");
 }
 
+// Emission test for one pair (a < b <= a + window, b < nv checked by the
+// caller): marks bit (b - a - 1) of row a and counts it.
+__device__ __forceinline__ void ld_mark(const LdScratch& sc, int64_t a, int64_t b, double r2_min,
+                                        int64_t n, int64_t sx, int64_t sy, int64_t sxx,
+                                        int64_t syy, int64_t sxy) {
+  const double r2 = ld_r2(n, sx, sy, sxx, syy, sxy);
+  if (r2 >= r2_min) {
+    const int64_t d = b - a - 1;
+    atomicOr(&sc.bitmap[a * sc.bm_words + (d >> 5)], 1u << (d & 31));
+    atomicAdd(&sc.rowcnt[a], 1u);
+  }
+}
+
+int ld_clear(const LdScratch& sc, int64_t rows_pad, hipStream_t st) {
+  int rc = fill_u32(sc.bitmap, rows_pad * sc.bm_words, 0u, st);
+  if (rc == PG_OK) rc = fill_u32(sc.rowcnt, rows_pad, 0u, st);
+  return rc;
+}
+
+// ---- banded popcount kernel ---------------------------------------------------------
+// Per 32-sample word of the planes P (homA2), Q (homA1), M (non-missing):
+//   Sx  += popc(Pa & Mb) - popc(Qa & Mb),  Sxx += popc(Pa & Mb) + popc(Qa & Mb),
+//   Sy  += popc(Pb & Ma) - popc(Qb & Ma),  Syy += popc(Pb & Ma) + popc(Qb & Ma),
+//   n   += popc(Ma & Mb),
+//   Sxy += popc((Pa & Pb) | (Qa & Qb)) - popc((Pa & Qb) | (Qa & Pb)).
+// (x*y is +1 for equal homozygotes, -1 for opposite ones, 0 otherwise.)
+// Block: 256 threads over a 64x64 tile, 4x4 pairs per thread.
+constexpr int kLP = 64;
+constexpr int kLPW = kLdPopcKWords;
+
+__global__ __launch_bounds__(256) void k_ld_popc(const uint32_t* __restrict__ P, int64_t words_pad,
+                                                 int64_t nv, int64_t rows_pad, int64_t n_band,
+                                                 int32_t window, double r2_min, LdScratch sc) {
+  const int64_t n_row_tiles = rows_pad / kLP;
+  const int64_t I = (int64_t)blockIdx.x / n_band;
+  const int64_t J = I + (int64_t)blockIdx.x % n_band;
+  if (J >= n_row_tiles) return;
+  __shared__ __attribute__((aligned(16))) uint32_t sA[kLPW * 3 * kLP];
+  __shared__ __attribute__((aligned(16))) uint32_t sB[kLPW * 3 * kLP];
+  const int t = threadIdx.x;
+  const int tx = t & 15, ty = t >> 4;
+  uint32_t al[4][4], be[4][4], ga[4][4], de[4][4], cn[4][4], sp[4][4], sm[4][4];
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c) al[r][c] = be[r][c] = ga[r][c] = de[r][c] = cn[r][c] = sp[r][c] = sm[r][c] = 0;
+
+  for (int64_t kc = 0; kc < words_pad; kc += kLPW) {
+    for (int h = 0; h < 3; ++h) {
+      const int e = t + 256 * h;
+      const int row = e >> 4;
+      const int col = (e & 15) * 4;
+      const int64_t gw = (kc * 3 + row) * rows_pad;
+      const uint4 a = *reinterpret_cast<const uint4*>(P + gw + I * kLP + col);
+      const uint4 b = *reinterpret_cast<const uint4*>(P + gw + J * kLP + col);
+      *reinterpret_cast<uint4*>(&sA[row * kLP + col]) = a;
+      *reinterpret_cast<uint4*>(&sB[row * kLP + col]) = b;
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int w = 0; w < kLPW; ++w) {
+      const uint4 ap = *reinterpret_cast<const uint4*>(&sA[(w * 3 + 0) * kLP + ty * 4]);
+      const uint4 aq = *reinterpret_cast<const uint4*>(&sA[(w * 3 + 1) * kLP + ty * 4]);
+      const uint4 am = *reinterpret_cast<const uint4*>(&sA[(w * 3 + 2) * kLP + ty * 4]);
+      const uint4 bp = *reinterpret_cast<const uint4*>(&sB[(w * 3 + 0) * kLP + tx * 4]);
+      const uint4 bq = *reinterpret_cast<const uint4*>(&sB[(w * 3 + 1) * kLP + tx * 4]);
+      const uint4 bm = *reinterpret_cast<const uint4*>(&sB[(w * 3 + 2) * kLP + tx * 4]);
+      const uint32_t AP[4] = {ap.x, ap.y, ap.z, ap.w}, AQ[4] = {aq.x, aq.y, aq.z, aq.w},
+                     AM[4] = {am.x, am.y, am.z, am.w};
+      const uint32_t BP[4] = {bp.x, bp.y, bp.z, bp.w}, BQ[4] = {bq.x, bq.y, bq.z, bq.w},
+                     BM[4] = {bm.x, bm.y, bm.z, bm.w};
+      for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) {
+          al[r][c] += __builtin_popcount(AP[r] & BM[c]);
+          be[r][c] += __builtin_popcount(AQ[r] & BM[c]);
+          ga[r][c] += __builtin_popcount(BP[c] & AM[r]);
+          de[r][c] += __builtin_popcount(BQ[c] & AM[r]);
+          cn[r][c] += __builtin_popcount(AM[r] & BM[c]);
+          sp[r][c] += __builtin_popcount((AP[r] & BP[c]) | (AQ[r] & BQ[c]));
+          sm[r][c] += __builtin_popcount((AP[r] & BQ[c]) | (AQ[r] & BP[c]));
+        }
+    }
+    __syncthreads();
+  }
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c) {
+      const int64_t a = I * kLP + ty * 4 + r;
+      const int64_t b = J * kLP + tx * 4 + c;
+      if (!(a < b && b - a <= window && b < nv)) continue;
+      ld_mark(sc, a, b, r2_min, cn[r][c], (int64_t)al[r][c] - be[r][c],
+              (int64_t)ga[r][c] - de[r][c], (int64_t)al[r][c] + be[r][c],
+              (int64_t)ga[r][c] + de[r][c], (int64_t)sp[r][c] - sm[r][c]);
+    }
+}
+
+int launch_ld_popc(const uint32_t* P, int64_t words_pad, int64_t nv, int64_t rows_pad,
+                   int32_t window, double r2_min, const LdScratch& sc, hipStream_t st) {
+  const int64_t n_band = ((int64_t)window + kLP - 1) / kLP + 1;
+  const int64_t blocks = rows_pad / kLP * n_band;
+  hipLaunchKernelGGL(k_ld_popc, dim3((unsigned)blocks), dim3(256), 0, st, P, words_pad, nv,
+                     rows_pad, n_band, window, r2_min, sc);
+  int rc = check_launch("ld_popc");
+  mark_stage(2, st);
+  return rc;
+}
+
 // ---- banded matrix-core kernel ----------------------------------------------------
 // Block: 256 threads = 4 waves (2x2) over a 64x64 tile (rows a, columns b);
 // each wave owns one 32x32 block and six v_mfma_i32_32x32x32_i8 accumulators.
@@ -74,7 +178,7 @@ __device__ __forceinline__ Feat3 ld_expand(uint32_t word) {
   return Feat3{ld_lookup(kLdLutM, c), ld_lookup(kLdLutX, c), ld_lookup(kLdLutH, c)};
 }
 
-__global__ __launch_bounds__(256) void k_ld_mfma(const uint32_t* __restrict__ D, int64_t wn,
+__global__ __launch_bounds__(256, 2) void k_ld_mfma(const uint32_t* __restrict__ D, int64_t wn,
                                                  int64_t nv, int64_t n_row_tiles, int64_t n_band,
                                                  int32_t window, double r2_min, LdScratch sc) {
   const int64_t I = (int64_t)blockIdx.x / n_band;
@@ -155,21 +259,13 @@ __global__ __launch_bounds__(256) void k_ld_mfma(const uint32_t* __restrict__ D,
     const int64_t a = a_lo + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
     const int64_t b = b_lo + (lane & 31);
     if (!(a < b && b - a <= window && b < nv)) continue;
-    const double r2 = ld_r2(s_n[v], s_x[v], s_y[v], s_xx[v], s_yy[v], s_xy[v]);
-    if (r2 >= r2_min) {
-      const int64_t d = b - a - 1;
-      atomicOr(&sc.bitmap[a * sc.bm_words + (d >> 5)], 1u << (d & 31));
-      atomicAdd(&sc.rowcnt[a], 1u);
-    }
+    ld_mark(sc, a, b, r2_min, s_n[v], s_x[v], s_y[v], s_xx[v], s_yy[v], s_xy[v]);
   }
 }
 
 int launch_ld_mfma(const uint32_t* D, int64_t wn, int64_t nv, int64_t rows_pad, int32_t window,
                    double r2_min, const LdScratch& sc, hipStream_t st) {
-  int rc = fill_u32(sc.bitmap, rows_pad * sc.bm_words, 0u, st);
-  if (rc == PG_OK) rc = fill_u32(sc.rowcnt, rows_pad, 0u, st);
-  if (rc != PG_OK) return rc;
-  mark_stage(1, st);
+  int rc;
   const int64_t n_row_tiles = rows_pad / kL;
   const int64_t n_band = ((int64_t)window + kL - 1) / kL + 1;
   const int64_t blocks = n_row_tiles * n_band;
@@ -254,11 +350,36 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__
 // ---- emit: one record per thread ---------------------------------------------------
 // Record r (< min(total, capacity)) belongs to the row a with off[a] <= r <
 // off[a+1] (binary search), and to the (r - off[a])-th marked bit of that
-// row's bitmap.  Its sums are recomputed with popcounts over the two rows'
-// 2-bit words.
-__global__ __launch_bounds__(256) void k_ld_emit(const uint32_t* __restrict__ D, int64_t wn,
-                                                 int64_t nv, int64_t v0, LdScratch sc,
-                                                 pg_ld_pair* __restrict__ out, int64_t capacity) {
+// row's bitmap.  Its sums are recomputed with popcounts over the operand the
+// pair kernel used (2-bit words or bit planes) -- an independent integer route
+// to the same exact values.
+struct Sums6 {
+  int n, sx, sy, sxx, syy, sxy;
+};
+
+__device__ __forceinline__ void add_plane_sums(Sums6& z, uint32_t pa, uint32_t qa, uint32_t ma,
+                                               uint32_t pb, uint32_t qb, uint32_t mb) {
+  z.n += __builtin_popcount(ma & mb);
+  z.sx += __builtin_popcount(pa & mb) - __builtin_popcount(qa & mb);
+  z.sy += __builtin_popcount(pb & ma) - __builtin_popcount(qb & ma);
+  z.sxx += __builtin_popcount((pa | qa) & mb);
+  z.syy += __builtin_popcount((pb | qb) & ma);
+  z.sxy += __builtin_popcount((pa & pb) | (qa & qb)) - __builtin_popcount((pa & qb) | (qa & pb));
+}
+
+// 2-bit word (16 codes) -> the three indicator masks at the even bit positions.
+__device__ __forceinline__ void masks_of_word(uint32_t x, uint32_t& p, uint32_t& q, uint32_t& m) {
+  const uint32_t lo = x & 0x55555555u, hi = (x >> 1) & 0x55555555u;
+  p = lo & hi;                       // homA2
+  q = ~(lo | hi) & 0x55555555u;      // homA1
+  m = ~(lo & ~hi) & 0x55555555u;     // not code 01
+}
+
+template <bool kPlanes>
+__global__ __launch_bounds__(256) void k_ld_emit(const uint32_t* __restrict__ X, int64_t words,
+                                                 int64_t rows_pad, int64_t nv, int64_t v0,
+                                                 LdScratch sc, pg_ld_pair* __restrict__ out,
+                                                 int64_t capacity) {
   const int64_t total = sc.rowoff[nv] < capacity ? sc.rowoff[nv] : capacity;
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < total;
        r += (int64_t)gridDim.x * blockDim.x) {
@@ -281,44 +402,42 @@ __global__ __launch_bounds__(256) void k_ld_emit(const uint32_t* __restrict__ D,
       k -= pc;
     }
     if (b < 0) continue;   // unreachable when counts and bitmap agree
-    const uint4* ra = reinterpret_cast<const uint4*>(D + a * wn);
-    const uint4* rb = reinterpret_cast<const uint4*>(D + b * wn);
-    int cn = 0, csx = 0, csy = 0, csxx = 0, csyy = 0, csxy = 0;
-    for (int64_t w4 = 0; w4 < wn / 4; ++w4) {
-      const uint4 A = ra[w4], B = rb[w4];
-      const uint32_t xs[4] = {A.x, A.y, A.z, A.w}, ys[4] = {B.x, B.y, B.z, B.w};
+    Sums6 z{0, 0, 0, 0, 0, 0};
+    if constexpr (kPlanes) {
+      for (int64_t w = 0; w < words; ++w) {
+        const uint32_t* pw = X + w * 3 * rows_pad;
+        add_plane_sums(z, pw[a], pw[rows_pad + a], pw[2 * rows_pad + a], pw[b],
+                       pw[rows_pad + b], pw[2 * rows_pad + b]);
+      }
+    } else {
+      const uint4* ra = reinterpret_cast<const uint4*>(X + a * words);
+      const uint4* rb = reinterpret_cast<const uint4*>(X + b * words);
+      for (int64_t w4 = 0; w4 < words / 4; ++w4) {
+        const uint4 A = ra[w4], B = rb[w4];
+        const uint32_t xs[4] = {A.x, A.y, A.z, A.w}, ys[4] = {B.x, B.y, B.z, B.w};
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const uint32_t xa = xs[e], xb = ys[e];
-        const uint32_t la = xa & 0x55555555u, ha = (xa >> 1) & 0x55555555u;
-        const uint32_t lb = xb & 0x55555555u, hb = (xb >> 1) & 0x55555555u;
-        const uint32_t ma = ~(la & ~ha) & 0x55555555u;   // code != 01
-        const uint32_t mb = ~(lb & ~hb) & 0x55555555u;
-        const uint32_t pa = la & ha, qa = ~(la | ha) & 0x55555555u;  // homA2, homA1
-        const uint32_t pb = lb & hb, qb = ~(lb | hb) & 0x55555555u;
-        cn += __builtin_popcount(ma & mb);
-        csx += __builtin_popcount(pa & mb) - __builtin_popcount(qa & mb);
-        csy += __builtin_popcount(pb & ma) - __builtin_popcount(qb & ma);
-        csxx += __builtin_popcount((pa | qa) & mb);
-        csyy += __builtin_popcount((pb | qb) & ma);
-        csxy += __builtin_popcount((pa & pb) | (qa & qb)) - __builtin_popcount((pa & qb) | (qa & pb));
+        for (int e = 0; e < 4; ++e) {
+          uint32_t pa, qa, ma, pb, qb, mb;
+          masks_of_word(xs[e], pa, qa, ma);
+          masks_of_word(ys[e], pb, qb, mb);
+          add_plane_sums(z, pa, qa, ma, pb, qb, mb);
+        }
       }
     }
     pg_ld_pair rec;
     rec.a = (int32_t)(v0 + a);
     rec.b = (int32_t)(v0 + b);
-    rec.n = cn; rec.sx = csx; rec.sy = csy; rec.sxx = csxx; rec.syy = csyy; rec.sxy = csxy;
-    rec.r2 = ld_r2(cn, csx, csy, csxx, csyy, csxy);
+    rec.n = z.n; rec.sx = z.sx; rec.sy = z.sy; rec.sxx = z.sxx; rec.syy = z.syy; rec.sxy = z.sxy;
+    rec.r2 = ld_r2(z.n, z.sx, z.sy, z.sxx, z.syy, z.sxy);
     out[r] = rec;
   }
 }
 
 int ld_scan_blocks(int64_t nv) { return (int)ceil_div(nv, kScanBlock); }
 
-int launch_ld_finish(const uint32_t* D, int64_t wn, int64_t nv, int64_t v0, int32_t window,
-                     const LdScratch& sc, pg_ld_pair* out, int64_t capacity, int64_t* n_out,
-                     hipStream_t st) {
-  (void)window;
+int launch_ld_finish(const uint32_t* X, bool planes, int64_t words, int64_t rows_pad, int64_t nv,
+                     int64_t v0, const LdScratch& sc, pg_ld_pair* out, int64_t capacity,
+                     int64_t* n_out, hipStream_t st) {
   const int64_t nb = ceil_div(nv, kScanBlock);
   hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nb), dim3(256), 0, st, sc.rowcnt, nv, sc.bsum);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, sc.bsum, nb, nv, sc.rowoff, n_out);
@@ -327,7 +446,12 @@ int launch_ld_finish(const uint32_t* D, int64_t wn, int64_t nv, int64_t v0, int3
   int rc = check_launch("ld_scan");
   mark_stage(3, st);
   if (rc == PG_OK && capacity > 0) {
-    hipLaunchKernelGGL(k_ld_emit, dim3(2048), dim3(256), 0, st, D, wn, nv, v0, sc, out, capacity);
+    if (planes)
+      hipLaunchKernelGGL(k_ld_emit<true>, dim3(2048), dim3(256), 0, st, X, words, rows_pad, nv, v0,
+                         sc, out, capacity);
+    else
+      hipLaunchKernelGGL(k_ld_emit<false>, dim3(2048), dim3(256), 0, st, X, words, rows_pad, nv, v0,
+                         sc, out, capacity);
     rc = check_launch("ld_emit");
   }
   mark_stage(4, st);

@@ -63,6 +63,12 @@ int launch_ibs_planes(const Sel& s, uint32_t* P, int64_t rows_pad, int64_t words
 int launch_variant_major_2bit(const Sel& s, uint32_t* D, int64_t rows_pad, int64_t wn,
                               hipStream_t st);
 
+// Variant-major bit planes for the popcount LD path: for 32-sample word w,
+// plane p (0 = homozygous A2, 1 = homozygous A1, 2 = non-missing) of selected
+// variant v at P[(w*3 + p)*rows_pad + v]; words_pad words.
+int launch_ld_planes(const Sel& s, uint32_t* P, int64_t rows_pad, int64_t words_pad,
+                     hipStream_t st);
+
 // ---- IBS ------------------------------------------------------------------
 struct IbsOut {
   uint32_t* ibs0;
@@ -96,11 +102,19 @@ struct LdScratch {
 // Number of per-block partial sums the row-offset scan needs.
 int ld_scan_blocks(int64_t nv);
 
+constexpr int kLdPopcKWords = 16;     // 32-bit plane words per K chunk
+
+// Clears the emission bitmap and row counts (stage 1 ends after this).
+int ld_clear(const LdScratch& sc, int64_t rows_pad, hipStream_t st);
 int launch_ld_mfma(const uint32_t* D, int64_t wn, int64_t nv, int64_t rows_pad, int32_t window,
                    double r2_min, const LdScratch& sc, hipStream_t st);
-int launch_ld_finish(const uint32_t* D, int64_t wn, int64_t nv, int64_t v0, int32_t window,
-                     const LdScratch& sc, pg_ld_pair* out, int64_t capacity, int64_t* n_out,
-                     hipStream_t st);
+int launch_ld_popc(const uint32_t* P, int64_t words_pad, int64_t nv, int64_t rows_pad,
+                   int32_t window, double r2_min, const LdScratch& sc, hipStream_t st);
+// Row-offset scan, *n_out, and the emit kernel.  X is the operand the pair
+// kernel used: 2-bit words (rows x words) or bit planes (planes == true).
+int launch_ld_finish(const uint32_t* X, bool planes, int64_t words, int64_t rows_pad, int64_t nv,
+                     int64_t v0, const LdScratch& sc, pg_ld_pair* out, int64_t capacity,
+                     int64_t* n_out, hipStream_t st);
 
 // r^2 from exact sums, as documented in pg.h; shared by every LD path so that
 // the emission decision and the emitted value are the same double.

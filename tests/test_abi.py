@@ -76,7 +76,9 @@ def test_bad_selection_and_range():
     assert _ibs_ws(g, vb=-1, ve=5)[0] == N.PG_EINVAL
     assert _ibs_ws(g, path=7)[0] == N.PG_EINVAL
     assert _ld_ws(g, 0)[0] == N.PG_EINVAL
-    assert _ld_ws(g, 10, path=N.PG_PATH_POPC)[0] == N.PG_EUNSUPPORTED
+    assert _ld_ws(g, 10, path=N.PG_PATH_POPC)[0] == 0
+    assert _ld_ws(g, 10, path=9)[0] == N.PG_EINVAL
+    assert _ld_ws(g, 10, path=1 << 16)[0] == N.PG_EINVAL
     assert _ibs_ws(g, vb=10, ve=20)[0] == 0
 
 

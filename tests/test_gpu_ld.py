@@ -14,6 +14,7 @@ pytestmark = pytest.mark.gpu
 pg = pytest.importorskip("paper_1410_4803_amd")
 
 TOL = 1e-12
+PATHS = ["mfma", "popc"]
 FIELDS = ("n", "sx", "sy", "sxx", "syy", "sxy")
 
 
@@ -39,30 +40,33 @@ def _run(bed, n, W, r2_min, mask=None, **kw):
     return pg.ld_records(c, W, r2_min, **kw)
 
 
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("n,V,W", [(1, 5, 3), (2, 40, 7), (17, 65, 64), (63, 130, 65),
                                    (64, 300, 1), (129, 257, 100), (300, 700, 257),
                                    (1000, 400, 1000)])
-def test_ld_all_pairs_small(n, V, W):
+def test_ld_all_pairs_small(n, V, W, path):
     """Every in-window pair with a defined r^2 (threshold -inf)."""
     bed = synth.mosaic(n, V, switch=0.02, miss=0.05, seed=n + V + W, garbage_pad=True)
     codes = oracle.unpack(bed, n, V)
     ref = oracle.ld_window(codes, W, -np.inf)
-    got = _run(bed, n, W, -np.inf)
+    got = _run(bed, n, W, -np.inf, path=path)
     assert len(got) == len(ref)
     _compare(got, ref, -np.inf)
 
 
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("r2_min", [0.2, 0.5, 0.9])
-def test_ld_threshold(r2_min):
+def test_ld_threshold(r2_min, path):
     n, V, W = 500, 3000, 300
     bed = synth.mosaic(n, V, switch=0.005, miss=0.01, seed=3)
     codes = oracle.unpack(bed, n, V)
     ref = oracle.ld_window(codes, W, r2_min)
-    got = _run(bed, n, W, r2_min)
+    got = _run(bed, n, W, r2_min, path=path)
     assert _compare(got, ref, r2_min) > 0
 
 
-def test_ld_mask_selection_range():
+@pytest.mark.parametrize("path", PATHS)
+def test_ld_mask_selection_range(path):
     n, V, W = 400, 2000, 150
     bed = synth.mosaic(n, V, switch=0.01, miss=0.01, seed=8, garbage_pad=True)
     mask = synth.missing_mask(n, V, 0.05, seed=9)
@@ -73,11 +77,13 @@ def test_ld_mask_selection_range():
     ref = oracle.ld_window(codes, W, 0.2)
     ref["a"] += vb
     ref["b"] += vb
-    got = _run(bed, n, W, 0.2, mask, sample_idx=torch.from_numpy(idx).cuda(), v_range=(vb, ve))
+    got = _run(bed, n, W, 0.2, mask, sample_idx=torch.from_numpy(idx).cuda(), v_range=(vb, ve),
+               path=path)
     assert _compare(got, ref, 0.2) > 0
 
 
-def test_ld_special_variants():
+@pytest.mark.parametrize("path", PATHS)
+def test_ld_special_variants(path):
     n, V = 200, 60
     bed = synth.mosaic(n, V, switch=0.05, miss=0.02, seed=12)
     codes = oracle.unpack(bed, n, V)
@@ -88,7 +94,7 @@ def test_ld_special_variants():
     packed = np.zeros((V, (n + 3) // 4), dtype=np.uint8)
     for k in range(n):
         packed[:, k // 4] |= (codes[:, k].astype(np.uint8) << (2 * (k % 4)))
-    got = _run(packed, n, 20, -np.inf)
+    got = _run(packed, n, 20, -np.inf, path=path)
     ref = oracle.ld_window(codes, 20, -np.inf)
     _compare(got, ref, -np.inf)
     dup = got[(got["a"] == 9) & (got["b"] == 10)]
@@ -104,6 +110,7 @@ def test_ld_capacity_protocol_and_determinism():
     bed = synth.mosaic(n, V, switch=0.005, miss=0.01, seed=5)
     c = pg.Cohort.from_numpy(bed, n)
     full = pg.ld_records(c, W, 0.2)
+    assert pg.ld_records(c, W, 0.2, path="popc").tobytes() == full.tobytes()
     assert len(full) > 50
     out, n_out = pg.ld_window(c, W, 0.2, capacity=50)
     assert int(n_out.item()) == len(full)
@@ -121,13 +128,14 @@ def ld_large():
     return w, pg.Cohort.from_numpy(w["bed"], w["n"])
 
 
-def test_ld_large_workload_sampled(ld_large):
+@pytest.mark.parametrize("path", PATHS)
+def test_ld_large_workload_sampled(ld_large, path):
     """5,000 samples x 500,000 variants, window 1,000, r^2 >= 0.2, in the
     benchmark's launch configuration; the oracle recomputes every pair of
     three row ranges (including the first and last rows)."""
     w, c = ld_large
     n, V, W = w["n"], w["V"], w["window"]
-    got = pg.ld_records(c, W, w["r2_min"])
+    got = pg.ld_records(c, W, w["r2_min"], path=path)
     assert len(got) > 0
     assert (np.diff(got["a"].astype(np.int64) * (1 << 32) + got["b"]) > 0).all()
     codes = oracle.unpack(w["bed"], n, V)
@@ -137,8 +145,9 @@ def test_ld_large_workload_sampled(ld_large):
         assert _compare(sel, ref, w["r2_min"]) > 0
 
 
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("n,extra", [(97, 0), (160, 5), (1000, 2)])
-def test_ld_mask_and_row_stride(n, extra):
+def test_ld_mask_and_row_stride(n, extra, path):
     V, W = 900, 120
     bed = synth.mosaic(n, V, switch=0.01, miss=0.01, seed=n + extra, garbage_pad=True)
     mask = synth.missing_mask(n, V, 0.03, seed=n + 7)
@@ -147,6 +156,6 @@ def test_ld_mask_and_row_stride(n, extra):
         bed = np.concatenate([bed, junk], axis=1)
     codes = oracle.unpack(bed, n, V, mask)
     ref = oracle.ld_window(codes, W, -np.inf)
-    got = _run(bed, n, W, -np.inf, mask)
+    got = _run(bed, n, W, -np.inf, mask, path=path)
     assert len(got) == len(ref)
     _compare(got, ref, -np.inf)
