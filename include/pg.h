@@ -169,6 +169,70 @@ int pg_ld_window(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_sel
                  int64_t capacity, int64_t* n_out, int path, void* workspace,
                  size_t workspace_bytes, void* stream);
 
+/* ---- batching ------------------------------------------------------------
+ *
+ * Many independent problems (IBS matrices and LD windows over different
+ * cohorts, sample lists and ranges) in one persistent kernel launch.  Each
+ * problem's arguments mean exactly what they mean for pg_ibs_matrix /
+ * pg_ld_window, and its outputs are identical to a separate call with the
+ * same path.  Usage:
+ *   pg_batch_plan -> pg_batch_workspace_bytes -> (allocate) -> pg_batch_upload
+ *   -> pg_batch_launch (any number of times; or pg_batch_capture once and
+ *   pg_graph_launch many times) -> pg_plan_free.
+ * Between launches the caller may change the genotype data in place but not
+ * any pointer or shape recorded in the plan.  Concurrent launches of one plan
+ * on one workspace race.
+ */
+enum pg_kind { PG_KIND_IBS = 0, PG_KIND_LD = 1 };
+
+typedef struct pg_problem {
+  int kind;                     /* PG_KIND_IBS or PG_KIND_LD */
+  int path;                     /* as the `path` of the one-problem calls */
+  pg_genotypes g;
+  const int32_t* sample_idx;    /* selection, as for the one-problem calls */
+  int64_t n_sel;
+  int64_t v_begin, v_end;
+  /* IBS outputs */
+  int out_layout;
+  uint32_t *ibs0, *ibs1, *ibs2, *nonmiss;
+  /* LD arguments and outputs */
+  int32_t window;
+  double r2_min;
+  pg_ld_pair* out;
+  int64_t capacity;
+  int64_t* n_out;
+} pg_problem;
+
+typedef struct pg_plan pg_plan;   /* host-side plan; owns no device memory */
+
+/* Validates the problems (any failure names the problem) and builds the
+ * schedule: the tiles of all problems in one list, problems with the longest
+ * tiles first.  *plan must be released with pg_plan_free. */
+int pg_batch_plan(const pg_problem* probs, int n_probs, pg_plan** plan);
+/* Device workspace the plan needs: every problem's operand layout and LD
+ * scratch, the tile table and the tile counter. */
+int pg_batch_workspace_bytes(const pg_plan* plan, size_t* bytes);
+/* Number of tiles in the list and persistent grid size (informational). */
+int pg_batch_tiles(const pg_plan* plan, int64_t* total_tiles, int* grid);
+/* Writes the tile table into `workspace` (a host-to-device copy on `stream`,
+ * waited for before returning).  Launches must use this same workspace. */
+int pg_batch_upload(pg_plan* plan, void* workspace, size_t workspace_bytes, void* stream);
+/* Enqueues the whole batch on `stream`: operand layouts, one persistent
+ * kernel over all tiles, then LD scans and emits.  Kernels only, so it may be
+ * captured into a HIP graph.  Stage events (pg_profile_events): 1 = layouts,
+ * 2 = persistent kernel, 3 = LD finish. */
+int pg_batch_launch(const pg_plan* plan, void* workspace, size_t workspace_bytes, void* stream);
+void pg_plan_free(pg_plan* plan);
+
+/* Captures pg_batch_launch into an instantiated HIP graph (*graph_exec is a
+ * hipGraphExec_t).  `stream` must not be the default stream. */
+int pg_batch_capture(const pg_plan* plan, void* workspace, size_t workspace_bytes, void* stream,
+                     void** graph_exec);
+/* Replays a captured graph on `stream`. */
+int pg_graph_launch(void* graph_exec, void* stream);
+/* Releases a captured graph (NULL is ignored). */
+int pg_graph_destroy(void* graph_exec);
+
 #ifdef __cplusplus
 }
 #endif

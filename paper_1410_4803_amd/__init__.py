@@ -11,7 +11,10 @@ from ._native import (LD_PAIR, PATHS, LAYOUTS, PgError, load as load_library,  #
                       last_error, status_str)
 from .api import (Cohort, ibs_matrix, ibs_workspace_bytes, ibs_output_size,  # noqa: F401
                   ld_window, ld_workspace_bytes, ld_records, records_to_numpy)
+from .batch import Batch, IbsProblem, LdProblem  # noqa: F401
+from .tune import Tuner  # noqa: F401
 
 __all__ = ["Cohort", "ibs_matrix", "ibs_workspace_bytes", "ibs_output_size", "ld_window",
            "ld_workspace_bytes", "ld_records", "records_to_numpy", "LD_PAIR", "PATHS",
-           "LAYOUTS", "PgError", "load_library", "last_error", "status_str"]
+           "LAYOUTS", "PgError", "load_library", "last_error", "status_str", "Batch",
+           "IbsProblem", "LdProblem", "Tuner"]

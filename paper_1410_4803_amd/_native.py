@@ -24,8 +24,11 @@ PATHS = {"auto": PG_PATH_AUTO, "popc": PG_PATH_POPC, "mfma": PG_PATH_MFMA}
 
 # ABI symbols (include/pg.h)
 SYMBOLS = ("pg_status_str", "pg_last_error", "pg_version", "pg_profile_events",
-           "pg_ibs_workspace_bytes",
-           "pg_ibs_matrix", "pg_ld_workspace_bytes", "pg_ld_window")
+           "pg_ibs_workspace_bytes", "pg_ibs_matrix", "pg_ld_workspace_bytes", "pg_ld_window",
+           "pg_batch_plan", "pg_batch_workspace_bytes", "pg_batch_tiles", "pg_batch_upload",
+           "pg_batch_launch", "pg_plan_free", "pg_batch_capture", "pg_graph_launch",
+           "pg_graph_destroy")
+PG_KIND_IBS, PG_KIND_LD = 0, 1
 
 LD_PAIR = np.dtype([("a", "<i4"), ("b", "<i4"), ("n", "<i8"), ("sx", "<i8"), ("sy", "<i8"),
                     ("sxx", "<i8"), ("syy", "<i8"), ("sxy", "<i8"), ("r2", "<f8")])
@@ -44,6 +47,19 @@ class Genotypes(ctypes.Structure):
                 ("n_variants", ctypes.c_int64), ("bytes_per_variant", ctypes.c_int64),
                 ("missing_mask", ctypes.c_void_p)]
 
+
+class Problem(ctypes.Structure):
+    """Mirror of pg_problem."""
+    _fields_ = [("kind", ctypes.c_int), ("path", ctypes.c_int), ("g", Genotypes),
+                ("sample_idx", ctypes.c_void_p), ("n_sel", ctypes.c_int64),
+                ("v_begin", ctypes.c_int64), ("v_end", ctypes.c_int64),
+                ("out_layout", ctypes.c_int), ("ibs0", ctypes.c_void_p),
+                ("ibs1", ctypes.c_void_p), ("ibs2", ctypes.c_void_p), ("nonmiss", ctypes.c_void_p),
+                ("window", ctypes.c_int32), ("r2_min", ctypes.c_double), ("out", ctypes.c_void_p),
+                ("capacity", ctypes.c_int64), ("n_out", ctypes.c_void_p)]
+
+
+assert ctypes.sizeof(Problem) == 160
 
 _lib = None
 
@@ -75,6 +91,25 @@ def load():
     lib.pg_ld_workspace_bytes.restype = ctypes.c_int
     lib.pg_ld_window.argtypes = [gp, p, i64, i64, i64, i32, dbl, p, i64, p, ctypes.c_int, p, sz, p]
     lib.pg_ld_window.restype = ctypes.c_int
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    lib.pg_batch_plan.argtypes = [ctypes.POINTER(Problem), ctypes.c_int, pp]
+    lib.pg_batch_plan.restype = ctypes.c_int
+    lib.pg_batch_workspace_bytes.argtypes = [p, ctypes.POINTER(sz)]
+    lib.pg_batch_workspace_bytes.restype = ctypes.c_int
+    lib.pg_batch_tiles.argtypes = [p, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_int)]
+    lib.pg_batch_tiles.restype = ctypes.c_int
+    lib.pg_batch_upload.argtypes = [p, p, sz, p]
+    lib.pg_batch_upload.restype = ctypes.c_int
+    lib.pg_batch_launch.argtypes = [p, p, sz, p]
+    lib.pg_batch_launch.restype = ctypes.c_int
+    lib.pg_plan_free.argtypes = [p]
+    lib.pg_plan_free.restype = None
+    lib.pg_batch_capture.argtypes = [p, p, sz, p, pp]
+    lib.pg_batch_capture.restype = ctypes.c_int
+    lib.pg_graph_launch.argtypes = [p, p]
+    lib.pg_graph_launch.restype = ctypes.c_int
+    lib.pg_graph_destroy.argtypes = [p]
+    lib.pg_graph_destroy.restype = ctypes.c_int
     _lib = lib
     return lib
 

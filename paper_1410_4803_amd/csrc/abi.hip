@@ -151,6 +151,44 @@ int plan_ld(const Sel& s, int32_t window, int path_arg, LdPlan& p) {
 }
 
 }  // namespace
+
+int batch_validate_ibs(const pg_problem& q, Sel& s, int& path, int& variant, int64_t& rows_pad,
+                       int64_t& words) {
+  int rc = make_sel(&q.g, q.sample_idx != nullptr, q.sample_idx, q.n_sel, q.v_begin, q.v_end, s);
+  if (rc != PG_OK) return rc;
+  if (q.out_layout != PG_FULL && q.out_layout != PG_TRI_UPPER)
+    return fail(PG_EINVAL, "unknown layout %d", q.out_layout);
+  const int64_t entries = q.out_layout == PG_FULL ? s.m * s.m : s.m * (s.m - 1) / 2;
+  if (entries > 0 && (!q.ibs0 || !q.ibs1 || !q.ibs2 || !q.nonmiss))
+    return fail(PG_EINVAL, "an output pointer is NULL");
+  IbsPlan p;
+  rc = plan_ibs(s, q.path, p);
+  if (rc != PG_OK) return rc;
+  path = p.path;
+  variant = p.variant;
+  rows_pad = p.rows_pad;
+  words = p.words;
+  return PG_OK;
+}
+
+int batch_validate_ld(const pg_problem& q, Sel& s, int& path, int& variant, int64_t& rows_pad,
+                      int64_t& words, int64_t& bm_words) {
+  int rc = make_sel(&q.g, q.sample_idx != nullptr, q.sample_idx, q.n_sel, q.v_begin, q.v_end, s);
+  if (rc != PG_OK) return rc;
+  if (!q.n_out) return fail(PG_EINVAL, "n_out is NULL");
+  if (q.capacity < 0) return fail(PG_EINVAL, "capacity < 0");
+  if (q.capacity > 0 && !q.out) return fail(PG_EINVAL, "out is NULL with capacity > 0");
+  LdPlan p;
+  rc = plan_ld(s, q.window, q.path, p);
+  if (rc != PG_OK) return rc;
+  path = p.path;
+  variant = p.variant;
+  rows_pad = p.rows_pad;
+  words = p.words;
+  bm_words = p.bm_words;
+  return PG_OK;
+}
+
 }  // namespace pg
 
 using namespace pg;

@@ -1,0 +1,351 @@
+// Batched execution: many independent IBS and LD problems in one persistent
+// launch.
+//
+// A plan validates every problem exactly as the one-problem entry points do,
+// carves one workspace into per-problem operands and LD scratch, and orders
+// the problems longest-tile-first, so that the tiles of all problems form one
+// global list.  A launch enqueues, on one stream: every problem's operand
+// layout (and LD scratch clearing), a reset of the tile counter, ONE
+// persistent kernel whose blocks take tiles from the list with an atomic
+// counter until it is exhausted, and every LD problem's scan and emit.  The
+// tile bodies are the same device functions the one-problem kernels run, so
+// results are identical to calling pg_ibs_matrix / pg_ld_window per problem.
+// The sequence contains kernels only (no memset or copy nodes), so it can be
+// captured into a HIP graph and replayed.
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "tiles.h"
+
+namespace pg {
+
+// Device descriptor of one problem, in schedule order.
+struct BatchItem {
+  int32_t kind;          // PG_KIND_IBS / PG_KIND_LD
+  int32_t path;          // PG_PATH_MFMA / PG_PATH_POPC (resolved)
+  int32_t variant;
+  int32_t window;
+  int64_t tile_begin;    // first global tile index
+  int64_t ntiles;
+  const uint32_t* X;     // operand layout in the workspace
+  int64_t words;         // K words of the operand
+  int64_t rows_pad;
+  int64_t nt;            // IBS: tiles per side; LD: row tiles
+  int64_t n_band;        // LD: column tiles per row tile
+  int64_t nv;            // LD: selected variants
+  double r2_min;
+  IbsOut o;
+  LdScratch sc;
+};
+
+__global__ __launch_bounds__(256, 1) void k_batch_persistent(const BatchItem* __restrict__ items,
+                                                             int n_items, int64_t total,
+                                                             unsigned long long* counter) {
+  __shared__ __attribute__((aligned(16))) uint32_t smem[kMaxTileSmem];
+  __shared__ int64_t s_tile;
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(counter, 1ull);
+    __syncthreads();
+    const int64_t t = s_tile;
+    __syncthreads();
+    if (t >= total) break;   // block-uniform: every block leaves once the list is used up
+    int lo = 0, hi = n_items;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (items[mid].tile_begin <= t) lo = mid; else hi = mid;
+    }
+    const BatchItem& it = items[lo];
+    const int64_t local = t - it.tile_begin;
+    if (it.kind == PG_KIND_IBS) {
+      int64_t I, J;
+      tri_tile(local, it.nt, I, J);
+      if (it.path == PG_PATH_MFMA) {
+        if (it.variant == 1)
+          ibs_mfma_tile<false>(it.X, it.words, I, J, it.o, smem);
+        else
+          ibs_mfma_tile<true>(it.X, it.words, I, J, it.o, smem);
+      } else {
+        ibs_popc_tile(it.X, it.rows_pad, it.words, I, J, it.o, smem);
+      }
+    } else {
+      const int64_t I = local / it.n_band;
+      const int64_t J = I + local % it.n_band;
+      if (J < it.nt) {
+        if (it.path == PG_PATH_MFMA)
+          ld_mfma_tile(it.X, it.words, it.nv, I, J, it.window, it.r2_min, it.sc, smem);
+        else
+          ld_popc_tile(it.X, it.words, it.nv, it.rows_pad, I, J, it.window, it.r2_min, it.sc, smem);
+      }
+    }
+    __syncthreads();   // LDS is reused by the next tile
+  }
+}
+
+}  // namespace pg
+
+// ---- host side -------------------------------------------------------------------
+
+using namespace pg;
+
+namespace {
+
+constexpr int64_t kAlign = 256;
+
+int64_t take(int64_t& off, int64_t bytes) {
+  const int64_t o = off;
+  off = round_up(off + bytes, kAlign);
+  return o;
+}
+
+struct ProblemPlan {
+  pg_problem p;
+  Sel s;
+  int path, variant;
+  int64_t rows_pad, words, nt, n_band, bm_words;
+  int64_t off_x, off_bm, off_cnt, off_off, off_bsum;
+  int64_t ntiles;
+  double tile_cost;
+};
+
+}  // namespace
+
+struct pg_plan {
+  std::vector<ProblemPlan> probs;
+  std::vector<int> order;          // schedule order (indices into probs)
+  int64_t total_tiles = 0;
+  int64_t off_items = 0, off_counter = 0, bytes = 0;
+  int grid = 256;
+  const void* uploaded_ws = nullptr;
+};
+
+namespace pg {
+// Defined in abi.hip: the same validation as the one-problem entry points.
+int batch_validate_ibs(const pg_problem& p, Sel& s, int& path, int& variant, int64_t& rows_pad,
+                       int64_t& words);
+int batch_validate_ld(const pg_problem& p, Sel& s, int& path, int& variant, int64_t& rows_pad,
+                      int64_t& words, int64_t& bm_words);
+}  // namespace pg
+
+extern "C" {
+
+int pg_batch_plan(const pg_problem* probs, int n_probs, pg_plan** out) {
+  if (!out) return fail(PG_EINVAL, "plan output pointer is NULL");
+  *out = nullptr;
+  if (!probs || n_probs < 1) return fail(PG_EINVAL, "no problems");
+  pg_plan* plan = new (std::nothrow) pg_plan;
+  if (!plan) return fail(PG_EINVAL, "host allocation failed");
+  int64_t off = 0;
+  for (int i = 0; i < n_probs; ++i) {
+    ProblemPlan q{};
+    q.p = probs[i];
+    int rc;
+    if (q.p.kind == PG_KIND_IBS) {
+      rc = batch_validate_ibs(q.p, q.s, q.path, q.variant, q.rows_pad, q.words);
+      if (rc == PG_OK) {
+        const int tile = q.path == PG_PATH_MFMA ? kIbsMfmaTile : kIbsPopcTile;
+        q.nt = q.rows_pad / tile;
+        q.ntiles = q.nt * (q.nt + 1) / 2;
+        const int64_t bytes = q.path == PG_PATH_MFMA ? q.rows_pad * q.words * 4
+                                                     : 3 * q.rows_pad * q.words * 4;
+        q.off_x = take(off, bytes);
+        // rough cycles per tile, for longest-first ordering
+        q.tile_cost = q.path == PG_PATH_MFMA ? (double)q.words * 430.0 : (double)q.words * 520.0;
+      }
+    } else if (q.p.kind == PG_KIND_LD) {
+      rc = batch_validate_ld(q.p, q.s, q.path, q.variant, q.rows_pad, q.words, q.bm_words);
+      if (rc == PG_OK) {
+        q.nt = q.rows_pad / kLdTile;
+        q.n_band = ((int64_t)q.p.window + kLdTile - 1) / kLdTile + 1;
+        q.ntiles = q.nt * q.n_band;
+        const int64_t bytes = q.path == PG_PATH_MFMA ? q.rows_pad * q.words * 4
+                                                     : 3 * q.rows_pad * q.words * 4;
+        q.off_x = take(off, bytes);
+        q.off_bm = take(off, q.rows_pad * q.bm_words * 4);
+        q.off_cnt = take(off, q.rows_pad * 4);
+        q.off_off = take(off, (q.rows_pad + 1) * 8);
+        q.off_bsum = take(off, (int64_t)ld_scan_blocks(q.rows_pad) * 8);
+        q.tile_cost = q.path == PG_PATH_MFMA ? (double)q.words * 172.0 : (double)q.words * 1024.0;
+      }
+    } else {
+      rc = fail(PG_EINVAL, "problem %d: unknown kind %d", i, q.p.kind);
+    }
+    if (rc != PG_OK) {
+      delete plan;
+      return fail(rc, "problem %d: %s", i, pg_last_error());
+    }
+    plan->probs.push_back(q);
+  }
+  plan->order.resize(n_probs);
+  for (int i = 0; i < n_probs; ++i) plan->order[i] = i;
+  std::stable_sort(plan->order.begin(), plan->order.end(), [&](int a, int b) {
+    return plan->probs[a].tile_cost > plan->probs[b].tile_cost;
+  });
+  int64_t t = 0;
+  for (int k : plan->order) t += plan->probs[k].ntiles;
+  plan->total_tiles = t;
+  plan->off_items = take(off, (int64_t)sizeof(BatchItem) * n_probs);
+  plan->off_counter = take(off, 8);
+  plan->bytes = off;
+  // persistent grid: resident blocks on this device
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_persistent, 256, 0) ==
+          hipSuccess &&
+      cus > 0 && per_cu > 0) {
+    plan->grid = cus * per_cu;
+  } else {
+    (void)hipGetLastError();
+    plan->grid = 256;
+  }
+  if (plan->grid > t) plan->grid = (int)std::max<int64_t>(t, 1);
+  *out = plan;
+  return PG_OK;
+}
+
+int pg_batch_workspace_bytes(const pg_plan* plan, size_t* bytes) {
+  if (!plan || !bytes) return fail(PG_EINVAL, "NULL argument");
+  *bytes = (size_t)plan->bytes;
+  return PG_OK;
+}
+
+int pg_batch_tiles(const pg_plan* plan, int64_t* total_tiles, int* grid) {
+  if (!plan) return fail(PG_EINVAL, "plan is NULL");
+  if (total_tiles) *total_tiles = plan->total_tiles;
+  if (grid) *grid = plan->grid;
+  return PG_OK;
+}
+
+int pg_batch_upload(pg_plan* plan, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!plan || !workspace) return fail(PG_EINVAL, "NULL argument");
+  if ((int64_t)workspace_bytes < plan->bytes)
+    return fail(PG_ENOMEM, "workspace of %llu bytes < %lld required",
+                (unsigned long long)workspace_bytes, (long long)plan->bytes);
+  char* ws = (char*)workspace;
+  std::vector<BatchItem> items;
+  int64_t t = 0;
+  for (int k : plan->order) {
+    const ProblemPlan& q = plan->probs[k];
+    BatchItem it{};
+    it.kind = q.p.kind;
+    it.path = q.path;
+    it.variant = q.variant;
+    it.tile_begin = t;
+    it.ntiles = q.ntiles;
+    it.X = (const uint32_t*)(ws + q.off_x);
+    it.words = q.words;
+    it.rows_pad = q.rows_pad;
+    it.nt = q.nt;
+    if (q.p.kind == PG_KIND_IBS) {
+      it.o = IbsOut{q.p.ibs0, q.p.ibs1, q.p.ibs2, q.p.nonmiss, q.s.m, q.p.out_layout == PG_FULL};
+    } else {
+      it.window = q.p.window;
+      it.n_band = q.n_band;
+      it.nv = q.s.nv;
+      it.r2_min = q.p.r2_min;
+      it.sc = LdScratch{(uint32_t*)(ws + q.off_bm), q.bm_words, (uint32_t*)(ws + q.off_cnt),
+                        (int64_t*)(ws + q.off_off), (int64_t*)(ws + q.off_bsum)};
+    }
+    items.push_back(it);
+    t += q.ntiles;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  if (hipMemcpyAsync(ws + plan->off_items, items.data(), sizeof(BatchItem) * items.size(),
+                     hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail(PG_EDEVICE, "tile table upload failed: %s", hipGetErrorString(hipGetLastError()));
+  plan->uploaded_ws = workspace;
+  return PG_OK;
+}
+
+int pg_batch_launch(const pg_plan* plan, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!plan || !workspace) return fail(PG_EINVAL, "NULL argument");
+  if ((int64_t)workspace_bytes < plan->bytes)
+    return fail(PG_ENOMEM, "workspace of %llu bytes < %lld required",
+                (unsigned long long)workspace_bytes, (long long)plan->bytes);
+  if (plan->uploaded_ws != workspace)
+    return fail(PG_EINVAL, "workspace differs from the one given to pg_batch_upload");
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  int rc = PG_OK;
+  mark_stage(0, st);
+  for (int k : plan->order) {
+    const ProblemPlan& q = plan->probs[k];
+    uint32_t* X = (uint32_t*)(ws + q.off_x);
+    if (q.p.kind == PG_KIND_IBS) {
+      rc = q.path == PG_PATH_MFMA ? launch_sample_major_2bit(q.s, X, q.rows_pad, q.words, st)
+                                  : launch_ibs_planes(q.s, X, q.rows_pad, q.words, st);
+    } else {
+      rc = q.path == PG_PATH_MFMA ? launch_variant_major_2bit(q.s, X, q.rows_pad, q.words, st)
+                                  : launch_ld_planes(q.s, X, q.rows_pad, q.words, st);
+      const LdScratch sc{(uint32_t*)(ws + q.off_bm), q.bm_words, (uint32_t*)(ws + q.off_cnt),
+                         (int64_t*)(ws + q.off_off), (int64_t*)(ws + q.off_bsum)};
+      if (rc == PG_OK) rc = ld_clear(sc, q.rows_pad, st);
+    }
+    if (rc != PG_OK) return rc;
+  }
+  unsigned long long* counter = (unsigned long long*)(ws + plan->off_counter);
+  rc = fill_u32((uint32_t*)counter, 2, 0u, st);
+  if (rc != PG_OK) return rc;
+  mark_stage(1, st);
+  hipLaunchKernelGGL(k_batch_persistent, dim3((unsigned)plan->grid), dim3(256), 0, st,
+                     (const BatchItem*)(ws + plan->off_items), (int)plan->probs.size(),
+                     plan->total_tiles, counter);
+  rc = check_launch("batch_persistent");
+  mark_stage(2, st);
+  if (rc != PG_OK) return rc;
+  for (int k : plan->order) {
+    const ProblemPlan& q = plan->probs[k];
+    if (q.p.kind != PG_KIND_LD) continue;
+    const LdScratch sc{(uint32_t*)(ws + q.off_bm), q.bm_words, (uint32_t*)(ws + q.off_cnt),
+                       (int64_t*)(ws + q.off_off), (int64_t*)(ws + q.off_bsum)};
+    rc = launch_ld_finish((uint32_t*)(ws + q.off_x), q.path == PG_PATH_POPC, q.words, q.rows_pad,
+                          q.s.nv, q.s.v0, sc, q.p.out, q.p.capacity, q.p.n_out, st, false);
+    if (rc != PG_OK) return rc;
+  }
+  mark_stage(3, st);
+  return PG_OK;
+}
+
+void pg_plan_free(pg_plan* plan) { delete plan; }
+
+int pg_batch_capture(const pg_plan* plan, void* workspace, size_t workspace_bytes, void* stream,
+                     void** graph_exec) {
+  if (!graph_exec) return fail(PG_EINVAL, "graph_exec is NULL");
+  *graph_exec = nullptr;
+  if (!stream) return fail(PG_EINVAL, "capture needs a non-default stream");
+  hipStream_t st = (hipStream_t)stream;
+  if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    return fail(PG_EDEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(hipGetLastError()));
+  const int rc = pg_batch_launch(plan, workspace, workspace_bytes, stream);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(st, &graph);
+  if (rc != PG_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess || !graph) return fail(PG_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e2 != hipSuccess) return fail(PG_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e2));
+  *graph_exec = (void*)exec;
+  return PG_OK;
+}
+
+int pg_graph_launch(void* graph_exec, void* stream) {
+  if (!graph_exec) return fail(PG_EINVAL, "graph_exec is NULL");
+  const hipError_t e = hipGraphLaunch((hipGraphExec_t)graph_exec, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(PG_EDEVICE, "hipGraphLaunch: %s", hipGetErrorString(e));
+  return PG_OK;
+}
+
+int pg_graph_destroy(void* graph_exec) {
+  if (!graph_exec) return PG_OK;
+  const hipError_t e = hipGraphExecDestroy((hipGraphExec_t)graph_exec);
+  if (e != hipSuccess) return fail(PG_EDEVICE, "hipGraphExecDestroy: %s", hipGetErrorString(e));
+  return PG_OK;
+}
+
+}  // extern "C"

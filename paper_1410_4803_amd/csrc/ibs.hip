@@ -21,281 +21,33 @@
 // 11 differ in both bits), IBS1 += popc((xh ^ xl) & m) (exactly one bit
 // differs: 00/10 or 10/11).  This is the paper's XOR / mask / popcount step,
 // with the one popcount it describes (IBS1 + 2 IBS0) split into two.
-#include "pg_internal.h"
+#include "tiles.h"
 
 namespace pg {
-
-typedef int v4i __attribute__((ext_vector_type(4)));
-typedef int v16i __attribute__((ext_vector_type(16)));
-
-// Byte c of each table is the int8 feature value of code c
-// (0 homA1, 1 missing, 2 het, 3 homA2).
-constexpr uint32_t kLutM = 0x01010001u;   //  1  0  1  1
-constexpr uint32_t kLutW = 0x01FF0001u;   //  1  0 -1  1
-constexpr uint32_t kLutH = 0x01000001u;   //  1  0  0  1
-constexpr uint32_t kLutC = 0x010000FFu;   // -1  0  0  1
-constexpr uint32_t kLutCn = 0xFF000001u;  //  1  0  0 -1
-
-// Sixteen 2-bit codes -> four dwords whose bytes are the codes.  Byte e of
-// dword d is the code at position 4e + d; A and B operands use the same
-// order, so the permutation of K inside a word is harmless.
-__device__ __forceinline__ void spread_codes(uint32_t w, uint32_t c[4]) {
-  c[0] = w & 0x03030303u;
-  c[1] = (w >> 2) & 0x03030303u;
-  c[2] = (w >> 4) & 0x03030303u;
-  c[3] = (w >> 6) & 0x03030303u;
-}
-
-__device__ __forceinline__ v4i lookup(uint32_t lut, const uint32_t c[4]) {
-  v4i r;
-  r[0] = (int)__builtin_amdgcn_perm(0u, lut, c[0]);
-  r[1] = (int)__builtin_amdgcn_perm(0u, lut, c[1]);
-  r[2] = (int)__builtin_amdgcn_perm(0u, lut, c[2]);
-  r[3] = (int)__builtin_amdgcn_perm(0u, lut, c[3]);
-  return r;
-}
-
-// Linear upper-triangle tile index -> (I, J), I <= J, row-major.
-__device__ __forceinline__ void tri_tile(int64_t b, int64_t nt, int64_t& I, int64_t& J) {
-  // rows start at s(I) = I*nt - I*(I-1)/2; estimate I, then correct.
-  const double fn = (double)nt + 0.5;
-  int64_t i = (int64_t)(fn - sqrt(fn * fn - 2.0 * (double)b));
-  if (i < 0) i = 0;
-  if (i > nt - 1) i = nt - 1;
-  while (i > 0 && i * nt - i * (i - 1) / 2 > b) --i;
-  while (i + 1 < nt && (i + 1) * nt - (i + 1) * i / 2 <= b) ++i;
-  I = i;
-  J = i + (b - (i * nt - i * (i - 1) / 2));
-}
-
-__device__ __forceinline__ void store_counts(const IbsOut& o, int64_t i, int64_t j, bool mirror,
-                                             uint32_t n, uint32_t z, uint32_t one) {
-  if (i >= o.m || j >= o.m) return;
-  const uint32_t two = n - z - one;
-  if (o.full) {
-    const int64_t a = i * o.m + j;
-    o.ibs0[a] = z; o.ibs1[a] = one; o.ibs2[a] = two; o.nonmiss[a] = n;
-    if (mirror) {
-      const int64_t b = j * o.m + i;
-      o.ibs0[b] = z; o.ibs1[b] = one; o.ibs2[b] = two; o.nonmiss[b] = n;
-    }
-  } else if (i < j) {
-    const int64_t a = i * o.m - i * (i + 1) / 2 + (j - i - 1);
-    o.ibs0[a] = z; o.ibs1[a] = one; o.ibs2[a] = two; o.nonmiss[a] = n;
-  }
-}
-
-// ---- matrix-core path ---------------------------------------------------------
-// Block: 256 threads = 4 waves in a 2x2 grid over a 128x128 tile; each wave
-// owns 64x64 = 2x2 blocks of v_mfma_i32_32x32x32_i8 and three accumulator sets
-// (G_m, G_w, G_h - G_c).  K runs over variants in chunks of 16 words (256
-// variants).  Lane group g = lane/32 of MFMA step s (0..7) holds the 16 codes
-// of word 8g + s of its row, i.e. one MFMA lane's 16 K values are one 2-bit
-// word.
-//
-// The pipelined kernel overlaps three things: the next chunk is fetched from
-// global memory into registers while the current one is consumed from one of
-// two LDS buffers; each lane reads its 8 words per row with two 128-bit LDS
-// reads; and the features of step s+1 are expanded while the MFMAs of step s
-// run.  Variant 0 (default) adds scheduling hints that interleave one MFMA
-// with a few VALU instructions; variant 1 leaves the order to the compiler;
-// variant 2 is the unpipelined form (single LDS buffer, no prefetch), kept as
-// a reference point for the tuner.
-constexpr int kT = kIbsMfmaTile;
-constexpr int kKW = kIbsMfmaKWords;
-constexpr int kLdsStride = kKW + 4;   // words per LDS row (padding vs. bank conflicts)
-
-struct Feat4 {
-  v4i m, w, h, c;
-};
-
-__device__ __forceinline__ Feat4 expand_a(uint32_t word) {
-  uint32_t c[4];
-  spread_codes(word, c);
-  return Feat4{lookup(kLutM, c), lookup(kLutW, c), lookup(kLutH, c), lookup(kLutC, c)};
-}
-
-__device__ __forceinline__ Feat4 expand_b(uint32_t word) {
-  uint32_t c[4];
-  spread_codes(word, c);
-  return Feat4{lookup(kLutM, c), lookup(kLutW, c), lookup(kLutH, c), lookup(kLutCn, c)};
-}
-
-struct IbsAcc {
-  v16i m[2][2], w[2][2], hc[2][2];
-};
-
-__device__ __forceinline__ void mfma_step(IbsAcc& acc, const Feat4 (&fa)[2], const Feat4 (&fb)[2]) {
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      acc.m[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a].m, fb[b].m, acc.m[a][b], 0, 0, 0);
-      acc.w[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a].w, fb[b].w, acc.w[a][b], 0, 0, 0);
-      acc.hc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a].h, fb[b].h, acc.hc[a][b], 0, 0, 0);
-      acc.hc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a].c, fb[b].c, acc.hc[a][b], 0, 0, 0);
-    }
-}
-
-// 32x32 accumulator layout: register v of lane l holds row
-// 8*(v/4) + 4*(l/32) + v%4 and column l%32 of the block.
-__device__ __forceinline__ void ibs_epilogue(const IbsAcc& acc, const IbsOut& o, int64_t I,
-                                             int64_t J, int wr, int wc, int lane) {
-  const bool mirror = (I != J);
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int64_t i = I * kT + wr * 64 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-        const int64_t j = J * kT + wc * 64 + b * 32 + (lane & 31);
-        const uint32_t n = (uint32_t)acc.m[a][b][v];
-        const uint32_t z = (uint32_t)acc.hc[a][b][v] >> 1;
-        const uint32_t one = (n - (uint32_t)acc.w[a][b][v]) >> 1;
-        store_counts(o, i, j, mirror, n, z, one);
-      }
-}
-
-__device__ __forceinline__ void zero_acc(IbsAcc& acc) {
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      acc.m[a][b] = (v16i){0};
-      acc.w[a][b] = (v16i){0};
-      acc.hc[a][b] = (v16i){0};
-    }
-}
 
 template <bool kHints>
 __global__ __launch_bounds__(256, 1) void k_ibs_mfma(const uint32_t* __restrict__ T, int64_t wp,
                                                      int64_t nt, IbsOut o) {
-  __shared__ __attribute__((aligned(16))) uint32_t sA[2][kT * kLdsStride];
-  __shared__ __attribute__((aligned(16))) uint32_t sB[2][kT * kLdsStride];
+  __shared__ __attribute__((aligned(16))) uint32_t smem[kIbsMfmaSmem];
   int64_t I, J;
   tri_tile(blockIdx.x, nt, I, J);
-  const int t = threadIdx.x;
-  const int lane = t & 63;
-  const int wid = t >> 6;
-  const int wr = wid >> 1, wc = wid & 1;
-  const int g = lane >> 5;
-  const int rl = lane & 31;
-
-  // this thread's share of a chunk: rows t/4 and t/4 + 64, words 4*(t%4)..+3
-  const int lrow = t >> 2;
-  const int lq = (t & 3) * 4;
-  const uint32_t* pa = T + (I * kT + lrow) * wp + lq;
-  const uint32_t* pb = T + (J * kT + lrow) * wp + lq;
-  const int64_t half = 64 * wp;
-  uint4 ga0, ga1, gb0, gb1;
-  auto gload = [&](int64_t kc) {
-    ga0 = *reinterpret_cast<const uint4*>(pa + kc);
-    ga1 = *reinterpret_cast<const uint4*>(pa + half + kc);
-    gb0 = *reinterpret_cast<const uint4*>(pb + kc);
-    gb1 = *reinterpret_cast<const uint4*>(pb + half + kc);
-  };
-  auto lstore = [&](int buf) {
-    *reinterpret_cast<uint4*>(&sA[buf][lrow * kLdsStride + lq]) = ga0;
-    *reinterpret_cast<uint4*>(&sA[buf][(lrow + 64) * kLdsStride + lq]) = ga1;
-    *reinterpret_cast<uint4*>(&sB[buf][lrow * kLdsStride + lq]) = gb0;
-    *reinterpret_cast<uint4*>(&sB[buf][(lrow + 64) * kLdsStride + lq]) = gb1;
-  };
-
-  IbsAcc acc;
-  zero_acc(acc);
-  const int64_t nchunks = wp / kKW;
-  gload(0);
-  lstore(0);
-  __syncthreads();
-  for (int64_t k = 0; k < nchunks; ++k) {
-    const int buf = (int)(k & 1);
-    if (k + 1 < nchunks) gload((k + 1) * kKW);
-    // this lane's 8 words of each of its two A rows and two B rows
-    uint32_t wa[2][8], wb[2][8];
-#pragma unroll
-    for (int x = 0; x < 2; ++x) {
-      const uint32_t* ra = &sA[buf][(wr * 64 + x * 32 + rl) * kLdsStride + g * 8];
-      const uint32_t* rb = &sB[buf][(wc * 64 + x * 32 + rl) * kLdsStride + g * 8];
-      const uint4 a0 = *reinterpret_cast<const uint4*>(ra);
-      const uint4 a1 = *reinterpret_cast<const uint4*>(ra + 4);
-      const uint4 b0 = *reinterpret_cast<const uint4*>(rb);
-      const uint4 b1 = *reinterpret_cast<const uint4*>(rb + 4);
-      wa[x][0] = a0.x; wa[x][1] = a0.y; wa[x][2] = a0.z; wa[x][3] = a0.w;
-      wa[x][4] = a1.x; wa[x][5] = a1.y; wa[x][6] = a1.z; wa[x][7] = a1.w;
-      wb[x][0] = b0.x; wb[x][1] = b0.y; wb[x][2] = b0.z; wb[x][3] = b0.w;
-      wb[x][4] = b1.x; wb[x][5] = b1.y; wb[x][6] = b1.z; wb[x][7] = b1.w;
-    }
-    Feat4 fa[2], fb[2];
-    fa[0] = expand_a(wa[0][0]); fa[1] = expand_a(wa[1][0]);
-    fb[0] = expand_b(wb[0][0]); fb[1] = expand_b(wb[1][0]);
-#pragma unroll
-    for (int s = 0; s < kKW / 2; ++s) {
-      Feat4 na[2], nb[2];
-      if (s + 1 < kKW / 2) {
-        na[0] = expand_a(wa[0][s + 1]); na[1] = expand_a(wa[1][s + 1]);
-        nb[0] = expand_b(wb[0][s + 1]); nb[1] = expand_b(wb[1][s + 1]);
-      }
-      mfma_step(acc, fa, fb);
-      if constexpr (kHints) {
-        // interleave: 1 MFMA, then up to 6 VALU instructions, 16 times
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-          __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);
-        }
-      }
-      if (s + 1 < kKW / 2) {
-        fa[0] = na[0]; fa[1] = na[1];
-        fb[0] = nb[0]; fb[1] = nb[1];
-      }
-    }
-    if (k + 1 < nchunks) lstore(buf ^ 1);
-    __syncthreads();
-  }
-  ibs_epilogue(acc, o, I, J, wr, wc, lane);
+  ibs_mfma_tile<kHints>(T, wp, I, J, o, smem);
 }
 
-// Unpipelined reference form (variant 2).
 __global__ __launch_bounds__(256, 1) void k_ibs_mfma_simple(const uint32_t* __restrict__ T,
                                                             int64_t wp, int64_t nt, IbsOut o) {
-  __shared__ __attribute__((aligned(16))) uint32_t sA[kT * kLdsStride];
-  __shared__ __attribute__((aligned(16))) uint32_t sB[kT * kLdsStride];
+  __shared__ __attribute__((aligned(16))) uint32_t smem[kIbsMfmaSimpleSmem];
   int64_t I, J;
   tri_tile(blockIdx.x, nt, I, J);
-  const int t = threadIdx.x;
-  const int lane = t & 63;
-  const int wid = t >> 6;
-  const int wr = wid >> 1, wc = wid & 1;
-  const uint32_t* gA = T + I * kT * wp;
-  const uint32_t* gB = T + J * kT * wp;
-  IbsAcc acc;
-  zero_acc(acc);
-  for (int64_t kc = 0; kc < wp; kc += kKW) {
-    for (int h = 0; h < 2; ++h) {
-      const int r = (t >> 2) + 64 * h;
-      const int q = t & 3;
-      const uint4 a = *reinterpret_cast<const uint4*>(gA + r * wp + kc + q * 4);
-      const uint4 b = *reinterpret_cast<const uint4*>(gB + r * wp + kc + q * 4);
-      *reinterpret_cast<uint4*>(&sA[r * kLdsStride + q * 4]) = a;
-      *reinterpret_cast<uint4*>(&sB[r * kLdsStride + q * 4]) = b;
-    }
-    __syncthreads();
-    const int g = lane >> 5;
-    const int rl = lane & 31;
-#pragma unroll 2
-    for (int s = 0; s < kKW / 2; ++s) {
-      const int kw = g * (kKW / 2) + s;
-      Feat4 fa[2], fb[2];
-      for (int x = 0; x < 2; ++x) {
-        fa[x] = expand_a(sA[(wr * 64 + x * 32 + rl) * kLdsStride + kw]);
-        fb[x] = expand_b(sB[(wc * 64 + x * 32 + rl) * kLdsStride + kw]);
-      }
-      mfma_step(acc, fa, fb);
-    }
-    __syncthreads();
-  }
-  ibs_epilogue(acc, o, I, J, wr, wc, lane);
+  ibs_mfma_tile_simple(T, wp, I, J, o, smem);
+}
+
+__global__ __launch_bounds__(256) void k_ibs_popc(const uint32_t* __restrict__ P, int64_t rows_pad,
+                                                  int64_t words_pad, int64_t nt, IbsOut o) {
+  __shared__ __attribute__((aligned(16))) uint32_t smem[kIbsPopcSmem];
+  int64_t I, J;
+  tri_tile(blockIdx.x, nt, I, J);
+  ibs_popc_tile(P, rows_pad, words_pad, I, J, o, smem);
 }
 
 int launch_ibs_mfma(const uint32_t* T, int64_t wp, const IbsOut& o, int variant, hipStream_t st) {
@@ -308,68 +60,6 @@ int launch_ibs_mfma(const uint32_t* T, int64_t wp, const IbsOut& o, int variant,
   else
     hipLaunchKernelGGL(k_ibs_mfma<true>, dim3((unsigned)blocks), dim3(256), 0, st, T, wp, nt, o);
   return check_launch("ibs_mfma");
-}
-
-// ---- popcount path --------------------------------------------------------------
-// Block: 256 threads over a 64x64 tile, 4x4 pairs per thread; K runs over
-// 32-variant plane words in chunks of 16 staged through LDS.
-constexpr int kP = kIbsPopcTile;
-constexpr int kPW = kIbsPopcKWords;
-
-__global__ __launch_bounds__(256) void k_ibs_popc(const uint32_t* __restrict__ P, int64_t rows_pad,
-                                                  int64_t words_pad, int64_t nt, IbsOut o) {
-  __shared__ __attribute__((aligned(16))) uint32_t sA[kPW * 3 * kP];
-  __shared__ __attribute__((aligned(16))) uint32_t sB[kPW * 3 * kP];
-  int64_t I, J;
-  tri_tile(blockIdx.x, nt, I, J);
-  const int t = threadIdx.x;
-  const int tx = t & 15, ty = t >> 4;
-  uint32_t cn[4][4], cz[4][4], co[4][4];
-  for (int r = 0; r < 4; ++r)
-    for (int c = 0; c < 4; ++c) cn[r][c] = cz[r][c] = co[r][c] = 0;
-
-  for (int64_t kc = 0; kc < words_pad; kc += kPW) {
-    // kPW*3 rows of 64 words for each operand: 768 uint4, 3 per thread
-    for (int h = 0; h < 3; ++h) {
-      const int e = t + 256 * h;          // uint4 index
-      const int row = e >> 4;             // (word, plane) row, 0..47
-      const int col = (e & 15) * 4;       // sample offset
-      const int64_t gw = (kc * 3 + row) * rows_pad;
-      const uint4 a = *reinterpret_cast<const uint4*>(P + gw + I * kP + col);
-      const uint4 b = *reinterpret_cast<const uint4*>(P + gw + J * kP + col);
-      *reinterpret_cast<uint4*>(&sA[row * kP + col]) = a;
-      *reinterpret_cast<uint4*>(&sB[row * kP + col]) = b;
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int w = 0; w < kPW; ++w) {
-      const uint4 ah = *reinterpret_cast<const uint4*>(&sA[(w * 3 + 0) * kP + ty * 4]);
-      const uint4 al = *reinterpret_cast<const uint4*>(&sA[(w * 3 + 1) * kP + ty * 4]);
-      const uint4 am = *reinterpret_cast<const uint4*>(&sA[(w * 3 + 2) * kP + ty * 4]);
-      const uint4 bh = *reinterpret_cast<const uint4*>(&sB[(w * 3 + 0) * kP + tx * 4]);
-      const uint4 bl = *reinterpret_cast<const uint4*>(&sB[(w * 3 + 1) * kP + tx * 4]);
-      const uint4 bm = *reinterpret_cast<const uint4*>(&sB[(w * 3 + 2) * kP + tx * 4]);
-      const uint32_t AH[4] = {ah.x, ah.y, ah.z, ah.w}, AL[4] = {al.x, al.y, al.z, al.w},
-                     AM[4] = {am.x, am.y, am.z, am.w};
-      const uint32_t BH[4] = {bh.x, bh.y, bh.z, bh.w}, BL[4] = {bl.x, bl.y, bl.z, bl.w},
-                     BM[4] = {bm.x, bm.y, bm.z, bm.w};
-      for (int r = 0; r < 4; ++r)
-        for (int c = 0; c < 4; ++c) {
-          const uint32_t m = AM[r] & BM[c];
-          const uint32_t xh = AH[r] ^ BH[c];
-          const uint32_t xl = AL[r] ^ BL[c];
-          cn[r][c] += __builtin_popcount(m);
-          cz[r][c] += __builtin_popcount(xh & xl & m);
-          co[r][c] += __builtin_popcount((xh ^ xl) & m);
-        }
-    }
-    __syncthreads();
-  }
-  const bool mirror = (I != J);
-  for (int r = 0; r < 4; ++r)
-    for (int c = 0; c < 4; ++c)
-      store_counts(o, I * kP + ty * 4 + r, J * kP + tx * 4 + c, mirror, cn[r][c], cz[r][c],
-                   co[r][c]);
 }
 
 int launch_ibs_popc(const uint32_t* P, int64_t rows_pad, int64_t words_pad, const IbsOut& o,

@@ -14,6 +14,8 @@ int fail(int status, const char* fmt, ...);
 int check_launch(const char* what);
 // Records the caller's stage event k (pg_profile_events) on `st`, if set.
 void mark_stage(int k, hipStream_t st);
+// Fills n words with v by a kernel (no memset node, so graph replays are safe).
+int fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
@@ -112,9 +114,10 @@ int launch_ld_popc(const uint32_t* P, int64_t words_pad, int64_t nv, int64_t row
                    int32_t window, double r2_min, const LdScratch& sc, hipStream_t st);
 // Row-offset scan, *n_out, and the emit kernel.  X is the operand the pair
 // kernel used: 2-bit words (rows x words) or bit planes (planes == true).
+// `marks` records stage events 3 and 4 (one-problem calls only).
 int launch_ld_finish(const uint32_t* X, bool planes, int64_t words, int64_t rows_pad, int64_t nv,
                      int64_t v0, const LdScratch& sc, pg_ld_pair* out, int64_t capacity,
-                     int64_t* n_out, hipStream_t st);
+                     int64_t* n_out, hipStream_t st, bool marks = true);
 
 // r^2 from exact sums, as documented in pg.h; shared by every LD path so that
 // the emission decision and the emitted value are the same double.

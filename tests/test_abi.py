@@ -116,3 +116,34 @@ def test_calls_reject_before_launch():
     rc = lib.pg_ld_window(ctypes.byref(g), None, 0, 0, 0, 10, 0.2, fake, 5, fake, 0, fake,
                           8, None)
     assert rc == N.PG_ENOMEM
+
+
+def test_batch_plan_validation_names_problem():
+    lib = N.load()
+    arr = (N.Problem * 3)()
+    for k in range(3):
+        arr[k].kind = N.PG_KIND_IBS
+        arr[k].g = _g(100, 50)
+        arr[k].out_layout = N.PG_TRI_UPPER
+        arr[k].ibs0 = arr[k].ibs1 = arr[k].ibs2 = arr[k].nonmiss = 0x3000
+    arr[2].kind = N.PG_KIND_LD
+    arr[2].window = 0                   # invalid window
+    arr[2].n_out = 0x4000
+    plan = ctypes.c_void_p()
+    rc = lib.pg_batch_plan(arr, 3, ctypes.byref(plan))
+    assert rc == N.PG_EINVAL and plan.value is None
+    assert "problem 2" in N.last_error()
+    arr[2].window = 10
+    rc = lib.pg_batch_plan(arr, 3, ctypes.byref(plan))
+    assert rc == N.PG_OK and plan.value
+    nbytes = ctypes.c_size_t()
+    assert lib.pg_batch_workspace_bytes(plan, ctypes.byref(nbytes)) == 0 and nbytes.value > 0
+    tiles = ctypes.c_int64()
+    assert lib.pg_batch_tiles(plan, ctypes.byref(tiles), None) == 0
+    # two 128-tile IBS problems (1 tile each) + LD 64-row tiles: 1 row tile x 2 band tiles
+    assert tiles.value == 1 + 1 + 2
+    # launching with a workspace that was never uploaded is rejected before any launch
+    rc = lib.pg_batch_launch(plan, 0x5000, nbytes.value, None)
+    assert rc == N.PG_EINVAL
+    lib.pg_plan_free(plan)
+    assert lib.pg_batch_plan(arr, 0, ctypes.byref(plan)) == N.PG_EINVAL

@@ -1,0 +1,128 @@
+"""GPU: a batch of uneven problems in one persistent launch (direct and
+captured in a HIP graph, replayed several times with other GPU work in
+between) gives byte-identical outputs to one call per problem, and both
+match the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+pg = pytest.importorskip("paper_1410_4803_amd")
+
+
+def _problems(seed=0):
+    rng = np.random.default_rng(seed)
+    specs = []
+    shapes = [(130, 900), (257, 1500), (64, 4000), (500, 700), (90, 333), (1, 50), (700, 2100)]
+    for k, (n, V) in enumerate(shapes):
+        bed = synth.hwe(n, V, (0.01, 0.5), 0.01, seed=seed * 100 + k, garbage_pad=True)
+        mask = synth.missing_mask(n, V, 0.02, seed=k) if k % 3 == 0 else None
+        specs.append((n, V, bed, mask))
+    c = [pg.Cohort.from_numpy(b, n, m) for (n, V, b, m) in specs]
+    idx = torch.from_numpy(rng.integers(0, 500, 211).astype(np.int32)).cuda()
+    probs = [
+        pg.IbsProblem(c[0], layout="tri", path="mfma"),
+        pg.LdProblem(c[1], window=100, r2_min=0.05, path="mfma"),
+        pg.IbsProblem(c[2], layout="full", path="popc"),
+        pg.LdProblem(c[3], window=64, r2_min=-np.inf, path="popc"),
+        pg.IbsProblem(c[3], sample_idx=idx, v_range=(50, 650), layout="full", path="mfma"),
+        pg.IbsProblem(c[4], layout="tri", path=2 | (1 << 8)),
+        pg.IbsProblem(c[5], layout="tri", path="popc"),
+        pg.LdProblem(c[6], window=300, r2_min=0.02, sample_idx=idx, v_range=(10, 2000),
+                     path="mfma"),
+        pg.IbsProblem(c[6], layout="tri", path="auto"),
+    ]
+    return specs, probs, idx
+
+
+def _single(p):
+    if isinstance(p, pg.IbsProblem):
+        return pg.ibs_matrix(p.cohort, sample_idx=p.sample_idx, v_range=p.v_range,
+                             layout=p.layout, path=p.path)
+    return pg.ld_records(p.cohort, p.window, p.r2_min, sample_idx=p.sample_idx,
+                         v_range=p.v_range, path=p.path)
+
+
+def _same(a, b):
+    if isinstance(a, tuple):
+        return all(torch.equal(x, y) for x, y in zip(a, b))
+    return a.tobytes() == b.tobytes()
+
+
+def test_batch_equals_single_calls_and_oracle():
+    specs, probs, idx = _problems()
+    singles = [_single(p) for p in probs]
+    b = pg.Batch(probs)
+    tiles, grid = b.tiles
+    assert tiles > 0 and grid > 0
+    b.launch()
+    got = b.results()
+    for k, (g, s) in enumerate(zip(got, singles)):
+        assert _same(g, s), f"problem {k} differs from its single call"
+    # oracle for two of them
+    n, V, bed, mask = specs[0]
+    ref = oracle.ibs_matrix(oracle.unpack(bed, n, V, mask), full=False)
+    for g, r in zip(got[0], ref):
+        assert np.array_equal(g.cpu().numpy().view(np.uint32), r)
+    n, V, bed, mask = specs[6]
+    codes = oracle.select(oracle.unpack(bed, n, V, mask), idx.cpu().numpy(), 10, 2000)
+    refl = oracle.ld_window(codes, 300, 0.02)
+    assert len(got[7]) == len(refl)
+    for f in ("n", "sx", "sy", "sxx", "syy", "sxy"):
+        assert np.array_equal(got[7][f], refl[f])
+    assert np.array_equal(got[7]["a"], refl["a"] + 10)
+    b.close()
+
+
+def test_batch_graph_replays():
+    specs, probs, idx = _problems(seed=1)
+    singles = [_single(p) for p in probs]
+    b = pg.Batch(probs)
+    b.capture()
+    for rep in range(3):
+        # scribble over the outputs, replay, and check every replay
+        for p in probs:
+            if isinstance(p, pg.IbsProblem):
+                for t in p.out:
+                    t.fill_(-7)
+            else:
+                p.out.zero_()
+                p.n_out.fill_(-1)
+        junk = torch.randn(512, 512, device="cuda") @ torch.randn(512, 512, device="cuda")
+        torch.cuda.synchronize()
+        b.replay()
+        got = b.results()
+        for k, (g, s) in enumerate(zip(got, singles)):
+            assert _same(g, s), f"replay {rep}: problem {k} differs"
+        del junk
+    b.close()
+
+
+def test_batch_generated_workload_subset():
+    """A slice of the batched workload generator (HWE, log-uniform shapes),
+    shrunk so the single calls stay quick; the tuner picks paths."""
+    probs_spec = synth.batch_problems(count=8, make_bed=False)
+    tuner = pg.Tuner()
+    probs = []
+    for d in probs_spec:
+        n, V = min(d["n"], 1500), min(d["V"], 6000)
+        bed = synth.hwe(n, V, (0.01, 0.5), 0.01, seed=d["seed"])
+        c = pg.Cohort.from_numpy(bed, n)
+        if d["kind"] == "ibs":
+            path = tuner.tune("ibs", c, layout="tri", reps=1)
+            probs.append(pg.IbsProblem(c, layout="tri", path=path))
+        else:
+            path = tuner.tune("ld", c, window=d["window"], r2_min=d["r2_min"], reps=1)
+            probs.append(pg.LdProblem(c, window=d["window"], r2_min=d["r2_min"], path=path))
+    singles = [_single(p) for p in probs]
+    b = pg.Batch(probs)
+    b.capture()
+    b.replay()
+    got = b.results()
+    for k, (g, s) in enumerate(zip(got, singles)):
+        assert _same(g, s), f"problem {k}"
+    b.close()
