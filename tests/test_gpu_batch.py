@@ -8,6 +8,7 @@ import torch
 
 import oracle
 import synth
+from ldcheck import compare_records
 
 pytestmark = pytest.mark.gpu
 
@@ -26,13 +27,14 @@ def _problems(seed=0):
     idx = torch.from_numpy(rng.integers(0, 500, 211).astype(np.int32)).cuda()
     probs = [
         pg.IbsProblem(c[0], layout="tri", path="mfma"),
-        pg.LdProblem(c[1], window=100, r2_min=0.05, path="mfma"),
+        pg.LdProblem(c[1], window=100, r2_min=0.05, capacity=200000, path="mfma"),
         pg.IbsProblem(c[2], layout="full", path="popc"),
-        pg.LdProblem(c[3], window=64, r2_min=-np.inf, path="popc"),
+        pg.LdProblem(c[3], window=64, r2_min=-np.inf, capacity=60000, path="popc"),
         pg.IbsProblem(c[3], sample_idx=idx, v_range=(50, 650), layout="full", path="mfma"),
         pg.IbsProblem(c[4], layout="tri", path=2 | (1 << 8)),
         pg.IbsProblem(c[5], layout="tri", path="popc"),
-        pg.LdProblem(c[6], window=300, r2_min=0.02, sample_idx=idx, v_range=(10, 2000),
+        pg.LdProblem(c[6], window=300, r2_min=0.02, capacity=200000, sample_idx=idx,
+                     v_range=(10, 2000),
                      path="mfma"),
         pg.IbsProblem(c[6], layout="tri", path="auto"),
     ]
@@ -71,10 +73,24 @@ def test_batch_equals_single_calls_and_oracle():
     n, V, bed, mask = specs[6]
     codes = oracle.select(oracle.unpack(bed, n, V, mask), idx.cpu().numpy(), 10, 2000)
     refl = oracle.ld_window(codes, 300, 0.02)
-    assert len(got[7]) == len(refl)
-    for f in ("n", "sx", "sy", "sxx", "syy", "sxy"):
-        assert np.array_equal(got[7][f], refl[f])
-    assert np.array_equal(got[7]["a"], refl["a"] + 10)
+    refl["a"] += 10
+    refl["b"] += 10
+    assert compare_records(got[7], refl, 0.02) > 40000
+    b.close()
+
+
+def test_batch_capacity_protocol():
+    """An LD problem whose emitted pairs exceed its capacity: n_out holds the
+    total, the buffer holds the first `capacity` pairs in (a, b) order."""
+    n, V = 300, 800
+    c = pg.Cohort.from_numpy(synth.mosaic(n, V, switch=0.01, miss=0.01, seed=4), n)
+    full = pg.ld_records(c, 50, -np.inf)
+    b = pg.Batch([pg.LdProblem(c, window=50, r2_min=-np.inf, capacity=100),
+                  pg.IbsProblem(c, layout="tri")])
+    b.launch()
+    got = b.results()[0]
+    assert int(b.problems[0].n_out.item()) == len(full)
+    assert got.tobytes() == full[:100].tobytes()
     b.close()
 
 

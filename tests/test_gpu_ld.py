@@ -13,26 +13,9 @@ pytestmark = pytest.mark.gpu
 
 pg = pytest.importorskip("paper_1410_4803_amd")
 
-TOL = 1e-12
+from ldcheck import compare_records as _compare
+
 PATHS = ["mfma", "popc"]
-FIELDS = ("n", "sx", "sy", "sxx", "syy", "sxy")
-
-
-def _compare(got, ref, r2_min):
-    kg = got["a"].astype(np.int64) * (1 << 32) + got["b"]
-    kr = ref["a"].astype(np.int64) * (1 << 32) + ref["b"]
-    assert (np.diff(kg) > 0).all(), "GPU records not in (a, b) order"
-    common, ig, ir = np.intersect1d(kg, kr, return_indices=True)
-    only_g = np.setdiff1d(np.arange(len(kg)), ig)
-    only_r = np.setdiff1d(np.arange(len(kr)), ir)
-    # pairs on one side only must sit on the threshold
-    assert all(abs(got["r2"][k] - r2_min) <= TOL for k in only_g), got[only_g][:5]
-    assert all(abs(ref["r2"][k] - r2_min) <= TOL for k in only_r), ref[only_r][:5]
-    for f in FIELDS:
-        assert np.array_equal(got[f][ig], ref[f][ir]), f
-    d = np.abs(got["r2"][ig] - ref["r2"][ir])
-    assert np.nanmax(d, initial=0.0) <= TOL
-    return len(common)
 
 
 def _run(bed, n, W, r2_min, mask=None, **kw):
