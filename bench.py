@@ -150,6 +150,78 @@ def cpu_baseline_ibs(bed, n, V, budget_s: float):
                       f"triangle ({comps:.3e} comparisons, {t:.1f} s)"}
 
 
+def bench_batch(torch, lib, hip, pg, synth, dev, steps):
+    """64 uneven problems: the autotuner picks each problem's path; then the
+    one-call-per-problem loop and the captured persistent batch are timed on
+    the same problems and outputs."""
+    log("batched workload: generating 64 problems")
+    specs = synth.batch_problems()
+    tuner = pg.Tuner()
+    probs, comps, calls = [], 0.0, []
+    t_tune = time.perf_counter()
+    for d in specs:
+        c = pg.Cohort.from_numpy(d["bed"], d["n"], device=dev)
+        d.pop("bed")
+        n, V = d["n"], d["V"]
+        if d["kind"] == "ibs":
+            path = tuner.tune("ibs", c, layout="tri", reps=1)
+            p = pg.IbsProblem(c, layout="tri", path=path)
+            comps += n * (n - 1) / 2 * V
+        else:
+            W = d["window"]
+            path = tuner.tune("ld", c, window=W, r2_min=d["r2_min"], reps=1)
+            cap = max(1 << 16, 64 * V)
+            p = pg.LdProblem(c, window=W, r2_min=d["r2_min"], capacity=cap, path=path)
+            comps += sum(min(W, V - 1 - a) for a in range(V)) * n
+        probs.append(p)
+    t_tune = time.perf_counter() - t_tune
+    b = pg.Batch(probs)        # allocates every problem's outputs
+    tiles, grid = b.tiles
+    # one call per problem, same paths and outputs, workspaces allocated up front
+    for p in probs:
+        if isinstance(p, pg.IbsProblem):
+            ws = torch.empty(max(pg.ibs_workspace_bytes(p.cohort, path=p.path), 1),
+                             dtype=torch.uint8, device=dev)
+            calls.append(lambda p=p, ws=ws: pg.ibs_matrix(p.cohort, layout="tri", path=p.path,
+                                                          out=p.out, workspace=ws))
+        else:
+            ws = torch.empty(max(pg.ld_workspace_bytes(p.cohort, p.window, path=p.path), 1),
+                             dtype=torch.uint8, device=dev)
+            calls.append(lambda p=p, ws=ws: pg.ld_window(p.cohort, p.window, p.r2_min,
+                                                         capacity=p.capacity, path=p.path,
+                                                         out=p.out, n_out=p.n_out, workspace=ws))
+
+    def loop():
+        for f in calls:
+            f()
+
+    ms_loop, _ = timed_steps(torch, lib, hip, loop, steps, 2, 2)
+    loop_ld = [int(p.n_out.item()) for p in probs if isinstance(p, pg.LdProblem)]
+    b.capture()
+    ms_graph, st = timed_steps(torch, lib, hip, b.replay, steps, 2, 2)
+    ms_direct, st_d = timed_steps(torch, lib, hip, b.launch, steps, 2, 4)
+    batch_ld = [int(p.n_out.item()) for p in probs if isinstance(p, pg.LdProblem)]
+    assert batch_ld == loop_ld, "batched LD counts differ from the per-problem loop"
+    choice = {}
+    for p in probs:
+        k = ("ibs_" if isinstance(p, pg.IbsProblem) else "ld_") + \
+            {1: "popc", 2: "mfma"}[int(p.path) & 0xFF]
+        choice[k] = choice.get(k, 0) + 1
+    b.close()
+    return {"workload": "batch_64_hwe", "problems": len(probs), "comparisons": comps,
+            "tiles": tiles, "persistent_grid": grid, "path_choices": choice,
+            "tune_s": round(t_tune, 2),
+            "graph": {"value": round(comps / (ms_graph * 1e-3) / 1e9, 1), "unit": "G/s",
+                      "ms_per_step": round(ms_graph, 3)},
+            "direct_launch": {"ms_per_step": round(ms_direct, 3),
+                              "layouts_ms": round(mean(st_d[0]), 3),
+                              "persistent_kernel_ms": round(mean(st_d[1]), 3),
+                              "ld_finish_ms": round(mean(st_d[2]), 3)},
+            "one_call_per_problem": {"value": round(comps / (ms_loop * 1e-3) / 1e9, 1),
+                                     "unit": "G/s", "ms_per_step": round(ms_loop, 3)},
+            "speedup_vs_loop": round(ms_loop / ms_graph, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -299,6 +371,9 @@ def main():
             extras[f"ld_large_{lpath}"] = rec
             del wkl
         del ol, cl
+
+    if not args.quick:
+        extras["batch"] = bench_batch(torch, lib, hip, pg, synth, dev, args.steps)
 
     if args.copy_calibration:
         # plain device copy of exactly 1 GiB, for the HBM byte counters
