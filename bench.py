@@ -88,16 +88,17 @@ def timed_steps(torch, lib, hip, call, steps, warmup, n_events):
     for _ in range(warmup):
         call()
     torch.cuda.synchronize()
-    evs = [hip.create(n_events) for _ in range(steps)]
+    evs = [hip.create(n_events) for _ in range(steps)] if n_events else []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
-        set_stage_events(lib, evs[k])
+        if n_events:
+            set_stage_events(lib, evs[k])
         call()
     set_stage_events(lib, None)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    stages = [[hip.ms(e[s], e[s + 1]) for e in evs] for s in range(n_events - 1)]
+    stages = [[hip.ms(e[s], e[s + 1]) for e in evs] for s in range(max(n_events - 1, 0))]
     for e in evs:
         hip.destroy(e)
     return (t1 - t0) * 1e3 / steps, stages
@@ -107,9 +108,9 @@ def mean(xs):
     return sum(xs) / len(xs)
 
 
-def traffic_from_profile(kernel_src: str, kernel: str):
+def traffic_from_profile(kernel: str):
     """HBM bytes per launch from the committed counter summary, if it was taken
-    on the current kernel source; else None."""
+    on the current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -117,9 +118,11 @@ def traffic_from_profile(kernel_src: str, kernel: str):
         rec = json.load(f).get(kernel)
     if not rec:
         return None
-    with open(kernel_src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
-    if rec.get("source_sha256") != sha:
+    h = hashlib.sha256()
+    for src in rec.get("sources", []):
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if rec.get("source_sha256") != h.hexdigest():
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -195,10 +198,10 @@ def bench_batch(torch, lib, hip, pg, synth, dev, steps):
         for f in calls:
             f()
 
-    ms_loop, _ = timed_steps(torch, lib, hip, loop, steps, 2, 2)
+    ms_loop, _ = timed_steps(torch, lib, hip, loop, steps, 2, 0)
     loop_ld = [int(p.n_out.item()) for p in probs if isinstance(p, pg.LdProblem)]
     b.capture()
-    ms_graph, st = timed_steps(torch, lib, hip, b.replay, steps, 2, 2)
+    ms_graph, _ = timed_steps(torch, lib, hip, b.replay, steps, 2, 0)
     ms_direct, st_d = timed_steps(torch, lib, hip, b.launch, steps, 2, 4)
     batch_ld = [int(p.n_out.item()) for p in probs if isinstance(p, pg.LdProblem)]
     assert batch_ld == loop_ld, "batched LD counts differ from the per-problem loop"
@@ -222,6 +225,56 @@ def bench_batch(torch, lib, hip, pg, synth, dev, steps):
             "speedup_vs_loop": round(ms_loop / ms_graph, 3)}
 
 
+def bench_serve(torch, pg, synth, dev, seconds, serial_seconds):
+    """8 resident cohorts (samples log-uniform in [1k, 50k], variants in
+    [10k, 200k], HWE, MAF~U[0.01,0.5], 1% missing); Poisson 200 requests/s,
+    70% IBS matrices (strict upper triangle) / 30% LD windows (500, r^2 >=
+    0.2); subsets of 100-5,000 samples, ranges of 1k-20k variants.  The
+    8-slot server is compared with one request at a time on the same arrivals."""
+    import numpy as np
+    from paper_1410_4803_amd.serve import GpuBackend, Server, poisson_requests
+    rng = np.random.Generator(np.random.PCG64(1004))
+    shapes = [(int(round(math.exp(rng.uniform(math.log(1000), math.log(50000))))),
+               int(round(math.exp(rng.uniform(math.log(10000), math.log(200000))))))
+              for _ in range(8)]
+    log(f"serving: generating 8 cohorts {shapes}")
+    cohorts = [pg.Cohort.from_numpy(synth.hwe(n, V, (0.01, 0.5), 0.01, seed=2000 + k), n,
+                                    device=dev) for k, (n, V) in enumerate(shapes)]
+    resident = sum(c.nbytes for c in cohorts)
+    budget = 64 << 30
+    reqs = poisson_requests(shapes, rate=200.0, seconds=seconds, seed=1005)
+
+    def work(r):
+        m, L = len(r.sample_idx), r.v_range[1] - r.v_range[0]
+        if r.kind == "ibs":
+            return m * (m - 1) / 2 * L
+        return sum(min(r.window, L - 1 - a) for a in range(L)) * m
+
+    # warm-up: a handful of requests (kernels, allocator pools, pinned buffers)
+    warm = poisson_requests(shapes, rate=200.0, seconds=0.1, seed=99)
+    Server(GpuBackend(cohorts, 8, keep_results=False), 8, budget).run(warm)
+    log(f"serving {len(reqs)} requests over {seconds} s with 8 slots")
+    srv = Server(GpuBackend(cohorts, 8, keep_results=False), 8, budget)
+    st = srv.run(reqs)
+    served = sum(work(r) for r in srv.finished)
+    span = max(r.done for r in srv.finished) - min(r.arrival for r in srv.finished)
+    st["value"] = round(served / span / 1e9, 1)
+    st["unit"] = "G/s"
+    ser_reqs = [r for r in poisson_requests(shapes, rate=200.0, seconds=serial_seconds,
+                                            seed=1005)]
+    log(f"serving {len(ser_reqs)} requests one at a time")
+    ser = Server(GpuBackend(cohorts, 1, keep_results=False), 1, budget)
+    sst = ser.run(ser_reqs)
+    served_s = sum(work(r) for r in ser.finished)
+    span_s = max(r.done for r in ser.finished) - min(r.arrival for r in ser.finished)
+    sst["value"] = round(served_s / span_s / 1e9, 1)
+    sst["unit"] = "G/s"
+    return {"workload": "serve_8_cohorts_poisson200", "cohorts": shapes,
+            "resident_bytes": resident, "memory_budget": budget, "seconds": seconds,
+            "requests": len(reqs), "server_8_slots": st,
+            "serial_one_at_a_time": dict(sst, seconds=serial_seconds)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -231,7 +284,11 @@ def main():
     ap.add_argument("--variant", type=int, default=0, help="kernel variant of the path (tuning)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--quick", action="store_true", help="default workload only, no extras")
+    ap.add_argument("--extras", default="all",
+                    help="comma list of extras: other,small,ld,batch,serve (or all / none)")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--serial-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -279,8 +336,7 @@ def main():
         roof = {"bound": "alu", "achieved": ops / (pair_ms * 1e-3) / 1e12, "peak": PEAK_VALU_TOPS,
                 "unit": "TOP/s", "kernel": "k_ibs_popc"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = traffic_from_profile(
-        os.path.join(ROOT, "paper_1410_4803_amd", "csrc", "ibs.hip"), roof["kernel"])
+    roof["traffic"] = traffic_from_profile(roof["kernel"])
     roof["achieved"] = round(roof["achieved"], 2)
     roof["frac"] = round(roof["frac"], 4)
     roof["launch_ms"] = round(pair_ms, 4)
@@ -310,7 +366,11 @@ def main():
     del out, call
 
     extras = {}
+    want = set()
     if not args.quick:
+        want = {"other", "small", "ld", "batch", "serve"} if args.extras == "all" else \
+            set(x for x in args.extras.split(",") if x and x != "none")
+    if "other" in want:
         other = "popc" if path == "mfma" else "mfma"
         call2, out2 = ibs_runner(other)
         log(f"timing the {other} path")
@@ -321,6 +381,7 @@ def main():
         del call2, out2
         torch.cuda.empty_cache()
 
+    if "small" in want:
         # IBS 500 x 5,000 (strict upper triangle): latency-bound
         ws_ = synth.ibs_small()
         c1 = pg.Cohort.from_numpy(ws_["bed"], ws_["n"], device=dev)
@@ -334,6 +395,7 @@ def main():
                                          "unit": "G/s", "us_per_call": round(ms1 * 1e3, 1),
                                          "pair_kernel_us": round(mean(st1[1]) * 1e3, 1)}
 
+    if "ld" in want:
         # LD 5,000 x 500,000, window 1,000, r^2 >= 0.2
         log("generating the 5000 x 500000 LD panel")
         wl = synth.ld_large()
@@ -362,18 +424,25 @@ def main():
                 ach = compsl * LD_MFMA_OPS / (band_ms * 1e-3) / 1e12
                 rec["roofline"] = {"bound": "mfma", "kernel": "k_ld_mfma", "unit": "TOP/s",
                                    "achieved": round(ach, 2), "peak": PEAK_INT8_TOPS,
-                                   "frac": round(ach / PEAK_INT8_TOPS, 4)}
+                                   "frac": round(ach / PEAK_INT8_TOPS, 4),
+                                   "traffic": traffic_from_profile("k_ld_mfma")}
             else:
                 ach = compsl * LD_POPC_OPS / (band_ms * 1e-3) / 1e12
                 rec["roofline"] = {"bound": "alu", "kernel": "k_ld_popc", "unit": "TOP/s",
                                    "achieved": round(ach, 2), "peak": round(PEAK_VALU_TOPS, 2),
-                                   "frac": round(ach / PEAK_VALU_TOPS, 4)}
+                                   "frac": round(ach / PEAK_VALU_TOPS, 4),
+                                   "traffic": traffic_from_profile("k_ld_popc")}
             extras[f"ld_large_{lpath}"] = rec
             del wkl
         del ol, cl
 
-    if not args.quick:
+    if "batch" in want:
         extras["batch"] = bench_batch(torch, lib, hip, pg, synth, dev, args.steps)
+        torch.cuda.empty_cache()
+    if "serve" in want and args.serve_seconds > 0:
+        extras["serve"] = bench_serve(torch, pg, synth, dev, args.serve_seconds,
+                                      args.serial_seconds)
+        torch.cuda.empty_cache()
 
     if args.copy_calibration:
         # plain device copy of exactly 1 GiB, for the HBM byte counters
