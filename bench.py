@@ -167,7 +167,7 @@ def bench_batch(torch, lib, hip, pg, synth, dev, steps):
         d.pop("bed")
         n, V = d["n"], d["V"]
         if d["kind"] == "ibs":
-            path = tuner.tune("ibs", c, layout="tri", reps=1)
+            path = tuner.tune("ibs", c, layout="tri", reps=1, for_batch=True)
             p = pg.IbsProblem(c, layout="tri", path=path)
             comps += n * (n - 1) / 2 * V
         else:
@@ -318,8 +318,8 @@ def main():
 
     def ibs_runner(path, variant=0):
         out = tuple(torch.empty((n, n), dtype=torch.int32, device=dev) for _ in range(4))
-        ws = torch.empty(pg.ibs_workspace_bytes(cohort, path=path), dtype=torch.uint8, device=dev)
         code = pg.PATHS[path] | (variant << 8)
+        ws = torch.empty(pg.ibs_workspace_bytes(cohort, path=code), dtype=torch.uint8, device=dev)
         return lambda: pg.ibs_matrix(cohort, layout="full", path=code, out=out, workspace=ws), out
 
     path = "mfma" if args.path == "auto" else args.path

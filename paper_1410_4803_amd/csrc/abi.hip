@@ -87,12 +87,6 @@ int make_sel(const pg_genotypes* g, bool list, const int32_t* idx, int64_t n_sel
   return PG_OK;
 }
 
-struct IbsPlan {
-  int path;
-  int variant;
-  int64_t rows_pad, words;  // operand rows and K words
-  int64_t bytes;
-};
 
 int plan_ibs(const Sel& s, int path_arg, IbsPlan& p) {
   int path = path_arg & 0xFF;
@@ -102,7 +96,15 @@ int plan_ibs(const Sel& s, int path_arg, IbsPlan& p) {
   if (path != PG_PATH_MFMA && path != PG_PATH_POPC)
     return fail(PG_EINVAL, "unknown path %d", path);
   p.path = path;
-  if (path == PG_PATH_MFMA) {
+  // fp4 operands accumulate in fp32: exact only while every sum stays below 2^24
+  if (path == PG_PATH_MFMA && (p.variant == kIbsVariantFp4 || p.variant == kIbsVariantFp4Rep) &&
+      s.nv >= ((int64_t)1 << 24))
+    p.variant = 0;
+  if (path == PG_PATH_MFMA && p.variant == kIbsVariantFp4Rep) {
+    p.rows_pad = round_up(s.m, kIbsMfmaTile);
+    p.words = round_up(s.nv, 4 * kIbsRepChunk) / 4;     // 2 words per 8 variants
+    p.bytes = p.rows_pad * p.words * 4;
+  } else if (path == PG_PATH_MFMA) {
     p.rows_pad = round_up(s.m, kIbsMfmaTile);
     p.words = round_up(ceil_div(s.nv, 16), kIbsMfmaKWords);
     p.bytes = p.rows_pad * p.words * 4;
@@ -112,7 +114,7 @@ int plan_ibs(const Sel& s, int path_arg, IbsPlan& p) {
     p.bytes = 3 * p.rows_pad * p.words * 4;
   }
   const int64_t nt = p.rows_pad / (path == PG_PATH_MFMA ? kIbsMfmaTile : kIbsPopcTile);
-  if (nt * (nt + 1) / 2 >= kMaxIndex) return fail(PG_EUNSUPPORTED, "too many samples for one call");
+  if (nt * (nt + 1) / 2 + 2 * nt >= kMaxIndex) return fail(PG_EUNSUPPORTED, "too many samples for one call");
   return PG_OK;
 }
 
@@ -151,6 +153,8 @@ int plan_ld(const Sel& s, int32_t window, int path_arg, LdPlan& p) {
 }
 
 }  // namespace
+
+int plan_ibs_default(const Sel& s, IbsPlan& p) { return plan_ibs(s, PG_PATH_MFMA, p); }
 
 int batch_validate_ibs(const pg_problem& q, Sel& s, int& path, int& variant, int64_t& rows_pad,
                        int64_t& words) {
@@ -253,7 +257,11 @@ int pg_ibs_matrix(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_se
   IbsOut o{ibs0, ibs1, ibs2, nonmiss, s.m, out_layout == PG_FULL};
   uint32_t* ws = (uint32_t*)workspace;
   mark_stage(0, st);
-  if (p.path == PG_PATH_MFMA) {
+  if (p.path == PG_PATH_MFMA && p.variant == kIbsVariantFp4Rep) {
+    rc = launch_sample_major_rep(s, ws, p.rows_pad, p.words, st);
+    mark_stage(1, st);
+    if (rc == PG_OK) rc = launch_ibs_fp4rep(ws, p.words, o, st);
+  } else if (p.path == PG_PATH_MFMA) {
     rc = launch_sample_major_2bit(s, ws, p.rows_pad, p.words, st);
     mark_stage(1, st);
     if (rc == PG_OK) rc = launch_ibs_mfma(ws, p.words, o, p.variant, st);

@@ -61,21 +61,18 @@ __global__ __launch_bounds__(256, 1) void k_batch_persistent(const BatchItem* __
       int64_t I, J;
       tri_tile(local, it.nt, I, J);
       if (it.path == PG_PATH_MFMA) {
-        if (it.variant == 1)
-          ibs_mfma_tile<false>(it.X, it.words, I, J, it.o, smem);
-        else
-          ibs_mfma_tile<true>(it.X, it.words, I, J, it.o, smem);
+        ibs_mfma_tile<true>(it.X, it.words, I, J, it.o, (lds_t*)smem);
       } else {
-        ibs_popc_tile(it.X, it.rows_pad, it.words, I, J, it.o, smem);
+        ibs_popc_tile(it.X, it.rows_pad, it.words, I, J, it.o, (lds_t*)smem);
       }
     } else {
       const int64_t I = local / it.n_band;
       const int64_t J = I + local % it.n_band;
       if (J < it.nt) {
         if (it.path == PG_PATH_MFMA)
-          ld_mfma_tile(it.X, it.words, it.nv, I, J, it.window, it.r2_min, it.sc, smem);
+          ld_mfma_tile(it.X, it.words, it.nv, I, J, it.window, it.r2_min, it.sc, (lds_t*)smem);
         else
-          ld_popc_tile(it.X, it.words, it.nv, it.rows_pad, I, J, it.window, it.r2_min, it.sc, smem);
+          ld_popc_tile(it.X, it.words, it.nv, it.rows_pad, I, J, it.window, it.r2_min, it.sc, (lds_t*)smem);
       }
     }
     __syncthreads();   // LDS is reused by the next tile
@@ -142,6 +139,16 @@ int pg_batch_plan(const pg_problem* probs, int n_probs, pg_plan** out) {
     int rc;
     if (q.p.kind == PG_KIND_IBS) {
       rc = batch_validate_ibs(q.p, q.s, q.path, q.variant, q.rows_pad, q.words);
+      // the persistent kernel hosts one matrix-core body (the int8 default):
+      // every matrix-core variant gives the same counts, and hosting more bodies
+      // would raise the kernel's register and LDS budget for every tile
+      if (rc == PG_OK && q.path == PG_PATH_MFMA && q.variant != 0) {
+        q.variant = 0;
+        IbsPlan dflt;
+        rc = plan_ibs_default(q.s, dflt);
+        q.rows_pad = dflt.rows_pad;
+        q.words = dflt.words;
+      }
       if (rc == PG_OK) {
         const int tile = q.path == PG_PATH_MFMA ? kIbsMfmaTile : kIbsPopcTile;
         q.nt = q.rows_pad / tile;
@@ -150,7 +157,7 @@ int pg_batch_plan(const pg_problem* probs, int n_probs, pg_plan** out) {
                                                      : 3 * q.rows_pad * q.words * 4;
         q.off_x = take(off, bytes);
         // rough cycles per tile, for longest-first ordering
-        q.tile_cost = q.path == PG_PATH_MFMA ? (double)q.words * 430.0 : (double)q.words * 520.0;
+        q.tile_cost = q.path == PG_PATH_MFMA ? (double)q.words * 460.0 : (double)q.words * 520.0;
       }
     } else if (q.p.kind == PG_KIND_LD) {
       rc = batch_validate_ld(q.p, q.s, q.path, q.variant, q.rows_pad, q.words, q.bm_words);

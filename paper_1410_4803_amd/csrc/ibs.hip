@@ -30,8 +30,8 @@ __global__ __launch_bounds__(256, 1) void k_ibs_mfma(const uint32_t* __restrict_
                                                      int64_t nt, IbsOut o) {
   __shared__ __attribute__((aligned(16))) uint32_t smem[kIbsMfmaSmem];
   int64_t I, J;
-  tri_tile(blockIdx.x, nt, I, J);
-  ibs_mfma_tile<kHints>(T, wp, I, J, o, smem);
+  if (!band_tile(xcd_swizzle(blockIdx.x, gridDim.x), nt, I, J)) return;
+  ibs_mfma_tile<kHints>(T, wp, I, J, o, (lds_t*)smem);
 }
 
 __global__ __launch_bounds__(256, 1) void k_ibs_mfma_simple(const uint32_t* __restrict__ T,
@@ -39,7 +39,23 @@ __global__ __launch_bounds__(256, 1) void k_ibs_mfma_simple(const uint32_t* __re
   __shared__ __attribute__((aligned(16))) uint32_t smem[kIbsMfmaSimpleSmem];
   int64_t I, J;
   tri_tile(blockIdx.x, nt, I, J);
-  ibs_mfma_tile_simple(T, wp, I, J, o, smem);
+  ibs_mfma_tile_simple(T, wp, I, J, o, (lds_t*)smem);
+}
+
+__global__ __launch_bounds__(256, 1) void k_ibs_fp4(const uint32_t* __restrict__ T, int64_t wp,
+                                                    int64_t nt, IbsOut o) {
+  __shared__ __attribute__((aligned(16))) uint32_t smem[kIbsMfmaSmem];
+  int64_t I, J;
+  if (!band_tile(xcd_swizzle(blockIdx.x, gridDim.x), nt, I, J)) return;
+  ibs_fp4_tile(T, wp, I, J, o, (lds_t*)smem);
+}
+
+__global__ __launch_bounds__(256, 1) void k_ibs_fp4rep(const uint32_t* __restrict__ R, int64_t rp,
+                                                       int64_t nt, IbsOut o) {
+  __shared__ __attribute__((aligned(16))) uint32_t smem[kIbsRepSmem];
+  int64_t I, J;
+  if (!band_tile(xcd_swizzle(blockIdx.x, gridDim.x), nt, I, J)) return;
+  ibs_fp4rep_tile(R, rp, I, J, o, (lds_t*)smem);
 }
 
 __global__ __launch_bounds__(256) void k_ibs_popc(const uint32_t* __restrict__ P, int64_t rows_pad,
@@ -47,19 +63,28 @@ __global__ __launch_bounds__(256) void k_ibs_popc(const uint32_t* __restrict__ P
   __shared__ __attribute__((aligned(16))) uint32_t smem[kIbsPopcSmem];
   int64_t I, J;
   tri_tile(blockIdx.x, nt, I, J);
-  ibs_popc_tile(P, rows_pad, words_pad, I, J, o, smem);
+  ibs_popc_tile(P, rows_pad, words_pad, I, J, o, (lds_t*)smem);
 }
 
 int launch_ibs_mfma(const uint32_t* T, int64_t wp, const IbsOut& o, int variant, hipStream_t st) {
   const int64_t nt = ceil_div(o.m, kT);
-  const int64_t blocks = nt * (nt + 1) / 2;
+  const int64_t blocks = variant == 2 ? nt * (nt + 1) / 2 : band_start((nt + 3) / 4, nt);
   if (variant == 1)
     hipLaunchKernelGGL(k_ibs_mfma<false>, dim3((unsigned)blocks), dim3(256), 0, st, T, wp, nt, o);
   else if (variant == 2)
     hipLaunchKernelGGL(k_ibs_mfma_simple, dim3((unsigned)blocks), dim3(256), 0, st, T, wp, nt, o);
+  else if (variant == 3)
+    hipLaunchKernelGGL(k_ibs_fp4, dim3((unsigned)blocks), dim3(256), 0, st, T, wp, nt, o);
   else
     hipLaunchKernelGGL(k_ibs_mfma<true>, dim3((unsigned)blocks), dim3(256), 0, st, T, wp, nt, o);
   return check_launch("ibs_mfma");
+}
+
+int launch_ibs_fp4rep(const uint32_t* R, int64_t rp, const IbsOut& o, hipStream_t st) {
+  const int64_t nt = ceil_div(o.m, kT);
+  const int64_t blocks = band_start((nt + 3) / 4, nt);
+  hipLaunchKernelGGL(k_ibs_fp4rep, dim3((unsigned)blocks), dim3(256), 0, st, R, rp, nt, o);
+  return check_launch("ibs_fp4rep");
 }
 
 int launch_ibs_popc(const uint32_t* P, int64_t rows_pad, int64_t words_pad, const IbsOut& o,

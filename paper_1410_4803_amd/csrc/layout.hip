@@ -197,6 +197,75 @@ __global__ __launch_bounds__(256) void k_ld_planes(Sel s, uint32_t* __restrict__
   }
 }
 
+// Replicated fp4 operand: for each sample and each group of 8 variants, two
+// words.  HR holds each code's high bit at nibble bits 1 and 3; LR holds its
+// low bit at nibble bits 1 and 3 and ones at nibble bits 0 and 2.  Missing
+// positions (and padding) are HR = 0, LR = ~0.  With this layout every fp4
+// feature nibble is one three-input bit function of (HR, LR, bit-1 mask).
+__device__ __forceinline__ void rep_pair(uint32_t codes8, uint32_t& hr, uint32_t& lr) {
+  // codes8: 8 codes in the low 16 bits, code t at bits 2t -> code t at bits 4t (nibbles)
+  uint32_t x = codes8 & 0xFFFFu;
+  x = (x | (x << 8)) & 0x00FF00FFu;
+  x = (x | (x << 4)) & 0x0F0F0F0Fu;
+  x = (x | (x << 2)) & 0x33333333u;
+  const uint32_t hi = (x >> 1) & 0x11111111u, lo = x & 0x11111111u;
+  hr = (hi << 1) | (hi << 3);
+  lr = (lo << 1) | (lo << 3) | 0x55555555u;
+}
+
+// Replicated operand without a sample list: a thread owns 16 samples x 64
+// variants (four 16x16 transposes) and writes 16 words per sample row.
+__global__ __launch_bounds__(256) void k_sample_major_rep(Sel s, uint32_t* __restrict__ R,
+                                                          int64_t rows_pad, int64_t rp,
+                                                          int aligned) {
+  const int64_t groups = rows_pad / 16;
+  const int64_t quads = rp / 16;               // 64 variants = 16 words per sample
+  const int64_t total = groups * quads;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t g = e % groups;
+    const int64_t q = e / groups;
+    uint32_t out[4][16];
+#pragma unroll
+    for (int ww = 0; ww < 4; ++ww) {
+      const int64_t w = 4 * q + ww;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) out[ww][r] = row_word16(s, 16 * w + r, g, aligned != 0);
+      transpose16_2bit(out[ww]);
+    }
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      uint32_t v[16];
+#pragma unroll
+      for (int ww = 0; ww < 4; ++ww) {
+        rep_pair(out[ww][c], v[4 * ww + 0], v[4 * ww + 1]);
+        rep_pair(out[ww][c] >> 16, v[4 * ww + 2], v[4 * ww + 3]);
+      }
+      uint4* dst = reinterpret_cast<uint4*>(R + (16 * g + c) * rp + 16 * q);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) dst[k] = make_uint4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+    }
+  }
+}
+
+// Replicated operand with a sample list: one 8-variant group per thread.
+__global__ __launch_bounds__(256) void k_sample_major_rep_gather(Sel s, uint32_t* __restrict__ R,
+                                                                 int64_t rows_pad, int64_t rp) {
+  const int64_t ngroups = rp / 2;
+  const int64_t total = rows_pad * ngroups;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / ngroups;
+    const int64_t q = e % ngroups;
+    uint32_t codes = 0;
+    for (int b = 0; b < 8; ++b) codes |= code_at(s, 8 * q + b, i) << (2 * b);
+    uint32_t hr, lr;
+    rep_pair(codes, hr, lr);
+    R[i * rp + 2 * q] = hr;
+    R[i * rp + 2 * q + 1] = lr;
+  }
+}
+
 // Variant-major 2-bit words without a sample list: one word per thread.
 __global__ __launch_bounds__(256) void k_variant_major_fast(Sel s, uint32_t* __restrict__ D,
                                                             int64_t rows_pad, int64_t wn,
@@ -326,11 +395,65 @@ int launch_variant_major_2bit(const Sel& s, uint32_t* D, int64_t rows_pad, int64
   return check_launch("variant_major_2bit");
 }
 
+// LD bit planes without a sample list, staged through LDS: a block owns 64
+// variants x 32 plane words (1,024 samples).  Lanes read consecutive dwords of
+// one variant row (coalesced), the three 16-bit half-planes of each dword go
+// to LDS, and lanes then write consecutive variants of one plane word
+// (coalesced).
+__global__ __launch_bounds__(256) void k_ld_planes_tiled(Sel s, uint32_t* __restrict__ P,
+                                                         int64_t rows_pad, int64_t words_pad,
+                                                         int aligned) {
+  __shared__ uint16_t half[3][64][65];
+  const int t = threadIdx.x;
+  const int64_t nrb = rows_pad / 64;
+  const int64_t v0 = ((int64_t)blockIdx.x % nrb) * 64;
+  const int64_t w0 = ((int64_t)blockIdx.x / nrb) * 32;      // first plane word
+#pragma unroll 4
+  for (int k = 0; k < 16; ++k) {
+    const int row = (t >> 6) + 4 * k;
+    const int d = t & 63;                                    // 16-sample group in the block
+    const uint32_t x = row_word16(s, v0 + row, 2 * w0 + d, aligned != 0);
+    const uint32_t lo = x & 0x55555555u, hi = (x >> 1) & 0x55555555u;
+    half[0][row][d] = (uint16_t)compact_even_bits(lo & hi);
+    half[1][row][d] = (uint16_t)compact_even_bits(~(lo | hi) & 0x55555555u);
+    half[2][row][d] = (uint16_t)compact_even_bits(~(lo & ~hi) & 0x55555555u);
+  }
+  __syncthreads();
+#pragma unroll 4
+  for (int k = 0; k < 24; ++k) {
+    const int e = t + 256 * k;
+    const int row = e & 63;
+    const int pw = e >> 6;                                   // 0..95
+    const int p = pw % 3, w = pw / 3;
+    if (w0 + w < words_pad)
+      P[((w0 + w) * 3 + p) * rows_pad + v0 + row] =
+          (uint32_t)half[p][row][2 * w] | ((uint32_t)half[p][row][2 * w + 1] << 16);
+  }
+}
+
 int launch_ld_planes(const Sel& s, uint32_t* P, int64_t rows_pad, int64_t words_pad,
                      hipStream_t st) {
-  hipLaunchKernelGGL(k_ld_planes, dim3(stride_grid(rows_pad * words_pad)), dim3(256), 0, st, s, P,
-                     rows_pad, words_pad, (int)rows_dword_aligned(s));
+  if (!s.idx) {
+    const int64_t blocks = (rows_pad / 64) * ceil_div(words_pad, 32);
+    hipLaunchKernelGGL(k_ld_planes_tiled, dim3((unsigned)blocks), dim3(256), 0, st, s, P, rows_pad,
+                       words_pad, (int)rows_dword_aligned(s));
+  } else {
+    hipLaunchKernelGGL(k_ld_planes, dim3(stride_grid(rows_pad * words_pad)), dim3(256), 0, st, s,
+                       P, rows_pad, words_pad, (int)rows_dword_aligned(s));
+  }
   return check_launch("ld_planes");
+}
+
+int launch_sample_major_rep(const Sel& s, uint32_t* R, int64_t rows_pad, int64_t rp,
+                            hipStream_t st) {
+  if (!s.idx) {
+    hipLaunchKernelGGL(k_sample_major_rep, dim3(stride_grid(rows_pad / 16 * (rp / 16))), dim3(256),
+                       0, st, s, R, rows_pad, rp, (int)rows_dword_aligned(s));
+  } else {
+    hipLaunchKernelGGL(k_sample_major_rep_gather, dim3(stride_grid(rows_pad * (rp / 2))), dim3(256),
+                       0, st, s, R, rows_pad, rp);
+  }
+  return check_launch("sample_major_rep");
 }
 
 }  // namespace pg

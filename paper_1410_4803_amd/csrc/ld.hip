@@ -37,11 +37,12 @@ int ld_clear(const LdScratch& sc, int64_t rows_pad, hipStream_t st) {
 __global__ __launch_bounds__(256) void k_ld_popc(const uint32_t* __restrict__ P, int64_t words_pad,
                                                  int64_t nv, int64_t rows_pad, int64_t n_band,
                                                  int32_t window, double r2_min, LdScratch sc) {
-  const int64_t I = (int64_t)blockIdx.x / n_band;
-  const int64_t J = I + (int64_t)blockIdx.x % n_band;
+  const int64_t b = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int64_t I = b / n_band;
+  const int64_t J = I + b % n_band;
   if (J >= rows_pad / kLP) return;
   __shared__ __attribute__((aligned(16))) uint32_t smem[kLdPopcSmem];
-  ld_popc_tile(P, words_pad, nv, rows_pad, I, J, window, r2_min, sc, smem);
+  ld_popc_tile(P, words_pad, nv, rows_pad, I, J, window, r2_min, sc, (lds_t*)smem);
 }
 
 int launch_ld_popc(const uint32_t* P, int64_t words_pad, int64_t nv, int64_t rows_pad,
@@ -58,11 +59,12 @@ int launch_ld_popc(const uint32_t* P, int64_t words_pad, int64_t nv, int64_t row
 __global__ __launch_bounds__(256, 2) void k_ld_mfma(const uint32_t* __restrict__ D, int64_t wn,
                                                     int64_t nv, int64_t n_row_tiles, int64_t n_band,
                                                     int32_t window, double r2_min, LdScratch sc) {
-  const int64_t I = (int64_t)blockIdx.x / n_band;
-  const int64_t J = I + (int64_t)blockIdx.x % n_band;
+  const int64_t b = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int64_t I = b / n_band;
+  const int64_t J = I + b % n_band;
   if (J >= n_row_tiles) return;
   __shared__ __attribute__((aligned(16))) uint32_t smem[kLdMfmaSmem];
-  ld_mfma_tile(D, wn, nv, I, J, window, r2_min, sc, smem);
+  ld_mfma_tile(D, wn, nv, I, J, window, r2_min, sc, (lds_t*)smem);
 }
 
 int launch_ld_mfma(const uint32_t* D, int64_t wn, int64_t nv, int64_t rows_pad, int32_t window,

@@ -55,6 +55,11 @@ constexpr uint32_t kAllMissing16 = 0x55555555u;
 // of selected sample i (code of variant 16w+t at bits 2t); rows_pad x wp.
 int launch_sample_major_2bit(const Sel& s, uint32_t* T, int64_t rows_pad, int64_t wp,
                              hipStream_t st);
+// Replicated fp4 operand (matrix-core variant 4): per sample, per group of 8
+// variants, words HR (high code bits at nibble bits 1 and 3) and LR (low code
+// bits at nibble bits 1 and 3, ones at bits 0 and 2); rp words per row.
+int launch_sample_major_rep(const Sel& s, uint32_t* R, int64_t rows_pad, int64_t rp,
+                            hipStream_t st);
 // Sample-major bit planes for the popcount IBS path: for 32-variant word w,
 // plane p (0 = high code bit, 1 = low code bit, 2 = non-missing) of sample i
 // at P[(w*3 + p)*rows_pad + i]; words_pad words.
@@ -83,10 +88,25 @@ struct IbsOut {
 
 constexpr int kIbsMfmaTile = 128;     // samples per tile side
 constexpr int kIbsMfmaKWords = 16;    // 2-bit words per K chunk (256 variants)
+constexpr int kIbsVariantFp4 = 3;     // matrix-core variant with fp4 operands
+constexpr int kIbsVariantFp4Rep = 4;  // fp4 operands from the replicated layout
+constexpr int kIbsRepChunk = 64;      // replicated words per K chunk (256 variants)
 constexpr int kIbsPopcTile = 64;
 constexpr int kIbsPopcKWords = 16;    // 32-bit plane words per K chunk
 
+// Operand plan of an IBS call: resolved path and variant, operand rows and K
+// words, workspace bytes.
+struct IbsPlan {
+  int path;
+  int variant;
+  int64_t rows_pad, words;
+  int64_t bytes;
+};
+// The plan of the default matrix-core kernel for a selection (abi.hip).
+int plan_ibs_default(const Sel& s, IbsPlan& p);
+
 int launch_ibs_mfma(const uint32_t* T, int64_t wp, const IbsOut& o, int variant, hipStream_t st);
+int launch_ibs_fp4rep(const uint32_t* R, int64_t rp, const IbsOut& o, hipStream_t st);
 int launch_ibs_popc(const uint32_t* P, int64_t rows_pad, int64_t words_pad, const IbsOut& o,
                     hipStream_t st);
 

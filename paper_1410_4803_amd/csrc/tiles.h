@@ -9,6 +9,22 @@
 
 namespace pg {
 
+// LDS scratch, typed in the LDS address space so every access is a ds_read /
+// ds_write (a generic pointer would compile to flat instructions).
+typedef __attribute__((address_space(3))) uint32_t lds_t;
+typedef unsigned int lds_v4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) lds_v4 lds_v4_t;
+
+__device__ __forceinline__ uint4 lds_ld4(const lds_t* p) {
+  const lds_v4 v = *reinterpret_cast<const lds_v4_t*>(p);
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void lds_st4(lds_t* p, const uint4& v) {
+  lds_v4 x;
+  x.x = v.x; x.y = v.y; x.z = v.z; x.w = v.w;
+  *reinterpret_cast<lds_v4_t*>(p) = x;
+}
+
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
@@ -50,6 +66,41 @@ __device__ __forceinline__ void tri_tile(int64_t b, int64_t nt, int64_t& I, int6
   while (i + 1 < nt && (i + 1) * nt - (i + 1) * i / 2 <= b) ++i;
   I = i;
   J = i + (b - (i * nt - i * (i - 1) / 2));
+}
+
+// Banded tile order for the stand-alone matrix-core kernels: tile rows are
+// taken four at a time (band P = rows 4P..4P+3) and, inside a band, columns
+// ascend with the four rows of a column adjacent.  Band P holds 4*(nt - 4P)
+// virtual tiles starting at 4*nt*P - 8*P*(P-1); virtual tiles below the
+// diagonal or past the matrix are empty (returns false).  Thirty-two
+// consecutive indices cover a 4 x 8 block of tiles, which shares 4 row panels
+// and 8 column panels.
+__host__ __device__ __forceinline__ int64_t band_start(int64_t P, int64_t nt) {
+  return 4 * nt * P - 8 * P * (P - 1);
+}
+
+__device__ __forceinline__ bool band_tile(int64_t b, int64_t nt, int64_t& I, int64_t& J) {
+  const double f = 4.0 * (double)nt + 8.0;
+  const double disc = f * f - 32.0 * (double)b;
+  int64_t P = (int64_t)((f - sqrt(disc > 0.0 ? disc : 0.0)) / 16.0);
+  const int64_t nb = (nt + 3) / 4;
+  if (P < 0) P = 0;
+  if (P > nb - 1) P = nb - 1;
+  while (P > 0 && band_start(P, nt) > b) --P;
+  while (P + 1 < nb && band_start(P + 1, nt) <= b) ++P;
+  const int64_t local = b - band_start(P, nt);
+  I = 4 * P + (local & 3);
+  J = 4 * P + (local >> 2);
+  return I < nt && J < nt && J >= I;
+}
+
+// Blocks are handed to the 8 XCDs round-robin (block b runs on XCD b % 8);
+// remap so each XCD takes a contiguous run of the tile order (for the first
+// 8*(B/8) blocks) and its L2 sees neighbouring tiles.
+__device__ __forceinline__ int64_t xcd_swizzle(int64_t b, int64_t nblocks) {
+  const int64_t full = (nblocks / 8) * 8;
+  if (b >= full) return b;
+  return (b % 8) * (full / 8) + b / 8;
 }
 
 __device__ __forceinline__ void store_counts(const IbsOut& o, int64_t i, int64_t j, bool mirror,
@@ -110,15 +161,23 @@ struct IbsAcc {
 };
 
 __device__ __forceinline__ void mfma_step(IbsAcc& acc, const Feat4 (&fa)[2], const Feat4 (&fb)[2]) {
+  // grouped by feature, so the two updates of each G_h - G_c accumulator are
+  // never back to back
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int q = 0; q < 4; ++q)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      acc.m[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a].m, fb[b].m, acc.m[a][b], 0, 0, 0);
-      acc.w[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a].w, fb[b].w, acc.w[a][b], 0, 0, 0);
-      acc.hc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a].h, fb[b].h, acc.hc[a][b], 0, 0, 0);
-      acc.hc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a].c, fb[b].c, acc.hc[a][b], 0, 0, 0);
-    }
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        if (q == 0)
+          acc.m[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a].m, fb[b].m, acc.m[a][b], 0, 0, 0);
+        else if (q == 1)
+          acc.w[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a].w, fb[b].w, acc.w[a][b], 0, 0, 0);
+        else if (q == 2)
+          acc.hc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a].h, fb[b].h, acc.hc[a][b], 0, 0, 0);
+        else
+          acc.hc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a].c, fb[b].c, acc.hc[a][b], 0, 0, 0);
+      }
 }
 
 // 32x32 accumulator layout: register v of lane l holds row
@@ -156,9 +215,10 @@ __device__ __forceinline__ void zero_acc(IbsAcc& acc) {
 template <bool kHints>
 __device__ __forceinline__ void ibs_mfma_tile(const uint32_t* __restrict__ T, int64_t wp,
                                               int64_t I, int64_t J, const IbsOut& o,
-                                              uint32_t* smem) {
-  uint32_t* sA[2] = {smem, smem + kT * kLdsStride};
-  uint32_t* sB[2] = {smem + 2 * kT * kLdsStride, smem + 3 * kT * kLdsStride};
+                                              lds_t* smem) {
+  constexpr int kBuf = kT * kLdsStride;
+  lds_t* const sA = smem;
+  lds_t* const sB = smem + 2 * kBuf;
   const int t = threadIdx.x;
   const int lane = t & 63;
   const int wid = t >> 6;
@@ -180,10 +240,10 @@ __device__ __forceinline__ void ibs_mfma_tile(const uint32_t* __restrict__ T, in
     gb1 = *reinterpret_cast<const uint4*>(pb + half + kc);
   };
   auto lstore = [&](int buf) {
-    *reinterpret_cast<uint4*>(&sA[buf][lrow * kLdsStride + lq]) = ga0;
-    *reinterpret_cast<uint4*>(&sA[buf][(lrow + 64) * kLdsStride + lq]) = ga1;
-    *reinterpret_cast<uint4*>(&sB[buf][lrow * kLdsStride + lq]) = gb0;
-    *reinterpret_cast<uint4*>(&sB[buf][(lrow + 64) * kLdsStride + lq]) = gb1;
+    lds_st4(&(sA + buf * kBuf)[lrow * kLdsStride + lq], ga0);
+    lds_st4(&(sA + buf * kBuf)[(lrow + 64) * kLdsStride + lq], ga1);
+    lds_st4(&(sB + buf * kBuf)[lrow * kLdsStride + lq], gb0);
+    lds_st4(&(sB + buf * kBuf)[(lrow + 64) * kLdsStride + lq], gb1);
   };
 
   IbsAcc acc;
@@ -199,12 +259,12 @@ __device__ __forceinline__ void ibs_mfma_tile(const uint32_t* __restrict__ T, in
     uint32_t wa[2][8], wb[2][8];
 #pragma unroll
     for (int x = 0; x < 2; ++x) {
-      const uint32_t* ra = &sA[buf][(wr * 64 + x * 32 + rl) * kLdsStride + g * 8];
-      const uint32_t* rb = &sB[buf][(wc * 64 + x * 32 + rl) * kLdsStride + g * 8];
-      const uint4 a0 = *reinterpret_cast<const uint4*>(ra);
-      const uint4 a1 = *reinterpret_cast<const uint4*>(ra + 4);
-      const uint4 b0 = *reinterpret_cast<const uint4*>(rb);
-      const uint4 b1 = *reinterpret_cast<const uint4*>(rb + 4);
+      const lds_t* ra = &(sA + buf * kBuf)[(wr * 64 + x * 32 + rl) * kLdsStride + g * 8];
+      const lds_t* rb = &(sB + buf * kBuf)[(wc * 64 + x * 32 + rl) * kLdsStride + g * 8];
+      const uint4 a0 = lds_ld4(ra);
+      const uint4 a1 = lds_ld4(ra + 4);
+      const uint4 b0 = lds_ld4(rb);
+      const uint4 b1 = lds_ld4(rb + 4);
       wa[x][0] = a0.x; wa[x][1] = a0.y; wa[x][2] = a0.z; wa[x][3] = a0.w;
       wa[x][4] = a1.x; wa[x][5] = a1.y; wa[x][6] = a1.z; wa[x][7] = a1.w;
       wb[x][0] = b0.x; wb[x][1] = b0.y; wb[x][2] = b0.z; wb[x][3] = b0.w;
@@ -244,9 +304,9 @@ __device__ __forceinline__ void ibs_mfma_tile(const uint32_t* __restrict__ T, in
 // Unpipelined reference form (variant 2).
 __device__ __forceinline__ void ibs_mfma_tile_simple(const uint32_t* __restrict__ T, int64_t wp,
                                                      int64_t I, int64_t J, const IbsOut& o,
-                                                     uint32_t* smem) {
-  uint32_t* sA = smem;
-  uint32_t* sB = smem + kT * kLdsStride;
+                                                     lds_t* smem) {
+  lds_t* const sA = smem;
+  lds_t* const sB = smem + kT * kLdsStride;
   const int t = threadIdx.x;
   const int lane = t & 63;
   const int wid = t >> 6;
@@ -261,8 +321,8 @@ __device__ __forceinline__ void ibs_mfma_tile_simple(const uint32_t* __restrict_
       const int q = t & 3;
       const uint4 a = *reinterpret_cast<const uint4*>(gA + r * wp + kc + q * 4);
       const uint4 b = *reinterpret_cast<const uint4*>(gB + r * wp + kc + q * 4);
-      *reinterpret_cast<uint4*>(&sA[r * kLdsStride + q * 4]) = a;
-      *reinterpret_cast<uint4*>(&sB[r * kLdsStride + q * 4]) = b;
+      lds_st4(&sA[r * kLdsStride + q * 4], a);
+      lds_st4(&sB[r * kLdsStride + q * 4], b);
     }
     __syncthreads();
     const int g = lane >> 5;
@@ -291,9 +351,9 @@ constexpr int kPW = kIbsPopcKWords;
 
 __device__ __forceinline__ void ibs_popc_tile(const uint32_t* __restrict__ P, int64_t rows_pad,
                                               int64_t words_pad, int64_t I, int64_t J,
-                                              const IbsOut& o, uint32_t* smem) {
-  uint32_t* sA = smem;
-  uint32_t* sB = smem + kPW * 3 * kP;
+                                              const IbsOut& o, lds_t* smem) {
+  lds_t* const sA = smem;
+  lds_t* const sB = smem + kPW * 3 * kP;
   const int t = threadIdx.x;
   const int tx = t & 15, ty = t >> 4;
   uint32_t cn[4][4], cz[4][4], co[4][4];
@@ -309,18 +369,18 @@ __device__ __forceinline__ void ibs_popc_tile(const uint32_t* __restrict__ P, in
       const int64_t gw = (kc * 3 + row) * rows_pad;
       const uint4 a = *reinterpret_cast<const uint4*>(P + gw + I * kP + col);
       const uint4 b = *reinterpret_cast<const uint4*>(P + gw + J * kP + col);
-      *reinterpret_cast<uint4*>(&sA[row * kP + col]) = a;
-      *reinterpret_cast<uint4*>(&sB[row * kP + col]) = b;
+      lds_st4(&sA[row * kP + col], a);
+      lds_st4(&sB[row * kP + col], b);
     }
     __syncthreads();
 #pragma unroll 4
     for (int w = 0; w < kPW; ++w) {
-      const uint4 ah = *reinterpret_cast<const uint4*>(&sA[(w * 3 + 0) * kP + ty * 4]);
-      const uint4 al = *reinterpret_cast<const uint4*>(&sA[(w * 3 + 1) * kP + ty * 4]);
-      const uint4 am = *reinterpret_cast<const uint4*>(&sA[(w * 3 + 2) * kP + ty * 4]);
-      const uint4 bh = *reinterpret_cast<const uint4*>(&sB[(w * 3 + 0) * kP + tx * 4]);
-      const uint4 bl = *reinterpret_cast<const uint4*>(&sB[(w * 3 + 1) * kP + tx * 4]);
-      const uint4 bm = *reinterpret_cast<const uint4*>(&sB[(w * 3 + 2) * kP + tx * 4]);
+      const uint4 ah = lds_ld4(&sA[(w * 3 + 0) * kP + ty * 4]);
+      const uint4 al = lds_ld4(&sA[(w * 3 + 1) * kP + ty * 4]);
+      const uint4 am = lds_ld4(&sA[(w * 3 + 2) * kP + ty * 4]);
+      const uint4 bh = lds_ld4(&sB[(w * 3 + 0) * kP + tx * 4]);
+      const uint4 bl = lds_ld4(&sB[(w * 3 + 1) * kP + tx * 4]);
+      const uint4 bm = lds_ld4(&sB[(w * 3 + 2) * kP + tx * 4]);
       const uint32_t AH[4] = {ah.x, ah.y, ah.z, ah.w}, AL[4] = {al.x, al.y, al.z, al.w},
                      AM[4] = {am.x, am.y, am.z, am.w};
       const uint32_t BH[4] = {bh.x, bh.y, bh.z, bh.w}, BL[4] = {bl.x, bl.y, bl.z, bl.w},
@@ -344,6 +404,294 @@ __device__ __forceinline__ void ibs_popc_tile(const uint32_t* __restrict__ P, in
                    co[r][c]);
 }
 
+
+// ---- matrix-core path, fp4 operands -----------------------------------------------
+// The same four Grams on the fp4 (e2m1) matrix cores: v_mfma_scale_f32_32x32x64_f8f6f4
+// with both operands in fp4 and unit scales.  Every feature value is -1, 0 or
+// +1, exact in e2m1 (0b0010 = 1.0, 0b1010 = -1.0); every partial sum is an
+// integer of magnitude <= V, exact in the fp32 accumulator while V < 2^24
+// (the caller falls back to the int8 kernel above that).  One MFMA lane holds
+// 32 K values = two 2-bit words; a word's codes are spread to nibbles (even
+// codes, then odd codes -- the same K order on both sides) and each nibble is
+// mapped to the four features with three-input bit operations.
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+
+struct Fp4Feat {
+  v8i m, w, h, c;
+};
+
+// Eight codes, one per nibble (bits 2-3 of each nibble clear) -> the fp4
+// nibbles of m, w, h and c (negc: -c, for the B side).
+__device__ __forceinline__ void fp4_nibbles(uint32_t x, bool negc, uint32_t& m, uint32_t& w,
+                                            uint32_t& h, uint32_t& c) {
+  constexpr uint32_t kMag = 0x22222222u;  // nibble bit 1: exponent LSB, |value| = 1.0
+  const uint32_t y = x << 1;              // code low bit now at nibble bit 1
+  m = (x | ~y) & kMag;                    // code != 01
+  const uint32_t het = x & ~y & kMag;     // code 10
+  w = m | (het << 2);                     // sign (nibble bit 3) for heterozygotes
+  h = ~(x ^ y) & kMag;                    // code 00 or 11
+  const uint32_t neg = negc ? (x & y & kMag) : (~x & ~y & kMag);  // 11 on B, 00 on A
+  c = h | (neg << 2);
+}
+
+__device__ __forceinline__ Fp4Feat fp4_expand(uint32_t w0, uint32_t w1, bool negc) {
+  Fp4Feat f;
+  const uint32_t xs[4] = {w0 & 0x33333333u, (w0 >> 2) & 0x33333333u, w1 & 0x33333333u,
+                          (w1 >> 2) & 0x33333333u};
+  f.m = (v8i){0}; f.w = (v8i){0}; f.h = (v8i){0}; f.c = (v8i){0};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    uint32_t m, w, h, c;
+    fp4_nibbles(xs[q], negc, m, w, h, c);
+    f.m[q] = (int)m; f.w[q] = (int)w; f.h[q] = (int)h; f.c[q] = (int)c;
+  }
+  return f;
+}
+
+struct Fp4Acc {
+  v16f m[2][2], w[2][2], hc[2][2];
+};
+
+__device__ __forceinline__ v16f mfma_fp4(const v8i& a, const v8i& b, const v16f& c) {
+  // formats 4/4 = e2m1 for A and B; scales 127 = 2^0 in e8m0
+  return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 4, 4, 0, 127, 0, 127);
+}
+
+__device__ __forceinline__ void fp4_step(Fp4Acc& acc, const Fp4Feat (&fa)[2],
+                                         const Fp4Feat (&fb)[2]) {
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc.m[a][b] = mfma_fp4(fa[a].m, fb[b].m, acc.m[a][b]);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc.w[a][b] = mfma_fp4(fa[a].w, fb[b].w, acc.w[a][b]);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc.hc[a][b] = mfma_fp4(fa[a].h, fb[b].h, acc.hc[a][b]);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc.hc[a][b] = mfma_fp4(fa[a].c, fb[b].c, acc.hc[a][b]);
+}
+
+__device__ __forceinline__ void fp4_epilogue(const Fp4Acc& acc, const IbsOut& o, int64_t I,
+                                             int64_t J, int wr, int wc, int lane) {
+  const bool mirror = (I != J);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t i = I * kT + wr * 64 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        const int64_t j = J * kT + wc * 64 + b * 32 + (lane & 31);
+        const uint32_t n = (uint32_t)(int)acc.m[a][b][v];
+        const uint32_t z = (uint32_t)(int)acc.hc[a][b][v] >> 1;
+        const uint32_t one = (n - (uint32_t)(int)acc.w[a][b][v]) >> 1;
+        store_counts(o, i, j, mirror, n, z, one);
+      }
+}
+
+__device__ __forceinline__ void ibs_fp4_tile(const uint32_t* __restrict__ T, int64_t wp,
+                                             int64_t I, int64_t J, const IbsOut& o,
+                                             lds_t* smem) {
+  constexpr int kBuf = kT * kLdsStride;
+  lds_t* const sA = smem;
+  lds_t* const sB = smem + 2 * kBuf;
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int wid = t >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  const int g = lane >> 5;
+  const int rl = lane & 31;
+  const int lrow = t >> 2;
+  const int lq = (t & 3) * 4;
+  const uint32_t* pa = T + (I * kT + lrow) * wp + lq;
+  const uint32_t* pb = T + (J * kT + lrow) * wp + lq;
+  const int64_t half = 64 * wp;
+  uint4 ga0, ga1, gb0, gb1;
+  auto gload = [&](int64_t kc) {
+    ga0 = *reinterpret_cast<const uint4*>(pa + kc);
+    ga1 = *reinterpret_cast<const uint4*>(pa + half + kc);
+    gb0 = *reinterpret_cast<const uint4*>(pb + kc);
+    gb1 = *reinterpret_cast<const uint4*>(pb + half + kc);
+  };
+  auto lstore = [&](int buf) {
+    lds_st4(&(sA + buf * kBuf)[lrow * kLdsStride + lq], ga0);
+    lds_st4(&(sA + buf * kBuf)[(lrow + 64) * kLdsStride + lq], ga1);
+    lds_st4(&(sB + buf * kBuf)[lrow * kLdsStride + lq], gb0);
+    lds_st4(&(sB + buf * kBuf)[(lrow + 64) * kLdsStride + lq], gb1);
+  };
+  Fp4Acc acc;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      acc.m[a][b] = (v16f){0};
+      acc.w[a][b] = (v16f){0};
+      acc.hc[a][b] = (v16f){0};
+    }
+  const int64_t nchunks = wp / kKW;
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int64_t k = 0; k < nchunks; ++k) {
+    const int buf = (int)(k & 1);
+    if (k + 1 < nchunks) gload((k + 1) * kKW);
+    uint32_t wa[2][8], wb[2][8];
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      const lds_t* ra = &(sA + buf * kBuf)[(wr * 64 + x * 32 + rl) * kLdsStride + g * 8];
+      const lds_t* rb = &(sB + buf * kBuf)[(wc * 64 + x * 32 + rl) * kLdsStride + g * 8];
+      const uint4 a0 = lds_ld4(ra);
+      const uint4 a1 = lds_ld4(ra + 4);
+      const uint4 b0 = lds_ld4(rb);
+      const uint4 b1 = lds_ld4(rb + 4);
+      wa[x][0] = a0.x; wa[x][1] = a0.y; wa[x][2] = a0.z; wa[x][3] = a0.w;
+      wa[x][4] = a1.x; wa[x][5] = a1.y; wa[x][6] = a1.z; wa[x][7] = a1.w;
+      wb[x][0] = b0.x; wb[x][1] = b0.y; wb[x][2] = b0.z; wb[x][3] = b0.w;
+      wb[x][4] = b1.x; wb[x][5] = b1.y; wb[x][6] = b1.z; wb[x][7] = b1.w;
+    }
+    Fp4Feat fa[2], fb[2];
+    fa[0] = fp4_expand(wa[0][0], wa[0][1], false);
+    fa[1] = fp4_expand(wa[1][0], wa[1][1], false);
+    fb[0] = fp4_expand(wb[0][0], wb[0][1], true);
+    fb[1] = fp4_expand(wb[1][0], wb[1][1], true);
+#pragma unroll
+    for (int s = 0; s < kKW / 4; ++s) {
+      Fp4Feat na[2], nb[2];
+      if (s + 1 < kKW / 4) {
+        na[0] = fp4_expand(wa[0][2 * s + 2], wa[0][2 * s + 3], false);
+        na[1] = fp4_expand(wa[1][2 * s + 2], wa[1][2 * s + 3], false);
+        nb[0] = fp4_expand(wb[0][2 * s + 2], wb[0][2 * s + 3], true);
+        nb[1] = fp4_expand(wb[1][2 * s + 2], wb[1][2 * s + 3], true);
+      }
+      fp4_step(acc, fa, fb);
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x002, 8, 0);
+      }
+      if (s + 1 < kKW / 4) {
+        fa[0] = na[0]; fa[1] = na[1];
+        fb[0] = nb[0]; fb[1] = nb[1];
+      }
+    }
+    if (k + 1 < nchunks) lstore(buf ^ 1);
+    __syncthreads();
+  }
+  fp4_epilogue(acc, o, I, J, wr, wc, lane);
+}
+
+// ---- matrix-core path, fp4 operands from the replicated layout ----------------------
+// Same Grams and MFMA as above; the operand is the replicated layout (per 8
+// variants, HR = high code bits and LR = low code bits at nibble bits 1 and 3,
+// LR with ones at bits 0 and 2), so each feature word is ONE three-input bit
+// function of (HR, LR, K = bit 1 of every nibble):
+//   m = K & (hi | ~lo)                       +1 unless missing
+//   w = K & (hi | ~lo)  |  ~K & hi & ~lo     sign at bit 3 for heterozygotes
+//   h = K & ~(hi ^ lo)                       homozygotes
+//   c = K & ~(hi ^ lo)  |  ~K & ~hi & ~lo    sign for homozygous A1 (A side)
+//  -c = K & ~(hi ^ lo)  |  ~K & hi & lo      sign for homozygous A2 (B side)
+// Bits 0 and 2 of every nibble evaluate to 0 because LR is 1 there and HR 0.
+// A chunk is 256 variants = 64 words per row; one MFMA lane takes 4 groups
+// (32 variants) per step.
+constexpr int kRC = kIbsRepChunk;
+constexpr int kRStride = kRC + 4;
+
+// Truth tables of v_bitop3_b32 (result bit = table[S0*4 + S1*2 + S2]) with
+// S0 = HR, S1 = LR, S2 = K; derived from the expressions above.
+constexpr int kB3M = 0xa2, kB3W = 0xb2, kB3H = 0x82, kB3C = 0x83, kB3Cn = 0xc2;
+
+__device__ __forceinline__ void rep_features(const uint4& p0, const uint4& p1, bool b_side,
+                                             Fp4Feat& f) {
+  constexpr uint32_t K = 0x22222222u;
+  const uint32_t hr[4] = {p0.x, p0.z, p1.x, p1.z};
+  const uint32_t lr[4] = {p0.y, p0.w, p1.y, p1.w};
+  f.m = (v8i){0}; f.w = (v8i){0}; f.h = (v8i){0}; f.c = (v8i){0};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    f.m[q] = (int)__builtin_amdgcn_bitop3_b32(hr[q], lr[q], K, kB3M);
+    f.w[q] = (int)__builtin_amdgcn_bitop3_b32(hr[q], lr[q], K, kB3W);
+    f.h[q] = (int)__builtin_amdgcn_bitop3_b32(hr[q], lr[q], K, kB3H);
+    f.c[q] = (int)(b_side ? __builtin_amdgcn_bitop3_b32(hr[q], lr[q], K, kB3Cn)
+                          : __builtin_amdgcn_bitop3_b32(hr[q], lr[q], K, kB3C));
+  }
+}
+
+__device__ __forceinline__ void ibs_fp4rep_tile(const uint32_t* __restrict__ R, int64_t rp,
+                                                int64_t I, int64_t J, const IbsOut& o,
+                                                lds_t* smem) {
+  constexpr int kBuf = kT * kRStride;
+  lds_t* const sA = smem;
+  lds_t* const sB = smem + 2 * kBuf;
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int wid = t >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  const int g = lane >> 5;
+  const int rl = lane & 31;
+  // global -> LDS: 128 rows x 16 uint4 per operand; thread t takes uint4 (t + 256k)
+  const uint32_t* baseA = R + I * kT * rp;
+  const uint32_t* baseB = R + J * kT * rp;
+  uint4 ga[8], gb[8];
+  auto gload = [&](int64_t kc) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int e = t + 256 * k;
+      const int64_t off = (int64_t)(e >> 4) * rp + kc + (e & 15) * 4;
+      ga[k] = *reinterpret_cast<const uint4*>(baseA + off);
+      gb[k] = *reinterpret_cast<const uint4*>(baseB + off);
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int e = t + 256 * k;
+      const int off = (e >> 4) * kRStride + (e & 15) * 4;
+      lds_st4(&(sA + buf * kBuf)[off], ga[k]);
+      lds_st4(&(sB + buf * kBuf)[off], gb[k]);
+    }
+  };
+  Fp4Acc acc;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      acc.m[a][b] = (v16f){0};
+      acc.w[a][b] = (v16f){0};
+      acc.hc[a][b] = (v16f){0};
+    }
+  const int64_t nchunks = rp / kRC;
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int64_t k = 0; k < nchunks; ++k) {
+    const int buf = (int)(k & 1);
+    if (k + 1 < nchunks) gload((k + 1) * kRC);
+#pragma unroll
+    for (int s = 0; s < kRC / 16; ++s) {
+      Fp4Feat fa[2], fb[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        const lds_t* ra = &(sA + buf * kBuf)[(wr * 64 + x * 32 + rl) * kRStride + g * 32 + s * 8];
+        const lds_t* rb = &(sB + buf * kBuf)[(wc * 64 + x * 32 + rl) * kRStride + g * 32 + s * 8];
+        rep_features(lds_ld4(ra), lds_ld4(ra + 4),
+                     false, fa[x]);
+        rep_features(lds_ld4(rb), lds_ld4(rb + 4),
+                     true, fb[x]);
+      }
+      fp4_step(acc, fa, fb);
+    }
+    if (k + 1 < nchunks) lstore(buf ^ 1);
+    __syncthreads();
+  }
+  fp4_epilogue(acc, o, I, J, wr, wc, lane);
+}
 
 // ---- LD ---------------------------------------------------------------------
 typedef int v4i __attribute__((ext_vector_type(4)));
@@ -397,9 +745,9 @@ constexpr int kLPW = kLdPopcKWords;
 __device__ __forceinline__ void ld_popc_tile(const uint32_t* __restrict__ P, int64_t words_pad,
                                              int64_t nv, int64_t rows_pad, int64_t I, int64_t J,
                                              int32_t window, double r2_min, const LdScratch& sc,
-                                             uint32_t* smem) {
-  uint32_t* sA = smem;
-  uint32_t* sB = smem + kLPW * 3 * kLP;
+                                             lds_t* smem) {
+  lds_t* const sA = smem;
+  lds_t* const sB = smem + kLPW * 3 * kLP;
   const int t = threadIdx.x;
   const int tx = t & 15, ty = t >> 4;
   uint32_t al[4][4], be[4][4], ga[4][4], de[4][4], cn[4][4], sp[4][4], sm[4][4];
@@ -414,18 +762,18 @@ __device__ __forceinline__ void ld_popc_tile(const uint32_t* __restrict__ P, int
       const int64_t gw = (kc * 3 + row) * rows_pad;
       const uint4 a = *reinterpret_cast<const uint4*>(P + gw + I * kLP + col);
       const uint4 b = *reinterpret_cast<const uint4*>(P + gw + J * kLP + col);
-      *reinterpret_cast<uint4*>(&sA[row * kLP + col]) = a;
-      *reinterpret_cast<uint4*>(&sB[row * kLP + col]) = b;
+      lds_st4(&sA[row * kLP + col], a);
+      lds_st4(&sB[row * kLP + col], b);
     }
     __syncthreads();
 #pragma unroll 2
     for (int w = 0; w < kLPW; ++w) {
-      const uint4 ap = *reinterpret_cast<const uint4*>(&sA[(w * 3 + 0) * kLP + ty * 4]);
-      const uint4 aq = *reinterpret_cast<const uint4*>(&sA[(w * 3 + 1) * kLP + ty * 4]);
-      const uint4 am = *reinterpret_cast<const uint4*>(&sA[(w * 3 + 2) * kLP + ty * 4]);
-      const uint4 bp = *reinterpret_cast<const uint4*>(&sB[(w * 3 + 0) * kLP + tx * 4]);
-      const uint4 bq = *reinterpret_cast<const uint4*>(&sB[(w * 3 + 1) * kLP + tx * 4]);
-      const uint4 bm = *reinterpret_cast<const uint4*>(&sB[(w * 3 + 2) * kLP + tx * 4]);
+      const uint4 ap = lds_ld4(&sA[(w * 3 + 0) * kLP + ty * 4]);
+      const uint4 aq = lds_ld4(&sA[(w * 3 + 1) * kLP + ty * 4]);
+      const uint4 am = lds_ld4(&sA[(w * 3 + 2) * kLP + ty * 4]);
+      const uint4 bp = lds_ld4(&sB[(w * 3 + 0) * kLP + tx * 4]);
+      const uint4 bq = lds_ld4(&sB[(w * 3 + 1) * kLP + tx * 4]);
+      const uint4 bm = lds_ld4(&sB[(w * 3 + 2) * kLP + tx * 4]);
       const uint32_t AP[4] = {ap.x, ap.y, ap.z, ap.w}, AQ[4] = {aq.x, aq.y, aq.z, aq.w},
                      AM[4] = {am.x, am.y, am.z, am.w};
       const uint32_t BP[4] = {bp.x, bp.y, bp.z, bp.w}, BQ[4] = {bq.x, bq.y, bq.z, bq.w},
@@ -478,9 +826,10 @@ __device__ __forceinline__ Feat3 ld_expand(uint32_t word) {
 
 __device__ __forceinline__ void ld_mfma_tile(const uint32_t* __restrict__ D, int64_t wn,
                                              int64_t nv, int64_t I, int64_t J, int32_t window,
-                                             double r2_min, const LdScratch& sc, uint32_t* smem) {
-  uint32_t* sA[2] = {smem, smem + kL * kLStride};
-  uint32_t* sB[2] = {smem + 2 * kL * kLStride, smem + 3 * kL * kLStride};
+                                             double r2_min, const LdScratch& sc, lds_t* smem) {
+  constexpr int kBuf = kL * kLStride;
+  lds_t* const sA = smem;
+  lds_t* const sB = smem + 2 * kBuf;
   const int t = threadIdx.x;
   const int lane = t & 63;
   const int wid = t >> 6;
@@ -501,8 +850,8 @@ __device__ __forceinline__ void ld_mfma_tile(const uint32_t* __restrict__ D, int
     gb = *reinterpret_cast<const uint4*>(pb + kc);
   };
   auto lstore = [&](int buf) {
-    *reinterpret_cast<uint4*>(&sA[buf][lrow * kLStride + lq]) = ga;
-    *reinterpret_cast<uint4*>(&sB[buf][lrow * kLStride + lq]) = gb;
+    lds_st4(&(sA + buf * kBuf)[lrow * kLStride + lq], ga);
+    lds_st4(&(sB + buf * kBuf)[lrow * kLStride + lq], gb);
   };
 
   v16i s_n = (v16i){0}, s_x = (v16i){0}, s_y = (v16i){0};
@@ -515,12 +864,12 @@ __device__ __forceinline__ void ld_mfma_tile(const uint32_t* __restrict__ D, int
     const int buf = (int)(k & 1);
     if (k + 1 < nchunks) gload((k + 1) * kLW);
     if (active) {
-      const uint32_t* ra = &sA[buf][(wr * 32 + rl) * kLStride + g * 8];
-      const uint32_t* rb = &sB[buf][(wc * 32 + rl) * kLStride + g * 8];
-      const uint4 a0 = *reinterpret_cast<const uint4*>(ra);
-      const uint4 a1 = *reinterpret_cast<const uint4*>(ra + 4);
-      const uint4 b0 = *reinterpret_cast<const uint4*>(rb);
-      const uint4 b1 = *reinterpret_cast<const uint4*>(rb + 4);
+      const lds_t* ra = &(sA + buf * kBuf)[(wr * 32 + rl) * kLStride + g * 8];
+      const lds_t* rb = &(sB + buf * kBuf)[(wc * 32 + rl) * kLStride + g * 8];
+      const uint4 a0 = lds_ld4(ra);
+      const uint4 a1 = lds_ld4(ra + 4);
+      const uint4 b0 = lds_ld4(rb);
+      const uint4 b1 = lds_ld4(rb + 4);
       const uint32_t wa[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
       const uint32_t wb[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
       Feat3 fa = ld_expand(wa[0]), fb = ld_expand(wb[0]);
@@ -565,6 +914,7 @@ constexpr int kIbsMfmaSimpleSmem = 2 * kT * kLdsStride;
 constexpr int kIbsPopcSmem = 2 * kPW * 3 * kP;
 constexpr int kLdPopcSmem = 2 * kLPW * 3 * kLP;
 constexpr int kLdMfmaSmem = 4 * kL * kLStride;
+constexpr int kIbsRepSmem = 4 * kT * kRStride;
 constexpr int kMaxTileSmem = kIbsMfmaSmem;
 static_assert(kIbsMfmaSimpleSmem <= kMaxTileSmem && kIbsPopcSmem <= kMaxTileSmem &&
               kLdPopcSmem <= kMaxTileSmem && kLdMfmaSmem <= kMaxTileSmem, "LDS budget");

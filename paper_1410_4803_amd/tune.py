@@ -18,8 +18,11 @@ import torch
 from . import _native as N
 from . import api
 
-IBS_CANDIDATES = {"mfma": N.PG_PATH_MFMA, "mfma_v1": N.PG_PATH_MFMA | (1 << 8),
-                  "popc": N.PG_PATH_POPC}
+IBS_CANDIDATES = {"mfma": N.PG_PATH_MFMA, "mfma_fp4": N.PG_PATH_MFMA | (3 << 8),
+                  "mfma_fp4rep": N.PG_PATH_MFMA | (4 << 8), "popc": N.PG_PATH_POPC}
+# inside a batch every matrix-core problem runs the default body, so only the
+# path is worth choosing there
+IBS_BATCH_CANDIDATES = {"mfma": N.PG_PATH_MFMA, "popc": N.PG_PATH_POPC}
 LD_CANDIDATES = {"mfma": N.PG_PATH_MFMA, "popc": N.PG_PATH_POPC}
 
 
@@ -80,19 +83,20 @@ class Tuner:
 
     def tune(self, kind: str, cohort: api.Cohort, *, sample_idx=None, v_range=None,
              layout: str = "tri", window: int | None = None, r2_min: float = 0.2,
-             reps: int = 2, force: bool = False) -> int:
+             reps: int = 2, force: bool = False, for_batch: bool = False) -> int:
         """Measures every candidate on this problem (outputs discarded) unless
         its shape bucket is already decided; returns the chosen path code."""
         m = sample_idx.numel() if sample_idx is not None else cohort.n_samples
         nv = (v_range[1] - v_range[0]) if v_range else cohort.n_variants
-        key = shape_key(kind, m, nv, window)
+        key = shape_key(kind, m, nv, window) + (":batch" if for_batch else "")
         if not force and key in self.cache:
             return int(self.cache[key]["path"])
         times = {}
         if kind == "ibs":
             out = tuple(torch.empty(api.ibs_output_size(m, layout), dtype=torch.int32,
                                     device=cohort.bed.device) for _ in range(4))
-            for name, code in IBS_CANDIDATES.items():
+            cands = IBS_BATCH_CANDIDATES if for_batch else IBS_CANDIDATES
+            for name, code in cands.items():
                 ws = torch.empty(max(api.ibs_workspace_bytes(cohort, sample_idx.numel()
                                                              if sample_idx is not None else 0,
                                                              v_range, code), 1),
@@ -101,7 +105,6 @@ class Tuner:
                     cohort, sample_idx=sample_idx, v_range=v_range, layout=layout, path=code,
                     out=out, workspace=ws), reps)
                 del ws
-            cands = IBS_CANDIDATES
         else:
             cap = max(1024, 4 * nv)
             o = torch.empty((cap, 64), dtype=torch.uint8, device=cohort.bed.device)

@@ -37,6 +37,8 @@ def _problems(seed=0):
                      v_range=(10, 2000),
                      path="mfma"),
         pg.IbsProblem(c[6], layout="tri", path="auto"),
+        pg.IbsProblem(c[2], layout="full", path=2 | (4 << 8)),
+        pg.IbsProblem(c[0], sample_idx=idx[:90], layout="tri", path=2 | (3 << 8)),
     ]
     return specs, probs, idx
 
@@ -129,7 +131,7 @@ def test_batch_generated_workload_subset():
         bed = synth.hwe(n, V, (0.01, 0.5), 0.01, seed=d["seed"])
         c = pg.Cohort.from_numpy(bed, n)
         if d["kind"] == "ibs":
-            path = tuner.tune("ibs", c, layout="tri", reps=1)
+            path = tuner.tune("ibs", c, layout="tri", reps=1, for_batch=True)
             probs.append(pg.IbsProblem(c, layout="tri", path=path))
         else:
             path = tuner.tune("ld", c, window=d["window"], r2_min=d["r2_min"], reps=1)

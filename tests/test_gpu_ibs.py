@@ -16,7 +16,10 @@ pytestmark = pytest.mark.gpu
 
 pg = pytest.importorskip("paper_1410_4803_amd")
 
-PATHS = ["popc", "mfma"]
+PATHS = ["popc", "mfma", "fp4", "fp4rep"]
+# path codes: "fp4" / "fp4rep" are matrix-core variants 3 and 4 (fp4 operands,
+# from the 2-bit and from the replicated layout)
+CODES = {"popc": 1, "mfma": 2, "fp4": 2 | (3 << 8), "fp4rep": 2 | (4 << 8)}
 
 
 def _cohort(bed, n, mask=None):
@@ -40,8 +43,8 @@ def test_ibs_shapes_full_and_tri(path, n, V):
     ref_full = oracle.ibs_matrix(codes, full=True)
     ref_tri = oracle.ibs_matrix(codes, full=False)
     c = _cohort(bed, n)
-    _check_full(pg.ibs_matrix(c, layout="full", path=path), ref_full)
-    got = pg.ibs_matrix(c, layout="tri", path=path)
+    _check_full(pg.ibs_matrix(c, layout="full", path=CODES[path]), ref_full)
+    got = pg.ibs_matrix(c, layout="tri", path=CODES[path])
     _check_full(got, ref_tri)
 
 
@@ -58,11 +61,11 @@ def test_ibs_mask_selection_range(path):
     ref = oracle.ibs_matrix(codes, full=True)
     c = _cohort(bed, n, mask)
     got = pg.ibs_matrix(c, sample_idx=torch.from_numpy(idx).cuda(), v_range=(vb, ve),
-                        layout="full", path=path)
+                        layout="full", path=CODES[path])
     _check_full(got, ref)
     ref_t = oracle.ibs_matrix(codes, full=False)
     got_t = pg.ibs_matrix(c, sample_idx=torch.from_numpy(idx).cuda(), v_range=(vb, ve),
-                          layout="tri", path=path)
+                          layout="tri", path=CODES[path])
     _check_full(got_t, ref_t)
 
 
@@ -79,10 +82,10 @@ def test_ibs_degenerate(path):
     for k in range(n):
         packed[:, k // 4] |= (codes[:, k].astype(np.uint8) << (2 * (k % 4)))
     ref = oracle.ibs_matrix(codes, full=True)
-    _check_full(pg.ibs_matrix(_cohort(packed, n), layout="full", path=path), ref)
+    _check_full(pg.ibs_matrix(_cohort(packed, n), layout="full", path=CODES[path]), ref)
     # a sample list with an out-of-range entry reads as all missing
     idx = np.array([0, 5, n + 7, 2], dtype=np.int32)
-    got = pg.ibs_matrix(_cohort(packed, n), sample_idx=torch.from_numpy(idx).cuda(), path=path)
+    got = pg.ibs_matrix(_cohort(packed, n), sample_idx=torch.from_numpy(idx).cuda(), path=CODES[path])
     assert (got[3].cpu().numpy()[2] == 0).all() and (got[3].cpu().numpy()[:, 2] == 0).all()
 
 
@@ -92,8 +95,10 @@ def test_ibs_paths_agree_and_deterministic():
     a = pg.ibs_matrix(c, layout="tri", path="popc")
     b = pg.ibs_matrix(c, layout="tri", path="mfma")
     b2 = pg.ibs_matrix(c, layout="tri", path="mfma")
-    for x, y, z in zip(a, b, b2):
-        assert torch.equal(x, y) and torch.equal(y, z)
+    f4 = pg.ibs_matrix(c, layout="tri", path=CODES["fp4"])
+    f4r = pg.ibs_matrix(c, layout="tri", path=CODES["fp4rep"])
+    for x, y, z, u, r in zip(a, b, b2, f4, f4r):
+        assert torch.equal(x, y) and torch.equal(y, z) and torch.equal(z, u) and torch.equal(u, r)
 
 
 @pytest.mark.parametrize("path", PATHS)
@@ -102,7 +107,7 @@ def test_ibs_small_workload_exact(path):
     w = synth.ibs_small()
     codes = oracle.unpack(w["bed"], w["n"], w["V"])
     ref = oracle.ibs_matrix(codes, full=False)
-    got = pg.ibs_matrix(_cohort(w["bed"], w["n"]), layout="tri", path=path)
+    got = pg.ibs_matrix(_cohort(w["bed"], w["n"]), layout="tri", path=CODES[path])
     assert got[0].numel() == 124750
     _check_full(got, ref)
 
@@ -121,7 +126,7 @@ def test_ibs_large_workload_sampled(large, path):
     corners) against the oracle, and whole-matrix properties."""
     w, c = large
     n, V = w["n"], w["V"]
-    out = pg.ibs_matrix(c, layout="full", path=path)
+    out = pg.ibs_matrix(c, layout="full", path=CODES[path])
     torch.cuda.synchronize()
     rng = np.random.default_rng(99)
     pi = rng.integers(0, n, 3000)
@@ -158,7 +163,7 @@ def test_ibs_mask_and_row_stride(path, n, extra):
         bed = np.concatenate([bed, junk], axis=1)
     codes = oracle.unpack(bed, n, V, mask)
     ref = oracle.ibs_matrix(codes, full=True)
-    got = pg.ibs_matrix(_cohort(bed, n, mask), layout="full", path=path)
+    got = pg.ibs_matrix(_cohort(bed, n, mask), layout="full", path=CODES[path])
     _check_full(got, ref)
     for variant in (1, 2):
         if path == "mfma":
