@@ -120,6 +120,60 @@ __device__ __forceinline__ void store_counts(const IbsOut& o, int64_t i, int64_t
   }
 }
 
+// Stores the counts of one 32x32 accumulator block (register v of lane l is
+// row 8*(v/4) + 4*(l/32) + v%4, column l%32).  The direct entries (i, j) go
+// out as 4-byte stores that are contiguous across lanes; the mirrored entries
+// (j, i) of an off-diagonal tile go out as one 16-byte store per four
+// consecutive i, so each row receives whole 32-byte pieces (scalar stores at
+// the matrix edge or when rows are not 16-byte aligned).
+__device__ __forceinline__ void store_block(const IbsOut& o, int64_t i_base, int64_t j,
+                                            bool mirror, int lane, const uint32_t (&n)[16],
+                                            const uint32_t (&z)[16], const uint32_t (&one)[16]) {
+  const int64_t ib = i_base + 4 * (lane >> 5);
+  if (!o.full) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v)
+      store_counts(o, ib + 8 * (v >> 2) + (v & 3), j, false, n[v], z[v], one[v]);
+    return;
+  }
+#pragma unroll
+  for (int v = 0; v < 16; ++v)
+    store_counts(o, ib + 8 * (v >> 2) + (v & 3), j, false, n[v], z[v], one[v]);
+  if (!mirror || j >= o.m) return;
+  const bool vec_ok = (o.m & 3) == 0 &&
+                      ((reinterpret_cast<uintptr_t>(o.ibs0) | reinterpret_cast<uintptr_t>(o.ibs1) |
+                        reinterpret_cast<uintptr_t>(o.ibs2) | reinterpret_cast<uintptr_t>(o.nonmiss)) &
+                       15) == 0;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const int64_t i0 = ib + 8 * g;
+    if (vec_ok && i0 + 3 < o.m) {
+      const int64_t a = j * o.m + i0;
+      uint4 t0, t1, t2, t3;
+      t0 = make_uint4(z[4 * g], z[4 * g + 1], z[4 * g + 2], z[4 * g + 3]);
+      t1 = make_uint4(one[4 * g], one[4 * g + 1], one[4 * g + 2], one[4 * g + 3]);
+      t2 = make_uint4(n[4 * g] - z[4 * g] - one[4 * g], n[4 * g + 1] - z[4 * g + 1] - one[4 * g + 1],
+                      n[4 * g + 2] - z[4 * g + 2] - one[4 * g + 2],
+                      n[4 * g + 3] - z[4 * g + 3] - one[4 * g + 3]);
+      t3 = make_uint4(n[4 * g], n[4 * g + 1], n[4 * g + 2], n[4 * g + 3]);
+      *reinterpret_cast<uint4*>(o.ibs0 + a) = t0;
+      *reinterpret_cast<uint4*>(o.ibs1 + a) = t1;
+      *reinterpret_cast<uint4*>(o.ibs2 + a) = t2;
+      *reinterpret_cast<uint4*>(o.nonmiss + a) = t3;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t i = i0 + e;
+        if (i < o.m) {
+          const int64_t a = j * o.m + i;
+          const int v = 4 * g + e;
+          o.ibs0[a] = z[v]; o.ibs1[a] = one[v]; o.ibs2[a] = n[v] - z[v] - one[v]; o.nonmiss[a] = n[v];
+        }
+      }
+    }
+  }
+}
+
 // ---- matrix-core path ---------------------------------------------------------
 // Block: 256 threads = 4 waves in a 2x2 grid over a 128x128 tile; each wave
 // owns 64x64 = 2x2 blocks of v_mfma_i32_32x32x32_i8 and three accumulator sets
@@ -188,16 +242,17 @@ __device__ __forceinline__ void ibs_epilogue(const IbsAcc& acc, const IbsOut& o,
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < 2; ++b) {
+      uint32_t n[16], z[16], one[16];
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const int64_t i = I * kT + wr * 64 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-        const int64_t j = J * kT + wc * 64 + b * 32 + (lane & 31);
-        const uint32_t n = (uint32_t)acc.m[a][b][v];
-        const uint32_t z = (uint32_t)acc.hc[a][b][v] >> 1;
-        const uint32_t one = (n - (uint32_t)acc.w[a][b][v]) >> 1;
-        store_counts(o, i, j, mirror, n, z, one);
+        n[v] = (uint32_t)acc.m[a][b][v];
+        z[v] = (uint32_t)acc.hc[a][b][v] >> 1;
+        one[v] = (n[v] - (uint32_t)acc.w[a][b][v]) >> 1;
       }
+      store_block(o, I * kT + wr * 64 + a * 32, J * kT + wc * 64 + b * 32 + (lane & 31), mirror,
+                  lane, n, z, one);
+    }
 }
 
 __device__ __forceinline__ void zero_acc(IbsAcc& acc) {
@@ -484,16 +539,17 @@ __device__ __forceinline__ void fp4_epilogue(const Fp4Acc& acc, const IbsOut& o,
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < 2; ++b) {
+      uint32_t n[16], z[16], one[16];
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const int64_t i = I * kT + wr * 64 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-        const int64_t j = J * kT + wc * 64 + b * 32 + (lane & 31);
-        const uint32_t n = (uint32_t)(int)acc.m[a][b][v];
-        const uint32_t z = (uint32_t)(int)acc.hc[a][b][v] >> 1;
-        const uint32_t one = (n - (uint32_t)(int)acc.w[a][b][v]) >> 1;
-        store_counts(o, i, j, mirror, n, z, one);
+        n[v] = (uint32_t)(int)acc.m[a][b][v];
+        z[v] = (uint32_t)(int)acc.hc[a][b][v] >> 1;
+        one[v] = (n[v] - (uint32_t)(int)acc.w[a][b][v]) >> 1;
       }
+      store_block(o, I * kT + wr * 64 + a * 32, J * kT + wc * 64 + b * 32 + (lane & 31), mirror,
+                  lane, n, z, one);
+    }
 }
 
 __device__ __forceinline__ void ibs_fp4_tile(const uint32_t* __restrict__ T, int64_t wp,
