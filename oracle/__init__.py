@@ -3,7 +3,9 @@
 The plain definitions of the IBS and LD statistics of Chang et al. 2015
 (arXiv 1410.4803), section "Bitwise parallelism" (the per-marker IBS loop)
 and section "Bit population count" (r between two markers with missing
-data), written over unpacked genotype codes in ``oracle.c``.
+data), and the greedy LD pruning of section "Linkage disequilibrium-based
+variant pruning" (under the reading stated in ``oracle.c``), written over
+unpacked genotype codes in ``oracle.c``.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's CPU-baseline
 leg may import this package.  It shares no code with the GPU library
@@ -61,6 +63,10 @@ def _load():
         lib.oracle_ld_pairs.restype = None
         lib.oracle_ld_window.argtypes = [p, i64, i64, i64, i64, i64, dbl, p, i64]
         lib.oracle_ld_window.restype = i64
+        lib.oracle_r2_counts.argtypes = [p]
+        lib.oracle_r2_counts.restype = dbl
+        lib.oracle_ld_prune.argtypes = [p, i64, i64, i64, i64, dbl, p]
+        lib.oracle_ld_prune.restype = i64
         lib.oracle_threads.argtypes = []
         lib.oracle_threads.restype = i32
         _lib = lib
@@ -162,3 +168,22 @@ def ld_window(codes_vm: np.ndarray, window: int, r2_min: float, a_begin: int = 0
     if total < 0:
         raise MemoryError("oracle_ld_window")
     return out[:min(total, capacity)]
+
+
+def r2_counts(s) -> float:
+    """r^2 as the pruning decision takes it: exact integer cov, vx, vy, then
+    (cov*cov)/(vx*vy) in IEEE double, clamped to 1 (NaN when undefined)."""
+    s = _c(s, np.int64)
+    return float(_load().oracle_r2_counts(s.ctypes.data))
+
+
+def ld_prune(codes_vm: np.ndarray, window: int, step: int, r2_max: float) -> np.ndarray:
+    """Greedy --indep-pairwise pruning; uint8 keep flag per variant."""
+    V, n = codes_vm.shape
+    codes_vm = _c(codes_vm, np.int8)
+    keep = np.zeros(V, dtype=np.uint8)
+    kept = _load().oracle_ld_prune(codes_vm.ctypes.data, n, V, int(window), int(step),
+                                   float(r2_max), keep.ctypes.data)
+    if kept < 0:
+        raise MemoryError("oracle_ld_prune")
+    return keep

@@ -235,3 +235,102 @@ int oracle_threads(void) {
   return 1;
 #endif
 }
+
+/*
+ * r^2 of the library's emission test, used where a floating-point value
+ * decides an integer result (LD pruning): from the exact integer
+ *   cov = n*Sxy - Sx*Sy,  vx = n*Sxx - Sx^2,  vy = n*Syy - Sy^2
+ * (the paper's r with missing data, multiplied through by n^2), evaluated as
+ * (cov*cov) / (vx*vy) with IEEE double operations, clamped to 1; NaN when
+ * n, vx or vy is 0.  Both sides take the pruning decision on this double.
+ */
+double oracle_r2_counts(const int64_t s[6]) {
+  const int64_t n = s[0];
+  const int64_t cov = n * s[5] - s[1] * s[2];
+  const int64_t vx = n * s[3] - s[1] * s[1];
+  const int64_t vy = n * s[4] - s[2] * s[2];
+  if (n == 0 || vx == 0 || vy == 0) return NAN;
+  const double num = (double)cov * (double)cov;
+  const double den = (double)vx * (double)vy;
+  const double r2 = num / den;
+  return r2 > 1.0 ? 1.0 : r2;
+}
+
+/*
+ * Minor allele frequency of one variant over its non-missing calls
+ * (dosage counts A2 alleles): min(A2, 2n - A2) / 2n, and 0 with no
+ * non-missing call.
+ */
+static double variant_maf(const int8_t* x, int64_t n) {
+  int64_t calls = 0, a2 = 0;
+  for (int64_t k = 0; k < n; ++k) {
+    if (x[k] == MISSING) continue;
+    calls += 1;
+    a2 += dosage(x[k]);
+  }
+  if (calls == 0) return 0.0;
+  const int64_t minor = a2 < 2 * calls - a2 ? a2 : 2 * calls - a2;
+  return (double)minor / (double)(2 * calls);
+}
+
+/*
+ * LD-based pruning, the --indep-pairwise operation the paper times (section
+ * "Linkage disequilibrium-based variant pruning", Table 4), which it names but
+ * does not spell out.  The reading implemented here:
+ *  - windows of `window` consecutive variants start at 0, step, 2*step, ...;
+ *    the last one is the first that reaches the end;
+ *  - in each window, pairs a < b of variants that are still kept are visited
+ *    in increasing a, then increasing b; when r^2 > r2_max (the double of
+ *    oracle_r2_counts; an undefined r^2 never triggers) the variant with the
+ *    lower minor allele frequency is dropped, the later one (b) on a tie;
+ *  - a dropped variant stays dropped.
+ * keep[v] = 1 for the variants that remain; returns their number.
+ * r^2 of every pair closer than `window` is computed first (in parallel);
+ * the greedy pass itself is the sequential loop above.
+ */
+int64_t oracle_ld_prune(const int8_t* codes_vm, int64_t n, int64_t V, int64_t window,
+                        int64_t step, double r2_max, uint8_t* keep) {
+  const int64_t span = window - 1;  /* largest b - a inside one window */
+  double* r2 = (double*)malloc((size_t)(V * (span > 0 ? span : 1)) * sizeof(double));
+  double* maf = (double*)malloc((size_t)V * sizeof(double));
+  if (!r2 || !maf) {
+    free(r2);
+    free(maf);
+    return -1;
+  }
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t a = 0; a < V; ++a) {
+    maf[a] = variant_maf(codes_vm + a * n, n);
+    for (int64_t d = 1; d <= span; ++d) {
+      double v = NAN;
+      if (a + d < V) {
+        int64_t s[6];
+        ld_sums(codes_vm + a * n, codes_vm + (a + d) * n, n, s);
+        v = oracle_r2_counts(s);
+      }
+      r2[a * span + d - 1] = v;
+    }
+  }
+  for (int64_t v = 0; v < V; ++v) keep[v] = 1;
+  for (int64_t start = 0; start < V; start += step) {
+    const int64_t end = start + window < V ? start + window : V;
+    for (int64_t a = start; a < end; ++a) {
+      if (!keep[a]) continue;
+      for (int64_t b = a + 1; b < end; ++b) {
+        if (!keep[b]) continue;
+        if (!(r2[a * span + (b - a) - 1] > r2_max)) continue;
+        if (maf[a] < maf[b]) {
+          keep[a] = 0;
+          break;
+        }
+        keep[b] = 0;
+      }
+    }
+    if (end == V) break;
+  }
+  int64_t kept = 0;
+  for (int64_t v = 0; v < V; ++v) kept += keep[v];
+  free(r2);
+  free(maf);
+  return kept;
+}

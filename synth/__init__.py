@@ -8,7 +8,7 @@ Code table (one 2-bit code per call, low bits first, four calls per byte,
 variant-major rows, no file header): 0 homozygous A1, 1 missing,
 2 heterozygous, 3 homozygous A2.
 
-The five workloads below stand in for the paper's datasets (HAPGEN2 /
+The workloads below stand in for the paper's datasets (HAPGEN2 /
 simuRare / 1000 Genomes panels, which are not available): they take the
 shapes and the value distributions the workloads are specified with.
 """
@@ -94,7 +94,7 @@ def missing_mask(n: int, V: int, rate: float, seed: int) -> np.ndarray:
     return out
 
 
-# --- the five workloads -----------------------------------------------------
+# --- workloads ---------------------------------------------------------------
 
 def ibs_small(seed: int = 1000) -> dict:
     """IBS matrix, 500 samples x 5,000 variants, HWE, MAF~U[0.05,0.5], 1% missing.
@@ -119,6 +119,27 @@ def ld_large(seed: int = 1002) -> dict:
     n, V = 5000, 500000
     return dict(name="ld_5000x500000_mosaic_w1000", n=n, V=V, window=1000, r2_min=0.2,
                 bed=mosaic(n, V, 20, 0.005, 0.001, 0.01, 0.01, seed))
+
+
+def prune_small(seed: int = 1005) -> dict:
+    """LD pruning, 1,000 samples x 100,000 variants, founder mosaic (10
+    founders, switch 0.01, mutation 0.001, MAF>=0.01), no missing calls;
+    --indep-pairwise 50 5 0.5.  The founder count is chosen so that about
+    three quarters of the variants survive, as in the paper's pruned
+    1,000-sample panel."""
+    n, V = 1000, 100000
+    return dict(name="prune_1000x100000_mosaic_50_5_0.5", n=n, V=V, window=50, step=5,
+                r2_max=0.5, bed=mosaic(n, V, 10, 0.01, 0.001, 0.01, 0.0, seed))
+
+
+def prune_large(seed: int = 1006) -> dict:
+    """LD pruning, 10,000 samples x 88,025 variants, founder mosaic (8
+    founders, switch 0.01, mutation 0.001, MAF>=0.01), no missing calls;
+    --indep-pairwise 700 70 0.7.  About four fifths of the variants survive,
+    as in the paper's pruned 10,000-sample panel."""
+    n, V = 10000, 88025
+    return dict(name="prune_10000x88025_mosaic_700_70_0.7", n=n, V=V, window=700, step=70,
+                r2_max=0.7, bed=mosaic(n, V, 8, 0.01, 0.001, 0.01, 0.0, seed))
 
 
 def batch_problems(seed: int = 1003, count: int = 64, make_bed: bool = True) -> list:
