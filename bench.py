@@ -153,6 +153,46 @@ def cpu_baseline_ibs(bed, n, V, budget_s: float):
                       f"triangle ({comps:.3e} comparisons, {t:.1f} s)"}
 
 
+def bench_prune(torch, lib, hip, pg, wp, dev, steps):
+    """Greedy LD pruning (--indep-pairwise window step r2): whole-call time
+    and its stages; comparisons = in-window variant pairs x samples of the
+    pair kernel (largest distance window - 1)."""
+    n, V, W, S, t = wp["n"], wp["V"], wp["window"], wp["step"], wp["r2_max"]
+    c = pg.Cohort.from_numpy(wp["bed"], n, device=dev)
+    keep = torch.empty(V, dtype=torch.uint8, device=dev)
+    n_kept = torch.empty(1, dtype=torch.int64, device=dev)
+    ws = torch.empty(pg.prune_workspace_bytes(c, W, path="mfma"), dtype=torch.uint8, device=dev)
+    ms, st = timed_steps(torch, lib, hip, lambda: pg.ld_prune(
+        c, W, S, t, path="mfma", keep=keep, n_kept=n_kept, workspace=ws), steps, 2, 5)
+    pairs = sum(min(W - 1, V - 1 - a) for a in range(V))
+    comps = pairs * n
+    band_ms = mean(st[1])
+    ach = comps * LD_MFMA_OPS / (band_ms * 1e-3) / 1e12
+    kept = int(n_kept.item())
+    assert kept == int(keep.sum().item())
+    return {"workload": wp["name"], "path": "mfma", "ms_per_call": round(ms, 3),
+            "value": round(comps / (ms * 1e-3) / 1e9, 1), "unit": "G/s",
+            "kept": kept, "variants": V,
+            "stages_ms": {"layout": round(mean(st[0]), 3), "band_kernel": round(band_ms, 3),
+                          "allele_counts": round(mean(st[2]), 3),
+                          "greedy": round(mean(st[3]), 3)},
+            "roofline": {"bound": "mfma", "kernel": "k_ld_mfma", "unit": "TOP/s",
+                         "achieved": round(ach, 2), "peak": PEAK_INT8_TOPS,
+                         "frac": round(ach / PEAK_INT8_TOPS, 4)}}
+
+
+def cpu_baseline_prune(wp):
+    """The oracle's pruning on the whole workload (OpenMP r^2 table, then its
+    sequential greedy pass)."""
+    import oracle
+    codes = oracle.unpack(wp["bed"], wp["n"], wp["V"])
+    t0 = time.perf_counter()
+    keep = oracle.ld_prune(codes, wp["window"], wp["step"], wp["r2_max"])
+    dt = time.perf_counter() - t0
+    return {"value": round(dt * 1e3, 1), "unit": "ms", "cores": oracle.threads(),
+            "kind": "oracle", "sample": "whole workload", "kept": int(keep.sum())}
+
+
 def bench_batch(torch, lib, hip, pg, synth, dev, steps):
     """64 uneven problems: the autotuner picks each problem's path; then the
     one-call-per-problem loop and the captured persistent batch are timed on
@@ -285,7 +325,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--quick", action="store_true", help="default workload only, no extras")
     ap.add_argument("--extras", default="all",
-                    help="comma list of extras: other,small,ld,batch,serve (or all / none)")
+                    help="comma list of extras: other,small,ld,prune,batch,serve (or all / none)")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serial-seconds", type=float, default=15.0)
@@ -368,7 +408,7 @@ def main():
     extras = {}
     want = set()
     if not args.quick:
-        want = {"other", "small", "ld", "batch", "serve"} if args.extras == "all" else \
+        want = {"other", "small", "ld", "prune", "batch", "serve"} if args.extras == "all" else \
             set(x for x in args.extras.split(",") if x and x != "none")
     if "other" in want:
         other = "popc" if path == "mfma" else "mfma"
@@ -436,6 +476,14 @@ def main():
             del wkl
         del ol, cl
 
+    prune_runs = []
+    if "prune" in want:
+        for wp in (synth.prune_small(), synth.prune_large()):
+            log(f"timing LD pruning on {wp['name']}")
+            extras[wp["name"]] = bench_prune(torch, lib, hip, pg, wp, dev, args.steps)
+            prune_runs.append(wp)
+        torch.cuda.empty_cache()
+
     if "batch" in want:
         extras["batch"] = bench_batch(torch, lib, hip, pg, synth, dev, args.steps)
         torch.cuda.empty_cache()
@@ -458,6 +506,10 @@ def main():
     if not args.no_cpu:
         log("timing the CPU oracle on a bounded sample")
         result["cpu_baseline"] = cpu_baseline_ibs(w["bed"], n, V, args.cpu_budget)
+        for wp in prune_runs:
+            if wp["n"] * wp["V"] * wp["window"] <= 1e10:     # whole problem in ~a second
+                log(f"timing the CPU oracle on {wp['name']}")
+                extras[wp["name"]]["cpu_baseline"] = cpu_baseline_prune(wp)
     print(json.dumps(result), flush=True)
 
 

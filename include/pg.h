@@ -169,6 +169,46 @@ int pg_ld_window(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_sel
                  int64_t capacity, int64_t* n_out, int path, void* workspace,
                  size_t workspace_bytes, void* stream);
 
+/* ---- LD-based pruning ------------------------------------------------------
+ *
+ * The --indep-pairwise operation (section "Linkage disequilibrium-based
+ * variant pruning", timed in Table 4; the paper does not spell out its greedy
+ * order, so the order below is this library's reading):
+ *  - windows of `window` consecutive selected variants start at 0, step,
+ *    2*step, ...; the last window is the first one that reaches the end of
+ *    the range;
+ *  - inside each window, pairs a < b of variants not yet dropped are visited
+ *    in increasing a, then increasing b; when r2 > r2_threshold (r2 exactly as
+ *    pg_ld_window defines it; NaN never exceeds), the variant with the lower
+ *    minor allele frequency is dropped, and b when the two are equal;
+ *  - a dropped variant stays dropped.
+ * Minor allele frequency of a variant: min(A2, 2n - A2) / 2n over its n
+ * non-missing calls among the selected samples (A2 counts A2 alleles;
+ * 0 when n = 0); frequencies are compared exactly, as rationals.
+ */
+
+/* Workspace bytes pg_ld_prune needs for this shape, window and path. */
+int pg_prune_workspace_bytes(const pg_genotypes* g, int64_t n_sel, int64_t v_begin,
+                             int64_t v_end, int32_t window, int path, size_t* bytes);
+
+/*
+ * Greedy LD pruning over the selected samples and variants.
+ *   window        variants per window, 2 <= window <= 65536
+ *   step          window shift in variants, 1 <= step <= window
+ *   r2_threshold  pairs with r2 strictly above it trigger a drop (not NaN)
+ *   keep          device uint8 array of v_end - v_begin flags: 1 = kept,
+ *                 0 = dropped; entry v belongs to variant v_begin + v
+ *   n_kept        optional device int64: number of kept variants
+ *   path          PG_PATH_MFMA or PG_PATH_POPC selects the pair kernel that
+ *                 evaluates r2 (both give identical results)
+ * Stages for pg_profile_events: 1 = operand layout and scratch clearing,
+ * 2 = banded pair kernel, 3 = allele counts, 4 = greedy pass.
+ */
+int pg_ld_prune(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_sel,
+                int64_t v_begin, int64_t v_end, int32_t window, int32_t step,
+                double r2_threshold, uint8_t* keep, int64_t* n_kept, int path,
+                void* workspace, size_t workspace_bytes, void* stream);
+
 /* ---- batching ------------------------------------------------------------
  *
  * Many independent problems (IBS matrices and LD windows over different

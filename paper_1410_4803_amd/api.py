@@ -4,6 +4,7 @@ every computation runs in the library's HIP kernels.
     cohort = Cohort.from_numpy(bed, n_samples)          # resident in HBM
     ibs0, ibs1, ibs2, n = ibs_matrix(cohort, layout="full")
     recs = ld_records(cohort, window=1000, r2_min=0.2)  # numpy LD_PAIR array
+    keep, n_kept = ld_prune(cohort, window=50, step=5, r2_threshold=0.5)
 """
 from __future__ import annotations
 
@@ -193,3 +194,39 @@ def ld_records(cohort: Cohort, window: int, r2_min: float, *, capacity: int | No
         out, n_out = ld_window(cohort, window, r2_min, capacity=total, **kw)
         total = int(n_out.item())
     return records_to_numpy(out, total)
+
+
+def prune_workspace_bytes(cohort: Cohort, window: int, n_sel: int = 0, v_range=None,
+                          path="auto") -> int:
+    vb, ve = (0, 0) if v_range is None else v_range
+    out = ctypes.c_size_t(0)
+    g = cohort.struct()
+    N.check(N.load().pg_prune_workspace_bytes(ctypes.byref(g), n_sel, vb, ve, int(window),
+                                              _path(path), ctypes.byref(out)),
+            "pg_prune_workspace_bytes")
+    return out.value
+
+
+def ld_prune(cohort: Cohort, window: int, step: int, r2_threshold: float, *,
+             sample_idx: torch.Tensor | None = None, v_range=None, path="auto", keep=None,
+             n_kept=None, workspace: torch.Tensor | None = None, stream=None):
+    """Asynchronous greedy LD pruning (--indep-pairwise window step threshold).
+    Returns (keep, n_kept): keep is a CUDA uint8 tensor with one flag per
+    selected variant (1 = kept), n_kept a CUDA int64 tensor."""
+    lib = N.load()
+    n_sel, vb, ve = _sel(cohort, sample_idx, v_range)
+    dev = cohort.bed.device
+    nv = (ve - vb) if (vb, ve) != (0, 0) else cohort.n_variants
+    if keep is None:
+        keep = torch.empty(nv, dtype=torch.uint8, device=dev)
+    if n_kept is None:
+        n_kept = torch.empty(1, dtype=torch.int64, device=dev)
+    need = prune_workspace_bytes(cohort, window, n_sel, (vb, ve), path)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    g = cohort.struct()
+    st = lib.pg_ld_prune(ctypes.byref(g), _ptr(sample_idx), n_sel, vb, ve, int(window), int(step),
+                         float(r2_threshold), _ptr(keep), _ptr(n_kept), _path(path),
+                         _ptr(workspace), workspace.numel(), _stream_handle(stream))
+    N.check(st, "pg_ld_prune")
+    return keep, n_kept

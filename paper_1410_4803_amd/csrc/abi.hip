@@ -1,6 +1,7 @@
 // C ABI of libpg.so: argument validation, workspace carving and dispatch.
 // Every check runs on the host before any launch; see include/pg.h for the
 // contract of each entry point.
+#include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -148,6 +149,26 @@ int plan_ld(const Sel& s, int32_t window, int path_arg, LdPlan& p) {
   p.off_cnt = c.take(p.rows_pad * 4);
   p.off_off = c.take((p.rows_pad + 1) * 8);
   p.off_bsum = c.take((int64_t)ld_scan_blocks(p.rows_pad) * 8);
+  p.bytes = c.off;
+  return PG_OK;
+}
+
+struct PrunePlan {
+  LdPlan ld;
+  int64_t off_stats, bytes;
+};
+
+// The LD plan for the pair kernel (largest distance window - 1) plus the
+// per-variant allele counts.
+int plan_prune(const Sel& s, int32_t window, int32_t step, int path_arg, PrunePlan& p) {
+  if (window < 2 || window > kPruneMaxWindow)
+    return fail(PG_EINVAL, "window %d outside [2, %lld]", (int)window, (long long)kPruneMaxWindow);
+  if (step < 1 || step > window) return fail(PG_EINVAL, "step %d outside [1, window]", (int)step);
+  int rc = plan_ld(s, window - 1, path_arg, p.ld);
+  if (rc != PG_OK) return rc;
+  Carve c;
+  c.off = p.ld.bytes;
+  p.off_stats = c.take(p.ld.rows_pad * (int64_t)sizeof(int2));
   p.bytes = c.off;
   return PG_OK;
 }
@@ -320,6 +341,61 @@ int pg_ld_window(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_sel
                 : launch_ld_mfma(D, p.words, s.nv, p.rows_pad, window, r2_min, sc, st);
   if (rc == PG_OK)
     rc = launch_ld_finish(D, planes, p.words, p.rows_pad, s.nv, s.v0, sc, out, capacity, n_out, st);
+  return rc;
+}
+
+int pg_prune_workspace_bytes(const pg_genotypes* g, int64_t n_sel, int64_t v_begin,
+                             int64_t v_end, int32_t window, int path, size_t* bytes) {
+  g_last_error[0] = 0;
+  if (!bytes) return fail(PG_EINVAL, "bytes is NULL");
+  Sel s;
+  int rc = make_sel(g, n_sel > 0, nullptr, n_sel, v_begin, v_end, s);
+  if (rc != PG_OK) return rc;
+  PrunePlan p;
+  rc = plan_prune(s, window, window, path, p);
+  if (rc != PG_OK) return rc;
+  *bytes = (size_t)p.bytes;
+  return PG_OK;
+}
+
+int pg_ld_prune(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_sel,
+                int64_t v_begin, int64_t v_end, int32_t window, int32_t step,
+                double r2_threshold, uint8_t* keep, int64_t* n_kept, int path, void* workspace,
+                size_t workspace_bytes, void* stream) {
+  g_last_error[0] = 0;
+  Sel s;
+  int rc = make_sel(g, sample_idx != nullptr, sample_idx, n_sel, v_begin, v_end, s);
+  if (rc != PG_OK) return rc;
+  if (!keep) return fail(PG_EINVAL, "keep is NULL");
+  if (r2_threshold != r2_threshold) return fail(PG_EINVAL, "r2_threshold is NaN");
+  PrunePlan p;
+  rc = plan_prune(s, window, step, path, p);
+  if (rc != PG_OK) return rc;
+  if ((int64_t)workspace_bytes < p.bytes || !workspace)
+    return fail(PG_ENOMEM, "workspace of %llu bytes < %lld required",
+                (unsigned long long)workspace_bytes, (long long)p.bytes);
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  const LdPlan& q = p.ld;
+  uint32_t* D = (uint32_t*)(ws + q.off_D);
+  LdScratch sc{(uint32_t*)(ws + q.off_bm), q.bm_words, (uint32_t*)(ws + q.off_cnt),
+               (int64_t*)(ws + q.off_off), (int64_t*)(ws + q.off_bsum)};
+  int2* stats = (int2*)(ws + p.off_stats);
+  const bool planes = q.path == PG_PATH_POPC;
+  // r2 > t  <=>  r2 >= the next double above t
+  const double r2_min = nextafter(r2_threshold, INFINITY);
+  mark_stage(0, st);
+  rc = planes ? launch_ld_planes(s, D, q.rows_pad, q.words, st)
+              : launch_variant_major_2bit(s, D, q.rows_pad, q.words, st);
+  if (rc == PG_OK) rc = ld_clear(sc, q.rows_pad, st);
+  mark_stage(1, st);
+  if (rc == PG_OK)
+    rc = planes ? launch_ld_popc(D, q.words, s.nv, q.rows_pad, window - 1, r2_min, sc, st)
+                : launch_ld_mfma(D, q.words, s.nv, q.rows_pad, window - 1, r2_min, sc, st);
+  if (rc == PG_OK) rc = launch_variant_stats(D, planes, q.words, q.rows_pad, s.nv, stats, st);
+  mark_stage(3, st);
+  if (rc == PG_OK) rc = launch_prune_greedy(sc, stats, s.nv, window, step, keep, n_kept, st);
+  mark_stage(4, st);
   return rc;
 }
 

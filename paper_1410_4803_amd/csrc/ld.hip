@@ -171,14 +171,6 @@ __device__ __forceinline__ void add_plane_sums(Sums6& z, uint32_t pa, uint32_t q
   z.sxy += __builtin_popcount((pa & pb) | (qa & qb)) - __builtin_popcount((pa & qb) | (qa & pb));
 }
 
-// 2-bit word (16 codes) -> the three indicator masks at the even bit positions.
-__device__ __forceinline__ void masks_of_word(uint32_t x, uint32_t& p, uint32_t& q, uint32_t& m) {
-  const uint32_t lo = x & 0x55555555u, hi = (x >> 1) & 0x55555555u;
-  p = lo & hi;                       // homA2
-  q = ~(lo | hi) & 0x55555555u;      // homA1
-  m = ~(lo & ~hi) & 0x55555555u;     // not code 01
-}
-
 template <bool kPlanes>
 __global__ __launch_bounds__(256) void k_ld_emit(const uint32_t* __restrict__ X, int64_t words,
                                                  int64_t rows_pad, int64_t nv, int64_t v0,

@@ -50,6 +50,14 @@ __device__ __forceinline__ uint32_t code_at(const Sel& s, int64_t v, int64_t k) 
 // Sixteen codes of one word, all positions "missing".
 constexpr uint32_t kAllMissing16 = 0x55555555u;
 
+// 2-bit word (16 codes) -> the three indicator masks at the even bit positions.
+__device__ __forceinline__ void masks_of_word(uint32_t x, uint32_t& p, uint32_t& q, uint32_t& m) {
+  const uint32_t lo = x & 0x55555555u, hi = (x >> 1) & 0x55555555u;
+  p = lo & hi;                       // homA2
+  q = ~(lo | hi) & 0x55555555u;      // homA1
+  m = ~(lo & ~hi) & 0x55555555u;     // not code 01
+}
+
 // ---- layout kernels (layout.hip) -------------------------------------------
 // Sample-major 2-bit words: T[i*wp + w] holds codes of variants 16w..16w+15
 // of selected sample i (code of variant 16w+t at bits 2t); rows_pad x wp.
@@ -138,6 +146,17 @@ int launch_ld_popc(const uint32_t* P, int64_t words_pad, int64_t nv, int64_t row
 int launch_ld_finish(const uint32_t* X, bool planes, int64_t words, int64_t rows_pad, int64_t nv,
                      int64_t v0, const LdScratch& sc, pg_ld_pair* out, int64_t capacity,
                      int64_t* n_out, hipStream_t st, bool marks = true);
+
+// ---- LD pruning (prune.hip) -------------------------------------------------
+// Per selected variant: {minor allele count, non-missing calls (at least 1)}
+// over the selected samples, from the operand of the LD pair kernel.
+int launch_variant_stats(const uint32_t* X, bool planes, int64_t words, int64_t rows_pad,
+                         int64_t nv, int2* stats, hipStream_t st);
+// The greedy pass over the windows, from the pair kernel's bitmap of pairs
+// with r^2 above the threshold (bitmap window = window - 1).
+int launch_prune_greedy(const LdScratch& sc, const int2* stats, int64_t nv, int64_t window,
+                        int64_t step, uint8_t* keep, int64_t* n_kept, hipStream_t st);
+constexpr int64_t kPruneMaxWindow = 1 << 16;
 
 // r^2 from exact sums, as documented in pg.h; shared by every LD path so that
 // the emission decision and the emitted value are the same double.

@@ -147,3 +147,36 @@ def test_batch_plan_validation_names_problem():
     assert rc == N.PG_EINVAL
     lib.pg_plan_free(plan)
     assert lib.pg_batch_plan(arr, 0, ctypes.byref(plan)) == N.PG_EINVAL
+
+
+def _prune_ws(g, W, n_sel=0, vb=0, ve=0, path=0):
+    b = ctypes.c_size_t(0)
+    rc = N.load().pg_prune_workspace_bytes(ctypes.byref(g), n_sel, vb, ve, W, path,
+                                           ctypes.byref(b))
+    return rc, b.value
+
+
+def test_prune_workspace_and_validation():
+    lib = N.load()
+    g = _g(1000, 100000)
+    rc, b = _prune_ws(g, 50)
+    _, ld = _ld_ws(g, 49)
+    # the LD scratch of the pair kernel (largest distance window - 1) plus
+    # one int2 of allele counts per padded variant
+    assert rc == 0 and b == ld + 100032 * 8
+    assert _prune_ws(g, 1)[0] == N.PG_EINVAL
+    assert _prune_ws(g, (1 << 16) + 1)[0] == N.PG_EINVAL
+    assert _prune_ws(g, 1 << 16)[0] == 0
+    fake = 0x2000
+
+    def call(W=50, S=5, t=0.5, keep=fake, ws=1 << 30, path=0):
+        return lib.pg_ld_prune(ctypes.byref(g), None, 0, 0, 0, W, S, t, keep, None, path, fake,
+                               ws, None)
+    assert call(S=0) == N.PG_EINVAL
+    assert call(S=51) == N.PG_EINVAL
+    assert call(W=1, S=1) == N.PG_EINVAL
+    assert call(t=float("nan")) == N.PG_EINVAL
+    assert call(keep=None) == N.PG_EINVAL
+    assert call(path=9) == N.PG_EINVAL
+    assert call(ws=16) == N.PG_ENOMEM
+    assert "workspace" in N.last_error()
