@@ -3,9 +3,10 @@
 The plain definitions of the IBS and LD statistics of Chang et al. 2015
 (arXiv 1410.4803), section "Bitwise parallelism" (the per-marker IBS loop)
 and section "Bit population count" (r between two markers with missing
-data), and the greedy LD pruning of section "Linkage disequilibrium-based
-variant pruning" (under the reading stated in ``oracle.c``), written over
-unpacked genotype codes in ``oracle.c``.
+data), the greedy LD pruning of section "Linkage disequilibrium-based
+variant pruning" and the genomic relationship matrix of section "Partial sum
+lookup" (under the readings stated in ``oracle.c``), written over unpacked
+genotype codes in ``oracle.c``.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's CPU-baseline
 leg may import this package.  It shares no code with the GPU library
@@ -67,6 +68,8 @@ def _load():
         lib.oracle_r2_counts.restype = dbl
         lib.oracle_ld_prune.argtypes = [p, i64, i64, i64, i64, dbl, p]
         lib.oracle_ld_prune.restype = i64
+        lib.oracle_grm.argtypes = [p, i64, i64, i32, p, p, p]
+        lib.oracle_grm.restype = None
         lib.oracle_threads.argtypes = []
         lib.oracle_threads.restype = i32
         _lib = lib
@@ -187,3 +190,20 @@ def ld_prune(codes_vm: np.ndarray, window: int, step: int, r2_max: float) -> np.
     if kept < 0:
         raise MemoryError("oracle_ld_prune")
     return keep
+
+
+def grm(codes_vm: np.ndarray, full: bool = True):
+    """(A float64, N uint32, abs_sum float64): the relationship matrix from
+    per-marker increment tables; (n, n) if full else the packed strict upper
+    triangle."""
+    V, n = codes_vm.shape
+    sm = np.ascontiguousarray(codes_vm.T)
+    size = n * n if full else n * (n - 1) // 2
+    A = np.zeros(size, dtype=np.float64)
+    N = np.zeros(size, dtype=np.uint32)
+    S = np.zeros(size, dtype=np.float64)
+    _load().oracle_grm(sm.ctypes.data, n, V, int(full), A.ctypes.data, N.ctypes.data,
+                       S.ctypes.data)
+    if full:
+        A, N, S = A.reshape(n, n), N.reshape(n, n), S.reshape(n, n)
+    return A, N, S

@@ -334,3 +334,74 @@ int64_t oracle_ld_prune(const int8_t* codes_vm, int64_t n, int64_t V, int64_t wi
   free(maf);
   return kept;
 }
+
+/*
+ * Genomic relationship matrix (section "Partial sum lookup": the weighted
+ * distance built from per-marker increments, with the GCTA relationship
+ * increments as its example), the paper's first-draft algorithm: per marker,
+ * a table of the increments of every genotype pair; per sample pair, the
+ * table entries summed over markers, where a marker with a missing call adds
+ * nothing and is not counted in that pair's denominator.
+ *
+ * Reading.  x = number of A2 alleles (0, 1, 2) and p = the A2 frequency over
+ * the marker's non-missing calls; the increment of genotypes (x, y) is
+ *   (x - 2p)(y - 2p) / (2p(1 - p)).
+ * The paper states the cases with major/minor labels and the minor allele
+ * frequency; counting either allele gives the same value as long as x and p
+ * refer to the same allele.  Markers with no non-missing call or with p equal
+ * to 0 or 1 (increments undefined) are left out of every pair.
+ * A[i,j] = sum of increments / N[i,j], N[i,j] = markers counted for the
+ * pair; NaN when N[i,j] = 0.  The diagonal uses the same increments with
+ * i = j.  full != 0: n x n row-major; else strict upper triangle as in
+ * oracle_ibs_matrix.  abs_sum (optional, same layout): the sum of the
+ * increments' absolute values, for error bounds.
+ */
+void oracle_grm(const int8_t* codes_sm, int64_t n, int64_t V, int full, double* A, uint32_t* N,
+                double* abs_sum) {
+  /* per-marker increment tables, indexed [marker][dosage_i][dosage_j] */
+  double* inc = (double*)malloc((size_t)V * 9 * sizeof(double));
+  uint8_t* used = (uint8_t*)malloc((size_t)V);
+  if (!inc || !used) {
+    free(inc);
+    free(used);
+    return;
+  }
+#pragma omp parallel for schedule(static)
+  for (int64_t v = 0; v < V; ++v) {
+    int64_t calls = 0, a2 = 0;
+    for (int64_t k = 0; k < n; ++k) {
+      const int8_t c = codes_sm[k * V + v];
+      if (c == MISSING) continue;
+      calls += 1;
+      a2 += dosage(c);
+    }
+    used[v] = calls > 0 && a2 > 0 && a2 < 2 * calls;
+    const double p = used[v] ? (double)a2 / (double)(2 * calls) : 0.0;
+    for (int x = 0; x < 3; ++x)
+      for (int y = 0; y < 3; ++y)
+        inc[v * 9 + x * 3 + y] =
+            used[v] ? ((double)x - 2.0 * p) * ((double)y - 2.0 * p) / (2.0 * p * (1.0 - p)) : 0.0;
+  }
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t i = 0; i < n; ++i) {
+    const int8_t* ci = codes_sm + i * V;
+    for (int64_t j = full ? 0 : i + 1; j < n; ++j) {
+      const int8_t* cj = codes_sm + j * V;
+      double sum = 0.0, asum = 0.0;
+      uint32_t cnt = 0;
+      for (int64_t v = 0; v < V; ++v) {
+        if (!used[v] || ci[v] == MISSING || cj[v] == MISSING) continue;
+        const double t = inc[v * 9 + dosage(ci[v]) * 3 + dosage(cj[v])];
+        sum += t;
+        asum += fabs(t);
+        cnt += 1;
+      }
+      const int64_t idx = full ? i * n + j : i * n - i * (i + 1) / 2 + (j - i - 1);
+      A[idx] = cnt ? sum / (double)cnt : NAN;
+      N[idx] = cnt;
+      if (abs_sum) abs_sum[idx] = asum;
+    }
+  }
+  free(inc);
+  free(used);
+}
