@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 PEAK_INT8_TOPS = 5000.0        # MI355X dense int8 MFMA, 5.0 POP/s
 PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12   # 32-bit integer VALU lane-ops/s, 39.3 T
 PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6         # MI355X dense fp64 MFMA
 # algorithmic work per unique genotype-pair comparison (one pair, one variant)
 IBS_MFMA_OPS = 4 * 2          # four int8 contractions: 4 MACs = 8 ops
 IBS_POPC_OPS = 10 / 32        # 10 VALU ops per 32-variant word
@@ -181,6 +182,31 @@ def bench_prune(torch, lib, hip, pg, wp, dev, steps):
                          "frac": round(ach / PEAK_INT8_TOPS, 4)}}
 
 
+def bench_grm(torch, lib, hip, pg, wg, dev, steps):
+    """Relationship matrix (full layout): whole-call time and its stages.
+    Algorithmic work: one fp64 multiply-add per (unique pair incl. the
+    diagonal) x variant, i.e. 2 * m(m+1)/2 * V flops."""
+    n, V = wg["n"], wg["V"]
+    c = pg.Cohort.from_numpy(wg["bed"], n, device=dev)
+    A = torch.empty((n, n), dtype=torch.float64, device=dev)
+    Nn = torch.empty((n, n), dtype=torch.int32, device=dev)
+    ws = torch.empty(pg.grm_workspace_bytes(c), dtype=torch.uint8, device=dev)
+    ms, st = timed_steps(torch, lib, hip, lambda: pg.grm_matrix(
+        c, layout="full", out=(A, Nn), workspace=ws), steps, 2, 3)
+    flops = 2.0 * n * (n + 1) / 2 * V
+    pair_ms = mean(st[1])
+    ach = flops / (pair_ms * 1e-3) / 1e12
+    torch.cuda.synchronize()
+    assert torch.equal(Nn, Nn.T)
+    return {"workload": wg["name"], "ms_per_call": round(ms, 3),
+            "value": round(n * (n - 1) / 2 * V / (ms * 1e-3) / 1e9, 1), "unit": "G/s",
+            "stages_ms": {"layout_and_tables": round(mean(st[0]), 3),
+                          "pair_kernel": round(pair_ms, 3)},
+            "roofline": {"bound": "mfma", "kernel": "k_grm_mfma", "unit": "TFLOP/s",
+                         "achieved": round(ach, 2), "peak": PEAK_FP64_TFLOPS,
+                         "frac": round(ach / PEAK_FP64_TFLOPS, 4)}}
+
+
 def cpu_baseline_prune(wp):
     """The oracle's pruning on the whole workload (OpenMP r^2 table, then its
     sequential greedy pass)."""
@@ -325,7 +351,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--quick", action="store_true", help="default workload only, no extras")
     ap.add_argument("--extras", default="all",
-                    help="comma list of extras: other,small,ld,prune,batch,serve (or all / none)")
+                    help="comma list of extras: other,small,ld,prune,grm,batch,serve (or all / none)")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serial-seconds", type=float, default=15.0)
@@ -408,7 +434,8 @@ def main():
     extras = {}
     want = set()
     if not args.quick:
-        want = {"other", "small", "ld", "prune", "batch", "serve"} if args.extras == "all" else \
+        everything = {"other", "small", "ld", "prune", "grm", "batch", "serve"}
+        want = everything if args.extras == "all" else \
             set(x for x in args.extras.split(",") if x and x != "none")
     if "other" in want:
         other = "popc" if path == "mfma" else "mfma"
@@ -483,6 +510,12 @@ def main():
             extras[wp["name"]] = bench_prune(torch, lib, hip, pg, wp, dev, args.steps)
             prune_runs.append(wp)
         torch.cuda.empty_cache()
+
+    if "grm" in want:
+        for wg in (synth.grm_small(), synth.grm_large()):
+            log(f"timing the relationship matrix on {wg['name']}")
+            extras[wg["name"]] = bench_grm(torch, lib, hip, pg, wg, dev, max(3, args.steps // 2))
+            torch.cuda.empty_cache()
 
     if "batch" in want:
         extras["batch"] = bench_batch(torch, lib, hip, pg, synth, dev, args.steps)

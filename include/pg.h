@@ -209,6 +209,41 @@ int pg_ld_prune(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_sel,
                 double r2_threshold, uint8_t* keep, int64_t* n_kept, int path,
                 void* workspace, size_t workspace_bytes, void* stream);
 
+/* ---- genomic relationship matrix -----------------------------------------
+ *
+ * The weighted distance of section "Partial sum lookup", with the GCTA
+ * relationship increments the paper gives as its example.  Reading: x = the
+ * number of A2 alleles of a call (0, 1, 2) and p = the marker's A2 frequency
+ * over its non-missing calls among the selected samples; the increment of a
+ * pair of calls is (x - 2p)(y - 2p) / (2p(1-p)) (the paper's major/minor
+ * case table gives the same value when x and p count the same allele).  A
+ * marker where either call is missing adds nothing and is not counted in the
+ * pair's denominator; a marker with no call or with p = 0 or 1 is left out of
+ * every pair.  For samples i, j of the selection:
+ *   N[i,j] = markers counted,  A[i,j] = (sum of increments) / N[i,j]
+ * (NaN when N[i,j] = 0).  The diagonal uses the same increments with i = j.
+ * The sums are formed in IEEE double (fp64 matrix cores, increments factored
+ * as z_i z_j with z = (x - 2p) / sqrt(2p(1-p))); they match a sequential
+ * double sum of the per-pair increments to within the rounding of a length-V
+ * double dot product (about V * 2^-53 times the sum of |increments|).
+ */
+
+/* Workspace bytes pg_grm_matrix needs for this shape. */
+int pg_grm_workspace_bytes(const pg_genotypes* g, int64_t n_sel, int64_t v_begin,
+                           int64_t v_end, size_t* bytes);
+
+/*
+ * Relationship matrix over the selected samples and variants.
+ *   out_layout  PG_FULL (m x m, diagonal included) or PG_TRI_UPPER
+ *   grm         device double array of the layout's size (A)
+ *   n_used      device uint32 array of the same size (N)
+ * Stages for pg_profile_events: 1 = operand layout and per-marker tables,
+ * 2 = pair kernel.
+ */
+int pg_grm_matrix(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_sel,
+                  int64_t v_begin, int64_t v_end, int out_layout, double* grm, uint32_t* n_used,
+                  void* workspace, size_t workspace_bytes, void* stream);
+
 /* ---- batching ------------------------------------------------------------
  *
  * Many independent problems (IBS matrices and LD windows over different

@@ -5,7 +5,8 @@ The statistics are those PLINK 1.9 accelerates with bit-parallel popcounts
 (Chang et al., "Second-generation PLINK", arXiv 1410.4803): identity-by-state
 counts per sample pair (section "Bitwise parallelism") and LD sums and r^2 per
 variant pair (section "Bit population count"), and the greedy LD pruning
-built on them (section "Linkage disequilibrium-based variant pruning").  All
+built on them (section "Linkage disequilibrium-based variant pruning"), and
+the genomic relationship matrix (section "Partial sum lookup").  All
 computation runs in the
 library's HIP kernels; this package only marshals arguments.
 """
@@ -13,11 +14,12 @@ from ._native import (LD_PAIR, PATHS, LAYOUTS, PgError, load as load_library,  #
                       last_error, status_str)
 from .api import (Cohort, ibs_matrix, ibs_workspace_bytes, ibs_output_size,  # noqa: F401
                   ld_window, ld_workspace_bytes, ld_records, records_to_numpy, ld_prune,
-                  prune_workspace_bytes)
+                  prune_workspace_bytes, grm_matrix, grm_workspace_bytes)
 from .batch import Batch, IbsProblem, LdProblem  # noqa: F401
 from .tune import Tuner  # noqa: F401
 
 __all__ = ["Cohort", "ibs_matrix", "ibs_workspace_bytes", "ibs_output_size", "ld_window",
            "ld_workspace_bytes", "ld_records", "records_to_numpy", "LD_PAIR", "PATHS",
            "LAYOUTS", "PgError", "load_library", "last_error", "status_str", "Batch",
-           "IbsProblem", "LdProblem", "Tuner", "ld_prune", "prune_workspace_bytes"]
+           "IbsProblem", "LdProblem", "Tuner", "ld_prune", "prune_workspace_bytes", "grm_matrix",
+           "grm_workspace_bytes"]

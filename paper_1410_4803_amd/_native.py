@@ -25,7 +25,7 @@ PATHS = {"auto": PG_PATH_AUTO, "popc": PG_PATH_POPC, "mfma": PG_PATH_MFMA}
 # ABI symbols (include/pg.h)
 SYMBOLS = ("pg_status_str", "pg_last_error", "pg_version", "pg_profile_events",
            "pg_ibs_workspace_bytes", "pg_ibs_matrix", "pg_ld_workspace_bytes", "pg_ld_window",
-           "pg_prune_workspace_bytes", "pg_ld_prune",
+           "pg_prune_workspace_bytes", "pg_ld_prune", "pg_grm_workspace_bytes", "pg_grm_matrix",
            "pg_batch_plan", "pg_batch_workspace_bytes", "pg_batch_tiles", "pg_batch_upload",
            "pg_batch_launch", "pg_plan_free", "pg_batch_capture", "pg_graph_launch",
            "pg_graph_destroy")
@@ -97,6 +97,10 @@ def load():
     lib.pg_prune_workspace_bytes.restype = ctypes.c_int
     lib.pg_ld_prune.argtypes = [gp, p, i64, i64, i64, i32, i32, dbl, p, p, ctypes.c_int, p, sz, p]
     lib.pg_ld_prune.restype = ctypes.c_int
+    lib.pg_grm_workspace_bytes.argtypes = [gp, i64, i64, i64, ctypes.POINTER(sz)]
+    lib.pg_grm_workspace_bytes.restype = ctypes.c_int
+    lib.pg_grm_matrix.argtypes = [gp, p, i64, i64, i64, ctypes.c_int, p, p, p, sz, p]
+    lib.pg_grm_matrix.restype = ctypes.c_int
     pp = ctypes.POINTER(ctypes.c_void_p)
     lib.pg_batch_plan.argtypes = [ctypes.POINTER(Problem), ctypes.c_int, pp]
     lib.pg_batch_plan.restype = ctypes.c_int

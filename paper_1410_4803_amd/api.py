@@ -5,6 +5,7 @@ every computation runs in the library's HIP kernels.
     ibs0, ibs1, ibs2, n = ibs_matrix(cohort, layout="full")
     recs = ld_records(cohort, window=1000, r2_min=0.2)  # numpy LD_PAIR array
     keep, n_kept = ld_prune(cohort, window=50, step=5, r2_threshold=0.5)
+    A, N = grm_matrix(cohort, layout="full")            # relationship matrix
 """
 from __future__ import annotations
 
@@ -230,3 +231,43 @@ def ld_prune(cohort: Cohort, window: int, step: int, r2_threshold: float, *,
                          _ptr(workspace), workspace.numel(), _stream_handle(stream))
     N.check(st, "pg_ld_prune")
     return keep, n_kept
+
+
+def grm_workspace_bytes(cohort: Cohort, n_sel: int = 0, v_range=None) -> int:
+    vb, ve = (0, 0) if v_range is None else v_range
+    out = ctypes.c_size_t(0)
+    g = cohort.struct()
+    N.check(N.load().pg_grm_workspace_bytes(ctypes.byref(g), n_sel, vb, ve, ctypes.byref(out)),
+            "pg_grm_workspace_bytes")
+    return out.value
+
+
+def grm_matrix(cohort: Cohort, *, sample_idx: torch.Tensor | None = None, v_range=None,
+               layout: str = "full", out=None, workspace: torch.Tensor | None = None,
+               stream=None):
+    """Asynchronous relationship matrix.  Returns (A, N): A float64 and N
+    int32 (holding uint32 counts) CUDA tensors, (m, m) for the full layout or
+    the packed strict upper triangle."""
+    lib = N.load()
+    n_sel, vb, ve = _sel(cohort, sample_idx, v_range)
+    m = n_sel if sample_idx is not None else cohort.n_samples
+    dev = cohort.bed.device
+    if out is None:
+        shape = (m, m) if layout == "full" else (ibs_output_size(m, layout),)
+        out = (torch.empty(shape, dtype=torch.float64, device=dev),
+               torch.empty(shape, dtype=torch.int32, device=dev))
+    A, Nn = out
+    size = ibs_output_size(m, layout)
+    _require_cuda(A, "A", torch.float64)
+    _require_cuda(Nn, "N", torch.int32)
+    if A.numel() < size or Nn.numel() < size:
+        raise ValueError(f"outputs need {size} entries")
+    need = grm_workspace_bytes(cohort, n_sel, (vb, ve))
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    g = cohort.struct()
+    st = lib.pg_grm_matrix(ctypes.byref(g), _ptr(sample_idx), n_sel, vb, ve, N.LAYOUTS[layout],
+                           _ptr(A), _ptr(Nn), _ptr(workspace), workspace.numel(),
+                           _stream_handle(stream))
+    N.check(st, "pg_grm_matrix")
+    return A, Nn

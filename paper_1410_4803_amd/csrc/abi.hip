@@ -173,6 +173,24 @@ int plan_prune(const Sel& s, int32_t window, int32_t step, int path_arg, PrunePl
   return PG_OK;
 }
 
+struct GrmPlan {
+  int64_t rows_pad, words;
+  int64_t off_T, off_z, off_used, bytes;
+};
+
+int plan_grm(const Sel& s, GrmPlan& p) {
+  p.rows_pad = round_up(s.m, 128);
+  p.words = round_up(ceil_div(s.nv, 16), 16);
+  const int64_t nt = p.rows_pad / 128;
+  if (nt * (nt + 1) / 2 >= kMaxIndex) return fail(PG_EUNSUPPORTED, "too many samples for one call");
+  Carve c;
+  p.off_T = c.take(p.rows_pad * p.words * 4);
+  p.off_z = c.take(p.words * 16 * 4 * 8);
+  p.off_used = c.take(p.words * 4);
+  p.bytes = c.off;
+  return PG_OK;
+}
+
 }  // namespace
 
 int plan_ibs_default(const Sel& s, IbsPlan& p) { return plan_ibs(s, PG_PATH_MFMA, p); }
@@ -396,6 +414,49 @@ int pg_ld_prune(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_sel,
   mark_stage(3, st);
   if (rc == PG_OK) rc = launch_prune_greedy(sc, stats, s.nv, window, step, keep, n_kept, st);
   mark_stage(4, st);
+  return rc;
+}
+
+int pg_grm_workspace_bytes(const pg_genotypes* g, int64_t n_sel, int64_t v_begin, int64_t v_end,
+                           size_t* bytes) {
+  g_last_error[0] = 0;
+  if (!bytes) return fail(PG_EINVAL, "bytes is NULL");
+  Sel s;
+  int rc = make_sel(g, n_sel > 0, nullptr, n_sel, v_begin, v_end, s);
+  if (rc != PG_OK) return rc;
+  GrmPlan p;
+  rc = plan_grm(s, p);
+  if (rc != PG_OK) return rc;
+  *bytes = (size_t)p.bytes;
+  return PG_OK;
+}
+
+int pg_grm_matrix(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_sel,
+                  int64_t v_begin, int64_t v_end, int out_layout, double* grm, uint32_t* n_used,
+                  void* workspace, size_t workspace_bytes, void* stream) {
+  g_last_error[0] = 0;
+  Sel s;
+  int rc = make_sel(g, sample_idx != nullptr, sample_idx, n_sel, v_begin, v_end, s);
+  if (rc != PG_OK) return rc;
+  if (out_layout != PG_FULL && out_layout != PG_TRI_UPPER)
+    return fail(PG_EINVAL, "unknown layout %d", out_layout);
+  const int64_t entries = out_layout == PG_FULL ? s.m * s.m : s.m * (s.m - 1) / 2;
+  if (entries > 0 && (!grm || !n_used)) return fail(PG_EINVAL, "an output pointer is NULL");
+  GrmPlan p;
+  rc = plan_grm(s, p);
+  if (rc != PG_OK) return rc;
+  if (entries == 0) return PG_OK;
+  if ((int64_t)workspace_bytes < p.bytes || !workspace)
+    return fail(PG_ENOMEM, "workspace of %llu bytes < %lld required",
+                (unsigned long long)workspace_bytes, (long long)p.bytes);
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  uint32_t* T = (uint32_t*)(ws + p.off_T);
+  mark_stage(0, st);
+  rc = launch_sample_major_2bit(s, T, p.rows_pad, p.words, st);
+  if (rc == PG_OK)
+    rc = launch_grm(s, T, p.rows_pad, p.words, (double*)(ws + p.off_z),
+                    (uint32_t*)(ws + p.off_used), grm, n_used, out_layout == PG_FULL, st);
   return rc;
 }
 

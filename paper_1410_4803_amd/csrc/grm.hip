@@ -1,0 +1,263 @@
+// Genomic relationship matrix (section "Partial sum lookup": a weighted
+// distance matrix as a sum of per-marker increments, with the GCTA
+// relationship increments (x - 2p)(y - 2p) / (2p(1-p)) as its example).
+//
+// The paper's CPU design precomputes, per marker, the increments of the seven
+// genotype-pair cases and adds table entries per pair.  Here the increment
+// factors: with z = (x - 2p) / sqrt(2p(1-p)) for a non-missing call and 0 for
+// a missing one, the numerator of every pair is a dot product over markers,
+//   S[i,j] = sum_v z[i,v] z[j,v],
+// i.e. one double-precision Gram matrix, run on the fp64 matrix cores
+// (v_mfma_f64_16x16x4_f64).  The operand is never materialised: tiles load
+// the packed 2-bit codes and look each call's z up in the marker's four-entry
+// table (indexed by the 2-bit code; code 1 = missing -> 0).  The denominator
+// N[i,j] (markers where both calls are present) is a popcount of AND-ed
+// non-missing masks, accumulated beside the fp64 sums.
+//
+// Markers whose increments are undefined (no call, or p equal to 0 or 1) are
+// treated as missing for every sample.
+#include "tiles.h"
+
+namespace pg {
+
+// ---- per-marker tables ---------------------------------------------------------
+// One wave per selected variant: counts over the selected samples, then
+// z for codes 0 (homozygous A1, x = 0), 2 (heterozygous, x = 1), 3
+// (homozygous A2, x = 2); missing and undefined -> 0.  used2 gets bit 2t of
+// word v/16 set (t = v % 16) for a variant with defined increments.
+__global__ __launch_bounds__(256) void k_grm_table(Sel s, int64_t nv_pad, double* __restrict__ ztab,
+                                                   uint32_t* __restrict__ used2) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; v < nv_pad;
+       v += ((int64_t)gridDim.x * blockDim.x) >> 6) {
+    int calls = 0, a2 = 0;
+    if (v < s.nv) {
+      for (int64_t k = lane; k < s.m; k += 64) {
+        const uint32_t c = code_at(s, v, k);
+        calls += c != 1u;
+        a2 += (int)(c >> 1) + (int)(c == 3u);   // 0 -> 0, 2 -> 1, 3 -> 2
+      }
+    }
+    for (int d = 32; d > 0; d >>= 1) {
+      calls += __shfl_xor(calls, d, 64);
+      a2 += __shfl_xor(a2, d, 64);
+    }
+    if (lane == 0) {
+      const bool used = calls > 0 && a2 > 0 && a2 < 2 * calls;
+      double z0 = 0.0, z1 = 0.0, z2 = 0.0;
+      if (used) {
+        const double p = __ddiv_rn((double)a2, (double)(2 * calls));
+        const double q = 1.0 - p;
+        const double inv = __ddiv_rn(1.0, __dsqrt_rn(__dmul_rn(2.0, __dmul_rn(p, q))));
+        const double tp = __dmul_rn(2.0, p);
+        z0 = __dmul_rn(-tp, inv);
+        z1 = __dmul_rn(__dsub_rn(1.0, tp), inv);
+        z2 = __dmul_rn(__dsub_rn(2.0, tp), inv);
+        atomicOr(&used2[v >> 4], 1u << (2 * (v & 15)));
+      }
+      double* t = ztab + v * 4;
+      t[0] = z0;
+      t[1] = 0.0;
+      t[2] = z1;
+      t[3] = z2;
+    }
+  }
+}
+
+// ---- the pair kernel ---------------------------------------------------------------
+// Block: 256 threads = 4 waves (2 x 2) over a 128 x 128 tile of sample pairs
+// (upper-triangle tiles only).  Each wave owns 64 x 64 = 4 x 4 blocks of
+// 16 x 16 fp64 accumulators.  K runs over variants in chunks of 64 (four
+// 2-bit words per sample): the loader stages both blocks' words (with
+// undefined markers overridden to missing), the chunk's z tables and each
+// row's 64-bit non-missing mask in LDS; the next chunk is fetched into
+// registers meanwhile.  v_mfma_f64_16x16x4_f64 operand layout: lane l holds
+// A[l % 16][l / 16] and B[l / 16][l % 16]; result register r of lane l is
+// D[l / 16 + 4 r][l % 16].
+constexpr int kGT = 128;          // samples per tile side
+constexpr int kGK = 64;           // variants per K chunk
+constexpr int kGKW = kGK / 16;    // 2-bit words per row per chunk
+
+typedef double grm_d4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) double lds_f64;
+typedef __attribute__((address_space(3))) uint64_t lds_u64;
+
+struct GrmOut {
+  double* grm;
+  uint32_t* n;
+  int64_t m;
+  int full;
+};
+
+// 16 codes -> 16-bit mask of non-missing calls (bit t <-> code t).
+__device__ __forceinline__ uint32_t present16(uint32_t w) {
+  uint32_t x = ~(w & ~(w >> 1)) & 0x55555555u;   // code != 01 at even bits
+  x = (x | (x >> 1)) & 0x33333333u;
+  x = (x | (x >> 2)) & 0x0f0f0f0fu;
+  x = (x | (x >> 4)) & 0x00ff00ffu;
+  x = (x | (x >> 8)) & 0x0000ffffu;
+  return x;
+}
+
+__global__ __launch_bounds__(256, 1) void k_grm_mfma(const uint32_t* __restrict__ T, int64_t wp,
+                                                     const double* __restrict__ ztab,
+                                                     const uint32_t* __restrict__ used2,
+                                                     int64_t nt, GrmOut o) {
+  // LDS (per buffer): codes of the I and J blocks [2][128][4] words, masks
+  // [2][128] uint64, z tables [64][4] doubles.
+  __shared__ uint32_t s_codes[2][2][kGT][kGKW];
+  __shared__ uint64_t s_mask[2][2][kGT];
+  __shared__ double s_z[2][kGK * 4];
+
+  int64_t I, J;
+  tri_tile(blockIdx.x, nt, I, J);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int nchunks = (int)(wp / kGKW);
+
+  // loader role: thread t stages row (t & 127) of block (t >> 7) and one
+  // double of the z table
+  const int lrow = tid & (kGT - 1), lblk = tid >> 7;
+  const int64_t grow = (lblk ? J : I) * kGT + lrow;
+  const uint4* src = reinterpret_cast<const uint4*>(T + grow * wp);
+  auto fetch = [&](int c, uint4& w, uint4& u, double& z) {
+    w = src[c];
+    u = reinterpret_cast<const uint4*>(used2)[c];
+    z = ztab[(int64_t)c * kGK * 4 + tid];
+  };
+  auto stage = [&](int buf, const uint4& w, const uint4& u, double z) {
+    // undefined markers read as missing (code 01)
+    const uint32_t ws[4] = {w.x, w.y, w.z, w.w}, us[4] = {u.x, u.y, u.z, u.w};
+    uint64_t mask = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const uint32_t undef = ~us[e] & 0x55555555u;
+      const uint32_t x = (ws[e] & ~(undef | (undef << 1))) | undef;
+      s_codes[buf][lblk][lrow][e] = x;
+      mask |= (uint64_t)present16(x) << (16 * e);
+    }
+    s_mask[buf][lblk][lrow] = mask;
+    s_z[buf][tid] = z;
+  };
+
+  grm_d4 acc[4][4];
+  uint32_t cnt[4][4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      acc[a][b] = grm_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) cnt[a][b][r] = 0;
+    }
+
+  uint4 pw, pu;
+  double pz;
+  if (nchunks > 0) {
+    fetch(0, pw, pu, pz);
+    stage(0, pw, pu, pz);
+  }
+  __syncthreads();
+  const int kq = lane >> 4;          // this lane's K index inside a step
+  const int r16 = lane & 15;
+  for (int c = 0; c < nchunks; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nchunks) fetch(c + 1, pw, pu, pz);
+    const lds_t* ci = (const lds_t*)&s_codes[buf][0][0][0];
+    const lds_t* cj = (const lds_t*)&s_codes[buf][1][0][0];
+    const lds_f64* zt = (const lds_f64*)&s_z[buf][0];
+#pragma unroll
+    for (int wd = 0; wd < kGKW; ++wd) {
+      uint32_t wa[4], wb[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        wa[q] = ci[(wr * 64 + q * 16 + r16) * kGKW + wd];
+        wb[q] = cj[(wc * 64 + q * 16 + r16) * kGKW + wd];
+      }
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const int t = st * 4 + kq;                 // variant inside the word
+        const int k = wd * 16 + t;                 // variant inside the chunk
+        double av[4], bv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          av[q] = zt[k * 4 + ((wa[q] >> (2 * t)) & 3u)];
+          bv[q] = zt[k * 4 + ((wb[q] >> (2 * t)) & 3u)];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+      }
+    }
+    // pair counts: rows l / 16 + 4 r of each 16-row block, column l % 16
+    {
+      const lds_u64* mi = (const lds_u64*)&s_mask[buf][0][0];
+      const lds_u64* mj = (const lds_u64*)&s_mask[buf][1][0];
+      uint64_t colm[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) colm[b] = mj[wc * 64 + b * 16 + r16];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const uint64_t rm = mi[wr * 64 + a * 16 + kq + 4 * r];
+#pragma unroll
+          for (int b = 0; b < 4; ++b) cnt[a][b][r] += (uint32_t)__popcll(rm & colm[b]);
+        }
+    }
+    if (c + 1 < nchunks) stage(buf ^ 1, pw, pu, pz);
+    __syncthreads();
+  }
+
+  // epilogue: A = S / N (NaN when N = 0)
+  const bool diag = I == J;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = I * kGT + wr * 64 + a * 16 + kq + 4 * r;
+        const int64_t j = J * kGT + wc * 64 + b * 16 + r16;
+        if (i >= o.m || j >= o.m) continue;
+        const uint32_t nn = cnt[a][b][r];
+        const double val = nn ? __ddiv_rn(acc[a][b][r], (double)nn)
+                              : __longlong_as_double(0x7ff8000000000000ll);
+        if (o.full) {
+          o.grm[i * o.m + j] = val;
+          o.n[i * o.m + j] = nn;
+          if (!diag) {
+            o.grm[j * o.m + i] = val;
+            o.n[j * o.m + i] = nn;
+          }
+        } else if (i < j) {
+          const int64_t idx = i * o.m - i * (i + 1) / 2 + (j - i - 1);
+          o.grm[idx] = val;
+          o.n[idx] = nn;
+        }
+      }
+}
+
+int launch_grm(const Sel& s, const uint32_t* T, int64_t rows_pad, int64_t wp, double* ztab,
+               uint32_t* used2, double* grm, uint32_t* n_used, int full, hipStream_t st) {
+  int rc = fill_u32(used2, wp, 0u, st);
+  if (rc != PG_OK) return rc;
+  const int64_t nv_pad = wp * 16;
+  const int64_t blocks = ceil_div(nv_pad, 4) < 65536 ? ceil_div(nv_pad, 4) : 65536;
+  hipLaunchKernelGGL(k_grm_table, dim3((unsigned)blocks), dim3(256), 0, st, s, nv_pad, ztab, used2);
+  rc = check_launch("grm_table");
+  mark_stage(1, st);
+  if (rc != PG_OK) return rc;
+  const int64_t nt = rows_pad / kGT;
+  const GrmOut o{grm, n_used, s.m, full};
+  hipLaunchKernelGGL(k_grm_mfma, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, st, T, wp,
+                     ztab, used2, nt, o);
+  rc = check_launch("grm_mfma");
+  mark_stage(2, st);
+  return rc;
+}
+
+}  // namespace pg

@@ -158,6 +158,12 @@ int launch_prune_greedy(const LdScratch& sc, const int2* stats, int64_t nv, int6
                         int64_t step, uint8_t* keep, int64_t* n_kept, hipStream_t st);
 constexpr int64_t kPruneMaxWindow = 1 << 16;
 
+// ---- relationship matrix (grm.hip) -------------------------------------------
+// Per-marker z tables and the fp64 matrix-core Gram over the sample-major
+// 2-bit operand T (rows_pad multiple of 128, wp multiple of 4 words).
+int launch_grm(const Sel& s, const uint32_t* T, int64_t rows_pad, int64_t wp, double* ztab,
+               uint32_t* used2, double* grm, uint32_t* n_used, int full, hipStream_t st);
+
 // r^2 from exact sums, as documented in pg.h; shared by every LD path so that
 // the emission decision and the emitted value are the same double.
 __device__ __forceinline__ double ld_r2(int64_t n, int64_t sx, int64_t sy, int64_t sxx,

@@ -87,7 +87,7 @@ int launch_variant_stats(const uint32_t* X, bool planes, int64_t words, int64_t 
 
 // ---- the greedy pass ----------------------------------------------------------
 constexpr int kPT = 1024;                 // threads of the one block
-constexpr int kPCells = 4;                // (window, row) cells per thread per pass
+constexpr int kPCells = 16;               // (window, row) cells per thread per pass
 constexpr int kPPass = kPT * kPCells;     // cells per pass
 constexpr int kRingBits = 1 << 18;        // keep bits held in LDS (32 KB)
 constexpr int kPBuf = 8192;               // pairs staged in LDS per slice (64 KB)

@@ -142,6 +142,24 @@ def prune_large(seed: int = 1006) -> dict:
                 r2_max=0.7, bed=mosaic(n, V, 8, 0.01, 0.001, 0.01, 0.0, seed))
 
 
+def grm_small(seed: int = 1007) -> dict:
+    """Relationship matrix, 1,000 samples x 76,124 variants (the size of the
+    paper's pruned 1,000-sample panel), founder mosaic (10 founders, switch
+    0.01), 1% missing; full matrix."""
+    n, V = 1000, 76124
+    return dict(name="grm_1000x76124_mosaic", n=n, V=V, layout="full",
+                bed=mosaic(n, V, 10, 0.01, 0.001, 0.01, 0.01, seed))
+
+
+def grm_large(seed: int = 1008) -> dict:
+    """Relationship matrix, 10,000 samples x 71,307 variants (the size of
+    the paper's pruned 10,000-sample panel), founder mosaic (8 founders,
+    switch 0.01), 1% missing; full matrix."""
+    n, V = 10000, 71307
+    return dict(name="grm_10000x71307_mosaic", n=n, V=V, layout="full",
+                bed=mosaic(n, V, 8, 0.01, 0.001, 0.01, 0.01, seed))
+
+
 def batch_problems(seed: int = 1003, count: int = 64, make_bed: bool = True) -> list:
     """Batched workload: `count` cohorts, samples log-uniform in [200, 20000],
     variants log-uniform in [2000, 50000], HWE MAF~U[0.01,0.5], 1% missing;

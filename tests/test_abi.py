@@ -180,3 +180,26 @@ def test_prune_workspace_and_validation():
     assert call(path=9) == N.PG_EINVAL
     assert call(ws=16) == N.PG_ENOMEM
     assert "workspace" in N.last_error()
+
+
+def test_grm_workspace_and_validation():
+    lib = N.load()
+    g = _g(10000, 71307)
+    b = ctypes.c_size_t(0)
+    assert lib.pg_grm_workspace_bytes(ctypes.byref(g), 0, 0, 0, ctypes.byref(b)) == 0
+    wp = -(-(-(-71307 // 16)) // 16) * 16
+    # sample-major 2-bit operand, four doubles per padded variant, one mask
+    # word per 16 variants (each piece aligned to 256 bytes)
+    assert b.value >= 10112 * wp * 4 + wp * 16 * 32 + wp * 4
+    fake = 0x2000
+    g2 = _g(100, 50)
+
+    def call(layout=N.PG_FULL, A=fake, n=fake, ws=1 << 30):
+        return lib.pg_grm_matrix(ctypes.byref(g2), None, 0, 0, 0, layout, A, n, fake, ws, None)
+    assert call(layout=7) == N.PG_EINVAL
+    assert call(A=None) == N.PG_EINVAL
+    assert call(n=None) == N.PG_EINVAL
+    assert call(ws=64) == N.PG_ENOMEM
+    g1 = _g(1, 50)
+    assert lib.pg_grm_matrix(ctypes.byref(g1), None, 0, 0, 0, N.PG_TRI_UPPER, None, None, None, 0,
+                             None) == N.PG_OK

@@ -106,3 +106,14 @@ def test_grm_triangle_layout_matches_full():
     At, Nt, _ = oracle.grm(codes, full=False)
     iu = np.triu_indices(n, 1)
     assert np.array_equal(At, A[iu]) and np.array_equal(Nt, N[iu])
+
+
+def test_grm_pair_list_matches_matrix():
+    n, V = 23, 150
+    codes = oracle.unpack(synth.hwe(n, V, (0.05, 0.5), 0.05, seed=7), n, V)
+    A, N, S = oracle.grm(codes, full=True)
+    rng = np.random.default_rng(3)
+    pi, pj = rng.integers(0, n, 40), rng.integers(0, n, 40)
+    Ap, Np, Sp = oracle.grm_pairs(np.ascontiguousarray(codes.T), pi, pj)
+    assert np.array_equal(Ap, A[pi, pj]) and np.array_equal(Np, N[pi, pj])
+    assert np.array_equal(Sp, S[pi, pj])
