@@ -70,6 +70,8 @@ def _load():
         lib.oracle_ld_prune.restype = i64
         lib.oracle_grm.argtypes = [p, i64, i64, i32, p, p, p]
         lib.oracle_grm.restype = None
+        lib.oracle_grm_pairs.argtypes = [p, i64, i64, p, p, i64, p, p, p]
+        lib.oracle_grm_pairs.restype = None
         lib.oracle_threads.argtypes = []
         lib.oracle_threads.restype = i32
         _lib = lib
@@ -206,4 +208,19 @@ def grm(codes_vm: np.ndarray, full: bool = True):
                        S.ctypes.data)
     if full:
         A, N, S = A.reshape(n, n), N.reshape(n, n), S.reshape(n, n)
+    return A, N, S
+
+
+def grm_pairs(codes_sm: np.ndarray, pi, pj):
+    """(A, N, abs_sum) of the relationship matrix for listed sample pairs;
+    codes_sm is (n, V) sample-major."""
+    n, V = codes_sm.shape
+    codes_sm = _c(codes_sm, np.int8)
+    pi = _c(pi, np.int64)
+    pj = _c(pj, np.int64)
+    A = np.zeros(len(pi), dtype=np.float64)
+    N = np.zeros(len(pi), dtype=np.uint32)
+    S = np.zeros(len(pi), dtype=np.float64)
+    _load().oracle_grm_pairs(codes_sm.ctypes.data, n, V, pi.ctypes.data, pj.ctypes.data, len(pi),
+                             A.ctypes.data, N.ctypes.data, S.ctypes.data)
     return A, N, S

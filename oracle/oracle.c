@@ -356,16 +356,9 @@ int64_t oracle_ld_prune(const int8_t* codes_vm, int64_t n, int64_t V, int64_t wi
  * oracle_ibs_matrix.  abs_sum (optional, same layout): the sum of the
  * increments' absolute values, for error bounds.
  */
-void oracle_grm(const int8_t* codes_sm, int64_t n, int64_t V, int full, double* A, uint32_t* N,
-                double* abs_sum) {
-  /* per-marker increment tables, indexed [marker][dosage_i][dosage_j] */
-  double* inc = (double*)malloc((size_t)V * 9 * sizeof(double));
-  uint8_t* used = (uint8_t*)malloc((size_t)V);
-  if (!inc || !used) {
-    free(inc);
-    free(used);
-    return;
-  }
+/* Fills the per-marker increment tables of the relationship matrix (see
+ * oracle_grm) and the markers' used flags. */
+static void grm_tables(const int8_t* codes_sm, int64_t n, int64_t V, double* inc, uint8_t* used) {
 #pragma omp parallel for schedule(static)
   for (int64_t v = 0; v < V; ++v) {
     int64_t calls = 0, a2 = 0;
@@ -382,26 +375,64 @@ void oracle_grm(const int8_t* codes_sm, int64_t n, int64_t V, int full, double* 
         inc[v * 9 + x * 3 + y] =
             used[v] ? ((double)x - 2.0 * p) * ((double)y - 2.0 * p) / (2.0 * p * (1.0 - p)) : 0.0;
   }
+}
+
+/* One pair's sum over markers of the table entries (markers left out or with
+ * a missing call skipped). */
+static void grm_pair(const int8_t* ci, const int8_t* cj, int64_t V, const double* inc,
+                     const uint8_t* used, double* A, uint32_t* N, double* abs_sum) {
+  double sum = 0.0, asum = 0.0;
+  uint32_t cnt = 0;
+  for (int64_t v = 0; v < V; ++v) {
+    if (!used[v] || ci[v] == MISSING || cj[v] == MISSING) continue;
+    const double t = inc[v * 9 + dosage(ci[v]) * 3 + dosage(cj[v])];
+    sum += t;
+    asum += fabs(t);
+    cnt += 1;
+  }
+  *A = cnt ? sum / (double)cnt : NAN;
+  *N = cnt;
+  if (abs_sum) *abs_sum = asum;
+}
+
+void oracle_grm(const int8_t* codes_sm, int64_t n, int64_t V, int full, double* A, uint32_t* N,
+                double* abs_sum) {
+  /* per-marker increment tables, indexed [marker][dosage_i][dosage_j] */
+  double* inc = (double*)malloc((size_t)V * 9 * sizeof(double));
+  uint8_t* used = (uint8_t*)malloc((size_t)V);
+  if (!inc || !used) {
+    free(inc);
+    free(used);
+    return;
+  }
+  grm_tables(codes_sm, n, V, inc, used);
 #pragma omp parallel for schedule(dynamic, 1)
   for (int64_t i = 0; i < n; ++i) {
-    const int8_t* ci = codes_sm + i * V;
     for (int64_t j = full ? 0 : i + 1; j < n; ++j) {
-      const int8_t* cj = codes_sm + j * V;
-      double sum = 0.0, asum = 0.0;
-      uint32_t cnt = 0;
-      for (int64_t v = 0; v < V; ++v) {
-        if (!used[v] || ci[v] == MISSING || cj[v] == MISSING) continue;
-        const double t = inc[v * 9 + dosage(ci[v]) * 3 + dosage(cj[v])];
-        sum += t;
-        asum += fabs(t);
-        cnt += 1;
-      }
       const int64_t idx = full ? i * n + j : i * n - i * (i + 1) / 2 + (j - i - 1);
-      A[idx] = cnt ? sum / (double)cnt : NAN;
-      N[idx] = cnt;
-      if (abs_sum) abs_sum[idx] = asum;
+      grm_pair(codes_sm + i * V, codes_sm + j * V, V, inc, used, A + idx, N + idx,
+               abs_sum ? abs_sum + idx : NULL);
     }
   }
+  free(inc);
+  free(used);
+}
+
+/* The relationship matrix entries of a list of sample pairs (pi[k], pj[k]). */
+void oracle_grm_pairs(const int8_t* codes_sm, int64_t n, int64_t V, const int64_t* pi,
+                      const int64_t* pj, int64_t npairs, double* A, uint32_t* N, double* abs_sum) {
+  double* inc = (double*)malloc((size_t)V * 9 * sizeof(double));
+  uint8_t* used = (uint8_t*)malloc((size_t)V);
+  if (!inc || !used) {
+    free(inc);
+    free(used);
+    return;
+  }
+  grm_tables(codes_sm, n, V, inc, used);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t k = 0; k < npairs; ++k)
+    grm_pair(codes_sm + pi[k] * V, codes_sm + pj[k] * V, V, inc, used, A + k, N + k,
+             abs_sum + k);
   free(inc);
   free(used);
 }
