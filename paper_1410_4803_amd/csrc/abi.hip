@@ -175,7 +175,7 @@ int plan_prune(const Sel& s, int32_t window, int32_t step, int path_arg, PrunePl
 
 struct GrmPlan {
   int64_t rows_pad, words;
-  int64_t off_T, off_z, off_used, bytes;
+  int64_t off_T, off_z, off_used, off_part, bytes;
 };
 
 int plan_grm(const Sel& s, GrmPlan& p) {
@@ -187,6 +187,7 @@ int plan_grm(const Sel& s, GrmPlan& p) {
   p.off_T = c.take(p.rows_pad * p.words * 4);
   p.off_z = c.take(p.words * 16 * 4 * 8);
   p.off_used = c.take(p.words * 4);
+  p.off_part = c.take(grm_part_bytes(p.rows_pad, p.words));
   p.bytes = c.off;
   return PG_OK;
 }
@@ -456,7 +457,8 @@ int pg_grm_matrix(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_se
   rc = launch_sample_major_2bit(s, T, p.rows_pad, p.words, st);
   if (rc == PG_OK)
     rc = launch_grm(s, T, p.rows_pad, p.words, (double*)(ws + p.off_z),
-                    (uint32_t*)(ws + p.off_used), grm, n_used, out_layout == PG_FULL, st);
+                    (uint32_t*)(ws + p.off_used), (double*)(ws + p.off_part), grm, n_used,
+                    out_layout == PG_FULL, st);
   return rc;
 }
 

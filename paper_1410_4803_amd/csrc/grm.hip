@@ -66,7 +66,9 @@ __global__ __launch_bounds__(256) void k_grm_table(Sel s, int64_t nv_pad, double
 
 // ---- the pair kernel ---------------------------------------------------------------
 // Block: 256 threads = 4 waves (2 x 2) over a 128 x 128 tile of sample pairs
-// (upper-triangle tiles only).  Each wave owns 64 x 64 = 4 x 4 blocks of
+// (upper-triangle tiles only) and one range of K chunks: when the tiles
+// alone cannot fill the chip, each tile's variants are split into ranges
+// whose partial sums a second kernel adds in a fixed order.  Each wave owns 64 x 64 = 4 x 4 blocks of
 // 16 x 16 fp64 accumulators.  K runs over variants in chunks of 64 (four
 // 2-bit words per sample): the loader stages both blocks' words (with
 // undefined markers overridden to missing), the chunk's z tables and each
@@ -87,7 +89,32 @@ struct GrmOut {
   uint32_t* n;
   int64_t m;
   int full;
+  int64_t n_tiles;      // upper-triangle tiles
+  int64_t n_split;      // K splits per tile (1: write the result directly)
+  int64_t cps;          // K chunks per split
+  double* part_s;       // n_split > 1: per (split, tile) 128 x 128 partial sums
+  uint32_t* part_n;     //   and partial counts
 };
+
+// Stores one entry (i, j) of tile (I, J): A = S / N (NaN when N = 0),
+// mirrored below the diagonal for the full layout.
+__device__ __forceinline__ void grm_store(const GrmOut& o, int64_t i, int64_t j, bool diag, double S,
+                                          uint32_t nn) {
+  if (i >= o.m || j >= o.m) return;
+  const double val = nn ? __ddiv_rn(S, (double)nn) : __longlong_as_double(0x7ff8000000000000ll);
+  if (o.full) {
+    o.grm[i * o.m + j] = val;
+    o.n[i * o.m + j] = nn;
+    if (!diag) {
+      o.grm[j * o.m + i] = val;
+      o.n[j * o.m + i] = nn;
+    }
+  } else if (i < j) {
+    const int64_t idx = i * o.m - i * (i + 1) / 2 + (j - i - 1);
+    o.grm[idx] = val;
+    o.n[idx] = nn;
+  }
+}
 
 // 16 codes -> 16-bit mask of non-missing calls (bit t <-> code t).
 __device__ __forceinline__ uint32_t present16(uint32_t w) {
@@ -109,12 +136,17 @@ __global__ __launch_bounds__(256, 1) void k_grm_mfma(const uint32_t* __restrict_
   __shared__ uint64_t s_mask[2][2][kGT];
   __shared__ double s_z[2][kGK * 4];
 
+  const int64_t tile = blockIdx.x % o.n_tiles;
+  const int64_t split = blockIdx.x / o.n_tiles;
   int64_t I, J;
-  tri_tile(blockIdx.x, nt, I, J);
+  tri_tile(tile, nt, I, J);
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
-  const int nchunks = (int)(wp / kGKW);
+  // this block's K chunks: [c_begin, c_end)
+  const int64_t all_chunks = wp / kGKW;
+  const int c_begin = (int)(split * o.cps);
+  const int c_end = (int)((split + 1) * o.cps < all_chunks ? (split + 1) * o.cps : all_chunks);
 
   // loader role: thread t stages row (t & 127) of block (t >> 7) and one
   // double of the z table
@@ -154,16 +186,16 @@ __global__ __launch_bounds__(256, 1) void k_grm_mfma(const uint32_t* __restrict_
 
   uint4 pw, pu;
   double pz;
-  if (nchunks > 0) {
-    fetch(0, pw, pu, pz);
+  if (c_begin < c_end) {
+    fetch(c_begin, pw, pu, pz);
     stage(0, pw, pu, pz);
   }
   __syncthreads();
   const int kq = lane >> 4;          // this lane's K index inside a step
   const int r16 = lane & 15;
-  for (int c = 0; c < nchunks; ++c) {
-    const int buf = c & 1;
-    if (c + 1 < nchunks) fetch(c + 1, pw, pu, pz);
+  for (int c = c_begin; c < c_end; ++c) {
+    const int buf = (c - c_begin) & 1;
+    if (c + 1 < c_end) fetch(c + 1, pw, pu, pz);
     const lds_t* ci = (const lds_t*)&s_codes[buf][0][0][0];
     const lds_t* cj = (const lds_t*)&s_codes[buf][1][0][0];
     const lds_f64* zt = (const lds_f64*)&s_z[buf][0];
@@ -208,11 +240,11 @@ __global__ __launch_bounds__(256, 1) void k_grm_mfma(const uint32_t* __restrict_
           for (int b = 0; b < 4; ++b) cnt[a][b][r] += (uint32_t)__popcll(rm & colm[b]);
         }
     }
-    if (c + 1 < nchunks) stage(buf ^ 1, pw, pu, pz);
+    if (c + 1 < c_end) stage(buf ^ 1, pw, pu, pz);
     __syncthreads();
   }
 
-  // epilogue: A = S / N (NaN when N = 0)
+  // epilogue: the result, or this split's partial sums and counts
   const bool diag = I == J;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
@@ -220,29 +252,41 @@ __global__ __launch_bounds__(256, 1) void k_grm_mfma(const uint32_t* __restrict_
     for (int b = 0; b < 4; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t i = I * kGT + wr * 64 + a * 16 + kq + 4 * r;
-        const int64_t j = J * kGT + wc * 64 + b * 16 + r16;
-        if (i >= o.m || j >= o.m) continue;
-        const uint32_t nn = cnt[a][b][r];
-        const double val = nn ? __ddiv_rn(acc[a][b][r], (double)nn)
-                              : __longlong_as_double(0x7ff8000000000000ll);
-        if (o.full) {
-          o.grm[i * o.m + j] = val;
-          o.n[i * o.m + j] = nn;
-          if (!diag) {
-            o.grm[j * o.m + i] = val;
-            o.n[j * o.m + i] = nn;
-          }
-        } else if (i < j) {
-          const int64_t idx = i * o.m - i * (i + 1) / 2 + (j - i - 1);
-          o.grm[idx] = val;
-          o.n[idx] = nn;
+        const int il = wr * 64 + a * 16 + kq + 4 * r;
+        const int jl = wc * 64 + b * 16 + r16;
+        if (o.n_split == 1) {
+          grm_store(o, I * kGT + il, J * kGT + jl, diag, acc[a][b][r], cnt[a][b][r]);
+        } else {
+          const int64_t e = ((split * o.n_tiles + tile) * kGT + il) * kGT + jl;
+          o.part_s[e] = acc[a][b][r];
+          o.part_n[e] = cnt[a][b][r];
         }
       }
 }
 
+// Sums the K splits of every tile entry in split order, then stores it.
+__global__ __launch_bounds__(256) void k_grm_reduce(int64_t nt, GrmOut o) {
+  const int64_t per_tile = (int64_t)kGT * kGT;
+  const int64_t total = o.n_tiles * per_tile;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t tile = e / per_tile;
+    const int il = (int)((e % per_tile) / kGT), jl = (int)(e % kGT);
+    double S = 0.0;
+    uint32_t nn = 0;
+    for (int64_t sp = 0; sp < o.n_split; ++sp) {
+      S = __dadd_rn(S, o.part_s[sp * total + e]);
+      nn += o.part_n[sp * total + e];
+    }
+    int64_t I, J;
+    tri_tile(tile, nt, I, J);
+    grm_store(o, I * kGT + il, J * kGT + jl, I == J, S, nn);
+  }
+}
+
 int launch_grm(const Sel& s, const uint32_t* T, int64_t rows_pad, int64_t wp, double* ztab,
-               uint32_t* used2, double* grm, uint32_t* n_used, int full, hipStream_t st) {
+               uint32_t* used2, double* part, double* grm, uint32_t* n_used, int full,
+               hipStream_t st) {
   int rc = fill_u32(used2, wp, 0u, st);
   if (rc != PG_OK) return rc;
   const int64_t nv_pad = wp * 16;
@@ -252,10 +296,21 @@ int launch_grm(const Sel& s, const uint32_t* T, int64_t rows_pad, int64_t wp, do
   mark_stage(1, st);
   if (rc != PG_OK) return rc;
   const int64_t nt = rows_pad / kGT;
-  const GrmOut o{grm, n_used, s.m, full};
-  hipLaunchKernelGGL(k_grm_mfma, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, st, T, wp,
+  const int64_t n_tiles = nt * (nt + 1) / 2;
+  int64_t n_split, cps;
+  grm_split(rows_pad, wp, n_split, cps);
+  const int64_t part_entries = n_split > 1 ? n_split * n_tiles * kGT * kGT : 0;
+  const GrmOut o{grm, n_used, s.m, full, n_tiles, n_split, cps, part,
+                 (uint32_t*)(part + part_entries)};
+  hipLaunchKernelGGL(k_grm_mfma, dim3((unsigned)(n_tiles * n_split)), dim3(256), 0, st, T, wp,
                      ztab, used2, nt, o);
   rc = check_launch("grm_mfma");
+  if (rc == PG_OK && n_split > 1) {
+    const int64_t blocks = ceil_div(n_tiles * kGT * kGT, 256);
+    hipLaunchKernelGGL(k_grm_reduce, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256),
+                       0, st, nt, o);
+    rc = check_launch("grm_reduce");
+  }
   mark_stage(2, st);
   return rc;
 }

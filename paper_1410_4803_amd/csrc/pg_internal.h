@@ -161,8 +161,28 @@ constexpr int64_t kPruneMaxWindow = 1 << 16;
 // ---- relationship matrix (grm.hip) -------------------------------------------
 // Per-marker z tables and the fp64 matrix-core Gram over the sample-major
 // 2-bit operand T (rows_pad multiple of 128, wp multiple of 4 words).
+// `part` holds the K-split partial sums and counts (grm_part_bytes).
 int launch_grm(const Sel& s, const uint32_t* T, int64_t rows_pad, int64_t wp, double* ztab,
-               uint32_t* used2, double* grm, uint32_t* n_used, int full, hipStream_t st);
+               uint32_t* used2, double* part, double* grm, uint32_t* n_used, int full,
+               hipStream_t st);
+// K split of the relationship-matrix kernel: with fewer than 512
+// upper-triangle tiles of 128 samples, each tile's K chunks of 64 variants
+// are split into up to 16 ranges of at least 16 chunks.
+inline void grm_split(int64_t rows_pad, int64_t wp, int64_t& n_split, int64_t& cps) {
+  const int64_t nt = rows_pad / 128, tiles = nt * (nt + 1) / 2, chunks = wp / 4;
+  int64_t want = ceil_div(512, tiles);
+  if (want > 16) want = 16;
+  if (want > chunks / 16) want = chunks / 16;
+  if (want < 1) want = 1;
+  cps = ceil_div(chunks, want);
+  n_split = chunks > 0 ? ceil_div(chunks, cps) : 1;
+}
+inline int64_t grm_part_bytes(int64_t rows_pad, int64_t wp) {
+  int64_t n_split, cps;
+  grm_split(rows_pad, wp, n_split, cps);
+  const int64_t nt = rows_pad / 128;
+  return n_split > 1 ? n_split * (nt * (nt + 1) / 2) * 128 * 128 * (8 + 4) : 0;
+}
 
 // r^2 from exact sums, as documented in pg.h; shared by every LD path so that
 // the emission decision and the emitted value are the same double.

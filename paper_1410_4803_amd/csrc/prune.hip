@@ -14,7 +14,7 @@
 // window only has to visit its new pairs (b in [s_{w-1} + W, s_w + W)), in
 // (a, b) order.  One block walks the (window, row) cells in that order:
 // all threads extract a slice of marked pairs from the bitmap into LDS
-// (with the drop side decided from the allele counts), then one thread
+// (with the drop side decided from the allele counts), then one wave
 // applies them in order to a ring of keep bits in LDS; variants no later
 // window can touch are flushed to the output as the windows advance.
 #include "pg_internal.h"
@@ -88,6 +88,7 @@ int launch_variant_stats(const uint32_t* X, bool planes, int64_t words, int64_t 
 // ---- the greedy pass ----------------------------------------------------------
 constexpr int kPT = 1024;                 // threads of the one block
 constexpr int kPCells = 16;               // (window, row) cells per thread per pass
+constexpr int kPGroup = 8;                // cells whose loads are issued together
 constexpr int kPPass = kPT * kPCells;     // cells per pass
 constexpr int kRingBits = 1 << 18;        // keep bits held in LDS (32 KB)
 constexpr int kPBuf = 8192;               // pairs staged in LDS per slice (64 KB)
@@ -96,32 +97,34 @@ struct PruneGeom {
   int64_t nv, W, S;
 };
 
-// Cell c = (window w, row r): variant a = w*S + r and the bitmap bits
-// [j0, j1) of row a (bit j <-> b = a + 1 + j) holding window w's new pairs.
-__device__ __forceinline__ bool cell_bits(const PruneGeom& g, int64_t c, int64_t& a, int64_t& j0,
-                                          int64_t& j1) {
-  const int64_t w = c / g.W;
+// Bits [j0, j1) of row a of the bitmap (bit j <-> b = a + 1 + j) that hold
+// window w's new pairs, for the cell (window w, row r), a = w*S + r; empty
+// (j0 == j1) when the cell has none.
+__device__ __forceinline__ void cell_bits(const PruneGeom& g, int64_t w, int r, int& a, int& j0,
+                                          int& j1) {
   const int64_t s = w * g.S;
-  a = s + (c - w * g.W);
+  const int64_t av = s + r;
   const int64_t hi = s + g.W < g.nv ? s + g.W : g.nv;
-  if (a + 1 >= hi) return false;
+  a = (int)av;
+  j0 = j1 = 0;
+  if (av + 1 >= hi) return;
   const int64_t lo = w == 0 ? 0 : (g.W > g.S ? s - g.S + g.W : s);
-  const int64_t d0 = lo - a > 1 ? lo - a : 1;
-  const int64_t d1 = hi - a;
-  if (d0 >= d1) return false;
-  j0 = d0 - 1;
-  j1 = d1 - 1;
-  return true;
+  const int64_t d0 = lo - av > 1 ? lo - av : 1;
+  const int64_t d1 = hi - av;
+  if (d0 >= d1) return;
+  j0 = (int)(d0 - 1);
+  j1 = (int)(d1 - 1);
 }
 
-// Word q of a row restricted to bits [j0, j1).
-__device__ __forceinline__ uint32_t seg_word(const uint32_t* row, int64_t q, int64_t j0,
-                                             int64_t j1) {
-  uint32_t x = row[q];
-  const int64_t b0 = q * 32;
+// Bitmap word x (word q of its row) restricted to bits [j0, j1).
+__device__ __forceinline__ uint32_t seg_bits(uint32_t x, int q, int j0, int j1) {
+  const int b0 = q * 32;
   if (j0 > b0) x &= ~0u << (j0 - b0);
   if (j1 < b0 + 32) x &= (1u << (j1 - b0)) - 1u;
   return x;
+}
+__device__ __forceinline__ uint32_t seg_word(const uint32_t* row, int q, int j0, int j1) {
+  return seg_bits(row[q], q, j0, j1);
 }
 
 // Exclusive scan over the block; *total gets the block sum.
@@ -149,16 +152,52 @@ __device__ __forceinline__ int block_scan(int v, int* wsum, int* total) {
   return base + x - v;
 }
 
+// Applies staged pairs buf[0, n) in order to the keep ring; wave 0 only.
+// 64 pairs at a time: one LDS round trip reads both keep bits of every pair
+// of the batch; the pairs are then taken one by one with lane reads, and a
+// variant dropped earlier in the same batch (held in the dropping pair's
+// lane) is found with one ballot.  The batch's drops are written back
+// before the next batch reads the ring (LDS operations of one wave complete
+// in order).
+__device__ __forceinline__ void apply_pairs(const uint2* buf, int n, uint32_t* ring, int lane) {
+  for (int p0 = 0; p0 < n; p0 += 64) {
+    const int np = n - p0 < 64 ? n - p0 : 64;
+    uint32_t ea = 0, eb = 0, da = 0, live = 0;
+    if (lane < np) {
+      const uint2 e = buf[p0 + lane];
+      ea = e.x;
+      eb = e.y & 0x7fffffffu;
+      da = e.y >> 31;
+      const uint32_t ia = ea & (kRingBits - 1), ib = eb & (kRingBits - 1);
+      live = (ring[ia >> 5] >> (ia & 31)) & (ring[ib >> 5] >> (ib & 31)) & 1u;
+    }
+    int dropped = -1;
+    for (int p = 0; p < np; ++p) {
+      if (!__builtin_amdgcn_readlane(live, p)) continue;
+      const int a = __builtin_amdgcn_readlane(ea, p);
+      const int b = __builtin_amdgcn_readlane(eb, p);
+      if (__ballot(dropped == a || dropped == b)) continue;
+      const int x = __builtin_amdgcn_readlane(da, p) ? a : b;
+      if (lane == p) dropped = x;
+    }
+    if (dropped >= 0) {
+      const uint32_t ix = (uint32_t)dropped & (kRingBits - 1);
+      atomicAnd(&ring[ix >> 5], ~(1u << (ix & 31)));
+    }
+  }
+}
+
 __global__ __launch_bounds__(kPT) void k_prune_greedy(const uint32_t* __restrict__ bitmap,
                                                       int64_t bm_words,
                                                       const int2* __restrict__ stats,
-                                                      PruneGeom g, int64_t n_cells,
+                                                      PruneGeom g, int64_t n_windows,
                                                       uint8_t* __restrict__ keep,
                                                       int64_t* __restrict__ n_kept) {
   __shared__ uint32_t ring[kRingBits / 32];
   __shared__ uint2 buf[kPBuf];
   __shared__ int wsum[kPT / 64];
   const int tid = threadIdx.x;
+  const int lane = tid & 63;
   for (int i = tid; i < kRingBits / 32; i += kPT) ring[i] = ~0u;
   __syncthreads();
   int64_t flushed = 0;
@@ -175,18 +214,53 @@ __global__ __launch_bounds__(kPT) void k_prune_greedy(const uint32_t* __restrict
     flushed = to;
     __syncthreads();
   };
+  const int W = (int)g.W;
+  const int64_t n_cells = n_windows * g.W;
   for (int64_t c0 = 0; c0 < n_cells; c0 += kPPass) {
     // variants before the first window of this pass are final
     const int64_t w_first = c0 / g.W;
     flush(w_first * g.S < g.nv ? w_first * g.S : g.nv);
+    // this thread's kPCells consecutive cells, as (window, row), then bits
+    const int rr = (int)(c0 - w_first * g.W) + tid * kPCells;
+    const int64_t w_start = w_first + rr / W;
+    const int r_start = rr % W;
+    // count: per group of kPGroup cells, the first two words of every
+    // segment are loaded together (one memory latency per group)
     int cnt = 0;
-    for (int k = 0; k < kPCells; ++k) {
-      int64_t a, j0, j1;
-      const int64_t c = c0 + (int64_t)tid * kPCells + k;
-      if (c >= n_cells || !cell_bits(g, c, a, j0, j1)) continue;
-      const uint32_t* row = bitmap + a * bm_words;
-      for (int64_t q = j0 >> 5; q <= (j1 - 1) >> 5; ++q)
-        cnt += __builtin_popcount(seg_word(row, q, j0, j1));
+    {
+      int64_t w = w_start;
+      int r = r_start;
+#pragma unroll
+      for (int kb = 0; kb < kPCells; kb += kPGroup) {
+        int ga[kPGroup], gj0[kPGroup], gj1[kPGroup];
+        uint32_t g0[kPGroup], g1[kPGroup];
+#pragma unroll
+        for (int k = 0; k < kPGroup; ++k) {
+          ga[k] = gj0[k] = gj1[k] = 0;
+          if (w < n_windows) cell_bits(g, w, r, ga[k], gj0[k], gj1[k]);
+          if (++r == W) {
+            r = 0;
+            ++w;
+          }
+          g0[k] = g1[k] = 0;
+          if (gj0[k] < gj1[k]) {
+            const uint32_t* row = bitmap + (int64_t)ga[k] * bm_words;
+            const int q0 = gj0[k] >> 5;
+            g0[k] = row[q0];
+            if (q0 + 1 <= (gj1[k] - 1) >> 5) g1[k] = row[q0 + 1];
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < kPGroup; ++k) {
+          if (gj0[k] >= gj1[k]) continue;
+          const int q0 = gj0[k] >> 5, qn = (gj1[k] - 1) >> 5;
+          cnt += __builtin_popcount(seg_bits(g0[k], q0, gj0[k], gj1[k]));
+          if (q0 + 1 <= qn) cnt += __builtin_popcount(seg_bits(g1[k], q0 + 1, gj0[k], gj1[k]));
+          const uint32_t* row = bitmap + (int64_t)ga[k] * bm_words;
+          for (int q = q0 + 2; q <= qn; ++q)
+            cnt += __builtin_popcount(seg_word(row, q, gj0[k], gj1[k]));
+        }
+      }
     }
     int total;
     const int base = block_scan(cnt, wsum, &total);
@@ -194,50 +268,66 @@ __global__ __launch_bounds__(kPT) void k_prune_greedy(const uint32_t* __restrict
       const int s1 = s0 + kPBuf < total ? s0 + kPBuf : total;
       if (base < s1 && base + cnt > s0) {
         int pos = base;
-        for (int k = 0; k < kPCells && pos < s1; ++k) {
-          int64_t a, j0, j1;
-          const int64_t c = c0 + (int64_t)tid * kPCells + k;
-          if (c >= n_cells || !cell_bits(g, c, a, j0, j1)) continue;
-          const uint32_t* row = bitmap + a * bm_words;
-          const int2 sa = stats[a];
-          for (int64_t q = j0 >> 5; q <= (j1 - 1) >> 5 && pos < s1; ++q) {
-            uint32_t bits = seg_word(row, q, j0, j1);
-            while (bits && pos < s1) {
-              const int t = __builtin_ctz(bits);
-              bits &= bits - 1;
-              if (pos >= s0) {
-                const int64_t b = a + 1 + q * 32 + t;
-                const int2 sb = stats[b];
-                // drop a when its minor allele frequency is strictly lower
-                const bool drop_a = (int64_t)sa.x * sb.y < (int64_t)sb.x * sa.y;
-                buf[pos - s0] = make_uint2((uint32_t)a, (uint32_t)b | (drop_a ? 0x80000000u : 0u));
+        int64_t w = w_start;
+        int r = r_start;
+        for (int kb = 0; kb < kPCells && pos < s1; kb += kPGroup) {
+          int ga[kPGroup], gj0[kPGroup], gj1[kPGroup];
+          uint32_t g0[kPGroup], g1[kPGroup];
+          int2 gs[kPGroup];
+#pragma unroll
+          for (int k = 0; k < kPGroup; ++k) {
+            ga[k] = gj0[k] = gj1[k] = 0;
+            if (w < n_windows) cell_bits(g, w, r, ga[k], gj0[k], gj1[k]);
+            if (++r == W) {
+              r = 0;
+              ++w;
+            }
+            g0[k] = g1[k] = 0;
+            gs[k] = make_int2(0, 1);
+            if (gj0[k] < gj1[k]) {
+              const uint32_t* row = bitmap + (int64_t)ga[k] * bm_words;
+              const int q0 = gj0[k] >> 5;
+              g0[k] = row[q0];
+              if (q0 + 1 <= (gj1[k] - 1) >> 5) g1[k] = row[q0 + 1];
+              gs[k] = stats[ga[k]];
+            }
+          }
+#pragma unroll
+          for (int k = 0; k < kPGroup; ++k) {
+            if (gj0[k] >= gj1[k] || pos >= s1) continue;
+            const int a = ga[k];
+            const uint32_t* row = bitmap + (int64_t)a * bm_words;
+            const int2 sa = gs[k];
+            const int q0 = gj0[k] >> 5, qn = (gj1[k] - 1) >> 5;
+            for (int q = q0; q <= qn && pos < s1; ++q) {
+              uint32_t bits = seg_bits(q == q0 ? g0[k] : q == q0 + 1 ? g1[k] : row[q], q, gj0[k],
+                                       gj1[k]);
+              while (bits && pos < s1) {
+                const int t = __builtin_ctz(bits);
+                bits &= bits - 1;
+                if (pos >= s0) {
+                  const int b = a + 1 + q * 32 + t;
+                  const int2 sb = stats[b];
+                  // drop a when its minor allele frequency is strictly lower
+                  const bool drop_a = (int64_t)sa.x * sb.y < (int64_t)sb.x * sa.y;
+                  buf[pos - s0] =
+                      make_uint2((uint32_t)a, (uint32_t)b | (drop_a ? 0x80000000u : 0u));
+                }
+                ++pos;
               }
-              ++pos;
             }
           }
         }
       }
       __syncthreads();
-      if (tid == 0) {
-        for (int p = 0; p < s1 - s0; ++p) {
-          const uint2 e = buf[p];
-          const uint32_t ia = e.x & (kRingBits - 1);
-          const uint32_t ib = (e.y & 0x7fffffffu) & (kRingBits - 1);
-          const uint32_t alive = (ring[ia >> 5] >> (ia & 31)) & (ring[ib >> 5] >> (ib & 31)) & 1u;
-          if (alive) {
-            const uint32_t x = (e.y >> 31) ? ia : ib;
-            ring[x >> 5] &= ~(1u << (x & 31));
-          }
-        }
-      }
+      if (tid < 64) apply_pairs(buf, s1 - s0, ring, lane);
       __syncthreads();
     }
   }
   flush(g.nv);
   // block sum of the kept counts
-  int k32 = (int)kept;
   int total;
-  block_scan(k32, wsum, &total);
+  block_scan((int)kept, wsum, &total);
   if (tid == 0 && n_kept) *n_kept = total;
 }
 
@@ -246,7 +336,7 @@ int launch_prune_greedy(const LdScratch& sc, const int2* stats, int64_t nv, int6
   const int64_t n_windows = nv <= window ? 1 : ceil_div(nv - window, step) + 1;
   const PruneGeom g{nv, window, step};
   hipLaunchKernelGGL(k_prune_greedy, dim3(1), dim3(kPT), 0, st, sc.bitmap, sc.bm_words, stats, g,
-                     n_windows * window, keep, n_kept);
+                     n_windows, keep, n_kept);
   return check_launch("prune_greedy");
 }
 
