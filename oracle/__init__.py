@@ -5,8 +5,9 @@ The plain definitions of the IBS and LD statistics of Chang et al. 2015
 and section "Bit population count" (r between two markers with missing
 data), the greedy LD pruning of section "Linkage disequilibrium-based
 variant pruning" and the genomic relationship matrix of section "Partial sum
-lookup" (under the readings stated in ``oracle.c``), written over unpacked
-genotype codes in ``oracle.c``.
+lookup", and the IBS distance with complete-linkage clustering of section
+"Identity-by-state matrices, complete linkage clustering" (under the readings
+stated in ``oracle.c``), written in ``oracle.c``.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's CPU-baseline
 leg may import this package.  It shares no code with the GPU library
@@ -72,6 +73,10 @@ def _load():
         lib.oracle_grm.restype = None
         lib.oracle_grm_pairs.argtypes = [p, i64, i64, p, p, i64, p, p, p]
         lib.oracle_grm_pairs.restype = None
+        lib.oracle_ibs_distance.argtypes = [p, p, p, i64, p]
+        lib.oracle_ibs_distance.restype = None
+        lib.oracle_cluster_complete.argtypes = [p, i64, p]
+        lib.oracle_cluster_complete.restype = i32
         lib.oracle_threads.argtypes = []
         lib.oracle_threads.restype = i32
         _lib = lib
@@ -224,3 +229,27 @@ def grm_pairs(codes_sm: np.ndarray, pi, pj):
     _load().oracle_grm_pairs(codes_sm.ctypes.data, n, V, pi.ctypes.data, pj.ctypes.data, len(pi),
                              A.ctypes.data, N.ctypes.data, S.ctypes.data)
     return A, N, S
+
+
+MERGE = np.dtype([("a", "<i4"), ("b", "<i4"), ("height", "<f8")])
+assert MERGE.itemsize == 16
+
+
+def ibs_distance(ibs0, ibs1, nonmiss) -> np.ndarray:
+    """(2*IBS0 + IBS1) / (2*N) elementwise (+inf where N = 0), same shape."""
+    i0, i1, nm = (_c(x, np.uint32) for x in (ibs0, ibs1, nonmiss))
+    out = np.zeros(i0.shape, dtype=np.float64)
+    _load().oracle_ibs_distance(i0.ctypes.data, i1.ctypes.data, nm.ctypes.data, i0.size,
+                                out.ctypes.data)
+    return out
+
+
+def cluster_complete(dist: np.ndarray) -> np.ndarray:
+    """Complete-linkage merge sequence (m-1 MERGE records) of an m x m
+    distance matrix; ties by the smallest (a, b)."""
+    d = _c(dist, np.float64)
+    m = d.shape[0]
+    out = np.zeros(max(m - 1, 1), dtype=MERGE)
+    if _load().oracle_cluster_complete(d.ctypes.data, m, out.ctypes.data) != 0:
+        raise MemoryError("oracle_cluster_complete")
+    return out[:m - 1]

@@ -436,3 +436,76 @@ void oracle_grm_pairs(const int8_t* codes_sm, int64_t n, int64_t V, const int64_
   free(inc);
   free(used);
 }
+
+/*
+ * IBS distance between two samples (the --distance / --cluster input the
+ * paper times in Table 2; it names the statistic but not its formula).
+ * Reading: the proportion of alleles not shared identical by state over the
+ * jointly non-missing markers, d = (2*IBS0 + IBS1) / (2*N), i.e. one minus
+ * the IBS similarity (IBS2 + IBS1/2) / N; +infinity when N = 0.  Both counts
+ * are integers, so d is their correctly rounded quotient.
+ */
+void oracle_ibs_distance(const uint32_t* ibs0, const uint32_t* ibs1, const uint32_t* nonmiss,
+                         int64_t count, double* d) {
+#pragma omp parallel for schedule(static)
+  for (int64_t e = 0; e < count; ++e)
+    d[e] = nonmiss[e] ? (double)(2 * (int64_t)ibs0[e] + ibs1[e]) / (double)(2 * (int64_t)nonmiss[e])
+                      : INFINITY;
+}
+
+/*
+ * Complete-linkage agglomerative clustering of m samples from their m x m
+ * distance matrix (section "Identity-by-state matrices, complete linkage
+ * clustering").  Plain definition: while more than one cluster remains,
+ * merge the two clusters whose largest member-to-member distance is
+ * smallest; ties go to the pair with the smallest first, then second,
+ * cluster index.  A cluster is indexed by its smallest sample index.
+ * merges[t] = {a, b, height} for step t (a < b, the two clusters' indices;
+ * the merged cluster is a).  O(m^3); dist is not modified.
+ */
+typedef struct {
+  int32_t a, b;
+  double height;
+} oracle_merge;
+
+int oracle_cluster_complete(const double* dist, int64_t m, oracle_merge* merges) {
+  double* d = (double*)malloc((size_t)(m * m) * sizeof(double));
+  uint8_t* active = (uint8_t*)malloc((size_t)m);
+  if (!d || !active) {
+    free(d);
+    free(active);
+    return -1;
+  }
+  memcpy(d, dist, (size_t)(m * m) * sizeof(double));
+  for (int64_t i = 0; i < m; ++i) active[i] = 1;
+  for (int64_t t = 0; t + 1 < m; ++t) {
+    int64_t bi = -1, bj = -1;
+    double best = 0.0;
+    for (int64_t i = 0; i < m; ++i) {
+      if (!active[i]) continue;
+      for (int64_t j = i + 1; j < m; ++j) {
+        if (!active[j]) continue;
+        if (bi < 0 || d[i * m + j] < best) {
+          best = d[i * m + j];
+          bi = i;
+          bj = j;
+        }
+      }
+    }
+    merges[t].a = (int32_t)bi;
+    merges[t].b = (int32_t)bj;
+    merges[t].height = best;
+    /* complete linkage: the merged cluster's distance to k is the larger of
+     * the two */
+    for (int64_t k = 0; k < m; ++k) {
+      if (!active[k] || k == bi || k == bj) continue;
+      const double v = d[bi * m + k] > d[bj * m + k] ? d[bi * m + k] : d[bj * m + k];
+      d[bi * m + k] = v;
+      d[k * m + bi] = v;
+    }
+    active[bj] = 0;
+  }
+  free(d);
+  free(active);
+  return 0;
+}
