@@ -207,6 +207,37 @@ def bench_grm(torch, lib, hip, pg, wg, dev, steps):
                          "frac": round(ach / PEAK_FP64_TFLOPS, 4)}}
 
 
+def bench_cluster(torch, lib, hip, pg, wc, dev, steps):
+    """IBS matrix (full) then complete-linkage clustering of all samples; the
+    clustering call is timed on its own (its input is the IBS result)."""
+    n = wc["n"]
+    c = pg.Cohort.from_numpy(wc["bed"], n, device=dev)
+    counts = pg.ibs_matrix(c, layout="full")
+    out = torch.empty((n - 1, 16), dtype=torch.uint8, device=dev)
+    ws = torch.empty(pg.cluster_workspace_bytes(n), dtype=torch.uint8, device=dev)
+    ms, st = timed_steps(torch, lib, hip, lambda: pg.ibs_cluster(*counts, out=out, workspace=ws),
+                         steps, 1, 3)
+    merges = pg.merges_to_numpy(out, n)
+    assert (merges["a"] < merges["b"]).all()
+    return {"workload": wc["name"], "samples": n, "ms_per_call": round(ms, 3),
+            "unit": "ms", "merges_per_s": round((n - 1) / (ms * 1e-3), 1),
+            "stages_ms": {"distances_and_neighbours": round(mean(st[0]), 3),
+                          "merge_loop": round(mean(st[1]), 3)}}
+
+
+def cpu_baseline_cluster(wc):
+    """The oracle's O(m^3) complete linkage on the same distances."""
+    import oracle
+    codes = oracle.unpack(wc["bed"], wc["n"], wc["V"])
+    i0, i1, _, nm = oracle.ibs_matrix(codes, full=True)
+    d = oracle.ibs_distance(i0, i1, nm)
+    t0 = time.perf_counter()
+    oracle.cluster_complete(d)
+    dt = time.perf_counter() - t0
+    return {"value": round(dt * 1e3, 1), "unit": "ms", "cores": 1, "kind": "oracle",
+            "sample": "clustering of the whole workload (distances given)"}
+
+
 def cpu_baseline_prune(wp):
     """The oracle's pruning on the whole workload (OpenMP r^2 table, then its
     sequential greedy pass)."""
@@ -351,7 +382,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--quick", action="store_true", help="default workload only, no extras")
     ap.add_argument("--extras", default="all",
-                    help="comma list of extras: other,small,ld,prune,grm,batch,serve (or all / none)")
+                    help="comma list of extras: other,small,ld,prune,grm,cluster,batch,serve "
+                         "(or all / none)")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serial-seconds", type=float, default=15.0)
@@ -434,7 +466,7 @@ def main():
     extras = {}
     want = set()
     if not args.quick:
-        everything = {"other", "small", "ld", "prune", "grm", "batch", "serve"}
+        everything = {"other", "small", "ld", "prune", "grm", "cluster", "batch", "serve"}
         want = everything if args.extras == "all" else \
             set(x for x in args.extras.split(",") if x and x != "none")
     if "other" in want:
@@ -517,6 +549,15 @@ def main():
             extras[wg["name"]] = bench_grm(torch, lib, hip, pg, wg, dev, max(3, args.steps // 2))
             torch.cuda.empty_cache()
 
+    cluster_runs = []
+    if "cluster" in want:
+        for wc in (synth.grm_small(), synth.grm_large()):
+            log(f"timing complete-linkage clustering on {wc['name']}")
+            key = "cluster_" + wc["name"].split("_")[1]
+            extras[key] = bench_cluster(torch, lib, hip, pg, wc, dev, 3)
+            cluster_runs.append((key, wc))
+            torch.cuda.empty_cache()
+
     if "batch" in want:
         extras["batch"] = bench_batch(torch, lib, hip, pg, synth, dev, args.steps)
         torch.cuda.empty_cache()
@@ -539,6 +580,10 @@ def main():
     if not args.no_cpu:
         log("timing the CPU oracle on a bounded sample")
         result["cpu_baseline"] = cpu_baseline_ibs(w["bed"], n, V, args.cpu_budget)
+        for key, wc in cluster_runs:
+            if wc["n"] <= 2000:
+                log(f"timing the CPU oracle's clustering on {wc['name']}")
+                extras[key]["cpu_baseline"] = cpu_baseline_cluster(wc)
         for wp in prune_runs:
             if wp["n"] * wp["V"] * wp["window"] <= 1e10:     # whole problem in ~a second
                 log(f"timing the CPU oracle on {wp['name']}")

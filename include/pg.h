@@ -244,6 +244,49 @@ int pg_grm_matrix(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_se
                   int64_t v_begin, int64_t v_end, int out_layout, double* grm, uint32_t* n_used,
                   void* workspace, size_t workspace_bytes, void* stream);
 
+/* ---- IBS distance and complete-linkage clustering ------------------------
+ *
+ * Consumers of the IBS counts (section "Identity-by-state matrices, complete
+ * linkage clustering"; Table 2 times an IBS matrix followed by clustering).
+ * The paper names the statistic but not its formula; the reading here:
+ *   d(i,j) = (2*IBS0 + IBS1) / (2*N)
+ * the proportion of alleles not shared identical by state over the jointly
+ * non-missing markers (one minus the IBS similarity (IBS2 + IBS1/2) / N),
+ * computed as the correctly rounded quotient of the two integers; +inf when
+ * N = 0.
+ */
+
+/* One merge of the clustering: clusters a < b (each indexed by its smallest
+ * sample index) merge at complete-linkage distance `height`; the merged
+ * cluster keeps index a. */
+typedef struct pg_merge {
+  int32_t a, b;
+  double height;
+} pg_merge;
+
+/* Elementwise IBS distance of `count` entries of pg_ibs_matrix output (any
+ * layout): dist[e] from ibs0[e], ibs1[e], nonmiss[e].  Device arrays. */
+int pg_ibs_distance(const uint32_t* ibs0, const uint32_t* ibs1, const uint32_t* nonmiss,
+                    int64_t count, double* dist, void* stream);
+
+/* Workspace bytes pg_ibs_cluster needs for m samples (an m x m double
+ * working matrix plus per-sample state). */
+int pg_cluster_workspace_bytes(int64_t m, size_t* bytes);
+
+/*
+ * Complete-linkage agglomerative clustering of m samples on the IBS
+ * distance, from full-layout (m x m) pg_ibs_matrix output.  While more than
+ * one cluster remains, the two clusters with the smallest complete-linkage
+ * distance (largest member-to-member distance) merge; ties go to the pair
+ * with the smallest a, then the smallest b.  merges (device, m - 1 records)
+ * receives the merge sequence in order; the result is exactly determined by
+ * the counts.  Stages for pg_profile_events: 1 = distances and nearest
+ * neighbours, 2 = the merge loop.
+ */
+int pg_ibs_cluster(const uint32_t* ibs0, const uint32_t* ibs1, const uint32_t* nonmiss,
+                   int64_t m, pg_merge* merges, void* workspace, size_t workspace_bytes,
+                   void* stream);
+
 /* ---- batching ------------------------------------------------------------
  *
  * Many independent problems (IBS matrices and LD windows over different

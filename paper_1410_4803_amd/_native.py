@@ -26,6 +26,7 @@ PATHS = {"auto": PG_PATH_AUTO, "popc": PG_PATH_POPC, "mfma": PG_PATH_MFMA}
 SYMBOLS = ("pg_status_str", "pg_last_error", "pg_version", "pg_profile_events",
            "pg_ibs_workspace_bytes", "pg_ibs_matrix", "pg_ld_workspace_bytes", "pg_ld_window",
            "pg_prune_workspace_bytes", "pg_ld_prune", "pg_grm_workspace_bytes", "pg_grm_matrix",
+           "pg_ibs_distance", "pg_cluster_workspace_bytes", "pg_ibs_cluster",
            "pg_batch_plan", "pg_batch_workspace_bytes", "pg_batch_tiles", "pg_batch_upload",
            "pg_batch_launch", "pg_plan_free", "pg_batch_capture", "pg_graph_launch",
            "pg_graph_destroy")
@@ -34,6 +35,9 @@ PG_KIND_IBS, PG_KIND_LD = 0, 1
 LD_PAIR = np.dtype([("a", "<i4"), ("b", "<i4"), ("n", "<i8"), ("sx", "<i8"), ("sy", "<i8"),
                     ("sxx", "<i8"), ("syy", "<i8"), ("sxy", "<i8"), ("r2", "<f8")])
 assert LD_PAIR.itemsize == 64
+
+MERGE = np.dtype([("a", "<i4"), ("b", "<i4"), ("height", "<f8")])
+assert MERGE.itemsize == 16
 
 
 class PgError(RuntimeError):
@@ -101,6 +105,12 @@ def load():
     lib.pg_grm_workspace_bytes.restype = ctypes.c_int
     lib.pg_grm_matrix.argtypes = [gp, p, i64, i64, i64, ctypes.c_int, p, p, p, sz, p]
     lib.pg_grm_matrix.restype = ctypes.c_int
+    lib.pg_ibs_distance.argtypes = [p, p, p, i64, p, p]
+    lib.pg_ibs_distance.restype = ctypes.c_int
+    lib.pg_cluster_workspace_bytes.argtypes = [i64, ctypes.POINTER(sz)]
+    lib.pg_cluster_workspace_bytes.restype = ctypes.c_int
+    lib.pg_ibs_cluster.argtypes = [p, p, p, i64, p, p, sz, p]
+    lib.pg_ibs_cluster.restype = ctypes.c_int
     pp = ctypes.POINTER(ctypes.c_void_p)
     lib.pg_batch_plan.argtypes = [ctypes.POINTER(Problem), ctypes.c_int, pp]
     lib.pg_batch_plan.restype = ctypes.c_int

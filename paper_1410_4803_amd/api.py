@@ -6,6 +6,7 @@ every computation runs in the library's HIP kernels.
     recs = ld_records(cohort, window=1000, r2_min=0.2)  # numpy LD_PAIR array
     keep, n_kept = ld_prune(cohort, window=50, step=5, r2_threshold=0.5)
     A, N = grm_matrix(cohort, layout="full")            # relationship matrix
+    merges = ibs_cluster(*ibs_matrix(cohort, layout="full"))   # complete linkage
 """
 from __future__ import annotations
 
@@ -271,3 +272,57 @@ def grm_matrix(cohort: Cohort, *, sample_idx: torch.Tensor | None = None, v_rang
                            _stream_handle(stream))
     N.check(st, "pg_grm_matrix")
     return A, Nn
+
+
+def ibs_distance(ibs0: torch.Tensor, ibs1: torch.Tensor, nonmiss: torch.Tensor, *, out=None,
+                 stream=None) -> torch.Tensor:
+    """(2*IBS0 + IBS1) / (2*N) elementwise (+inf where N = 0), float64, the
+    shape of the inputs (any pg_ibs_matrix layout)."""
+    for t, name in ((ibs0, "ibs0"), (ibs1, "ibs1"), (nonmiss, "nonmiss")):
+        _require_cuda(t, name, torch.int32)
+    if out is None:
+        out = torch.empty(ibs0.shape, dtype=torch.float64, device=ibs0.device)
+    _require_cuda(out, "out", torch.float64)
+    if not (ibs0.numel() == ibs1.numel() == nonmiss.numel() == out.numel()):
+        raise ValueError("inputs and output must have the same number of entries")
+    N.check(N.load().pg_ibs_distance(_ptr(ibs0), _ptr(ibs1), _ptr(nonmiss), ibs0.numel(),
+                                     _ptr(out), _stream_handle(stream)), "pg_ibs_distance")
+    return out
+
+
+def cluster_workspace_bytes(m: int) -> int:
+    out = ctypes.c_size_t(0)
+    N.check(N.load().pg_cluster_workspace_bytes(int(m), ctypes.byref(out)),
+            "pg_cluster_workspace_bytes")
+    return out.value
+
+
+def ibs_cluster(ibs0: torch.Tensor, ibs1: torch.Tensor, ibs2: torch.Tensor | None = None,
+                nonmiss: torch.Tensor | None = None, *, out=None,
+                workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Complete-linkage clustering on the IBS distance of a full (m, m)
+    pg_ibs_matrix result (pass its four tensors as returned; ibs2 is not
+    needed).  Returns a CUDA uint8 tensor of (m - 1) x 16 bytes: pg_merge
+    records in merge order (see merges_to_numpy)."""
+    if nonmiss is None:
+        raise TypeError("pass the four pg_ibs_matrix outputs (ibs0, ibs1, ibs2, nonmiss)")
+    m = ibs0.shape[0]
+    if ibs0.dim() != 2 or ibs0.shape != (m, m):
+        raise ValueError("clustering needs the full (m, m) layout")
+    for t, name in ((ibs0, "ibs0"), (ibs1, "ibs1"), (nonmiss, "nonmiss")):
+        _require_cuda(t, name, torch.int32)
+    dev = ibs0.device
+    if out is None:
+        out = torch.empty((max(m - 1, 1), 16), dtype=torch.uint8, device=dev)
+    if workspace is None:
+        workspace = torch.empty(cluster_workspace_bytes(m), dtype=torch.uint8, device=dev)
+    N.check(N.load().pg_ibs_cluster(_ptr(ibs0), _ptr(ibs1), _ptr(nonmiss), m, _ptr(out),
+                                    _ptr(workspace), workspace.numel(), _stream_handle(stream)),
+            "pg_ibs_cluster")
+    return out
+
+
+def merges_to_numpy(out: torch.Tensor, m: int) -> np.ndarray:
+    """The m - 1 merge records of an ibs_cluster output as a numpy MERGE array."""
+    raw = out[:max(m - 1, 0)].contiguous().cpu().numpy()
+    return raw.reshape(-1).view(N.MERGE)[:max(m - 1, 0)].copy()

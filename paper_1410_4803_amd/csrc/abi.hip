@@ -462,4 +462,57 @@ int pg_grm_matrix(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_se
   return rc;
 }
 
+int pg_ibs_distance(const uint32_t* ibs0, const uint32_t* ibs1, const uint32_t* nonmiss,
+                    int64_t count, double* dist, void* stream) {
+  g_last_error[0] = 0;
+  if (count < 0) return fail(PG_EINVAL, "count < 0");
+  if (count > 0 && (!ibs0 || !ibs1 || !nonmiss || !dist))
+    return fail(PG_EINVAL, "an input or output pointer is NULL");
+  return launch_ibs_distance(ibs0, ibs1, nonmiss, count, dist, (hipStream_t)stream);
+}
+
+namespace {
+struct ClusterPlan {
+  int64_t off_D, off_nnd, off_nnj, bytes;
+};
+int plan_cluster(int64_t m, ClusterPlan& p) {
+  if (m < 1 || m >= kMaxIndex) return fail(PG_EINVAL, "m %lld outside [1, 2^31)", (long long)m);
+  Carve c;
+  p.off_D = c.take(m * m * 8);
+  p.off_nnd = c.take(m * 8);
+  p.off_nnj = c.take(m * 4);
+  p.bytes = c.off;
+  return PG_OK;
+}
+}  // namespace
+
+int pg_cluster_workspace_bytes(int64_t m, size_t* bytes) {
+  g_last_error[0] = 0;
+  if (!bytes) return fail(PG_EINVAL, "bytes is NULL");
+  ClusterPlan p;
+  const int rc = plan_cluster(m, p);
+  if (rc != PG_OK) return rc;
+  *bytes = (size_t)p.bytes;
+  return PG_OK;
+}
+
+int pg_ibs_cluster(const uint32_t* ibs0, const uint32_t* ibs1, const uint32_t* nonmiss,
+                   int64_t m, pg_merge* merges, void* workspace, size_t workspace_bytes,
+                   void* stream) {
+  g_last_error[0] = 0;
+  ClusterPlan p;
+  int rc = plan_cluster(m, p);
+  if (rc != PG_OK) return rc;
+  if (!ibs0 || !ibs1 || !nonmiss) return fail(PG_EINVAL, "an input pointer is NULL");
+  if (m > 1 && !merges) return fail(PG_EINVAL, "merges is NULL");
+  if ((int64_t)workspace_bytes < p.bytes || !workspace)
+    return fail(PG_ENOMEM, "workspace of %llu bytes < %lld required",
+                (unsigned long long)workspace_bytes, (long long)p.bytes);
+  char* ws = (char*)workspace;
+  hipStream_t st = (hipStream_t)stream;
+  mark_stage(0, st);
+  return launch_ibs_cluster(ibs0, ibs1, nonmiss, m, (double*)(ws + p.off_D),
+                            (double*)(ws + p.off_nnd), (int*)(ws + p.off_nnj), merges, st);
+}
+
 }  // extern "C"

@@ -1,0 +1,242 @@
+// IBS distance and complete-linkage clustering (section "Identity-by-state
+// matrices, complete linkage clustering": an IBS matrix followed by complete
+// linkage clustering, timed in Table 2).
+//
+// Distance (reading; the paper names the statistic but not its formula): the
+// proportion of alleles not shared identical by state over the jointly
+// non-missing markers, d = (2 IBS0 + IBS1) / (2 N), +inf when N = 0 -- the
+// correctly rounded quotient of two integers, so any implementation gets the
+// same double.
+//
+// Clustering: while more than one cluster remains, merge the two clusters
+// with the smallest complete-linkage distance (largest member-to-member
+// distance); ties go to the smallest (a, b) pair of cluster indices, a
+// cluster being indexed by its smallest sample.  Every decision compares
+// doubles that are maxima of the input doubles, so the merge sequence is
+// exactly determined.
+//
+// GPU plan: the working matrix D (m x m doubles) lives in the workspace.
+// For each active cluster k the cached nearest neighbour among l > k,
+// nn[k] = argmin over (D[k][l], l), is kept; the globally closest pair is the
+// argmin over k of (nn_d[k], k), which is exactly the lexicographic rule.
+// One block runs the m - 1 steps: pick the pair (i, j), fold row and column
+// j into i with max(), retire j, then rescan only the rows whose cached
+// neighbour could have changed -- row i, rows k < i whose neighbour was i or
+// j, and rows i < k < j whose neighbour was j (distances only grow, so no
+// other row's minimum moves).  A retired cluster's column and cache entry
+// hold NaN, which never wins a minimum, so scans need no activity flags;
+// each rescan is done by the whole block with several loads in flight per
+// thread.
+#include "pg_internal.h"
+
+namespace pg {
+
+__global__ __launch_bounds__(256) void k_ibs_distance(const uint32_t* __restrict__ i0,
+                                                      const uint32_t* __restrict__ i1,
+                                                      const uint32_t* __restrict__ nm,
+                                                      int64_t count, double* __restrict__ d) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t n = nm[e];
+    d[e] = n ? __ddiv_rn((double)(2 * (int64_t)i0[e] + i1[e]), (double)(2 * (int64_t)n))
+             : __longlong_as_double(0x7ff0000000000000ll);
+  }
+}
+
+int launch_ibs_distance(const uint32_t* i0, const uint32_t* i1, const uint32_t* nm, int64_t count,
+                        double* d, hipStream_t st) {
+  if (count <= 0) return PG_OK;
+  const int64_t blocks = ceil_div(count, 256) < 65536 ? ceil_div(count, 256) : 65536;
+  hipLaunchKernelGGL(k_ibs_distance, dim3((unsigned)blocks), dim3(256), 0, st, i0, i1, nm, count,
+                     d);
+  return check_launch("ibs_distance");
+}
+
+// (value, index) minimum with the smaller index on equal values.
+__device__ __forceinline__ void take_min(double& bv, int& bi, double v, int i) {
+  if (v < bv || (v == bv && (unsigned)i < (unsigned)bi)) {
+    bv = v;
+    bi = i;
+  }
+}
+
+__device__ __forceinline__ void wave_min(double& v, int& i) {
+  for (int d = 32; d > 0; d >>= 1) {
+    const double ov = __shfl_xor(v, d, 64);
+    const int oi = __shfl_xor(i, d, 64);
+    take_min(v, i, ov, oi);
+  }
+}
+
+constexpr uint64_t kNaN = 0x7ff8000000000000ull;
+
+__global__ __launch_bounds__(256) void k_nn_init(const double* __restrict__ D, int64_t m,
+                                                 double* nn_d, int* nn_j) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; k < m;
+       k += ((int64_t)gridDim.x * blockDim.x) >> 6) {
+    double bv = __longlong_as_double(0x7ff0000000000000ll);
+    int bi = -1;
+    const double* row = D + k * m;
+    for (int64_t l = k + 1 + lane; l < m; l += 64) take_min(bv, bi, row[l], (int)l);
+    wave_min(bv, bi);
+    if (lane == 0) {
+      nn_d[k] = bi >= 0 ? bv : __longlong_as_double(kNaN);
+      nn_j[k] = bi;
+    }
+  }
+}
+
+constexpr int kCT = 1024;
+constexpr int kCW = kCT / 64;   // waves
+constexpr int kCU = 4;          // loads in flight per thread in scans
+
+__global__ __launch_bounds__(kCT) void k_cluster(double* __restrict__ D, int64_t m,
+                                                 double* __restrict__ nn_d, int* __restrict__ nn_j,
+                                                 pg_merge* __restrict__ merges) {
+  __shared__ double s_v[kCW];
+  __shared__ int s_i[kCW];
+  __shared__ int s_rows[kCT];
+  __shared__ int s_nrows;
+  const double inf = __longlong_as_double(0x7ff0000000000000ll);
+  const double nan = __longlong_as_double(kNaN);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int64_t t = 0; t + 1 < m; ++t) {
+    // (a) the globally closest pair: argmin over k of (nn_d[k], k); retired
+    // rows and rows without a neighbour hold NaN
+    double bv = inf;
+    int bi = -1;
+    for (int64_t k0 = tid; k0 < m; k0 += kCT * kCU) {
+      double v[kCU];
+#pragma unroll
+      for (int u = 0; u < kCU; ++u) v[u] = k0 + u * kCT < m ? nn_d[k0 + u * kCT] : nan;
+#pragma unroll
+      for (int u = 0; u < kCU; ++u) take_min(bv, bi, v[u], (int)(k0 + u * kCT));
+    }
+    wave_min(bv, bi);
+    if (lane == 0) {
+      s_v[wave] = bv;
+      s_i[wave] = bi;
+    }
+    __syncthreads();
+    double hv = s_v[0];
+    int i = s_i[0];
+    for (int w = 1; w < kCW; ++w) take_min(hv, i, s_v[w], s_i[w]);
+    if (i < 0) break;   // unreachable: two active clusters always pair
+    const int j = nn_j[i];
+    if (tid == 0) {
+      merges[t].a = i;
+      merges[t].b = j;
+      merges[t].height = hv;
+      s_nrows = 0;
+    }
+    // (b) fold j into i: D[i][k] = D[k][i] = max(D[i][k], D[j][k]) for the
+    // active k (a retired k has NaN in row i); retire j: its column and its
+    // cache entry become NaN
+    const double* ri = D + (int64_t)i * m;
+    const double* rj = D + (int64_t)j * m;
+    for (int64_t k0 = tid; k0 < m; k0 += kCT * kCU) {
+      double a[kCU], b[kCU];
+#pragma unroll
+      for (int u = 0; u < kCU; ++u) {
+        const int64_t k = k0 + u * kCT;
+        a[u] = k < m ? ri[k] : nan;
+        b[u] = k < m ? rj[k] : nan;
+      }
+#pragma unroll
+      for (int u = 0; u < kCU; ++u) {
+        const int64_t k = k0 + u * kCT;
+        if (k >= m || k == j || a[u] != a[u]) continue;
+        if (k != i) {
+          const double v = a[u] > b[u] ? a[u] : b[u];
+          D[(int64_t)i * m + k] = v;
+          D[k * m + i] = v;
+        }
+        D[k * m + j] = nan;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) nn_d[j] = nan;
+    // (c) active rows (cache entry not NaN) whose neighbour may have moved
+    for (int64_t k = tid; k < j; k += kCT) {
+      const double dk = nn_d[k];
+      if (dk != dk) continue;
+      const int nk = nn_j[k];
+      if (k == i || (k < i && (nk == i || nk == j)) || (k > i && nk == j)) {
+        const int slot = atomicAdd(&s_nrows, 1);
+        if (slot < kCT) s_rows[slot] = (int)k;
+      }
+    }
+    __syncthreads();
+    const int nrows = s_nrows;
+    // (d) rescan them: groups of g waves per row, kCW / g rows at a time
+    // (more rows than the list holds: walk every row below j, g = 1)
+    const bool listed = nrows <= kCT;
+    const int64_t nscan = listed ? nrows : j;
+    int g = kCW;
+    while (g > 1 && (int64_t)(kCW / g) < nscan) g >>= 1;
+    const int groups = kCW / g, grp = wave / g, gt = tid - grp * g * 64;
+    for (int64_t r0 = 0; r0 < nscan; r0 += groups) {
+      const int64_t rr = r0 + grp;
+      int k = -1;
+      if (rr < nscan) {
+        if (listed) {
+          k = s_rows[rr];
+        } else {
+          const int kk = (int)rr;
+          const double dk = nn_d[kk];
+          const int nk = nn_j[kk];
+          if (dk == dk && (kk == i || (kk < i && (nk == i || nk == j)) || (kk > i && nk == j)))
+            k = kk;
+        }
+      }
+      double v = inf;
+      int l = -1;
+      if (k >= 0) {
+        const double* row = D + (int64_t)k * m;
+        for (int64_t c0 = k + 1 + gt; c0 < m; c0 += (int64_t)g * 64 * kCU) {
+          double x[kCU];
+#pragma unroll
+          for (int u = 0; u < kCU; ++u) {
+            const int64_t c = c0 + (int64_t)u * g * 64;
+            x[u] = c < m ? row[c] : nan;
+          }
+#pragma unroll
+          for (int u = 0; u < kCU; ++u) take_min(v, l, x[u], (int)(c0 + (int64_t)u * g * 64));
+        }
+      }
+      wave_min(v, l);
+      __syncthreads();   // s_v / s_i free (their last readers are past here)
+      if (lane == 0) {
+        s_v[wave] = v;
+        s_i[wave] = l;
+      }
+      __syncthreads();
+      if (k >= 0 && gt == 0) {
+        double rv = s_v[grp * g];
+        int rl = s_i[grp * g];
+        for (int w = 1; w < g; ++w) take_min(rv, rl, s_v[grp * g + w], s_i[grp * g + w]);
+        nn_d[k] = rl >= 0 ? rv : nan;
+        nn_j[k] = rl;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+int launch_ibs_cluster(const uint32_t* i0, const uint32_t* i1, const uint32_t* nm, int64_t m,
+                       double* D, double* nn_d, int* nn_j, pg_merge* merges, hipStream_t st) {
+  int rc = launch_ibs_distance(i0, i1, nm, m * m, D, st);
+  if (rc != PG_OK) return rc;
+  const int64_t blocks = ceil_div(m, 4) < 65536 ? ceil_div(m, 4) : 65536;
+  hipLaunchKernelGGL(k_nn_init, dim3((unsigned)blocks), dim3(256), 0, st, D, m, nn_d, nn_j);
+  rc = check_launch("cluster_init");
+  mark_stage(1, st);
+  if (rc != PG_OK || m < 2) return rc;
+  hipLaunchKernelGGL(k_cluster, dim3(1), dim3(kCT), 0, st, D, m, nn_d, nn_j, merges);
+  rc = check_launch("cluster");
+  mark_stage(2, st);
+  return rc;
+}
+
+}  // namespace pg

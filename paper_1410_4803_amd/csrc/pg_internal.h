@@ -184,6 +184,13 @@ inline int64_t grm_part_bytes(int64_t rows_pad, int64_t wp) {
   return n_split > 1 ? n_split * (nt * (nt + 1) / 2) * 128 * 128 * (8 + 4) : 0;
 }
 
+// ---- IBS distance and clustering (cluster.hip) ------------------------------
+int launch_ibs_distance(const uint32_t* i0, const uint32_t* i1, const uint32_t* nm, int64_t count,
+                        double* d, hipStream_t st);
+// D: m x m doubles; nn_d: m doubles; nn_j: m ints.
+int launch_ibs_cluster(const uint32_t* i0, const uint32_t* i1, const uint32_t* nm, int64_t m,
+                       double* D, double* nn_d, int* nn_j, pg_merge* merges, hipStream_t st);
+
 // r^2 from exact sums, as documented in pg.h; shared by every LD path so that
 // the emission decision and the emitted value are the same double.
 __device__ __forceinline__ double ld_r2(int64_t n, int64_t sx, int64_t sy, int64_t sxx,

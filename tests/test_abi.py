@@ -203,3 +203,18 @@ def test_grm_workspace_and_validation():
     g1 = _g(1, 50)
     assert lib.pg_grm_matrix(ctypes.byref(g1), None, 0, 0, 0, N.PG_TRI_UPPER, None, None, None, 0,
                              None) == N.PG_OK
+
+
+def test_distance_and_cluster_validation():
+    lib = N.load()
+    fake = 0x2000
+    assert lib.pg_ibs_distance(fake, fake, fake, -1, fake, None) == N.PG_EINVAL
+    assert lib.pg_ibs_distance(None, fake, fake, 10, fake, None) == N.PG_EINVAL
+    assert lib.pg_ibs_distance(None, None, None, 0, None, None) == N.PG_OK
+    b = ctypes.c_size_t(0)
+    assert lib.pg_cluster_workspace_bytes(0, ctypes.byref(b)) == N.PG_EINVAL
+    assert lib.pg_cluster_workspace_bytes(10000, ctypes.byref(b)) == N.PG_OK
+    assert b.value >= 10000 * 10000 * 8 + 10000 * 12
+    assert lib.pg_ibs_cluster(fake, fake, None, 100, fake, fake, 1 << 30, None) == N.PG_EINVAL
+    assert lib.pg_ibs_cluster(fake, fake, fake, 100, None, fake, 1 << 30, None) == N.PG_EINVAL
+    assert lib.pg_ibs_cluster(fake, fake, fake, 100, fake, fake, 1000, None) == N.PG_ENOMEM
