@@ -155,7 +155,7 @@ int plan_ld(const Sel& s, int32_t window, int path_arg, LdPlan& p) {
 
 struct PrunePlan {
   LdPlan ld;
-  int64_t off_stats, bytes;
+  int64_t off_stats, off_drop, bytes;
 };
 
 // The LD plan for the pair kernel (largest distance window - 1) plus the
@@ -169,6 +169,7 @@ int plan_prune(const Sel& s, int32_t window, int32_t step, int path_arg, PrunePl
   Carve c;
   c.off = p.ld.bytes;
   p.off_stats = c.take(p.ld.rows_pad * (int64_t)sizeof(int2));
+  p.off_drop = c.take(p.ld.rows_pad * p.ld.bm_words * 4);
   p.bytes = c.off;
   return PG_OK;
 }
@@ -413,7 +414,9 @@ int pg_ld_prune(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_sel,
                 : launch_ld_mfma(D, q.words, s.nv, q.rows_pad, window - 1, r2_min, sc, st);
   if (rc == PG_OK) rc = launch_variant_stats(D, planes, q.words, q.rows_pad, s.nv, stats, st);
   mark_stage(3, st);
-  if (rc == PG_OK) rc = launch_prune_greedy(sc, stats, s.nv, window, step, keep, n_kept, st);
+  if (rc == PG_OK)
+    rc = launch_prune_greedy(sc, stats, (uint32_t*)(ws + p.off_drop), s.nv, window, step, keep,
+                             n_kept, st);
   mark_stage(4, st);
   return rc;
 }

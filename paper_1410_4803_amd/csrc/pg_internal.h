@@ -153,9 +153,11 @@ int launch_ld_finish(const uint32_t* X, bool planes, int64_t words, int64_t rows
 int launch_variant_stats(const uint32_t* X, bool planes, int64_t words, int64_t rows_pad,
                          int64_t nv, int2* stats, hipStream_t st);
 // The greedy pass over the windows, from the pair kernel's bitmap of pairs
-// with r^2 above the threshold (bitmap window = window - 1).
-int launch_prune_greedy(const LdScratch& sc, const int2* stats, int64_t nv, int64_t window,
-                        int64_t step, uint8_t* keep, int64_t* n_kept, hipStream_t st);
+// with r^2 above the threshold (bitmap window = window - 1); `drop` is
+// scratch of the bitmap's size for the drop side of every marked pair.
+int launch_prune_greedy(const LdScratch& sc, const int2* stats, uint32_t* drop, int64_t nv,
+                        int64_t window, int64_t step, uint8_t* keep, int64_t* n_kept,
+                        hipStream_t st);
 constexpr int64_t kPruneMaxWindow = 1 << 16;
 
 // ---- relationship matrix (grm.hip) -------------------------------------------

@@ -14,9 +14,10 @@
 // window only has to visit its new pairs (b in [s_{w-1} + W, s_w + W)), in
 // (a, b) order.  One block walks the (window, row) cells in that order:
 // all threads extract a slice of marked pairs from the bitmap into LDS
-// (with the drop side decided from the allele counts), then one wave
-// applies them in order to a ring of keep bits in LDS; variants no later
-// window can touch are flushed to the output as the windows advance.
+// (with the drop side, decided beforehand from the allele counts by a
+// grid-wide kernel into a second bitmap), then one wave applies them in
+// order to a ring of keep bits in LDS; variants no later window can touch
+// are flushed to the output as the windows advance.
 #include "pg_internal.h"
 
 namespace pg {
@@ -89,6 +90,7 @@ int launch_variant_stats(const uint32_t* X, bool planes, int64_t words, int64_t 
 constexpr int kPT = 1024;                 // threads of the one block
 constexpr int kPCells = 16;               // (window, row) cells per thread per pass
 constexpr int kPGroup = 8;                // cells whose loads are issued together
+constexpr int kPWords = 4;                // bitmap words per cell loaded up front
 constexpr int kPPass = kPT * kPCells;     // cells per pass
 constexpr int kRingBits = 1 << 18;        // keep bits held in LDS (32 KB)
 constexpr int kPBuf = 8192;               // pairs staged in LDS per slice (64 KB)
@@ -153,49 +155,102 @@ __device__ __forceinline__ int block_scan(int v, int* wsum, int* total) {
 }
 
 // Applies staged pairs buf[0, n) in order to the keep ring; wave 0 only.
-// 64 pairs at a time: one LDS round trip reads both keep bits of every pair
-// of the batch; the pairs are then taken one by one with lane reads, and a
-// variant dropped earlier in the same batch (held in the dropping pair's
-// lane) is found with one ballot.  The batch's drops are written back
-// before the next batch reads the ring (LDS operations of one wave complete
-// in order).
-__device__ __forceinline__ void apply_pairs(const uint2* buf, int n, uint32_t* ring, int lane) {
+// 64 pairs at a time.  One LDS round trip reads both keep bits of every
+// pair (the snapshot).  A pair whose snapshot is live acts -- drops its
+// variant x -- unless an earlier pair of the batch that acted dropped one of
+// its two variants.  Each lane collects the mask K of earlier live pairs
+// whose x is one of its variants (every lane's x is broadcast through LDS).
+// Live pairs with K = 0 act whatever else happens; only the others are taken
+// one by one in pair order, acting when K misses every pair that acted.  The
+// batch's drops are written before the next batch reads the ring (LDS
+// operations of one wave complete in order).
+__device__ __forceinline__ void apply_pairs(const uint2* buf, int n, uint32_t* ring, uint32_t* xs,
+                                            int lane) {
   for (int p0 = 0; p0 < n; p0 += 64) {
     const int np = n - p0 < 64 ? n - p0 : 64;
-    uint32_t ea = 0, eb = 0, da = 0, live = 0;
+    // variants are below 2^31: 0xfffffffe / 0xffffffff never match
+    uint32_t ea = 0xfffffffeu, eb = 0xfffffffeu, x = 0xffffffffu;
+    bool live = false;
     if (lane < np) {
       const uint2 e = buf[p0 + lane];
       ea = e.x;
       eb = e.y & 0x7fffffffu;
-      da = e.y >> 31;
       const uint32_t ia = ea & (kRingBits - 1), ib = eb & (kRingBits - 1);
-      live = (ring[ia >> 5] >> (ia & 31)) & (ring[ib >> 5] >> (ib & 31)) & 1u;
+      live = ((ring[ia >> 5] >> (ia & 31)) & (ring[ib >> 5] >> (ib & 31)) & 1u) != 0;
+      x = live ? ((e.y >> 31) ? ea : eb) : 0xffffffffu;
     }
-    int dropped = -1;
-    for (int p = 0; p < np; ++p) {
-      if (!__builtin_amdgcn_readlane(live, p)) continue;
-      const int a = __builtin_amdgcn_readlane(ea, p);
-      const int b = __builtin_amdgcn_readlane(eb, p);
-      if (__ballot(dropped == a || dropped == b)) continue;
-      const int x = __builtin_amdgcn_readlane(da, p) ? a : b;
-      if (lane == p) dropped = x;
+    xs[lane] = x;
+    uint32_t klo = 0, khi = 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      uint32_t kk = 0;
+#pragma unroll
+      for (int q4 = 0; q4 < 8; ++q4) {
+        const uint4 v = *reinterpret_cast<const uint4*>(xs + h * 32 + q4 * 4);
+        const uint32_t vs[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (ea == vs[e] || eb == vs[e]) kk |= 1u << (q4 * 4 + e);
+      }
+      // only earlier pairs count
+      const int below = lane - h * 32;
+      kk &= below >= 32 ? 0xffffffffu : below <= 0 ? 0u : (1u << below) - 1u;
+      if (h == 0) klo = kk;
+      else khi = kk;
     }
-    if (dropped >= 0) {
-      const uint32_t ix = (uint32_t)dropped & (kRingBits - 1);
+    const bool free_pair = live && (klo | khi) == 0;
+    uint64_t acted = __ballot(free_pair);
+    const uint64_t conflicted = __ballot(live && !free_pair);
+    for (uint64_t rest = conflicted; rest; rest &= rest - 1) {
+      const int p = __builtin_ctzll(rest);
+      // readlane yields int: widen through uint32_t so bit 31 does not spread
+      const uint64_t kp = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(khi, p) << 32) |
+                          (uint64_t)(uint32_t)__builtin_amdgcn_readlane(klo, p);
+      if (!(kp & acted)) acted |= 1ull << p;
+    }
+    if ((acted >> lane) & 1ull) {
+      const uint32_t ix = x & (kRingBits - 1);
       atomicAnd(&ring[ix >> 5], ~(1u << (ix & 31)));
     }
   }
 }
 
+// Drop side of every marked pair, beside the bitmap: bit (b - a - 1) of row
+// a is set when a has the strictly lower minor allele frequency.  One thread
+// per bitmap word.
+__global__ __launch_bounds__(256) void k_prune_dropbits(const uint32_t* __restrict__ bitmap,
+                                                        int64_t bm_words, int64_t nv,
+                                                        const int2* __restrict__ stats,
+                                                        uint32_t* __restrict__ drop) {
+  const int64_t total = nv * bm_words;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t bits = bitmap[e], out = 0;
+    if (bits) {
+      const int64_t a = e / bm_words, q = e - a * bm_words;
+      const int2 sa = stats[a];
+      while (bits) {
+        const int t = __builtin_ctz(bits);
+        bits &= bits - 1;
+        const int2 sb = stats[a + 1 + q * 32 + t];
+        if ((int64_t)sa.x * sb.y < (int64_t)sb.x * sa.y) out |= 1u << t;
+      }
+    }
+    drop[e] = out;
+  }
+}
+
 __global__ __launch_bounds__(kPT) void k_prune_greedy(const uint32_t* __restrict__ bitmap,
                                                       int64_t bm_words,
-                                                      const int2* __restrict__ stats,
+                                                      const uint32_t* __restrict__ drop,
                                                       PruneGeom g, int64_t n_windows,
                                                       uint8_t* __restrict__ keep,
                                                       int64_t* __restrict__ n_kept) {
   __shared__ uint32_t ring[kRingBits / 32];
   __shared__ uint2 buf[kPBuf];
   __shared__ int wsum[kPT / 64];
+  __shared__ __attribute__((aligned(16))) uint32_t xs[64];
+  __shared__ uint16_t s_cc[kPCells * kPT];   // per-cell counts, [cell][thread]
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   for (int i = tid; i < kRingBits / 32; i += kPT) ring[i] = ~0u;
@@ -224,8 +279,9 @@ __global__ __launch_bounds__(kPT) void k_prune_greedy(const uint32_t* __restrict
     const int rr = (int)(c0 - w_first * g.W) + tid * kPCells;
     const int64_t w_start = w_first + rr / W;
     const int r_start = rr % W;
-    // count: per group of kPGroup cells, the first two words of every
-    // segment are loaded together (one memory latency per group)
+    // count: per group of kPGroup cells, the first kPWords words of every
+    // segment are loaded together (one memory latency per group); the
+    // per-cell counts are kept in LDS for the write phase
     int cnt = 0;
     {
       int64_t w = w_start;
@@ -233,7 +289,7 @@ __global__ __launch_bounds__(kPT) void k_prune_greedy(const uint32_t* __restrict
 #pragma unroll
       for (int kb = 0; kb < kPCells; kb += kPGroup) {
         int ga[kPGroup], gj0[kPGroup], gj1[kPGroup];
-        uint32_t g0[kPGroup], g1[kPGroup];
+        uint32_t gw[kPGroup][kPWords];
 #pragma unroll
         for (int k = 0; k < kPGroup; ++k) {
           ga[k] = gj0[k] = gj1[k] = 0;
@@ -242,23 +298,30 @@ __global__ __launch_bounds__(kPT) void k_prune_greedy(const uint32_t* __restrict
             r = 0;
             ++w;
           }
-          g0[k] = g1[k] = 0;
+#pragma unroll
+          for (int u = 0; u < kPWords; ++u) gw[k][u] = 0;
           if (gj0[k] < gj1[k]) {
             const uint32_t* row = bitmap + (int64_t)ga[k] * bm_words;
-            const int q0 = gj0[k] >> 5;
-            g0[k] = row[q0];
-            if (q0 + 1 <= (gj1[k] - 1) >> 5) g1[k] = row[q0 + 1];
+            const int q0 = gj0[k] >> 5, qn = (gj1[k] - 1) >> 5;
+#pragma unroll
+            for (int u = 0; u < kPWords; ++u)
+              if (q0 + u <= qn) gw[k][u] = row[q0 + u];
           }
         }
 #pragma unroll
         for (int k = 0; k < kPGroup; ++k) {
-          if (gj0[k] >= gj1[k]) continue;
-          const int q0 = gj0[k] >> 5, qn = (gj1[k] - 1) >> 5;
-          cnt += __builtin_popcount(seg_bits(g0[k], q0, gj0[k], gj1[k]));
-          if (q0 + 1 <= qn) cnt += __builtin_popcount(seg_bits(g1[k], q0 + 1, gj0[k], gj1[k]));
-          const uint32_t* row = bitmap + (int64_t)ga[k] * bm_words;
-          for (int q = q0 + 2; q <= qn; ++q)
-            cnt += __builtin_popcount(seg_word(row, q, gj0[k], gj1[k]));
+          int c = 0;
+          if (gj0[k] < gj1[k]) {
+            const int q0 = gj0[k] >> 5, qn = (gj1[k] - 1) >> 5;
+#pragma unroll
+            for (int u = 0; u < kPWords; ++u)
+              if (q0 + u <= qn) c += __builtin_popcount(seg_bits(gw[k][u], q0 + u, gj0[k], gj1[k]));
+            const uint32_t* row = bitmap + (int64_t)ga[k] * bm_words;
+            for (int q = q0 + kPWords; q <= qn; ++q)
+              c += __builtin_popcount(seg_word(row, q, gj0[k], gj1[k]));
+          }
+          cnt += c;
+          s_cc[(kb + k) * kPT + tid] = (uint16_t)c;
         }
       }
     }
@@ -270,57 +333,42 @@ __global__ __launch_bounds__(kPT) void k_prune_greedy(const uint32_t* __restrict
         int pos = base;
         int64_t w = w_start;
         int r = r_start;
-        for (int kb = 0; kb < kPCells && pos < s1; kb += kPGroup) {
-          int ga[kPGroup], gj0[kPGroup], gj1[kPGroup];
-          uint32_t g0[kPGroup], g1[kPGroup];
-          int2 gs[kPGroup];
-#pragma unroll
-          for (int k = 0; k < kPGroup; ++k) {
-            ga[k] = gj0[k] = gj1[k] = 0;
-            if (w < n_windows) cell_bits(g, w, r, ga[k], gj0[k], gj1[k]);
-            if (++r == W) {
-              r = 0;
-              ++w;
-            }
-            g0[k] = g1[k] = 0;
-            gs[k] = make_int2(0, 1);
-            if (gj0[k] < gj1[k]) {
-              const uint32_t* row = bitmap + (int64_t)ga[k] * bm_words;
-              const int q0 = gj0[k] >> 5;
-              g0[k] = row[q0];
-              if (q0 + 1 <= (gj1[k] - 1) >> 5) g1[k] = row[q0 + 1];
-              gs[k] = stats[ga[k]];
-            }
+        for (int k = 0; k < kPCells; ++k) {
+          const int c = s_cc[k * kPT + tid];
+          const int64_t wk = w;
+          const int rk = r;
+          if (++r == W) {
+            r = 0;
+            ++w;
           }
-#pragma unroll
-          for (int k = 0; k < kPGroup; ++k) {
-            if (gj0[k] >= gj1[k] || pos >= s1) continue;
-            const int a = ga[k];
-            const uint32_t* row = bitmap + (int64_t)a * bm_words;
-            const int2 sa = gs[k];
-            const int q0 = gj0[k] >> 5, qn = (gj1[k] - 1) >> 5;
-            for (int q = q0; q <= qn && pos < s1; ++q) {
-              uint32_t bits = seg_bits(q == q0 ? g0[k] : q == q0 + 1 ? g1[k] : row[q], q, gj0[k],
-                                       gj1[k]);
-              while (bits && pos < s1) {
-                const int t = __builtin_ctz(bits);
-                bits &= bits - 1;
-                if (pos >= s0) {
-                  const int b = a + 1 + q * 32 + t;
-                  const int2 sb = stats[b];
-                  // drop a when its minor allele frequency is strictly lower
-                  const bool drop_a = (int64_t)sa.x * sb.y < (int64_t)sb.x * sa.y;
-                  buf[pos - s0] =
-                      make_uint2((uint32_t)a, (uint32_t)b | (drop_a ? 0x80000000u : 0u));
-                }
-                ++pos;
+          // cells wholly before this slice, or empty, are skipped unread
+          if (c == 0 || pos >= s1) continue;
+          if (pos + c <= s0) {
+            pos += c;
+            continue;
+          }
+          int a, j0, j1;
+          cell_bits(g, wk, rk, a, j0, j1);
+          const int64_t base_w = (int64_t)a * bm_words;
+          int left = c;
+          for (int q = j0 >> 5; left > 0 && pos < s1; ++q) {
+            uint32_t bits = seg_bits(bitmap[base_w + q], q, j0, j1);
+            const uint32_t dw = drop[base_w + q];
+            while (bits && pos < s1) {
+              const int t = __builtin_ctz(bits);
+              bits &= bits - 1;
+              --left;
+              if (pos >= s0) {
+                const int b = a + 1 + q * 32 + t;
+                buf[pos - s0] = make_uint2((uint32_t)a, (uint32_t)b | (((dw >> t) & 1u) << 31));
               }
+              ++pos;
             }
           }
         }
       }
       __syncthreads();
-      if (tid < 64) apply_pairs(buf, s1 - s0, ring, lane);
+      if (tid < 64) apply_pairs(buf, s1 - s0, ring, xs, lane);
       __syncthreads();
     }
   }
@@ -331,11 +379,18 @@ __global__ __launch_bounds__(kPT) void k_prune_greedy(const uint32_t* __restrict
   if (tid == 0 && n_kept) *n_kept = total;
 }
 
-int launch_prune_greedy(const LdScratch& sc, const int2* stats, int64_t nv, int64_t window,
-                        int64_t step, uint8_t* keep, int64_t* n_kept, hipStream_t st) {
+int launch_prune_greedy(const LdScratch& sc, const int2* stats, uint32_t* drop, int64_t nv,
+                        int64_t window, int64_t step, uint8_t* keep, int64_t* n_kept,
+                        hipStream_t st) {
+  const int64_t words = nv * sc.bm_words;
+  const int64_t blocks = ceil_div(words, 256) < 65536 ? ceil_div(words, 256) : 65536;
+  hipLaunchKernelGGL(k_prune_dropbits, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(256), 0, st,
+                     sc.bitmap, sc.bm_words, nv, stats, drop);
+  int rc = check_launch("prune_dropbits");
+  if (rc != PG_OK) return rc;
   const int64_t n_windows = nv <= window ? 1 : ceil_div(nv - window, step) + 1;
   const PruneGeom g{nv, window, step};
-  hipLaunchKernelGGL(k_prune_greedy, dim3(1), dim3(kPT), 0, st, sc.bitmap, sc.bm_words, stats, g,
+  hipLaunchKernelGGL(k_prune_greedy, dim3(1), dim3(kPT), 0, st, sc.bitmap, sc.bm_words, drop, g,
                      n_windows, keep, n_kept);
   return check_launch("prune_greedy");
 }

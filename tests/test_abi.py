@@ -161,9 +161,10 @@ def test_prune_workspace_and_validation():
     g = _g(1000, 100000)
     rc, b = _prune_ws(g, 50)
     _, ld = _ld_ws(g, 49)
-    # the LD scratch of the pair kernel (largest distance window - 1) plus
-    # one int2 of allele counts per padded variant
-    assert rc == 0 and b == ld + 100032 * 8
+    # the LD scratch of the pair kernel (largest distance window - 1), one
+    # int2 of allele counts per padded variant, and a drop-side bitmap of the
+    # pair kernel's bitmap size (2 words per row for window 50)
+    assert rc == 0 and b == ld + 100032 * 8 + 100032 * 2 * 4
     assert _prune_ws(g, 1)[0] == N.PG_EINVAL
     assert _prune_ws(g, (1 << 16) + 1)[0] == N.PG_EINVAL
     assert _prune_ws(g, 1 << 16)[0] == 0
