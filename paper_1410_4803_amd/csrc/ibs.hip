@@ -34,6 +34,15 @@ __global__ __launch_bounds__(256, 1) void k_ibs_mfma(const uint32_t* __restrict_
   ibs_mfma_tile<kHints>(T, wp, I, J, o, (lds_t*)smem);
 }
 
+template <bool kHints>
+__global__ __launch_bounds__(512, 1) void k_ibs_mfma_w8(const uint32_t* __restrict__ T, int64_t wp,
+                                                        int64_t nt, IbsOut o) {
+  __shared__ __attribute__((aligned(16))) uint32_t smem[kIbsMfmaSmem];
+  int64_t I, J;
+  if (!band_tile(xcd_swizzle(blockIdx.x, gridDim.x), nt, I, J)) return;
+  ibs_mfma_tile_w8<kHints>(T, wp, I, J, o, (lds_t*)smem);
+}
+
 __global__ __launch_bounds__(256, 1) void k_ibs_mfma_simple(const uint32_t* __restrict__ T,
                                                             int64_t wp, int64_t nt, IbsOut o) {
   __shared__ __attribute__((aligned(16))) uint32_t smem[kIbsMfmaSimpleSmem];
@@ -75,6 +84,11 @@ int launch_ibs_mfma(const uint32_t* T, int64_t wp, const IbsOut& o, int variant,
     hipLaunchKernelGGL(k_ibs_mfma_simple, dim3((unsigned)blocks), dim3(256), 0, st, T, wp, nt, o);
   else if (variant == 3)
     hipLaunchKernelGGL(k_ibs_fp4, dim3((unsigned)blocks), dim3(256), 0, st, T, wp, nt, o);
+  else if (variant == kIbsVariantW8)
+    hipLaunchKernelGGL(k_ibs_mfma_w8<true>, dim3((unsigned)blocks), dim3(512), 0, st, T, wp, nt, o);
+  else if (variant == kIbsVariantW8 + 1)
+    hipLaunchKernelGGL(k_ibs_mfma_w8<false>, dim3((unsigned)blocks), dim3(512), 0, st, T, wp, nt,
+                       o);
   else
     hipLaunchKernelGGL(k_ibs_mfma<true>, dim3((unsigned)blocks), dim3(256), 0, st, T, wp, nt, o);
   return check_launch("ibs_mfma");

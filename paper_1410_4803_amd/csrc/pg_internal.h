@@ -98,6 +98,7 @@ constexpr int kIbsMfmaTile = 128;     // samples per tile side
 constexpr int kIbsMfmaKWords = 16;    // 2-bit words per K chunk (256 variants)
 constexpr int kIbsVariantFp4 = 3;     // matrix-core variant with fp4 operands
 constexpr int kIbsVariantFp4Rep = 4;  // fp4 operands from the replicated layout
+constexpr int kIbsVariantW8 = 5;      // eight waves of 64x32 (6: without scheduling hints)
 constexpr int kIbsRepChunk = 64;      // replicated words per K chunk (256 variants)
 constexpr int kIbsPopcTile = 64;
 constexpr int kIbsPopcKWords = 16;    // 32-bit plane words per K chunk

@@ -356,6 +356,132 @@ __device__ __forceinline__ void ibs_mfma_tile(const uint32_t* __restrict__ T, in
 }
 
 
+// Eight-wave form (variant 5): 512 threads = 8 waves in a 2x4 grid over the
+// same 128x128 tile, each wave 64x32 = 2x1 blocks and three accumulator sets
+// (96 accumulator registers), so two waves share each SIMD and one wave's
+// feature expansion can run while the other's MFMAs do.  Each wave expands
+// three words per step for eight MFMAs (the four-wave form: four words for
+// sixteen).
+struct IbsAcc21 {
+  v16i m[2], w[2], hc[2];
+};
+
+__device__ __forceinline__ void mfma_step21(IbsAcc21& acc, const Feat4 (&fa)[2], const Feat4& fb) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      if (q == 0)
+        acc.m[a] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a].m, fb.m, acc.m[a], 0, 0, 0);
+      else if (q == 1)
+        acc.w[a] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a].w, fb.w, acc.w[a], 0, 0, 0);
+      else if (q == 2)
+        acc.hc[a] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a].h, fb.h, acc.hc[a], 0, 0, 0);
+      else
+        acc.hc[a] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a].c, fb.c, acc.hc[a], 0, 0, 0);
+    }
+}
+
+template <bool kHints>
+__device__ __forceinline__ void ibs_mfma_tile_w8(const uint32_t* __restrict__ T, int64_t wp,
+                                                 int64_t I, int64_t J, const IbsOut& o,
+                                                 lds_t* smem) {
+  constexpr int kBuf = kT * kLdsStride;
+  lds_t* const sA = smem;
+  lds_t* const sB = smem + 2 * kBuf;
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int wid = t >> 6;
+  const int wr = wid >> 2, wc = wid & 3;
+  const int g = lane >> 5;
+  const int rl = lane & 31;
+
+  // this thread's share of a chunk: row t/4 of both tiles, words 4*(t%4)..+3
+  const int lrow = t >> 2;
+  const int lq = (t & 3) * 4;
+  const uint32_t* pa = T + (I * kT + lrow) * wp + lq;
+  const uint32_t* pb = T + (J * kT + lrow) * wp + lq;
+  uint4 ga, gb;
+  auto gload = [&](int64_t kc) {
+    ga = *reinterpret_cast<const uint4*>(pa + kc);
+    gb = *reinterpret_cast<const uint4*>(pb + kc);
+  };
+  auto lstore = [&](int buf) {
+    lds_st4(&(sA + buf * kBuf)[lrow * kLdsStride + lq], ga);
+    lds_st4(&(sB + buf * kBuf)[lrow * kLdsStride + lq], gb);
+  };
+
+  IbsAcc21 acc;
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    acc.m[a] = (v16i){0};
+    acc.w[a] = (v16i){0};
+    acc.hc[a] = (v16i){0};
+  }
+  const int64_t nchunks = wp / kKW;
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int64_t k = 0; k < nchunks; ++k) {
+    const int buf = (int)(k & 1);
+    if (k + 1 < nchunks) gload((k + 1) * kKW);
+    uint32_t wa[2][8], wb[8];
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      const lds_t* ra = &(sA + buf * kBuf)[(wr * 64 + x * 32 + rl) * kLdsStride + g * 8];
+      const uint4 a0 = lds_ld4(ra);
+      const uint4 a1 = lds_ld4(ra + 4);
+      wa[x][0] = a0.x; wa[x][1] = a0.y; wa[x][2] = a0.z; wa[x][3] = a0.w;
+      wa[x][4] = a1.x; wa[x][5] = a1.y; wa[x][6] = a1.z; wa[x][7] = a1.w;
+    }
+    {
+      const lds_t* rb = &(sB + buf * kBuf)[(wc * 32 + rl) * kLdsStride + g * 8];
+      const uint4 b0 = lds_ld4(rb);
+      const uint4 b1 = lds_ld4(rb + 4);
+      wb[0] = b0.x; wb[1] = b0.y; wb[2] = b0.z; wb[3] = b0.w;
+      wb[4] = b1.x; wb[5] = b1.y; wb[6] = b1.z; wb[7] = b1.w;
+    }
+    Feat4 fa[2], fb;
+    fa[0] = expand_a(wa[0][0]); fa[1] = expand_a(wa[1][0]);
+    fb = expand_b(wb[0]);
+#pragma unroll
+    for (int s = 0; s < kKW / 2; ++s) {
+      Feat4 na[2], nb;
+      if (s + 1 < kKW / 2) {
+        na[0] = expand_a(wa[0][s + 1]); na[1] = expand_a(wa[1][s + 1]);
+        nb = expand_b(wb[s + 1]);
+      }
+      mfma_step21(acc, fa, fb);
+      if constexpr (kHints) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x002, 9, 0);
+        }
+      }
+      if (s + 1 < kKW / 2) {
+        fa[0] = na[0]; fa[1] = na[1];
+        fb = nb;
+      }
+    }
+    if (k + 1 < nchunks) lstore(buf ^ 1);
+    __syncthreads();
+  }
+  const bool mirror = (I != J);
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    uint32_t n[16], z[16], one[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      n[v] = (uint32_t)acc.m[a][v];
+      z[v] = (uint32_t)acc.hc[a][v] >> 1;
+      one[v] = (n[v] - (uint32_t)acc.w[a][v]) >> 1;
+    }
+    store_block(o, I * kT + wr * 64 + a * 32, J * kT + wc * 32 + (lane & 31), mirror, lane, n, z,
+                one);
+  }
+}
+
 // Unpipelined reference form (variant 2).
 __device__ __forceinline__ void ibs_mfma_tile_simple(const uint32_t* __restrict__ T, int64_t wp,
                                                      int64_t I, int64_t J, const IbsOut& o,

@@ -19,7 +19,8 @@ from . import _native as N
 from . import api
 
 IBS_CANDIDATES = {"mfma": N.PG_PATH_MFMA, "mfma_fp4": N.PG_PATH_MFMA | (3 << 8),
-                  "mfma_fp4rep": N.PG_PATH_MFMA | (4 << 8), "popc": N.PG_PATH_POPC}
+                  "mfma_fp4rep": N.PG_PATH_MFMA | (4 << 8), "mfma_w8": N.PG_PATH_MFMA | (5 << 8),
+                  "mfma_w8nh": N.PG_PATH_MFMA | (6 << 8), "popc": N.PG_PATH_POPC}
 # inside a batch every matrix-core problem runs the default body, so only the
 # path is worth choosing there
 IBS_BATCH_CANDIDATES = {"mfma": N.PG_PATH_MFMA, "popc": N.PG_PATH_POPC}

@@ -16,10 +16,12 @@ pytestmark = pytest.mark.gpu
 
 pg = pytest.importorskip("paper_1410_4803_amd")
 
-PATHS = ["popc", "mfma", "fp4", "fp4rep"]
+PATHS = ["popc", "mfma", "fp4", "fp4rep", "w8", "w8nh"]
 # path codes: "fp4" / "fp4rep" are matrix-core variants 3 and 4 (fp4 operands,
-# from the 2-bit and from the replicated layout)
-CODES = {"popc": 1, "mfma": 2, "fp4": 2 | (3 << 8), "fp4rep": 2 | (4 << 8)}
+# from the 2-bit and from the replicated layout); "w8" / "w8nh" are variants
+# 5 and 6 (eight waves of 64x32, with and without scheduling hints)
+CODES = {"popc": 1, "mfma": 2, "fp4": 2 | (3 << 8), "fp4rep": 2 | (4 << 8), "w8": 2 | (5 << 8),
+         "w8nh": 2 | (6 << 8)}
 
 
 def _cohort(bed, n, mask=None):
