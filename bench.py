@@ -182,7 +182,7 @@ def bench_prune(torch, lib, hip, pg, wp, dev, steps):
                          "frac": round(ach / PEAK_INT8_TOPS, 4)}}
 
 
-def bench_grm(torch, lib, hip, pg, wg, dev, steps):
+def bench_grm(torch, lib, hip, pg, wg, dev, steps, path="auto"):
     """Relationship matrix (full layout): whole-call time and its stages.
     Algorithmic work: one fp64 multiply-add per (unique pair incl. the
     diagonal) x variant, i.e. 2 * m(m+1)/2 * V flops."""
@@ -192,7 +192,7 @@ def bench_grm(torch, lib, hip, pg, wg, dev, steps):
     Nn = torch.empty((n, n), dtype=torch.int32, device=dev)
     ws = torch.empty(pg.grm_workspace_bytes(c), dtype=torch.uint8, device=dev)
     ms, st = timed_steps(torch, lib, hip, lambda: pg.grm_matrix(
-        c, layout="full", out=(A, Nn), workspace=ws), steps, 2, 3)
+        c, layout="full", path=path, out=(A, Nn), workspace=ws), steps, 2, 3)
     flops = 2.0 * n * (n + 1) / 2 * V
     pair_ms = mean(st[1])
     ach = flops / (pair_ms * 1e-3) / 1e12
@@ -387,6 +387,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serial-seconds", type=float, default=15.0)
+    ap.add_argument("--grm-path", type=int, default=0,
+                    help="path code of the relationship-matrix calls (0 = library default)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -546,7 +548,8 @@ def main():
     if "grm" in want:
         for wg in (synth.grm_small(), synth.grm_large()):
             log(f"timing the relationship matrix on {wg['name']}")
-            extras[wg["name"]] = bench_grm(torch, lib, hip, pg, wg, dev, max(3, args.steps // 2))
+            extras[wg["name"]] = bench_grm(torch, lib, hip, pg, wg, dev, max(3, args.steps // 2),
+                                           args.grm_path)
             torch.cuda.empty_cache()
 
     cluster_runs = []

@@ -235,14 +235,18 @@ int pg_grm_workspace_bytes(const pg_genotypes* g, int64_t n_sel, int64_t v_begin
 /*
  * Relationship matrix over the selected samples and variants.
  *   out_layout  PG_FULL (m x m, diagonal included) or PG_TRI_UPPER
+ *   path        PG_PATH_AUTO or PG_PATH_MFMA (fp64 matrix cores); bits 8-15
+ *               select the kernel variant: 0 the library's default (= 2),
+ *               1 four waves of 64 x 64 per 128 x 128 tile, 2 eight waves of
+ *               32 x 64, 3 sixteen waves of 32 x 32 (all give the same sums)
  *   grm         device double array of the layout's size (A)
  *   n_used      device uint32 array of the same size (N)
  * Stages for pg_profile_events: 1 = operand layout and per-marker tables,
  * 2 = pair kernel.
  */
 int pg_grm_matrix(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_sel,
-                  int64_t v_begin, int64_t v_end, int out_layout, double* grm, uint32_t* n_used,
-                  void* workspace, size_t workspace_bytes, void* stream);
+                  int64_t v_begin, int64_t v_end, int out_layout, int path, double* grm,
+                  uint32_t* n_used, void* workspace, size_t workspace_bytes, void* stream);
 
 /* ---- IBS distance and complete-linkage clustering ------------------------
  *

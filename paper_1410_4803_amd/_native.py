@@ -103,7 +103,8 @@ def load():
     lib.pg_ld_prune.restype = ctypes.c_int
     lib.pg_grm_workspace_bytes.argtypes = [gp, i64, i64, i64, ctypes.POINTER(sz)]
     lib.pg_grm_workspace_bytes.restype = ctypes.c_int
-    lib.pg_grm_matrix.argtypes = [gp, p, i64, i64, i64, ctypes.c_int, p, p, p, sz, p]
+    lib.pg_grm_matrix.argtypes = [gp, p, i64, i64, i64, ctypes.c_int, ctypes.c_int, p, p, p, sz,
+                                  p]
     lib.pg_grm_matrix.restype = ctypes.c_int
     lib.pg_ibs_distance.argtypes = [p, p, p, i64, p, p]
     lib.pg_ibs_distance.restype = ctypes.c_int

@@ -244,8 +244,8 @@ def grm_workspace_bytes(cohort: Cohort, n_sel: int = 0, v_range=None) -> int:
 
 
 def grm_matrix(cohort: Cohort, *, sample_idx: torch.Tensor | None = None, v_range=None,
-               layout: str = "full", out=None, workspace: torch.Tensor | None = None,
-               stream=None):
+               layout: str = "full", path="auto", out=None,
+               workspace: torch.Tensor | None = None, stream=None):
     """Asynchronous relationship matrix.  Returns (A, N): A float64 and N
     int32 (holding uint32 counts) CUDA tensors, (m, m) for the full layout or
     the packed strict upper triangle."""
@@ -268,7 +268,7 @@ def grm_matrix(cohort: Cohort, *, sample_idx: torch.Tensor | None = None, v_rang
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
     g = cohort.struct()
     st = lib.pg_grm_matrix(ctypes.byref(g), _ptr(sample_idx), n_sel, vb, ve, N.LAYOUTS[layout],
-                           _ptr(A), _ptr(Nn), _ptr(workspace), workspace.numel(),
+                           _path(path), _ptr(A), _ptr(Nn), _ptr(workspace), workspace.numel(),
                            _stream_handle(stream))
     N.check(st, "pg_grm_matrix")
     return A, Nn

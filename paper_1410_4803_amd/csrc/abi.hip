@@ -436,14 +436,18 @@ int pg_grm_workspace_bytes(const pg_genotypes* g, int64_t n_sel, int64_t v_begin
 }
 
 int pg_grm_matrix(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_sel,
-                  int64_t v_begin, int64_t v_end, int out_layout, double* grm, uint32_t* n_used,
-                  void* workspace, size_t workspace_bytes, void* stream) {
+                  int64_t v_begin, int64_t v_end, int out_layout, int path, double* grm,
+                  uint32_t* n_used, void* workspace, size_t workspace_bytes, void* stream) {
   g_last_error[0] = 0;
   Sel s;
   int rc = make_sel(g, sample_idx != nullptr, sample_idx, n_sel, v_begin, v_end, s);
   if (rc != PG_OK) return rc;
   if (out_layout != PG_FULL && out_layout != PG_TRI_UPPER)
     return fail(PG_EINVAL, "unknown layout %d", out_layout);
+  if (path < 0 || (path >> 16) != 0 ||
+      ((path & 0xFF) != PG_PATH_AUTO && (path & 0xFF) != PG_PATH_MFMA))
+    return fail(PG_EINVAL, "bad path argument %d", path);
+  const int variant = (path >> 8) & 0xFF;
   const int64_t entries = out_layout == PG_FULL ? s.m * s.m : s.m * (s.m - 1) / 2;
   if (entries > 0 && (!grm || !n_used)) return fail(PG_EINVAL, "an output pointer is NULL");
   GrmPlan p;
@@ -461,7 +465,7 @@ int pg_grm_matrix(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_se
   if (rc == PG_OK)
     rc = launch_grm(s, T, p.rows_pad, p.words, (double*)(ws + p.off_z),
                     (uint32_t*)(ws + p.off_used), (double*)(ws + p.off_part), grm, n_used,
-                    out_layout == PG_FULL, st);
+                    out_layout == PG_FULL, variant == 1 ? 4 : variant == 3 ? 16 : 8, st);
   return rc;
 }
 

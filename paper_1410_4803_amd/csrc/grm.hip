@@ -126,10 +126,17 @@ __device__ __forceinline__ uint32_t present16(uint32_t w) {
   return x;
 }
 
-__global__ __launch_bounds__(256, 1) void k_grm_mfma(const uint32_t* __restrict__ T, int64_t wp,
-                                                     const double* __restrict__ ztab,
-                                                     const uint32_t* __restrict__ used2,
-                                                     int64_t nt, GrmOut o) {
+// Wave grid kWR x kWC over the tile: each wave owns (128 / kWR) x (128 / kWC)
+// = kNA x kNB blocks of 16 x 16: 2 x 2 waves (one per SIMD), 4 x 2 (two per
+// SIMD) or 4 x 4 (four per SIMD).  More waves per SIMD hide the latency of
+// the fp64 MFMAs at the cost of more table lookups per MFMA.
+template <int kWR, int kWC>
+__global__ __launch_bounds__(64 * kWR * kWC, 1) void k_grm_mfma(const uint32_t* __restrict__ T,
+                                                                int64_t wp,
+                                                                const double* __restrict__ ztab,
+                                                                const uint32_t* __restrict__ used2,
+                                                                int64_t nt, GrmOut o) {
+  constexpr int kNA = kGT / kWR / 16, kNB = kGT / kWC / 16;
   // LDS (per buffer): codes of the I and J blocks [2][128][4] words, masks
   // [2][128] uint64, z tables [64][4] doubles.
   __shared__ uint32_t s_codes[2][2][kGT][kGKW];
@@ -142,15 +149,16 @@ __global__ __launch_bounds__(256, 1) void k_grm_mfma(const uint32_t* __restrict_
   tri_tile(tile, nt, I, J);
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
+  const int wr = wave / kWC, wc = wave % kWC;
+  const bool loader = tid < 256;
   // this block's K chunks: [c_begin, c_end)
   const int64_t all_chunks = wp / kGKW;
   const int c_begin = (int)(split * o.cps);
   const int c_end = (int)((split + 1) * o.cps < all_chunks ? (split + 1) * o.cps : all_chunks);
 
-  // loader role: thread t stages row (t & 127) of block (t >> 7) and one
-  // double of the z table
-  const int lrow = tid & (kGT - 1), lblk = tid >> 7;
+  // loader role (threads 0..255): thread t stages row (t & 127) of block
+  // (t >> 7) and one double of the z table
+  const int lrow = tid & (kGT - 1), lblk = (tid >> 7) & 1;
   const int64_t grow = (lblk ? J : I) * kGT + lrow;
   const uint4* src = reinterpret_cast<const uint4*>(T + grow * wp);
   auto fetch = [&](int c, uint4& w, uint4& u, double& z) {
@@ -173,12 +181,12 @@ __global__ __launch_bounds__(256, 1) void k_grm_mfma(const uint32_t* __restrict_
     s_z[buf][tid] = z;
   };
 
-  grm_d4 acc[4][4];
-  uint32_t cnt[4][4][4];
+  grm_d4 acc[kNA][kNB];
+  uint32_t cnt[kNA][kNB][4];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < kNA; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
+    for (int b = 0; b < kNB; ++b) {
       acc[a][b] = grm_d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int r = 0; r < 4; ++r) cnt[a][b][r] = 0;
@@ -186,7 +194,7 @@ __global__ __launch_bounds__(256, 1) void k_grm_mfma(const uint32_t* __restrict_
 
   uint4 pw, pu;
   double pz;
-  if (c_begin < c_end) {
+  if (c_begin < c_end && loader) {
     fetch(c_begin, pw, pu, pz);
     stage(0, pw, pu, pz);
   }
@@ -195,32 +203,30 @@ __global__ __launch_bounds__(256, 1) void k_grm_mfma(const uint32_t* __restrict_
   const int r16 = lane & 15;
   for (int c = c_begin; c < c_end; ++c) {
     const int buf = (c - c_begin) & 1;
-    if (c + 1 < c_end) fetch(c + 1, pw, pu, pz);
+    if (c + 1 < c_end && loader) fetch(c + 1, pw, pu, pz);
     const lds_t* ci = (const lds_t*)&s_codes[buf][0][0][0];
     const lds_t* cj = (const lds_t*)&s_codes[buf][1][0][0];
     const lds_f64* zt = (const lds_f64*)&s_z[buf][0];
 #pragma unroll
     for (int wd = 0; wd < kGKW; ++wd) {
-      uint32_t wa[4], wb[4];
+      uint32_t wa[kNA], wb[kNB];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        wa[q] = ci[(wr * 64 + q * 16 + r16) * kGKW + wd];
-        wb[q] = cj[(wc * 64 + q * 16 + r16) * kGKW + wd];
-      }
+      for (int q = 0; q < kNA; ++q) wa[q] = ci[(wr * kNA * 16 + q * 16 + r16) * kGKW + wd];
+#pragma unroll
+      for (int q = 0; q < kNB; ++q) wb[q] = cj[(wc * kNB * 16 + q * 16 + r16) * kGKW + wd];
 #pragma unroll
       for (int st = 0; st < 4; ++st) {
         const int t = st * 4 + kq;                 // variant inside the word
         const int k = wd * 16 + t;                 // variant inside the chunk
-        double av[4], bv[4];
+        double av[kNA], bv[kNB];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          av[q] = zt[k * 4 + ((wa[q] >> (2 * t)) & 3u)];
-          bv[q] = zt[k * 4 + ((wb[q] >> (2 * t)) & 3u)];
-        }
+        for (int q = 0; q < kNA; ++q) av[q] = zt[k * 4 + ((wa[q] >> (2 * t)) & 3u)];
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int q = 0; q < kNB; ++q) bv[q] = zt[k * 4 + ((wb[q] >> (2 * t)) & 3u)];
 #pragma unroll
-          for (int b = 0; b < 4; ++b)
+        for (int a = 0; a < kNA; ++a)
+#pragma unroll
+          for (int b = 0; b < kNB; ++b)
             acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
       }
     }
@@ -228,32 +234,32 @@ __global__ __launch_bounds__(256, 1) void k_grm_mfma(const uint32_t* __restrict_
     {
       const lds_u64* mi = (const lds_u64*)&s_mask[buf][0][0];
       const lds_u64* mj = (const lds_u64*)&s_mask[buf][1][0];
-      uint64_t colm[4];
+      uint64_t colm[kNB];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) colm[b] = mj[wc * 64 + b * 16 + r16];
+      for (int b = 0; b < kNB; ++b) colm[b] = mj[wc * kNB * 16 + b * 16 + r16];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < kNA; ++a)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const uint64_t rm = mi[wr * 64 + a * 16 + kq + 4 * r];
+          const uint64_t rm = mi[wr * kNA * 16 + a * 16 + kq + 4 * r];
 #pragma unroll
-          for (int b = 0; b < 4; ++b) cnt[a][b][r] += (uint32_t)__popcll(rm & colm[b]);
+          for (int b = 0; b < kNB; ++b) cnt[a][b][r] += (uint32_t)__popcll(rm & colm[b]);
         }
     }
-    if (c + 1 < c_end) stage(buf ^ 1, pw, pu, pz);
+    if (c + 1 < c_end && loader) stage(buf ^ 1, pw, pu, pz);
     __syncthreads();
   }
 
   // epilogue: the result, or this split's partial sums and counts
   const bool diag = I == J;
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < kNA; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < kNB; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int il = wr * 64 + a * 16 + kq + 4 * r;
-        const int jl = wc * 64 + b * 16 + r16;
+        const int il = wr * kNA * 16 + a * 16 + kq + 4 * r;
+        const int jl = wc * kNB * 16 + b * 16 + r16;
         if (o.n_split == 1) {
           grm_store(o, I * kGT + il, J * kGT + jl, diag, acc[a][b][r], cnt[a][b][r]);
         } else {
@@ -286,7 +292,7 @@ __global__ __launch_bounds__(256) void k_grm_reduce(int64_t nt, GrmOut o) {
 
 int launch_grm(const Sel& s, const uint32_t* T, int64_t rows_pad, int64_t wp, double* ztab,
                uint32_t* used2, double* part, double* grm, uint32_t* n_used, int full,
-               hipStream_t st) {
+               int waves, hipStream_t st) {
   int rc = fill_u32(used2, wp, 0u, st);
   if (rc != PG_OK) return rc;
   const int64_t nv_pad = wp * 16;
@@ -302,8 +308,15 @@ int launch_grm(const Sel& s, const uint32_t* T, int64_t rows_pad, int64_t wp, do
   const int64_t part_entries = n_split > 1 ? n_split * n_tiles * kGT * kGT : 0;
   const GrmOut o{grm, n_used, s.m, full, n_tiles, n_split, cps, part,
                  (uint32_t*)(part + part_entries)};
-  hipLaunchKernelGGL(k_grm_mfma, dim3((unsigned)(n_tiles * n_split)), dim3(256), 0, st, T, wp,
-                     ztab, used2, nt, o);
+  if (waves == 16)
+    hipLaunchKernelGGL((k_grm_mfma<4, 4>), dim3((unsigned)(n_tiles * n_split)), dim3(1024), 0, st,
+                       T, wp, ztab, used2, nt, o);
+  else if (waves == 8)
+    hipLaunchKernelGGL((k_grm_mfma<4, 2>), dim3((unsigned)(n_tiles * n_split)), dim3(512), 0, st, T,
+                       wp, ztab, used2, nt, o);
+  else
+    hipLaunchKernelGGL((k_grm_mfma<2, 2>), dim3((unsigned)(n_tiles * n_split)), dim3(256), 0, st, T,
+                       wp, ztab, used2, nt, o);
   rc = check_launch("grm_mfma");
   if (rc == PG_OK && n_split > 1) {
     const int64_t blocks = ceil_div(n_tiles * kGT * kGT, 256);

@@ -165,9 +165,11 @@ constexpr int64_t kPruneMaxWindow = 1 << 16;
 // Per-marker z tables and the fp64 matrix-core Gram over the sample-major
 // 2-bit operand T (rows_pad multiple of 128, wp multiple of 4 words).
 // `part` holds the K-split partial sums and counts (grm_part_bytes).
+// waves: 4 (64 x 64 each), 8 (32 x 64) or 16 (32 x 32) waves per 128 x 128
+// tile.
 int launch_grm(const Sel& s, const uint32_t* T, int64_t rows_pad, int64_t wp, double* ztab,
                uint32_t* used2, double* part, double* grm, uint32_t* n_used, int full,
-               hipStream_t st);
+               int waves, hipStream_t st);
 // K split of the relationship-matrix kernel: with fewer than 512
 // upper-triangle tiles of 128 samples, each tile's K chunks of 64 variants
 // are split into up to 16 ranges of at least 16 chunks.

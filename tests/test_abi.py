@@ -195,15 +195,18 @@ def test_grm_workspace_and_validation():
     fake = 0x2000
     g2 = _g(100, 50)
 
-    def call(layout=N.PG_FULL, A=fake, n=fake, ws=1 << 30):
-        return lib.pg_grm_matrix(ctypes.byref(g2), None, 0, 0, 0, layout, A, n, fake, ws, None)
+    def call(layout=N.PG_FULL, A=fake, n=fake, ws=1 << 30, path=0):
+        return lib.pg_grm_matrix(ctypes.byref(g2), None, 0, 0, 0, layout, path, A, n, fake, ws,
+                                 None)
     assert call(layout=7) == N.PG_EINVAL
+    assert call(path=N.PG_PATH_POPC) == N.PG_EINVAL
+    assert call(path=1 << 16) == N.PG_EINVAL
     assert call(A=None) == N.PG_EINVAL
     assert call(n=None) == N.PG_EINVAL
     assert call(ws=64) == N.PG_ENOMEM
     g1 = _g(1, 50)
-    assert lib.pg_grm_matrix(ctypes.byref(g1), None, 0, 0, 0, N.PG_TRI_UPPER, None, None, None, 0,
-                             None) == N.PG_OK
+    assert lib.pg_grm_matrix(ctypes.byref(g1), None, 0, 0, 0, N.PG_TRI_UPPER, 0, None, None, None,
+                             0, None) == N.PG_OK
 
 
 def test_distance_and_cluster_validation():

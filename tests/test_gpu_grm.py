@@ -39,16 +39,22 @@ def _gpu(bed, n, layout, mask=None, **kw):
     return A.cpu().numpy(), N.cpu().numpy().view(np.uint32)
 
 
+# kernel variants: 1 = four waves of 64x64, 2 = eight waves of 32x64 (the
+# default), 3 = sixteen waves of 32x32
+VARIANTS = {"w4": 2 | (1 << 8), "w8": 2 | (2 << 8), "w16": 2 | (3 << 8)}
+
+
+@pytest.mark.parametrize("variant", list(VARIANTS))
 @pytest.mark.parametrize("layout", ["full", "tri"])
 @pytest.mark.parametrize("n,V", [(1, 10), (2, 17), (5, 100), (127, 300), (128, 1000),
                                  (129, 1025), (300, 2000), (513, 700)])
-def test_grm_parity(n, V, layout):
+def test_grm_parity(n, V, layout, variant):
     bed = synth.hwe(n, V, (0.01, 0.5), 0.02, seed=n * 7 + V, garbage_pad=True)
     codes = oracle.unpack(bed, n, V)
     Ar, Nr, Sr = oracle.grm(codes, full=layout == "full")
     if n < 2 and layout == "tri":
         return
-    A, N = _gpu(bed, n, layout)
+    A, N = _gpu(bed, n, layout, path=VARIANTS[variant])
     _compare(A.reshape(Ar.shape), N.reshape(Nr.shape), Ar, Nr, Sr, V)
 
 
@@ -83,13 +89,14 @@ def test_grm_mask_selection_range():
     _compare(A, N, Ar, Nr, Sr, ve - vb)
 
 
-def test_grm_full_size_sampled():
+@pytest.mark.parametrize("variant", list(VARIANTS))
+def test_grm_full_size_sampled(variant):
     """The 10,000 x 71,307 workload the benchmark times: sampled pairs,
     the diagonal and the first row against the oracle, and symmetry."""
     w = synth.grm_large()
     n, V = w["n"], w["V"]
     codes_sm = np.ascontiguousarray(oracle.unpack(w["bed"], n, V).T)
-    A, N = _gpu(w["bed"], n, "full")
+    A, N = _gpu(w["bed"], n, "full", path=VARIANTS[variant])
     assert np.array_equal(A, A.T, equal_nan=True) and np.array_equal(N, N.T)
     rng = np.random.default_rng(5)
     pi = np.concatenate([rng.integers(0, n, 3000), np.arange(n), np.zeros(n, dtype=np.int64)])
