@@ -69,7 +69,7 @@ __global__ __launch_bounds__(256) void k_grm_table(Sel s, int64_t nv_pad, double
 // (upper-triangle tiles only) and one range of K chunks: when the tiles
 // alone cannot fill the chip, each tile's variants are split into ranges
 // whose partial sums a second kernel adds in a fixed order.  Each wave owns 64 x 64 = 4 x 4 blocks of
-// 16 x 16 fp64 accumulators.  K runs over variants in chunks of 64 (four
+// 16 x 16 fp64 accumulators.  K runs over variants in chunks of 128 (eight
 // 2-bit words per sample): the loader stages both blocks' words (with
 // undefined markers overridden to missing), the chunk's z tables and each
 // row's 64-bit non-missing mask in LDS; the next chunk is fetched into
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(256) void k_grm_table(Sel s, int64_t nv_pad, double
 // A[l % 16][l / 16] and B[l / 16][l % 16]; result register r of lane l is
 // D[l / 16 + 4 r][l % 16].
 constexpr int kGT = 128;          // samples per tile side
-constexpr int kGK = 64;           // variants per K chunk
+constexpr int kGK = 128;          // variants per K chunk
 constexpr int kGKW = kGK / 16;    // 2-bit words per row per chunk
 
 typedef double grm_d4 __attribute__((ext_vector_type(4)));
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(64 * kWR * kWC, 1) void k_grm_mfma(const uint32_t* 
   // LDS (per buffer): codes of the I and J blocks [2][128][4] words, masks
   // [2][128] uint64, z tables [64][4] doubles.
   __shared__ uint32_t s_codes[2][2][kGT][kGKW];
-  __shared__ uint64_t s_mask[2][2][kGT];
+  __shared__ uint64_t s_mask[2][2][kGT][kGKW / 4];
   __shared__ double s_z[2][kGK * 4];
 
   const int64_t tile = blockIdx.x % o.n_tiles;
@@ -161,24 +161,38 @@ __global__ __launch_bounds__(64 * kWR * kWC, 1) void k_grm_mfma(const uint32_t* 
   const int lrow = tid & (kGT - 1), lblk = (tid >> 7) & 1;
   const int64_t grow = (lblk ? J : I) * kGT + lrow;
   const uint4* src = reinterpret_cast<const uint4*>(T + grow * wp);
-  auto fetch = [&](int c, uint4& w, uint4& u, double& z) {
-    w = src[c];
-    u = reinterpret_cast<const uint4*>(used2)[c];
-    z = ztab[(int64_t)c * kGK * 4 + tid];
+  constexpr int kQ = kGKW / 4;      // uint4 pieces per row per chunk
+  struct Fetch {
+    uint4 w[kQ], u[kQ];
+    double z[kGK * 4 / 256];
   };
-  auto stage = [&](int buf, const uint4& w, const uint4& u, double z) {
-    // undefined markers read as missing (code 01)
-    const uint32_t ws[4] = {w.x, w.y, w.z, w.w}, us[4] = {u.x, u.y, u.z, u.w};
-    uint64_t mask = 0;
+  auto fetch = [&](int c, Fetch& f) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const uint32_t undef = ~us[e] & 0x55555555u;
-      const uint32_t x = (ws[e] & ~(undef | (undef << 1))) | undef;
-      s_codes[buf][lblk][lrow][e] = x;
-      mask |= (uint64_t)present16(x) << (16 * e);
+    for (int q = 0; q < kQ; ++q) {
+      f.w[q] = src[c * kQ + q];
+      f.u[q] = reinterpret_cast<const uint4*>(used2)[c * kQ + q];
     }
-    s_mask[buf][lblk][lrow] = mask;
-    s_z[buf][tid] = z;
+#pragma unroll
+    for (int q = 0; q < kGK * 4 / 256; ++q) f.z[q] = ztab[(int64_t)c * kGK * 4 + q * 256 + tid];
+  };
+  auto stage = [&](int buf, const Fetch& f) {
+    // undefined markers read as missing (code 01)
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      const uint32_t ws[4] = {f.w[q].x, f.w[q].y, f.w[q].z, f.w[q].w};
+      const uint32_t us[4] = {f.u[q].x, f.u[q].y, f.u[q].z, f.u[q].w};
+      uint64_t mask = 0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const uint32_t undef = ~us[e] & 0x55555555u;
+        const uint32_t x = (ws[e] & ~(undef | (undef << 1))) | undef;
+        s_codes[buf][lblk][lrow][q * 4 + e] = x;
+        mask |= (uint64_t)present16(x) << (16 * e);
+      }
+      s_mask[buf][lblk][lrow][q] = mask;
+    }
+#pragma unroll
+    for (int q = 0; q < kGK * 4 / 256; ++q) s_z[buf][q * 256 + tid] = f.z[q];
   };
 
   grm_d4 acc[kNA][kNB];
@@ -192,18 +206,17 @@ __global__ __launch_bounds__(64 * kWR * kWC, 1) void k_grm_mfma(const uint32_t* 
       for (int r = 0; r < 4; ++r) cnt[a][b][r] = 0;
     }
 
-  uint4 pw, pu;
-  double pz;
+  Fetch pf;
   if (c_begin < c_end && loader) {
-    fetch(c_begin, pw, pu, pz);
-    stage(0, pw, pu, pz);
+    fetch(c_begin, pf);
+    stage(0, pf);
   }
   __syncthreads();
   const int kq = lane >> 4;          // this lane's K index inside a step
   const int r16 = lane & 15;
   for (int c = c_begin; c < c_end; ++c) {
     const int buf = (c - c_begin) & 1;
-    if (c + 1 < c_end && loader) fetch(c + 1, pw, pu, pz);
+    if (c + 1 < c_end && loader) fetch(c + 1, pf);
     const lds_t* ci = (const lds_t*)&s_codes[buf][0][0][0];
     const lds_t* cj = (const lds_t*)&s_codes[buf][1][0][0];
     const lds_f64* zt = (const lds_f64*)&s_z[buf][0];
@@ -232,21 +245,24 @@ __global__ __launch_bounds__(64 * kWR * kWC, 1) void k_grm_mfma(const uint32_t* 
     }
     // pair counts: rows l / 16 + 4 r of each 16-row block, column l % 16
     {
-      const lds_u64* mi = (const lds_u64*)&s_mask[buf][0][0];
-      const lds_u64* mj = (const lds_u64*)&s_mask[buf][1][0];
-      uint64_t colm[kNB];
+      const lds_u64* mi = (const lds_u64*)&s_mask[buf][0][0][0];
+      const lds_u64* mj = (const lds_u64*)&s_mask[buf][1][0][0];
 #pragma unroll
-      for (int b = 0; b < kNB; ++b) colm[b] = mj[wc * kNB * 16 + b * 16 + r16];
+      for (int q = 0; q < kQ; ++q) {
+        uint64_t colm[kNB];
 #pragma unroll
-      for (int a = 0; a < kNA; ++a)
+        for (int b = 0; b < kNB; ++b) colm[b] = mj[(wc * kNB * 16 + b * 16 + r16) * kQ + q];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const uint64_t rm = mi[wr * kNA * 16 + a * 16 + kq + 4 * r];
+        for (int a = 0; a < kNA; ++a)
 #pragma unroll
-          for (int b = 0; b < kNB; ++b) cnt[a][b][r] += (uint32_t)__popcll(rm & colm[b]);
-        }
+          for (int r = 0; r < 4; ++r) {
+            const uint64_t rm = mi[(wr * kNA * 16 + a * 16 + kq + 4 * r) * kQ + q];
+#pragma unroll
+            for (int b = 0; b < kNB; ++b) cnt[a][b][r] += (uint32_t)__popcll(rm & colm[b]);
+          }
+      }
     }
-    if (c + 1 < c_end && loader) stage(buf ^ 1, pw, pu, pz);
+    if (c + 1 < c_end && loader) stage(buf ^ 1, pf);
     __syncthreads();
   }
 
