@@ -382,7 +382,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--quick", action="store_true", help="default workload only, no extras")
     ap.add_argument("--extras", default="all",
-                    help="comma list of extras: other,small,ld,prune,grm,cluster,batch,serve "
+                    help="comma list of extras: other,small,ld,prune,grm,cluster,peaks,batch,serve "
                          "(or all / none)")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--serve-seconds", type=float, default=60.0)
@@ -468,7 +468,7 @@ def main():
     extras = {}
     want = set()
     if not args.quick:
-        everything = {"other", "small", "ld", "prune", "grm", "cluster", "batch", "serve"}
+        everything = {"other", "small", "ld", "prune", "grm", "cluster", "peaks", "batch", "serve"}
         want = everything if args.extras == "all" else \
             set(x for x in args.extras.split(",") if x and x != "none")
     if "other" in want:
@@ -560,6 +560,16 @@ def main():
             extras[key] = bench_cluster(torch, lib, hip, pg, wc, dev, 3)
             cluster_runs.append((key, wc))
             torch.cuda.empty_cache()
+
+    if "peaks" in want:
+        log("measuring unit throughputs (peak probes)")
+        pk = pg.peak_rates()
+        pk = {k: round(v, 1) for k, v in pk.items()}
+        pk["published"] = {"int8_mfma_tops": PEAK_INT8_TOPS, "fp64_mfma_tflops": PEAK_FP64_TFLOPS,
+                           "valu_bcnt_tops": round(PEAK_VALU_TOPS, 1), "hbm_copy_gbs": PEAK_HBM_GBS}
+        pk["ibs_pair_kernel_frac_of_measured_int8"] = round(
+            roof["achieved"] / pk["int8_mfma_tops"], 4) if path == "mfma" else None
+        extras["peaks"] = pk
 
     if "batch" in want:
         extras["batch"] = bench_batch(torch, lib, hip, pg, synth, dev, args.steps)

@@ -291,6 +291,20 @@ int pg_ibs_cluster(const uint32_t* ibs0, const uint32_t* ibs1, const uint32_t* n
                    int64_t m, pg_merge* merges, void* workspace, size_t workspace_bytes,
                    void* stream);
 
+/* ---- diagnostics -----------------------------------------------------------
+ *
+ * Measured throughput of the units the kernels are bound by, on the current
+ * device, as context for the published peaks:
+ *   out[0]  int8 matrix cores, TOP/s (v_mfma_i32_32x32x32_i8, 2 ops per MAC)
+ *   out[1]  fp64 matrix cores, TFLOP/s (v_mfma_f64_16x16x4_f64)
+ *   out[2]  vector popcount-add, T lane-ops/s (v_bcnt_u32_b32)
+ *   out[3]  HBM device-to-device copy, GB/s counting bytes read + written
+ * Each probe is timed with HIP events on the default stream after a warm-up
+ * run; the call returns when all are done.  `workspace` (device) needs at
+ * least 4 MiB + 64 MiB; the copy uses the rest of it (split in two halves).
+ */
+int pg_peak_rates(void* workspace, size_t workspace_bytes, double* out);
+
 /* ---- batching ------------------------------------------------------------
  *
  * Many independent problems (IBS matrices and LD windows over different

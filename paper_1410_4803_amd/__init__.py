@@ -16,7 +16,7 @@ from ._native import (LD_PAIR, PATHS, LAYOUTS, PgError, load as load_library,  #
 from .api import (Cohort, ibs_matrix, ibs_workspace_bytes, ibs_output_size,  # noqa: F401
                   ld_window, ld_workspace_bytes, ld_records, records_to_numpy, ld_prune,
                   prune_workspace_bytes, grm_matrix, grm_workspace_bytes, ibs_distance,
-                  ibs_cluster, cluster_workspace_bytes, merges_to_numpy)
+                  ibs_cluster, cluster_workspace_bytes, merges_to_numpy, peak_rates)
 from .batch import Batch, IbsProblem, LdProblem  # noqa: F401
 from .tune import Tuner  # noqa: F401
 
@@ -25,4 +25,4 @@ __all__ = ["Cohort", "ibs_matrix", "ibs_workspace_bytes", "ibs_output_size", "ld
            "LAYOUTS", "PgError", "load_library", "last_error", "status_str", "Batch",
            "IbsProblem", "LdProblem", "Tuner", "ld_prune", "prune_workspace_bytes", "grm_matrix",
            "grm_workspace_bytes", "ibs_distance", "ibs_cluster", "cluster_workspace_bytes",
-           "merges_to_numpy"]
+           "merges_to_numpy", "peak_rates"]

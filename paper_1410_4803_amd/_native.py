@@ -26,7 +26,7 @@ PATHS = {"auto": PG_PATH_AUTO, "popc": PG_PATH_POPC, "mfma": PG_PATH_MFMA}
 SYMBOLS = ("pg_status_str", "pg_last_error", "pg_version", "pg_profile_events",
            "pg_ibs_workspace_bytes", "pg_ibs_matrix", "pg_ld_workspace_bytes", "pg_ld_window",
            "pg_prune_workspace_bytes", "pg_ld_prune", "pg_grm_workspace_bytes", "pg_grm_matrix",
-           "pg_ibs_distance", "pg_cluster_workspace_bytes", "pg_ibs_cluster",
+           "pg_ibs_distance", "pg_cluster_workspace_bytes", "pg_ibs_cluster", "pg_peak_rates",
            "pg_batch_plan", "pg_batch_workspace_bytes", "pg_batch_tiles", "pg_batch_upload",
            "pg_batch_launch", "pg_plan_free", "pg_batch_capture", "pg_graph_launch",
            "pg_graph_destroy")
@@ -112,6 +112,8 @@ def load():
     lib.pg_cluster_workspace_bytes.restype = ctypes.c_int
     lib.pg_ibs_cluster.argtypes = [p, p, p, i64, p, p, sz, p]
     lib.pg_ibs_cluster.restype = ctypes.c_int
+    lib.pg_peak_rates.argtypes = [p, sz, p]
+    lib.pg_peak_rates.restype = ctypes.c_int
     pp = ctypes.POINTER(ctypes.c_void_p)
     lib.pg_batch_plan.argtypes = [ctypes.POINTER(Problem), ctypes.c_int, pp]
     lib.pg_batch_plan.restype = ctypes.c_int

@@ -326,3 +326,14 @@ def merges_to_numpy(out: torch.Tensor, m: int) -> np.ndarray:
     """The m - 1 merge records of an ibs_cluster output as a numpy MERGE array."""
     raw = out[:max(m - 1, 0)].contiguous().cpu().numpy()
     return raw.reshape(-1).view(N.MERGE)[:max(m - 1, 0)].copy()
+
+
+def peak_rates(workspace_bytes: int = 2 << 30) -> dict:
+    """Measured int8 / fp64 matrix-core, popcount and HBM-copy throughput of
+    the current device (pg_peak_rates)."""
+    ws = torch.empty(workspace_bytes, dtype=torch.uint8, device="cuda")
+    out = (ctypes.c_double * 4)()
+    N.check(N.load().pg_peak_rates(_ptr(ws), ws.numel(), out), "pg_peak_rates")
+    del ws
+    return {"int8_mfma_tops": out[0], "fp64_mfma_tflops": out[1], "valu_bcnt_tops": out[2],
+            "hbm_copy_gbs": out[3]}

@@ -222,3 +222,11 @@ def test_distance_and_cluster_validation():
     assert lib.pg_ibs_cluster(fake, fake, None, 100, fake, fake, 1 << 30, None) == N.PG_EINVAL
     assert lib.pg_ibs_cluster(fake, fake, fake, 100, None, fake, 1 << 30, None) == N.PG_EINVAL
     assert lib.pg_ibs_cluster(fake, fake, fake, 100, fake, fake, 1000, None) == N.PG_ENOMEM
+
+
+def test_peak_rates_validation():
+    lib = N.load()
+    out = (ctypes.c_double * 4)()
+    assert lib.pg_peak_rates(0x2000, 1 << 30, None) == N.PG_EINVAL
+    assert lib.pg_peak_rates(0x2000, 1 << 20, out) == N.PG_ENOMEM
+    assert lib.pg_peak_rates(None, 1 << 30, out) == N.PG_ENOMEM
