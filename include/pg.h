@@ -3,7 +3,8 @@
  *
  * C ABI of libpg.so.  The library computes, on the GPU, the two pairwise
  * kernels that PLINK 1.9 accelerates with word-level bit operations (Chang et
- * al., "Second-generation PLINK", GigaScience 2015, arXiv 1410.4803):
+ * al., "Second-generation PLINK", GigaScience 2015, arXiv 1410.4803), and the
+ * analyses the paper times on top of them:
  *
  *  - identity-by-state: for every sample pair, the number of markers where
  *    the two samples share 2, 1 or 0 alleles identical by state, and the
@@ -13,7 +14,13 @@
  *  - linkage disequilibrium: for every variant pair within a window, the six
  *    sums n, Sx, Sy, Sxx, Syy, Sxy over the samples where neither call is
  *    missing, and r^2 (section "Bit population count", the expression for r
- *    with missing data).
+ *    with missing data);
+ *  - LD-based pruning, --indep-pairwise (section "Linkage disequilibrium-based
+ *    variant pruning", Table 4);
+ *  - the genomic relationship matrix (section "Partial sum lookup", Table 3);
+ *  - the IBS distance and complete-linkage clustering on it (section
+ *    "Identity-by-state matrices, complete linkage clustering", Table 2);
+ *  - batched execution of many IBS / LD problems in one persistent launch.
  *
  * Input is the PLINK 1 binary genotype payload (.bed without its 3-byte
  * header): variant-major rows of 2-bit codes, four calls per byte, sample k of
@@ -67,7 +74,9 @@ int pg_version(void);
  * kernel and events[k] after its k-th stage, for k < n_events:
  *   pg_ibs_matrix: stage 1 = operand layout, stage 2 = pair kernel;
  *   pg_ld_window:  stage 1 = operand layout and scratch clearing,
- *                  stage 2 = banded pair kernel, 3 = scan, 4 = emit.
+ *                  stage 2 = banded pair kernel, 3 = scan, 4 = emit;
+ *   pg_ld_prune, pg_grm_matrix, pg_ibs_cluster, pg_batch_launch: as
+ *                  documented at each of them.
  * events are hipEvent_t handles created and owned by the caller; they must
  * stay valid while set.  NULL (or n_events = 0) turns recording off.
  * Returns PG_EINVAL for n_events < 0 or > 16.
