@@ -89,7 +89,8 @@ __global__ __launch_bounds__(256) void k_nn_init(const double* __restrict__ D, i
 
 constexpr int kCT = 1024;
 constexpr int kCW = kCT / 64;   // waves
-constexpr int kCU = 4;          // loads in flight per thread in scans
+constexpr int kCU = 4;          // loads in flight per thread in the argmin and the fold
+constexpr int kCR = 8;          // loads in flight per thread in row rescans
 
 __global__ __launch_bounds__(kCT) void k_cluster(double* __restrict__ D, int64_t m,
                                                  double* __restrict__ nn_d, int* __restrict__ nn_j,
@@ -194,15 +195,15 @@ __global__ __launch_bounds__(kCT) void k_cluster(double* __restrict__ D, int64_t
       int l = -1;
       if (k >= 0) {
         const double* row = D + (int64_t)k * m;
-        for (int64_t c0 = k + 1 + gt; c0 < m; c0 += (int64_t)g * 64 * kCU) {
-          double x[kCU];
+        for (int64_t c0 = k + 1 + gt; c0 < m; c0 += (int64_t)g * 64 * kCR) {
+          double x[kCR];
 #pragma unroll
-          for (int u = 0; u < kCU; ++u) {
+          for (int u = 0; u < kCR; ++u) {
             const int64_t c = c0 + (int64_t)u * g * 64;
             x[u] = c < m ? row[c] : nan;
           }
 #pragma unroll
-          for (int u = 0; u < kCU; ++u) take_min(v, l, x[u], (int)(c0 + (int64_t)u * g * 64));
+          for (int u = 0; u < kCR; ++u) take_min(v, l, x[u], (int)(c0 + (int64_t)u * g * 64));
         }
       }
       wave_min(v, l);
