@@ -171,7 +171,21 @@ def bench_prune(torch, lib, hip, pg, wp, dev, steps):
     ach = comps * LD_MFMA_OPS / (band_ms * 1e-3) / 1e12
     kept = int(n_kept.item())
     assert kept == int(keep.sum().item())
-    return {"workload": wp["name"], "path": "mfma", "ms_per_call": round(ms, 3),
+    # the missing-call correction path on the same call (these panels have no
+    # missing calls); identical flags
+    ref_keep = keep.clone()
+    ws_s = torch.empty(pg.prune_workspace_bytes(c, W, path="sparse"), dtype=torch.uint8,
+                       device=dev)
+    ms_s, st_s = timed_steps(torch, lib, hip, lambda: pg.ld_prune(
+        c, W, S, t, path="sparse", keep=keep, n_kept=n_kept, workspace=ws_s), steps, 2, 5)
+    assert torch.equal(keep, ref_keep)
+    del ws_s
+    sparse = {"ms_per_call": round(ms_s, 3),
+              "stages_ms": {"layout": round(mean(st_s[0]), 3),
+                            "band_kernel": round(mean(st_s[1]), 3),
+                            "allele_counts": round(mean(st_s[2]), 3),
+                            "greedy": round(mean(st_s[3]), 3)}}
+    return {"workload": wp["name"], "path": "mfma", "ms_per_call": round(ms, 3), "sparse": sparse,
             "value": round(comps / (ms * 1e-3) / 1e9, 1), "unit": "G/s",
             "kept": kept, "variants": V,
             "stages_ms": {"layout": round(mean(st[0]), 3), "band_kernel": round(band_ms, 3),
@@ -269,7 +283,7 @@ def bench_batch(torch, lib, hip, pg, synth, dev, steps):
             comps += n * (n - 1) / 2 * V
         else:
             W = d["window"]
-            path = tuner.tune("ld", c, window=W, r2_min=d["r2_min"], reps=1)
+            path = tuner.tune("ld", c, window=W, r2_min=d["r2_min"], reps=1, for_batch=True)
             cap = max(1 << 16, 64 * V)
             p = pg.LdProblem(c, window=W, r2_min=d["r2_min"], capacity=cap, path=path)
             comps += sum(min(W, V - 1 - a) for a in range(V)) * n
@@ -497,45 +511,53 @@ def main():
                                          "pair_kernel_us": round(mean(st1[1]) * 1e3, 1)}
 
     if "ld" in want:
-        # LD 5,000 x 500,000, window 1,000, r^2 >= 0.2
-        log("generating the 5000 x 500000 LD panel")
-        wl = synth.ld_large()
-        cl = pg.Cohort.from_numpy(wl["bed"], wl["n"], device=dev)
-        W = wl["window"]
-        Vl = wl["V"]
-        pairs = sum(min(W, Vl - 1 - a) for a in range(Vl))
-        compsl = pairs * wl["n"]
+        # LD 5,000 x 500,000, window 1,000, r^2 >= 0.2 (1% missing calls), and the
+        # same panel without missing calls, where the correction path pays
         cap = 4_000_000
         ol = torch.empty((cap, 64), dtype=torch.uint8, device=dev)
         nl = torch.empty(1, dtype=torch.int64, device=dev)
-        for lpath in ("mfma", "popc"):
-            wkl = torch.empty(pg.ld_workspace_bytes(cl, W, path=lpath), dtype=torch.uint8,
-                              device=dev)
-            msl, stl = timed_steps(torch, lib, hip, lambda: pg.ld_window(
-                cl, W, wl["r2_min"], capacity=cap, out=ol, n_out=nl, workspace=wkl, path=lpath),
-                args.steps if lpath == "mfma" else 3, 2 if lpath == "mfma" else 1, 5)
-            band_ms = mean(stl[1])
-            rec = {"workload": wl["name"], "path": lpath,
-                   "value": round(compsl / (msl * 1e-3) / 1e9, 1), "unit": "G/s",
-                   "ms_per_step": round(msl, 3), "pairs": pairs, "emitted": int(nl.item()),
-                   "stages_ms": {"layout": round(mean(stl[0]), 3),
-                                 "band_kernel": round(band_ms, 3),
-                                 "scan": round(mean(stl[2]), 3), "emit": round(mean(stl[3]), 3)}}
-            if lpath == "mfma":
-                ach = compsl * LD_MFMA_OPS / (band_ms * 1e-3) / 1e12
-                rec["roofline"] = {"bound": "mfma", "kernel": "k_ld_mfma", "unit": "TOP/s",
-                                   "achieved": round(ach, 2), "peak": PEAK_INT8_TOPS,
-                                   "frac": round(ach / PEAK_INT8_TOPS, 4),
-                                   "traffic": traffic_from_profile("k_ld_mfma")}
-            else:
-                ach = compsl * LD_POPC_OPS / (band_ms * 1e-3) / 1e12
-                rec["roofline"] = {"bound": "alu", "kernel": "k_ld_popc", "unit": "TOP/s",
-                                   "achieved": round(ach, 2), "peak": round(PEAK_VALU_TOPS, 2),
-                                   "frac": round(ach / PEAK_VALU_TOPS, 4),
-                                   "traffic": traffic_from_profile("k_ld_popc")}
-            extras[f"ld_large_{lpath}"] = rec
-            del wkl
-        del ol, cl
+        for wl, key, lpaths in ((synth.ld_large(), "ld_large", ("mfma", "sparse", "popc")),
+                                (synth.ld_large_nomiss(), "ld_large_nomiss", ("mfma", "sparse"))):
+            log(f"timing LD windows on {wl['name']}")
+            cl = pg.Cohort.from_numpy(wl["bed"], wl["n"], device=dev)
+            W = wl["window"]
+            Vl = wl["V"]
+            pairs = sum(min(W, Vl - 1 - a) for a in range(Vl))
+            compsl = pairs * wl["n"]
+            for lpath in lpaths:
+                wkl = torch.empty(pg.ld_workspace_bytes(cl, W, path=lpath), dtype=torch.uint8,
+                                  device=dev)
+                msl, stl = timed_steps(torch, lib, hip, lambda: pg.ld_window(
+                    cl, W, wl["r2_min"], capacity=cap, out=ol, n_out=nl, workspace=wkl,
+                    path=lpath), args.steps if lpath != "popc" else 3,
+                    2 if lpath != "popc" else 1, 5)
+                band_ms = mean(stl[1])
+                rec = {"workload": wl["name"], "path": lpath,
+                       "value": round(compsl / (msl * 1e-3) / 1e9, 1), "unit": "G/s",
+                       "ms_per_step": round(msl, 3), "pairs": pairs, "emitted": int(nl.item()),
+                       "stages_ms": {"layout": round(mean(stl[0]), 3),
+                                     "band_kernel": round(band_ms, 3),
+                                     "scan": round(mean(stl[2]), 3),
+                                     "emit": round(mean(stl[3]), 3)}}
+                if lpath == "mfma":
+                    ach = compsl * LD_MFMA_OPS / (band_ms * 1e-3) / 1e12
+                    rec["roofline"] = {"bound": "mfma", "kernel": "k_ld_mfma", "unit": "TOP/s",
+                                       "achieved": round(ach, 2), "peak": PEAK_INT8_TOPS,
+                                       "frac": round(ach / PEAK_INT8_TOPS, 4),
+                                       "traffic": traffic_from_profile("k_ld_mfma")
+                                       if key == "ld_large" else None}
+                elif lpath == "popc":
+                    ach = compsl * LD_POPC_OPS / (band_ms * 1e-3) / 1e12
+                    rec["roofline"] = {"bound": "alu", "kernel": "k_ld_popc", "unit": "TOP/s",
+                                       "achieved": round(ach, 2), "peak": round(PEAK_VALU_TOPS, 2),
+                                       "frac": round(ach / PEAK_VALU_TOPS, 4),
+                                       "traffic": traffic_from_profile("k_ld_popc")}
+                else:
+                    rec["vs_mfma"] = round(extras[f"{key}_mfma"]["ms_per_step"] / msl, 3)
+                extras[f"{key}_{lpath}"] = rec
+                del wkl
+            del cl
+        del ol
 
     prune_runs = []
     if "prune" in want:

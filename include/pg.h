@@ -109,8 +109,27 @@ enum pg_layout {
 enum pg_path {
   PG_PATH_AUTO = 0, /* library picks per shape */
   PG_PATH_POPC = 1, /* bit planes + popcount on the vector ALUs */
-  PG_PATH_MFMA = 2  /* 2-bit codes expanded to int8 indicator features and
+  PG_PATH_MFMA = 2, /* 2-bit codes expanded to int8 indicator features and
                        contracted on the int8 matrix cores */
+  PG_PATH_SPARSE = 3 /* LD only: sum x_a x_b on the int8 matrix cores, the
+                       other five sums from per-variant totals corrected at
+                       the other variant's missing calls (section "Bit
+                       population count": without missing calls only
+                       sum x_a x_b varies per pair).  A tile of 64 x 64
+                       variants runs the PG_PATH_MFMA kernel instead when
+                       one of its variants has more missing calls than a
+                       list slot holds (max(64, ceil(m/16) rounded up to a
+                       multiple of 8), at most 65,528, for m selected
+                       samples) or its 128 variants have more than 4m in
+                       all; variant 1 drops the second limit.  Exact like
+                       the other paths; not available in batches.
+                       Variant 2 (pg_ld_window only) is a diagnostic: no
+                       emission; every pair (a, b) of a tile the path takes
+                       (under variant 1's rule) gets the kernel's own record
+                       at out[(a - v_begin) * window + (b - a - 1)], other
+                       slots are left as they were, capacity must be at
+                       least (v_end - v_begin) * window and *n_out receives
+                       that product. */
 };
 
 /*
@@ -172,6 +191,8 @@ int pg_ld_workspace_bytes(const pg_genotypes* g, int64_t n_sel, int64_t v_begin,
  * number of emitted pairs.  If that exceeds `capacity`, only the first
  * `capacity` pairs (in the same order) are written; the call still succeeds,
  * and the caller may retry with a larger buffer.
+ * path: PG_PATH_POPC, PG_PATH_MFMA (AUTO) or PG_PATH_SPARSE; all give
+ * identical records.
  */
 int pg_ld_window(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_sel,
                  int64_t v_begin, int64_t v_end, int32_t window, double r2_min, pg_ld_pair* out,
@@ -208,8 +229,8 @@ int pg_prune_workspace_bytes(const pg_genotypes* g, int64_t n_sel, int64_t v_beg
  *   keep          device uint8 array of v_end - v_begin flags: 1 = kept,
  *                 0 = dropped; entry v belongs to variant v_begin + v
  *   n_kept        optional device int64: number of kept variants
- *   path          PG_PATH_MFMA or PG_PATH_POPC selects the pair kernel that
- *                 evaluates r2 (both give identical results)
+ *   path          PG_PATH_MFMA, PG_PATH_POPC or PG_PATH_SPARSE selects the
+ *                 pair kernels that evaluate r2 (all give identical results)
  * Stages for pg_profile_events: 1 = operand layout and scratch clearing,
  * 2 = banded pair kernel, 3 = allele counts, 4 = greedy pass.
  */

@@ -17,10 +17,11 @@ LIB_PATH = os.path.join(_HERE, "libpg.so")
 
 PG_OK, PG_EINVAL, PG_ENOMEM, PG_EDEVICE, PG_EUNSUPPORTED = 0, -1, -2, -3, -4
 PG_TRI_UPPER, PG_FULL = 0, 1
-PG_PATH_AUTO, PG_PATH_POPC, PG_PATH_MFMA = 0, 1, 2
+PG_PATH_AUTO, PG_PATH_POPC, PG_PATH_MFMA, PG_PATH_SPARSE = 0, 1, 2, 3
 
 LAYOUTS = {"tri": PG_TRI_UPPER, "full": PG_FULL}
-PATHS = {"auto": PG_PATH_AUTO, "popc": PG_PATH_POPC, "mfma": PG_PATH_MFMA}
+PATHS = {"auto": PG_PATH_AUTO, "popc": PG_PATH_POPC, "mfma": PG_PATH_MFMA,
+         "sparse": PG_PATH_SPARSE}
 
 # ABI symbols (include/pg.h)
 SYMBOLS = ("pg_status_str", "pg_last_error", "pg_version", "pg_profile_events",

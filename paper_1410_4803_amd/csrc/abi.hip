@@ -123,6 +123,9 @@ struct LdPlan {
   int path, variant;
   int64_t rows_pad, words, bm_words;
   int64_t off_D, off_bm, off_cnt, off_off, off_bsum, bytes;
+  // correction path: sample-major operand (t_rows x t_words), lists, stats
+  int64_t t_rows, t_words, off_T, off_lists, off_vst, off_gsum, off_gmax, off_any;
+  int cap;
 };
 
 int plan_ld(const Sel& s, int32_t window, int path_arg, LdPlan& p) {
@@ -131,12 +134,13 @@ int plan_ld(const Sel& s, int32_t window, int path_arg, LdPlan& p) {
   int path = path_arg & 0xFF;
   p.variant = (path_arg >> 8) & 0xFF;
   if (path == PG_PATH_AUTO) path = PG_PATH_MFMA;
-  if (path != PG_PATH_MFMA && path != PG_PATH_POPC) return fail(PG_EINVAL, "unknown path %d", path);
+  if (path != PG_PATH_MFMA && path != PG_PATH_POPC && path != PG_PATH_SPARSE)
+    return fail(PG_EINVAL, "unknown path %d", path);
   p.path = path;
   p.rows_pad = round_up(s.nv, kLdTile);
   p.bm_words = ceil_div(window, 32);
   int64_t operand_bytes;
-  if (path == PG_PATH_MFMA) {
+  if (path == PG_PATH_MFMA || path == PG_PATH_SPARSE) {
     p.words = round_up(ceil_div(s.m, 16), kLdKWords);
     operand_bytes = p.rows_pad * p.words * 4;
   } else {
@@ -149,8 +153,66 @@ int plan_ld(const Sel& s, int32_t window, int path_arg, LdPlan& p) {
   p.off_cnt = c.take(p.rows_pad * 4);
   p.off_off = c.take((p.rows_pad + 1) * 8);
   p.off_bsum = c.take((int64_t)ld_scan_blocks(p.rows_pad) * 8);
+  if (path == PG_PATH_SPARSE) {
+    p.t_rows = round_up(s.m, kIbsMfmaTile);
+    p.t_words = round_up(ceil_div(s.nv, 16), kIbsMfmaKWords);
+    p.cap = ld_sparse_cap(s.m);
+    p.off_T = c.take(p.t_rows * p.t_words * 4);
+    p.off_lists = c.take(p.rows_pad * p.cap * 4);
+    p.off_vst = c.take(p.rows_pad * 16);
+    p.off_gsum = c.take(p.rows_pad / kLdTile * 8);
+    p.off_gmax = c.take(p.rows_pad / kLdTile * 4);
+    p.off_any = c.take(4);
+  }
   p.bytes = c.off;
   return PG_OK;
+}
+
+// Band tiles take the correction path when their two 64-variant groups hold
+// at most 3m/4 missing calls (m selected samples), and only once a quarter
+// of the groups have a diagonal tile that does, so that the sample-major
+// operand is worth building.  Measured on 5,000 samples: the correction
+// kernel costs as much as the dense one at about 0.9m per tile.  Variants 1
+// and 2 take every tile whose lists fit.
+int64_t ld_sparse_budget(const LdPlan& p, int64_t m) {
+  return p.variant == 1 || p.variant == 2 ? INT64_MAX : 3 * m / 4;
+}
+uint32_t ld_sparse_min_groups(const LdPlan& p) {
+  const int64_t g = p.rows_pad / kLdTile;
+  return p.variant == 1 || p.variant == 2 ? 1u : (uint32_t)(g < 4 ? 1 : g / 4);
+}
+
+// Operand layouts and the pair kernels of an LD plan, up to the emission
+// bitmap (stage events 1 and 2).
+int ld_pairs(const Sel& s, const LdPlan& p, char* ws, int32_t window, double r2_min,
+             const LdScratch& sc, hipStream_t st, pg_ld_pair* dbg = nullptr) {
+  uint32_t* D = (uint32_t*)(ws + p.off_D);
+  int rc;
+  if (p.path == PG_PATH_POPC) {
+    rc = launch_ld_planes(s, D, p.rows_pad, p.words, st);
+    if (rc == PG_OK) rc = ld_clear(sc, p.rows_pad, st);
+    mark_stage(1, st);
+    if (rc != PG_OK) return rc;
+    return launch_ld_popc(D, p.words, s.nv, p.rows_pad, window, r2_min, sc, st);
+  }
+  rc = launch_variant_major_2bit(s, D, p.rows_pad, p.words, st);
+  if (rc == PG_OK) rc = ld_clear(sc, p.rows_pad, st);
+  if (p.path == PG_PATH_MFMA) {
+    mark_stage(1, st);
+    if (rc != PG_OK) return rc;
+    return launch_ld_mfma(D, p.words, s.nv, p.rows_pad, window, r2_min, sc, st);
+  }
+  LdSparse sp{(uint32_t*)(ws + p.off_lists), (int4*)(ws + p.off_vst), (int64_t*)(ws + p.off_gsum),
+              (int*)(ws + p.off_gmax), (uint32_t*)(ws + p.off_any), ld_sparse_min_groups(p),
+              p.cap, ld_sparse_budget(p, s.m)};
+  uint32_t* T = (uint32_t*)(ws + p.off_T);
+  if (rc == PG_OK) rc = launch_ld_sparse_stats(D, p.words, p.t_words, s.m, s.nv, p.rows_pad, sp, st);
+  // the sample-major operand only when the path is on
+  if (rc == PG_OK) rc = launch_ld_transpose(D, p.rows_pad, p.words, T, p.t_rows, p.t_words, sp, st);
+  mark_stage(1, st);
+  if (rc != PG_OK) return rc;
+  return launch_ld_sparse(D, p.words, T, p.t_words, s.m, s.nv, p.rows_pad, window, r2_min, sc, sp,
+                          st, dbg, s.v0);
 }
 
 struct PrunePlan {
@@ -226,6 +288,8 @@ int batch_validate_ld(const pg_problem& q, Sel& s, int& path, int& variant, int6
   LdPlan p;
   rc = plan_ld(s, q.window, q.path, p);
   if (rc != PG_OK) return rc;
+  if (p.path == PG_PATH_SPARSE)
+    return fail(PG_EUNSUPPORTED, "the missing-call correction path is not available in batches");
   path = p.path;
   variant = p.variant;
   rows_pad = p.rows_pad;
@@ -350,17 +414,22 @@ int pg_ld_window(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_sel
   uint32_t* D = (uint32_t*)(ws + p.off_D);
   LdScratch sc{(uint32_t*)(ws + p.off_bm), p.bm_words, (uint32_t*)(ws + p.off_cnt),
                (int64_t*)(ws + p.off_off), (int64_t*)(ws + p.off_bsum)};
-  const bool planes = p.path == PG_PATH_POPC;
   mark_stage(0, st);
-  rc = planes ? launch_ld_planes(s, D, p.rows_pad, p.words, st)
-              : launch_variant_major_2bit(s, D, p.rows_pad, p.words, st);
-  if (rc == PG_OK) rc = ld_clear(sc, p.rows_pad, st);
-  mark_stage(1, st);
+  if (p.path == PG_PATH_SPARSE && p.variant == 2) {
+    // diagnostic: the correction kernel's own record of every pair it takes
+    const int64_t slots = s.nv * (int64_t)window;
+    if (capacity < slots)
+      return fail(PG_EINVAL, "capacity %lld < %lld slots of the diagnostic variant",
+                  (long long)capacity, (long long)slots);
+    rc = ld_pairs(s, p, ws, window, r2_min, sc, st, out);
+    if (rc == PG_OK) rc = fill_u32((uint32_t*)n_out, 1, (uint32_t)(slots & 0xFFFFFFFF), st);
+    if (rc == PG_OK) rc = fill_u32((uint32_t*)n_out + 1, 1, (uint32_t)(slots >> 32), st);
+    return rc;
+  }
+  rc = ld_pairs(s, p, ws, window, r2_min, sc, st);
   if (rc == PG_OK)
-    rc = planes ? launch_ld_popc(D, p.words, s.nv, p.rows_pad, window, r2_min, sc, st)
-                : launch_ld_mfma(D, p.words, s.nv, p.rows_pad, window, r2_min, sc, st);
-  if (rc == PG_OK)
-    rc = launch_ld_finish(D, planes, p.words, p.rows_pad, s.nv, s.v0, sc, out, capacity, n_out, st);
+    rc = launch_ld_finish(D, p.path == PG_PATH_POPC, p.words, p.rows_pad, s.nv, s.v0, sc, out,
+                          capacity, n_out, st);
   return rc;
 }
 
@@ -391,6 +460,8 @@ int pg_ld_prune(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_sel,
   PrunePlan p;
   rc = plan_prune(s, window, step, path, p);
   if (rc != PG_OK) return rc;
+  if (p.ld.path == PG_PATH_SPARSE && p.ld.variant == 2)
+    return fail(PG_EINVAL, "variant 2 of the correction path is a pg_ld_window diagnostic");
   if ((int64_t)workspace_bytes < p.bytes || !workspace)
     return fail(PG_ENOMEM, "workspace of %llu bytes < %lld required",
                 (unsigned long long)workspace_bytes, (long long)p.bytes);
@@ -405,13 +476,7 @@ int pg_ld_prune(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_sel,
   // r2 > t  <=>  r2 >= the next double above t
   const double r2_min = nextafter(r2_threshold, INFINITY);
   mark_stage(0, st);
-  rc = planes ? launch_ld_planes(s, D, q.rows_pad, q.words, st)
-              : launch_variant_major_2bit(s, D, q.rows_pad, q.words, st);
-  if (rc == PG_OK) rc = ld_clear(sc, q.rows_pad, st);
-  mark_stage(1, st);
-  if (rc == PG_OK)
-    rc = planes ? launch_ld_popc(D, q.words, s.nv, q.rows_pad, window - 1, r2_min, sc, st)
-                : launch_ld_mfma(D, q.words, s.nv, q.rows_pad, window - 1, r2_min, sc, st);
+  rc = ld_pairs(s, q, ws, window - 1, r2_min, sc, st);
   if (rc == PG_OK) rc = launch_variant_stats(D, planes, q.words, q.rows_pad, s.nv, stats, st);
   mark_stage(3, st);
   if (rc == PG_OK)

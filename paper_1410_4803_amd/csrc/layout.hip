@@ -46,45 +46,16 @@ __device__ __forceinline__ uint32_t row_word16(const Sel& s, int64_t v, int64_t 
   return w;
 }
 
-// In-place transpose of a 16x16 matrix of 2-bit elements: element (r, c) at
-// bits 2c of x[r] moves to bits 2r of x[c].  Recursive block swap: exchange
-// the off-diagonal halves, then transpose each half-size block.
-__device__ __forceinline__ void transpose16_2bit(uint32_t x[16]) {
-#pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    const uint32_t t = ((x[r] >> 16) ^ x[r + 8]) & 0x0000FFFFu;
-    x[r] ^= t << 16;
-    x[r + 8] ^= t;
-  }
-#pragma unroll
-  for (int r = 0; r < 16; ++r)
-    if ((r & 4) == 0) {
-      const uint32_t t = ((x[r] >> 8) ^ x[r + 4]) & 0x00FF00FFu;
-      x[r] ^= t << 8;
-      x[r + 4] ^= t;
-    }
-#pragma unroll
-  for (int r = 0; r < 16; ++r)
-    if ((r & 2) == 0) {
-      const uint32_t t = ((x[r] >> 4) ^ x[r + 2]) & 0x0F0F0F0Fu;
-      x[r] ^= t << 4;
-      x[r + 2] ^= t;
-    }
-#pragma unroll
-  for (int r = 0; r < 16; r += 2) {
-    const uint32_t t = ((x[r] >> 2) ^ x[r + 1]) & 0x33333333u;
-    x[r] ^= t << 2;
-    x[r + 1] ^= t;
-  }
-}
-
 // Sample-major 2-bit words without a sample list: a thread owns 16 samples x
 // 64 variants (four 16x16 transposes) and writes four consecutive words per
 // sample row.  Lanes take consecutive sample groups, so the row reads
 // coalesce.
 __global__ __launch_bounds__(256) void k_sample_major_fast(Sel s, uint32_t* __restrict__ T,
                                                            int64_t rows_pad, int64_t wp,
-                                                           int aligned) {
+                                                           int aligned,
+                                                           const uint32_t* __restrict__ gate,
+                                                           uint32_t gate_min) {
+  if (gate && *gate < gate_min) return;
   const int64_t groups = rows_pad / 16;
   const int64_t quads = wp / 4;
   const int64_t total = groups * quads;
@@ -297,7 +268,10 @@ constexpr int kSmSamples = 64;
 constexpr int kSmWords = 64;
 
 __global__ __launch_bounds__(256) void k_sample_major_2bit(Sel s, uint32_t* __restrict__ T,
-                                                           int64_t rows_pad, int64_t wp) {
+                                                           int64_t rows_pad, int64_t wp,
+                                                           const uint32_t* __restrict__ gate,
+                                                           uint32_t gate_min) {
+  if (gate && *gate < gate_min) return;
   __shared__ uint32_t tile[kSmSamples][kSmWords + 1];
   const int t = threadIdx.x;
   const int64_t nbi = ceil_div(rows_pad, kSmSamples);
@@ -329,14 +303,15 @@ __global__ __launch_bounds__(256) void k_sample_major_2bit(Sel s, uint32_t* __re
 }
 
 int launch_sample_major_2bit(const Sel& s, uint32_t* T, int64_t rows_pad, int64_t wp,
-                             hipStream_t st) {
+                             hipStream_t st, const uint32_t* gate, uint32_t gate_min) {
   if (!s.idx && (wp % 4) == 0) {
     hipLaunchKernelGGL(k_sample_major_fast, dim3(stride_grid(rows_pad / 16 * (wp / 4))), dim3(256),
-                       0, st, s, T, rows_pad, wp, (int)rows_dword_aligned(s));
+                       0, st, s, T, rows_pad, wp, (int)rows_dword_aligned(s), gate, gate_min);
     return check_launch("sample_major_fast");
   }
   dim3 grid((unsigned)(ceil_div(rows_pad, kSmSamples) * ceil_div(wp, kSmWords)));
-  hipLaunchKernelGGL(k_sample_major_2bit, grid, dim3(256), 0, st, s, T, rows_pad, wp);
+  hipLaunchKernelGGL(k_sample_major_2bit, grid, dim3(256), 0, st, s, T, rows_pad, wp, gate,
+                     gate_min);
   return check_launch("sample_major_2bit");
 }
 

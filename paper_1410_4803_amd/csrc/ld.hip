@@ -58,25 +58,33 @@ int launch_ld_popc(const uint32_t* P, int64_t words_pad, int64_t nv, int64_t row
 
 __global__ __launch_bounds__(256, 2) void k_ld_mfma(const uint32_t* __restrict__ D, int64_t wn,
                                                     int64_t nv, int64_t n_row_tiles, int64_t n_band,
-                                                    int32_t window, double r2_min, LdScratch sc) {
+                                                    int32_t window, double r2_min, LdScratch sc,
+                                                    const int64_t* __restrict__ gsum,
+                                                    const int* __restrict__ gmax,
+                                                    const uint32_t* __restrict__ groups_ok,
+                                                    uint32_t min_groups, int cap, int64_t budget) {
   const int64_t b = xcd_swizzle(blockIdx.x, gridDim.x);
   const int64_t I = b / n_band;
   const int64_t J = I + b % n_band;
   if (J >= n_row_tiles) return;
+  if (gsum && ld_tile_sparse(gsum, gmax, groups_ok, min_groups, I, J, cap, budget))
+    return;   // the correction path's
   __shared__ __attribute__((aligned(16))) uint32_t smem[kLdMfmaSmem];
   ld_mfma_tile(D, wn, nv, I, J, window, r2_min, sc, (lds_t*)smem);
 }
 
 int launch_ld_mfma(const uint32_t* D, int64_t wn, int64_t nv, int64_t rows_pad, int32_t window,
-                   double r2_min, const LdScratch& sc, hipStream_t st) {
+                   double r2_min, const LdScratch& sc, hipStream_t st, const LdSparse* sp) {
   int rc;
   const int64_t n_row_tiles = rows_pad / kL;
   const int64_t n_band = ((int64_t)window + kL - 1) / kL + 1;
   const int64_t blocks = n_row_tiles * n_band;
   hipLaunchKernelGGL(k_ld_mfma, dim3((unsigned)blocks), dim3(256), 0, st, D, wn, nv, n_row_tiles,
-                     n_band, window, r2_min, sc);
+                     n_band, window, r2_min, sc, sp ? sp->gsum : nullptr,
+                     sp ? sp->gmax : nullptr, sp ? sp->groups_ok : nullptr,
+                     sp ? sp->min_groups : 0u, sp ? sp->cap : 0, sp ? sp->budget : 0);
   rc = check_launch("ld_mfma");
-  mark_stage(2, st);
+  if (!sp) mark_stage(2, st);
   return rc;
 }
 

@@ -58,11 +58,46 @@ __device__ __forceinline__ void masks_of_word(uint32_t x, uint32_t& p, uint32_t&
   m = ~(lo & ~hi) & 0x55555555u;     // not code 01
 }
 
+// In-place transpose of a 16x16 matrix of 2-bit elements: element (r, c) at
+// bits 2c of x[r] moves to bits 2r of x[c].  Recursive block swap: exchange
+// the off-diagonal halves, then transpose each half-size block.
+__device__ __forceinline__ void transpose16_2bit(uint32_t x[16]) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const uint32_t t = ((x[r] >> 16) ^ x[r + 8]) & 0x0000FFFFu;
+    x[r] ^= t << 16;
+    x[r + 8] ^= t;
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r)
+    if ((r & 4) == 0) {
+      const uint32_t t = ((x[r] >> 8) ^ x[r + 4]) & 0x00FF00FFu;
+      x[r] ^= t << 8;
+      x[r + 4] ^= t;
+    }
+#pragma unroll
+  for (int r = 0; r < 16; ++r)
+    if ((r & 2) == 0) {
+      const uint32_t t = ((x[r] >> 4) ^ x[r + 2]) & 0x0F0F0F0Fu;
+      x[r] ^= t << 4;
+      x[r + 2] ^= t;
+    }
+#pragma unroll
+  for (int r = 0; r < 16; r += 2) {
+    const uint32_t t = ((x[r] >> 2) ^ x[r + 1]) & 0x33333333u;
+    x[r] ^= t << 2;
+    x[r + 1] ^= t;
+  }
+}
+
 // ---- layout kernels (layout.hip) -------------------------------------------
 // Sample-major 2-bit words: T[i*wp + w] holds codes of variants 16w..16w+15
 // of selected sample i (code of variant 16w+t at bits 2t); rows_pad x wp.
+// With `gate`, the kernel does nothing while the device word *gate is below
+// gate_min.
 int launch_sample_major_2bit(const Sel& s, uint32_t* T, int64_t rows_pad, int64_t wp,
-                             hipStream_t st);
+                             hipStream_t st, const uint32_t* gate = nullptr,
+                             uint32_t gate_min = 0);
 // Replicated fp4 operand (matrix-core variant 4): per sample, per group of 8
 // variants, words HR (high code bits at nibble bits 1 and 3) and LR (low code
 // bits at nibble bits 1 and 3, ones at bits 0 and 2); rp words per row.
@@ -135,10 +170,59 @@ int ld_scan_blocks(int64_t nv);
 
 constexpr int kLdPopcKWords = 16;     // 32-bit plane words per K chunk
 
+// Missing-call correction path (ldsparse.hip): per-variant missing-call
+// lists (cap entries per variant, a multiple of 8), counts and totals
+// {c, sum x, sum x^2, 0}, and per 64-variant group the total and largest
+// count.  A tile (I, J) takes the path when ld_tile_sparse holds.
+struct LdSparse {
+  uint32_t* lists;     // rows_pad x cap entries (T byte offsets or sample indices)
+  int4* vst;           // rows_pad
+  int64_t* gsum;       // rows_pad / 64
+  int* gmax;           // rows_pad / 64
+  uint32_t* groups_ok; // 1 word: groups whose diagonal tile qualifies
+  uint32_t min_groups; // the path is on when groups_ok reaches this
+  int cap;
+  int64_t budget;      // largest missing-call total of a tile's two groups
+};
+__device__ inline bool ld_tile_sparse(const int64_t* gsum, const int* gmax,
+                                      const uint32_t* groups_ok, uint32_t min_groups, int64_t I,
+                                      int64_t J, int cap, int64_t budget) {
+  return *groups_ok >= min_groups && gmax[I] <= cap && gmax[J] <= cap &&
+         gsum[I] + gsum[J] <= budget;
+}
+// Slot length of the missing-call lists for m selected samples.
+inline int ld_sparse_cap(int64_t m) {
+  int64_t c = round_up(ceil_div(m, 16), 8);
+  if (c < 64) c = 64;
+  if (c > 65528) c = 65528;
+  return (int)c;
+}
+
 // Clears the emission bitmap and row counts (stage 1 ends after this).
 int ld_clear(const LdScratch& sc, int64_t rows_pad, hipStream_t st);
+// Dense pair kernel over the band; with `sp`, tiles the correction path
+// takes are skipped (and stage 2 is left to that path).
 int launch_ld_mfma(const uint32_t* D, int64_t wn, int64_t nv, int64_t rows_pad, int32_t window,
-                   double r2_min, const LdScratch& sc, hipStream_t st);
+                   double r2_min, const LdScratch& sc, hipStream_t st,
+                   const LdSparse* sp = nullptr);
+// Correction path, first part: lists, counts and totals from D
+// (variant-major, wn words), the group statistics and groups_ok.
+int launch_ld_sparse_stats(const uint32_t* D, int64_t wn, int64_t tw, int64_t m, int64_t nv,
+                           int64_t rows_pad, const LdSparse& sp, hipStream_t st);
+// The sample-major operand of the gathers, transposed from D (t_rows =
+// round_up(m, 128) rows of tw words); nothing when the path is off.
+int launch_ld_transpose(const uint32_t* D, int64_t rows_pad, int64_t wn, uint32_t* T,
+                        int64_t t_rows, int64_t tw, const LdSparse& sp, hipStream_t st);
+// Second part: the dense kernel on the tiles this path leaves, then the
+// correction kernel with D for the Gram and T (sample-major, round_up(m, 128)
+// rows of tw words, built after the first part) for the gathers.  With `dbg`,
+// the dense kernel is not run and each pair of a correction tile writes its
+// record to dbg[a * window + (b - a - 1)] (a, b local; the record holds
+// v0 + a, v0 + b) instead of the emission test.
+int launch_ld_sparse(const uint32_t* D, int64_t wn, const uint32_t* T, int64_t tw, int64_t m,
+                     int64_t nv, int64_t rows_pad, int32_t window, double r2_min,
+                     const LdScratch& sc, const LdSparse& sp, hipStream_t st,
+                     pg_ld_pair* dbg = nullptr, int64_t v0 = 0);
 int launch_ld_popc(const uint32_t* P, int64_t words_pad, int64_t nv, int64_t rows_pad,
                    int32_t window, double r2_min, const LdScratch& sc, hipStream_t st);
 // Row-offset scan, *n_out, and the emit kernel.  X is the operand the pair
@@ -198,8 +282,9 @@ int launch_ibs_cluster(const uint32_t* i0, const uint32_t* i1, const uint32_t* n
 
 // r^2 from exact sums, as documented in pg.h; shared by every LD path so that
 // the emission decision and the emitted value are the same double.
-__device__ __forceinline__ double ld_r2(int64_t n, int64_t sx, int64_t sy, int64_t sxx,
-                                        int64_t syy, int64_t sxy) {
+// Integer route of ld_r2 for sums beyond 2^26 (kept out of line: rare).
+__device__ __noinline__ double ld_r2_wide(int64_t n, int64_t sx, int64_t sy, int64_t sxx,
+                                          int64_t syy, int64_t sxy) {
   const int64_t c = n * sxy - sx * sy;
   const int64_t va = n * sxx - sx * sx;
   const int64_t vb = n * syy - sy * sy;
@@ -207,6 +292,21 @@ __device__ __forceinline__ double ld_r2(int64_t n, int64_t sx, int64_t sy, int64
   const double num = __dmul_rn((double)c, (double)c);
   const double den = __dmul_rn((double)va, (double)vb);
   const double r2 = __ddiv_rn(num, den);
+  return r2 > 1.0 ? 1.0 : r2;
+}
+
+__device__ __forceinline__ double ld_r2(int64_t n, int64_t sx, int64_t sy, int64_t sxx,
+                                        int64_t syy, int64_t sxy) {
+  if (n >= ((int64_t)1 << 26)) return ld_r2_wide(n, sx, sy, sxx, syy, sxy);
+  // every sum is at most n in magnitude, so each product is below 2^52 and
+  // each difference below 2^53: all exact in double, the same values as the
+  // integer route, without 64-bit integer multiplies
+  const double dn = (double)(int)n, dx = (double)(int)sx, dy = (double)(int)sy;
+  const double c = __dsub_rn(__dmul_rn(dn, (double)(int)sxy), __dmul_rn(dx, dy));
+  const double va = __dsub_rn(__dmul_rn(dn, (double)(int)sxx), __dmul_rn(dx, dx));
+  const double vb = __dsub_rn(__dmul_rn(dn, (double)(int)syy), __dmul_rn(dy, dy));
+  if (n == 0 || va == 0.0 || vb == 0.0) return __longlong_as_double(0x7ff8000000000000ll);
+  const double r2 = __ddiv_rn(__dmul_rn(c, c), __dmul_rn(va, vb));
   return r2 > 1.0 ? 1.0 : r2;
 }
 

@@ -24,7 +24,10 @@ IBS_CANDIDATES = {"mfma": N.PG_PATH_MFMA, "mfma_fp4": N.PG_PATH_MFMA | (3 << 8),
 # inside a batch every matrix-core problem runs the default body, so only the
 # path is worth choosing there
 IBS_BATCH_CANDIDATES = {"mfma": N.PG_PATH_MFMA, "popc": N.PG_PATH_POPC}
-LD_CANDIDATES = {"mfma": N.PG_PATH_MFMA, "popc": N.PG_PATH_POPC}
+# batches run the matrix-core and popcount LD tiles; one-problem calls (the
+# serving loop) also have the missing-call correction path
+LD_BATCH_CANDIDATES = {"mfma": N.PG_PATH_MFMA, "popc": N.PG_PATH_POPC}
+LD_CANDIDATES = {"mfma": N.PG_PATH_MFMA, "popc": N.PG_PATH_POPC, "sparse": N.PG_PATH_SPARSE}
 
 
 def _bucket(x: int) -> int:
@@ -110,11 +113,11 @@ class Tuner:
             cap = max(1024, 4 * nv)
             o = torch.empty((cap, 64), dtype=torch.uint8, device=cohort.bed.device)
             n_out = torch.empty(1, dtype=torch.int64, device=cohort.bed.device)
-            for name, code in LD_CANDIDATES.items():
+            cands = LD_BATCH_CANDIDATES if for_batch else LD_CANDIDATES
+            for name, code in cands.items():
                 times[name] = self._time(lambda: api.ld_window(
                     cohort, window, r2_min, capacity=cap, sample_idx=sample_idx, v_range=v_range,
                     path=code, out=o, n_out=n_out), reps)
-            cands = LD_CANDIDATES
         best = min(times, key=times.get)
         self.cache[key] = {"path": cands[best], "choice": best,
                            "ms": {k: round(v, 4) for k, v in times.items()}}

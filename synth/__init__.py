@@ -121,6 +121,14 @@ def ld_large(seed: int = 1002) -> dict:
                 bed=mosaic(n, V, 20, 0.005, 0.001, 0.01, 0.01, seed))
 
 
+def ld_large_nomiss(seed: int = 1002) -> dict:
+    """The LD window workload without missing calls (same generator and
+    seed, missing rate 0): the case where only sum x_a x_b varies per pair."""
+    n, V = 5000, 500000
+    return dict(name="ld_5000x500000_mosaic_w1000_nomiss", n=n, V=V, window=1000, r2_min=0.2,
+                bed=mosaic(n, V, 20, 0.005, 0.001, 0.01, 0.0, seed))
+
+
 def prune_small(seed: int = 1005) -> dict:
     """LD pruning, 1,000 samples x 100,000 variants, founder mosaic (10
     founders, switch 0.01, mutation 0.001, MAF>=0.01), no missing calls;

@@ -58,6 +58,20 @@ def test_workspace_sizes():
     assert rc == 0 and b == 128 * 16 * 4
     rc, b = _ld_ws(_g(5000, 500000), 1000)
     assert rc == 0 and b > 500000 * 320 * 4
+    # correction path: + sample-major operand (5120 x 31264 words), lists of
+    # 320 entries per variant, 16 bytes of totals per variant
+    rc, bs = _ld_ws(_g(5000, 500000), 1000, path=N.PG_PATH_SPARSE)
+    assert rc == 0 and bs >= b + 5120 * 31264 * 4 + 500032 * 320 * 4 + 500032 * 16
+    assert bs < b + 5120 * 31264 * 4 + 500032 * 320 * 4 + 500032 * 16 + (1 << 20)
+    # list slots: max(64, ceil(m/16) rounded up to 8), at most 65528
+    for m, cap in [(1, 64), (1000, 64), (1040, 72), (5000, 320), (2000000, 65528)]:
+        rc, b0 = _ld_ws(_g(m, 64), 1, path=N.PG_PATH_MFMA)
+        rc1, b1 = _ld_ws(_g(m, 64), 1, path=N.PG_PATH_SPARSE)
+        t_rows = -(-m // 128) * 128
+        assert rc == rc1 == 0
+        # operand, lists, totals, then group sums, group maxima and a flag
+        # (each carve rounded up to 256 bytes)
+        assert b1 - b0 == t_rows * 16 * 4 + 64 * cap * 4 + 64 * 16 + 3 * 256, (m, b1 - b0)
 
 
 @pytest.mark.parametrize("kw,code", [
@@ -116,6 +130,10 @@ def test_calls_reject_before_launch():
     rc = lib.pg_ld_window(ctypes.byref(g), None, 0, 0, 0, 10, 0.2, fake, 5, fake, 0, fake,
                           8, None)
     assert rc == N.PG_ENOMEM
+    # diagnostic variant of the correction path: one slot per (variant, distance)
+    rc = lib.pg_ld_window(ctypes.byref(g), None, 0, 0, 0, 10, 0.2, fake, 5, fake,
+                          N.PG_PATH_SPARSE | (2 << 8), fake, 1 << 30, None)
+    assert rc == N.PG_EINVAL and "slots" in N.last_error()
 
 
 def test_batch_plan_validation_names_problem():
@@ -147,6 +165,9 @@ def test_batch_plan_validation_names_problem():
     assert rc == N.PG_EINVAL
     lib.pg_plan_free(plan)
     assert lib.pg_batch_plan(arr, 0, ctypes.byref(plan)) == N.PG_EINVAL
+    arr[2].path = N.PG_PATH_SPARSE      # the correction path is for one-problem calls
+    rc = lib.pg_batch_plan(arr, 3, ctypes.byref(plan))
+    assert rc == N.PG_EUNSUPPORTED and "problem 2" in N.last_error()
 
 
 def _prune_ws(g, W, n_sel=0, vb=0, ve=0, path=0):
@@ -179,6 +200,7 @@ def test_prune_workspace_and_validation():
     assert call(t=float("nan")) == N.PG_EINVAL
     assert call(keep=None) == N.PG_EINVAL
     assert call(path=9) == N.PG_EINVAL
+    assert call(path=N.PG_PATH_SPARSE | (2 << 8)) == N.PG_EINVAL
     assert call(ws=16) == N.PG_ENOMEM
     assert "workspace" in N.last_error()
 

@@ -134,7 +134,8 @@ def test_batch_generated_workload_subset():
             path = tuner.tune("ibs", c, layout="tri", reps=1, for_batch=True)
             probs.append(pg.IbsProblem(c, layout="tri", path=path))
         else:
-            path = tuner.tune("ld", c, window=d["window"], r2_min=d["r2_min"], reps=1)
+            path = tuner.tune("ld", c, window=d["window"], r2_min=d["r2_min"], reps=1,
+                              for_batch=True)
             probs.append(pg.LdProblem(c, window=d["window"], r2_min=d["r2_min"], path=path))
     singles = [_single(p) for p in probs]
     b = pg.Batch(probs)

@@ -15,7 +15,7 @@ pg = pytest.importorskip("paper_1410_4803_amd")
 
 from ldcheck import compare_records as _compare
 
-PATHS = ["mfma", "popc"]
+PATHS = ["mfma", "popc", "sparse"]
 
 
 def _run(bed, n, W, r2_min, mask=None, **kw):

@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 
 pg = pytest.importorskip("paper_1410_4803_amd")
 
-PATHS = ["mfma", "popc"]
+PATHS = ["mfma", "popc", "sparse"]
 
 
 def _gpu(bed, n, W, S, t, mask=None, **kw):
@@ -124,5 +124,6 @@ def test_prune_full_size_small_workload():
     wp = synth.prune_small()
     codes = oracle.unpack(wp["bed"], wp["n"], wp["V"])
     ref = oracle.ld_prune(codes, wp["window"], wp["step"], wp["r2_max"])
-    got = _gpu(wp["bed"], wp["n"], wp["window"], wp["step"], wp["r2_max"], path="mfma")
-    assert np.array_equal(got, ref)
+    for path in ("mfma", "sparse"):
+        got = _gpu(wp["bed"], wp["n"], wp["window"], wp["step"], wp["r2_max"], path=path)
+        assert np.array_equal(got, ref), path
