@@ -123,10 +123,12 @@ enum pg_path {
                        samples) or its 128 variants have more than 3m/4 in
                        all, and every tile does unless a quarter of the
                        64-variant groups pass these tests on their own
-                       (then the extra sample-major operand pays); variant
-                       1 drops the last two rules.  Exact like the other
-                       paths; not available in batches.
-                       Variant 2 (pg_ld_window only) is a diagnostic: no
+                       (then the extra sample-major operand pays).  Exact
+                       like the other paths; not available in batches.
+                       Variant bits: 1 drops the last two rules; 4 forces
+                       the 64-bit gather addressing that operands above
+                       4 GiB use anyway; 2 (pg_ld_window only) is a
+                       diagnostic that implies 1: no
                        emission; every pair (a, b) of a tile the path takes
                        (under variant 1's rule) gets the kernel's own record
                        at out[(a - v_begin) * window + (b - a - 1)], other

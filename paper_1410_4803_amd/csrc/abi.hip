@@ -168,18 +168,22 @@ int plan_ld(const Sel& s, int32_t window, int path_arg, LdPlan& p) {
   return PG_OK;
 }
 
+// Variant bits of the correction path: every tile whose lists fit (1), the
+// diagnostic records (2, implies 1), 64-bit gather addressing (4; always on
+// when the sample-major operand exceeds 4 GiB).
+constexpr int kLdAllTiles = 1, kLdDiag = 2, kLdWide = 4;
+
 // Band tiles take the correction path when their two 64-variant groups hold
 // at most 3m/4 missing calls (m selected samples), and only once a quarter
 // of the groups have a diagonal tile that does, so that the sample-major
 // operand is worth building.  Measured on 5,000 samples: the correction
-// kernel costs as much as the dense one at about 0.9m per tile.  Variants 1
-// and 2 take every tile whose lists fit.
+// kernel costs as much as the dense one at about 0.9m per tile.
 int64_t ld_sparse_budget(const LdPlan& p, int64_t m) {
-  return p.variant == 1 || p.variant == 2 ? INT64_MAX : 3 * m / 4;
+  return p.variant & (kLdAllTiles | kLdDiag) ? INT64_MAX : 3 * m / 4;
 }
 uint32_t ld_sparse_min_groups(const LdPlan& p) {
   const int64_t g = p.rows_pad / kLdTile;
-  return p.variant == 1 || p.variant == 2 ? 1u : (uint32_t)(g < 4 ? 1 : g / 4);
+  return p.variant & (kLdAllTiles | kLdDiag) ? 1u : (uint32_t)(g < 4 ? 1 : g / 4);
 }
 
 // Operand layouts and the pair kernels of an LD plan, up to the emission
@@ -204,7 +208,8 @@ int ld_pairs(const Sel& s, const LdPlan& p, char* ws, int32_t window, double r2_
   }
   LdSparse sp{(uint32_t*)(ws + p.off_lists), (int4*)(ws + p.off_vst), (int64_t*)(ws + p.off_gsum),
               (int*)(ws + p.off_gmax), (uint32_t*)(ws + p.off_any), ld_sparse_min_groups(p),
-              p.cap, ld_sparse_budget(p, s.m)};
+              p.cap, ld_sparse_budget(p, s.m),
+              (p.variant & kLdWide) != 0 || p.t_rows * p.t_words * 4 > (int64_t)UINT32_MAX};
   uint32_t* T = (uint32_t*)(ws + p.off_T);
   if (rc == PG_OK) rc = launch_ld_sparse_stats(D, p.words, p.t_words, s.m, s.nv, p.rows_pad, sp, st);
   // the sample-major operand only when the path is on
@@ -415,7 +420,7 @@ int pg_ld_window(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_sel
   LdScratch sc{(uint32_t*)(ws + p.off_bm), p.bm_words, (uint32_t*)(ws + p.off_cnt),
                (int64_t*)(ws + p.off_off), (int64_t*)(ws + p.off_bsum)};
   mark_stage(0, st);
-  if (p.path == PG_PATH_SPARSE && p.variant == 2) {
+  if (p.path == PG_PATH_SPARSE && (p.variant & kLdDiag)) {
     // diagnostic: the correction kernel's own record of every pair it takes
     const int64_t slots = s.nv * (int64_t)window;
     if (capacity < slots)
@@ -460,7 +465,7 @@ int pg_ld_prune(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_sel,
   PrunePlan p;
   rc = plan_prune(s, window, step, path, p);
   if (rc != PG_OK) return rc;
-  if (p.ld.path == PG_PATH_SPARSE && p.ld.variant == 2)
+  if (p.ld.path == PG_PATH_SPARSE && (p.ld.variant & kLdDiag))
     return fail(PG_EINVAL, "variant 2 of the correction path is a pg_ld_window diagnostic");
   if ((int64_t)workspace_bytes < p.bytes || !workspace)
     return fail(PG_ENOMEM, "workspace of %llu bytes < %lld required",

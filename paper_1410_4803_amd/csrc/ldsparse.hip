@@ -465,14 +465,10 @@ __global__ __launch_bounds__(256) void k_ld_transpose(const uint32_t* __restrict
   }
 }
 
-static bool ld_wide_offsets(int64_t m, int64_t tw) {
-  return round_up(m, kIbsMfmaTile) * tw * 4 > (int64_t)UINT32_MAX;
-}
-
 int launch_ld_sparse_stats(const uint32_t* D, int64_t wn, int64_t tw, int64_t m, int64_t nv,
                            int64_t rows_pad, const LdSparse& sp, hipStream_t st) {
   const dim3 grid((unsigned)ceil_div(rows_pad, 4));
-  if (ld_wide_offsets(m, tw))
+  if (sp.wide)
     hipLaunchKernelGGL(k_ld_vstats<true>, grid, dim3(256), 0, st, D, wn, m, nv, rows_pad, sp.cap,
                        tw * 4, sp.lists, sp.vst);
   else
@@ -508,7 +504,7 @@ int launch_ld_sparse(const uint32_t* D, int64_t wn, const uint32_t* T, int64_t t
   }
   const int64_t n_row_tiles = rows_pad / kLdTile;
   const int64_t n_band = ((int64_t)window + kLdTile - 1) / kLdTile + 1;
-  auto kern = ld_wide_offsets(m, tw) ? k_ld_sparse<true> : k_ld_sparse<false>;
+  auto kern = sp.wide ? k_ld_sparse<true> : k_ld_sparse<false>;
   hipLaunchKernelGGL(kern, dim3((unsigned)(n_row_tiles * n_band)), dim3(256), 0, st, D, wn, T, tw,
                      sp.lists, sp.vst, sp.gsum, sp.gmax, sp.groups_ok, sp.min_groups, sp.cap,
                      sp.budget, m, nv, n_row_tiles, n_band, window, r2_min, sc, dbg, v0);

@@ -183,6 +183,7 @@ struct LdSparse {
   uint32_t min_groups; // the path is on when groups_ok reaches this
   int cap;
   int64_t budget;      // largest missing-call total of a tile's two groups
+  bool wide;           // list entries are sample indices (64-bit gather addresses)
 };
 __device__ inline bool ld_tile_sparse(const int64_t* gsum, const int* gmax,
                                       const uint32_t* groups_ok, uint32_t min_groups, int64_t I,

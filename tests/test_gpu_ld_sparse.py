@@ -18,6 +18,7 @@ pg = pytest.importorskip("paper_1410_4803_amd")
 from ldcheck import compare_records as _compare
 
 SPARSE, FORCE, DIAG = 3, 3 | (1 << 8), 3 | (2 << 8)
+WIDE = 4 << 8     # 64-bit gather addressing (what operands above 4 GiB use)
 FIELDS = ("n", "sx", "sy", "sxx", "syy", "sxy")
 
 
@@ -47,11 +48,11 @@ def _r2(s):
     return r2
 
 
-def _diag(c, W, nv, sample_idx=None, v_range=None):
+def _diag(c, W, nv, sample_idx=None, v_range=None, wide=False):
     slots = nv * W
     out = torch.full((slots, 64), 0xFF, dtype=torch.uint8, device="cuda")
-    out, n_out = pg.ld_window(c, W, 0.0, capacity=slots, path=DIAG, out=out,
-                              sample_idx=sample_idx, v_range=v_range)
+    out, n_out = pg.ld_window(c, W, 0.0, capacity=slots, path=DIAG | (WIDE if wide else 0),
+                              out=out, sample_idx=sample_idx, v_range=v_range)
     assert int(n_out.item()) == slots
     return pg.records_to_numpy(out, slots)
 
@@ -85,18 +86,20 @@ def _check_diag(rec, codes, W, v0=0):
     return int(taken.sum())
 
 
+@pytest.mark.parametrize("wide", [False, True])
 @pytest.mark.parametrize("n,V,W,miss", [(1, 5, 3, 0.05), (2, 40, 7, 0.05), (17, 65, 64, 0.05),
                                         (63, 130, 65, 0.0), (64, 300, 1, 0.05),
                                         (129, 257, 100, 0.02), (300, 700, 257, 0.01),
                                         (1000, 400, 1000, 0.05)])
-def test_sparse_diag_all_pairs(n, V, W, miss):
+def test_sparse_diag_all_pairs(n, V, W, miss, wide):
     bed = synth.mosaic(n, V, switch=0.02, miss=miss, seed=n + V + W, garbage_pad=True)
     codes = oracle.unpack(bed, n, V)
-    rec = _diag(pg.Cohort.from_numpy(bed, n), W, V)
+    rec = _diag(pg.Cohort.from_numpy(bed, n), W, V, wide=wide)
     assert _check_diag(rec, codes, W) > 0
 
 
-def test_sparse_diag_counter_flush():
+@pytest.mark.parametrize("wide", [False, True])
+def test_sparse_diag_counter_flush(wide):
     """More than 248 missing calls per variant: the byte counters are flushed
     into the per-pair cells more than once."""
     n, V, W = 8192, 200, 64
@@ -104,7 +107,7 @@ def test_sparse_diag_counter_flush():
     codes = oracle.unpack(bed, n, V)
     miss = (codes == 1).sum(axis=1)
     assert miss.max() > 248 and miss.max() <= _cap(n)
-    rec = _diag(pg.Cohort.from_numpy(bed, n), W, V)
+    rec = _diag(pg.Cohort.from_numpy(bed, n), W, V, wide=wide)
     assert _check_diag(rec, codes, W) == sum(min(W, V - 1 - a) for a in range(V))
 
 
@@ -130,7 +133,8 @@ def test_sparse_diag_list_slot_boundary():
     _compare(got, ref, -np.inf)
 
 
-def test_sparse_diag_mask_selection_range():
+@pytest.mark.parametrize("wide", [False, True])
+def test_sparse_diag_mask_selection_range(wide):
     n, V, W = 400, 1000, 150
     bed = synth.mosaic(n, V, switch=0.01, miss=0.01, seed=8, garbage_pad=True)
     mask = synth.missing_mask(n, V, 0.03, seed=9)
@@ -139,11 +143,12 @@ def test_sparse_diag_mask_selection_range():
     vb, ve = 77, 911
     codes = oracle.select(oracle.unpack(bed, n, V, mask), idx, vb, ve)
     c = pg.Cohort.from_numpy(bed, n, mask)
-    rec = _diag(c, W, ve - vb, sample_idx=torch.from_numpy(idx).cuda(), v_range=(vb, ve))
+    rec = _diag(c, W, ve - vb, sample_idx=torch.from_numpy(idx).cuda(), v_range=(vb, ve),
+                wide=wide)
     assert _check_diag(rec, codes, W, v0=vb) > 0
 
 
-@pytest.mark.parametrize("path", [SPARSE, FORCE])
+@pytest.mark.parametrize("path", [SPARSE, FORCE, FORCE | WIDE])
 def test_sparse_mixed_tiles_emission(path):
     """Variants 600-700 miss 40% of their calls, so their tiles exceed the
     budget (and the list slots); the dense kernel takes those, the correction
