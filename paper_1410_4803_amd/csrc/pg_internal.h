@@ -311,4 +311,23 @@ __device__ __forceinline__ double ld_r2(int64_t n, int64_t sx, int64_t sy, int64
   return r2 > 1.0 ? 1.0 : r2;
 }
 
+// ld_r2(...) >= r2_min, the emission test, with the division skipped for
+// pairs whose quotient is clearly below r2_min: if c^2 < fl(fl(r2_min * den)
+// * (1 - 2^-50)) then c^2 / den < r2_min (1 - 2^-51), whose rounding is still
+// below r2_min, so the test fails exactly as the full evaluation would.
+// NaN r2 (n, va or vb zero) never passes.
+__device__ __forceinline__ bool ld_r2_reaches(int64_t n, int64_t sx, int64_t sy, int64_t sxx,
+                                              int64_t syy, int64_t sxy, double r2_min) {
+  if (n >= ((int64_t)1 << 26)) return ld_r2_wide(n, sx, sy, sxx, syy, sxy) >= r2_min;
+  const double dn = (double)(int)n, dx = (double)(int)sx, dy = (double)(int)sy;
+  const double c = __dsub_rn(__dmul_rn(dn, (double)(int)sxy), __dmul_rn(dx, dy));
+  const double va = __dsub_rn(__dmul_rn(dn, (double)(int)sxx), __dmul_rn(dx, dx));
+  const double vb = __dsub_rn(__dmul_rn(dn, (double)(int)syy), __dmul_rn(dy, dy));
+  if (n == 0 || va == 0.0 || vb == 0.0) return false;
+  const double num = __dmul_rn(c, c), den = __dmul_rn(va, vb);
+  if (num < __dmul_rn(__dmul_rn(r2_min, den), 1.0 - 0x1p-50)) return false;
+  const double r2 = __ddiv_rn(num, den);
+  return (r2 > 1.0 ? 1.0 : r2) >= r2_min;
+}
+
 }  // namespace pg

@@ -905,8 +905,7 @@ __device__ __forceinline__ v4i ld_lookup(uint32_t lut, const uint32_t c[4]) {
 __device__ __forceinline__ void ld_mark(const LdScratch& sc, int64_t a, int64_t b, double r2_min,
                                         int64_t n, int64_t sx, int64_t sy, int64_t sxx,
                                         int64_t syy, int64_t sxy) {
-  const double r2 = ld_r2(n, sx, sy, sxx, syy, sxy);
-  if (r2 >= r2_min) {
+  if (ld_r2_reaches(n, sx, sy, sxx, syy, sxy, r2_min)) {
     const int64_t d = b - a - 1;
     atomicOr(&sc.bitmap[a * sc.bm_words + (d >> 5)], 1u << (d & 31));
     atomicAdd(&sc.rowcnt[a], 1u);

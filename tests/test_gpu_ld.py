@@ -142,3 +142,34 @@ def test_ld_mask_and_row_stride(n, extra, path):
     got = _run(bed, n, W, -np.inf, mask, path=path)
     assert len(got) == len(ref)
     _compare(got, ref, -np.inf)
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_ld_threshold_exactly_at_pair_values(path):
+    """The emission test is r2 >= r2_min on the library's own double (products,
+    one division, from the exact sums).  With r2_min set to a pair's exact r2,
+    that pair is emitted; one ulp above, it is not; every other pair follows
+    the same rule.  Pins the division-skipping screen of the test."""
+    n, V, W = 300, 400, 50
+    bed = synth.mosaic(n, V, switch=0.02, miss=0.02, seed=57)
+    codes = oracle.unpack(bed, n, V)
+    a = np.repeat(np.arange(V), W)
+    b = a + np.tile(np.arange(1, W + 1), V)
+    a, b = a[b < V], b[b < V]
+    s, _ = oracle.ld_pairs(codes, a, b)
+    nn, sx, sy, sxx, syy, sxy = (s[:, i] for i in range(6))
+    cov, vx, vy = nn * sxy - sx * sy, nn * sxx - sx * sx, nn * syy - sy * sy
+    with np.errstate(divide="ignore", invalid="ignore"):
+        r2 = (cov.astype(np.float64) * cov) / (vx.astype(np.float64) * vy.astype(np.float64))
+    r2 = np.minimum(r2, 1.0)
+    r2[(nn == 0) | (vx == 0) | (vy == 0)] = np.nan
+    c = pg.Cohort.from_numpy(bed, n)
+    rng = np.random.default_rng(3)
+    defined = np.nonzero(~np.isnan(r2))[0]
+    picks = rng.choice(defined, 4, replace=False)
+    for t in [float(r2[k]) for k in picks] + [float(np.nextafter(r2[picks[0]], np.inf))]:
+        got = pg.ld_records(c, W, t, path=path)
+        want = ~np.isnan(r2) & (r2 >= t)
+        key_g = got["a"].astype(np.int64) * V + got["b"]
+        key_w = a[want].astype(np.int64) * V + b[want]
+        assert np.array_equal(np.sort(key_g), np.sort(key_w)), t
