@@ -24,6 +24,11 @@
 // `budget` over its two 64-variant groups) that the corrections cost less
 // than the five dense Grams they replace; the dense kernel runs the other
 // tiles and skips these.
+//
+// Launch order: k_ld_vstats (lists, counts, totals) and k_ld_groups (group
+// statistics, and whether enough groups qualify for the path to be on),
+// k_ld_transpose (T, only when it is on), then the dense kernel and
+// k_ld_sparse, each taking its own tiles.
 #include "tiles.h"
 
 namespace pg {
