@@ -20,7 +20,7 @@
  *  - the genomic relationship matrix (section "Partial sum lookup", Table 3);
  *  - the IBS distance and complete-linkage clustering on it (section
  *    "Identity-by-state matrices, complete linkage clustering", Table 2);
- *  - batched execution of many IBS / LD problems in one persistent launch.
+ *  - batched execution of many IBS / LD problems in persistent launches.
  *
  * Input is the PLINK 1 binary genotype payload (.bed without its 3-byte
  * header): variant-major rows of 2-bit codes, four calls per byte, sample k of
@@ -343,7 +343,8 @@ int pg_peak_rates(void* workspace, size_t workspace_bytes, double* out);
 /* ---- batching ------------------------------------------------------------
  *
  * Many independent problems (IBS matrices and LD windows over different
- * cohorts, sample lists and ranges) in one persistent kernel launch.  Each
+ * cohorts, sample lists and ranges) in persistent kernel launches, one per
+ * kind of tile body (IBS; LD matrix-core; LD popcount).  Each
  * problem's arguments mean exactly what they mean for pg_ibs_matrix /
  * pg_ld_window, and its outputs are identical to a separate call with the
  * same path.  Usage:
@@ -377,21 +378,23 @@ typedef struct pg_problem {
 typedef struct pg_plan pg_plan;   /* host-side plan; owns no device memory */
 
 /* Validates the problems (any failure names the problem) and builds the
- * schedule: the tiles of all problems in one list, problems with the longest
- * tiles first.  *plan must be released with pg_plan_free. */
+ * schedule: the tiles of all problems in one list, grouped by tile body and
+ * with the longest tiles first within a group.  *plan must be released with
+ * pg_plan_free. */
 int pg_batch_plan(const pg_problem* probs, int n_probs, pg_plan** plan);
 /* Device workspace the plan needs: every problem's operand layout and LD
  * scratch, the tile table and the tile counter. */
 int pg_batch_workspace_bytes(const pg_plan* plan, size_t* bytes);
-/* Number of tiles in the list and persistent grid size (informational). */
+/* Number of tiles in the list and the largest persistent grid size
+ * (informational). */
 int pg_batch_tiles(const pg_plan* plan, int64_t* total_tiles, int* grid);
 /* Writes the tile table into `workspace` (a host-to-device copy on `stream`,
  * waited for before returning).  Launches must use this same workspace. */
 int pg_batch_upload(pg_plan* plan, void* workspace, size_t workspace_bytes, void* stream);
-/* Enqueues the whole batch on `stream`: operand layouts, one persistent
- * kernel over all tiles, then LD scans and emits.  Kernels only, so it may be
- * captured into a HIP graph.  Stage events (pg_profile_events): 1 = layouts,
- * 2 = persistent kernel, 3 = LD finish. */
+/* Enqueues the whole batch on `stream`: operand layouts, the persistent
+ * kernels (each over its group of tiles), then LD scans and emits.  Kernels
+ * only, so it may be captured into a HIP graph.  Stage events
+ * (pg_profile_events): 1 = layouts, 2 = persistent kernels, 3 = LD finish. */
 int pg_batch_launch(const pg_plan* plan, void* workspace, size_t workspace_bytes, void* stream);
 void pg_plan_free(pg_plan* plan);
 

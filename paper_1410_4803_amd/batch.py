@@ -2,13 +2,13 @@
 
     probs = [IbsProblem(cohort_a, layout="tri"), LdProblem(cohort_b, window=500, r2_min=0.2)]
     b = Batch(probs)          # plan, workspace, tile table upload; outputs allocated
-    b.capture()               # one HIP graph: layouts, ONE persistent kernel, LD finish
+    b.capture()               # one HIP graph: layouts, persistent kernels, LD finish
     b.replay()                # asynchronous on the current stream
     b.results()               # per problem: IBS tensors or LD records (synchronises)
 
 Every problem's outputs equal a separate pg_ibs_matrix / pg_ld_window call
 with the same path; the library runs all tiles of all problems in one
-persistent kernel.
+persistent kernel per kind of tile body (IBS, LD matrix-core, LD popcount).
 """
 from __future__ import annotations
 

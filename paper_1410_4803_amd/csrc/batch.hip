@@ -1,13 +1,14 @@
-// Batched execution: many independent IBS and LD problems in one persistent
-// launch.
+// Batched execution: many independent IBS and LD problems in at most three
+// persistent launches, one per kind of tile body.
 //
 // A plan validates every problem exactly as the one-problem entry points do,
 // carves one workspace into per-problem operands and LD scratch, and orders
-// the problems longest-tile-first, so that the tiles of all problems form one
-// global list.  A launch enqueues, on one stream: every problem's operand
-// layout (and LD scratch clearing), a reset of the tile counter, ONE
-// persistent kernel whose blocks take tiles from the list with an atomic
-// counter until it is exhausted, and every LD problem's scan and emit.  The
+// the problems by part (IBS, LD matrix-core, LD popcount), longest tile first
+// within each part, so that the tiles of all problems form one global list.
+// A launch enqueues, on one stream: every problem's operand layout (and LD
+// scratch clearing), a reset of the tile counters, one persistent kernel per
+// non-empty part (its blocks take tiles of that part with an atomic counter
+// until the part is exhausted), and every LD problem's scan and emit.  The
 // tile bodies are the same device functions the one-problem kernels run, so
 // results are identical to calling pg_ibs_matrix / pg_ld_window per problem.
 // The sequence contains kernels only (no memset or copy nodes), so it can be
@@ -39,17 +40,33 @@ struct BatchItem {
   LdScratch sc;
 };
 
-__global__ __launch_bounds__(256, 1) void k_batch_persistent(const BatchItem* __restrict__ items,
-                                                             int n_items, int64_t total,
-                                                             unsigned long long* counter) {
-  __shared__ __attribute__((aligned(16))) uint32_t smem[kMaxTileSmem];
+// The global tile list in three parts, one persistent kernel each, so that
+// every tile body runs at its own occupancy: IBS tiles (both paths) at one
+// block per CU (the matrix-core tile's register budget), then LD matrix-core
+// tiles, then LD popcount tiles.
+enum { kPartIbs = 0, kPartLdMfma = 1, kPartLdPopc = 2, kParts = 3 };
+
+__host__ __device__ inline int batch_part(int kind, int path) {
+  return kind == PG_KIND_IBS ? kPartIbs : path == PG_PATH_MFMA ? kPartLdMfma : kPartLdPopc;
+}
+
+// Persistent loop over the tiles [t_begin, t_end) of the global list: every
+// block takes tiles from `counter` until the range is used up.
+template <int kPart>
+__global__ __launch_bounds__(256, kPart == kPartIbs ? 1 : 2) void k_batch_persistent(
+    const BatchItem* __restrict__ items, int n_items, int64_t t_begin, int64_t t_end,
+    unsigned long long* counter) {
+  constexpr int kSmem = kPart == kPartIbs
+                            ? (kIbsMfmaSmem > kIbsPopcSmem ? kIbsMfmaSmem : kIbsPopcSmem)
+                            : kPart == kPartLdMfma ? kLdMfmaSmem : kLdPopcSmem;
+  __shared__ __attribute__((aligned(16))) uint32_t smem[kSmem];
   __shared__ int64_t s_tile;
   for (;;) {
-    if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(counter, 1ull);
+    if (threadIdx.x == 0) s_tile = t_begin + (int64_t)atomicAdd(counter, 1ull);
     __syncthreads();
     const int64_t t = s_tile;
     __syncthreads();
-    if (t >= total) break;   // block-uniform: every block leaves once the list is used up
+    if (t >= t_end) break;   // block-uniform: every block leaves once the range is used up
     int lo = 0, hi = n_items;
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
@@ -57,7 +74,7 @@ __global__ __launch_bounds__(256, 1) void k_batch_persistent(const BatchItem* __
     }
     const BatchItem& it = items[lo];
     const int64_t local = t - it.tile_begin;
-    if (it.kind == PG_KIND_IBS) {
+    if constexpr (kPart == kPartIbs) {
       int64_t I, J;
       tri_tile(local, it.nt, I, J);
       if (it.path == PG_PATH_MFMA) {
@@ -69,10 +86,11 @@ __global__ __launch_bounds__(256, 1) void k_batch_persistent(const BatchItem* __
       const int64_t I = local / it.n_band;
       const int64_t J = I + local % it.n_band;
       if (J < it.nt) {
-        if (it.path == PG_PATH_MFMA)
+        if constexpr (kPart == kPartLdMfma)
           ld_mfma_tile(it.X, it.words, it.nv, I, J, it.window, it.r2_min, it.sc, (lds_t*)smem);
         else
-          ld_popc_tile(it.X, it.words, it.nv, it.rows_pad, I, J, it.window, it.r2_min, it.sc, (lds_t*)smem);
+          ld_popc_tile(it.X, it.words, it.nv, it.rows_pad, I, J, it.window, it.r2_min, it.sc,
+                       (lds_t*)smem);
       }
     }
     __syncthreads();   // LDS is reused by the next tile
@@ -109,10 +127,11 @@ struct ProblemPlan {
 
 struct pg_plan {
   std::vector<ProblemPlan> probs;
-  std::vector<int> order;          // schedule order (indices into probs)
+  std::vector<int> order;          // schedule order (indices into probs), by part
   int64_t total_tiles = 0;
+  int64_t part_begin[kParts + 1] = {0, 0, 0, 0};   // tile range of each part
   int64_t off_items = 0, off_counter = 0, bytes = 0;
-  int grid = 256;
+  int grid[kParts] = {256, 256, 256};
   const void* uploaded_ws = nullptr;
 };
 
@@ -185,28 +204,39 @@ int pg_batch_plan(const pg_problem* probs, int n_probs, pg_plan** out) {
   }
   plan->order.resize(n_probs);
   for (int i = 0; i < n_probs; ++i) plan->order[i] = i;
+  // by part (IBS, LD matrix-core, LD popcount), longest tiles first within one
+  auto part = [&](int k) { return batch_part(plan->probs[k].p.kind, plan->probs[k].path); };
   std::stable_sort(plan->order.begin(), plan->order.end(), [&](int a, int b) {
+    if (part(a) != part(b)) return part(a) < part(b);
     return plan->probs[a].tile_cost > plan->probs[b].tile_cost;
   });
-  int64_t t = 0;
-  for (int k : plan->order) t += plan->probs[k].ntiles;
+  int64_t tiles[kParts] = {0, 0, 0};
+  for (int k : plan->order) tiles[part(k)] += plan->probs[k].ntiles;
+  for (int q = 0; q < kParts; ++q) plan->part_begin[q + 1] = plan->part_begin[q] + tiles[q];
+  const int64_t t = plan->part_begin[kParts];
   plan->total_tiles = t;
   plan->off_items = take(off, (int64_t)sizeof(BatchItem) * n_probs);
-  plan->off_counter = take(off, 8);
+  plan->off_counter = take(off, 8 * kParts);   // one tile counter per kernel
   plan->bytes = off;
-  // persistent grid: resident blocks on this device
-  int dev = 0, cus = 0, per_cu = 0;
-  if (hipGetDevice(&dev) == hipSuccess &&
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_persistent, 256, 0) ==
-          hipSuccess &&
-      cus > 0 && per_cu > 0) {
-    plan->grid = cus * per_cu;
-  } else {
-    (void)hipGetLastError();
-    plan->grid = 256;
-  }
-  if (plan->grid > t) plan->grid = (int)std::max<int64_t>(t, 1);
+  // persistent grids: resident blocks of each kernel on this device
+  auto resident = [](const void* kernel, int64_t tiles) {
+    int dev = 0, cus = 0, per_cu = 0;
+    int64_t g = 256;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) == hipSuccess &&
+        cus > 0 && per_cu > 0) {
+      g = (int64_t)cus * per_cu;
+    } else {
+      (void)hipGetLastError();
+    }
+    return (int)std::max<int64_t>(std::min<int64_t>(g, tiles), 1);
+  };
+  plan->grid[kPartIbs] = resident((const void*)k_batch_persistent<kPartIbs>, tiles[kPartIbs]);
+  plan->grid[kPartLdMfma] =
+      resident((const void*)k_batch_persistent<kPartLdMfma>, tiles[kPartLdMfma]);
+  plan->grid[kPartLdPopc] =
+      resident((const void*)k_batch_persistent<kPartLdPopc>, tiles[kPartLdPopc]);
   *out = plan;
   return PG_OK;
 }
@@ -220,7 +250,11 @@ int pg_batch_workspace_bytes(const pg_plan* plan, size_t* bytes) {
 int pg_batch_tiles(const pg_plan* plan, int64_t* total_tiles, int* grid) {
   if (!plan) return fail(PG_EINVAL, "plan is NULL");
   if (total_tiles) *total_tiles = plan->total_tiles;
-  if (grid) *grid = plan->grid;
+  if (grid) {
+    *grid = 0;   // blocks of the largest persistent launch
+    for (int q = 0; q < kParts; ++q)
+      if (plan->part_begin[q + 1] > plan->part_begin[q]) *grid = std::max(*grid, plan->grid[q]);
+  }
   return PG_OK;
 }
 
@@ -293,12 +327,21 @@ int pg_batch_launch(const pg_plan* plan, void* workspace, size_t workspace_bytes
     if (rc != PG_OK) return rc;
   }
   unsigned long long* counter = (unsigned long long*)(ws + plan->off_counter);
-  rc = fill_u32((uint32_t*)counter, 2, 0u, st);
+  rc = fill_u32((uint32_t*)counter, 2 * kParts, 0u, st);
   if (rc != PG_OK) return rc;
   mark_stage(1, st);
-  hipLaunchKernelGGL(k_batch_persistent, dim3((unsigned)plan->grid), dim3(256), 0, st,
-                     (const BatchItem*)(ws + plan->off_items), (int)plan->probs.size(),
-                     plan->total_tiles, counter);
+  const BatchItem* items = (const BatchItem*)(ws + plan->off_items);
+  const int n_items = (int)plan->probs.size();
+  const int64_t* pb = plan->part_begin;
+  if (pb[1] > pb[0])
+    hipLaunchKernelGGL(k_batch_persistent<kPartIbs>, dim3((unsigned)plan->grid[kPartIbs]),
+                       dim3(256), 0, st, items, n_items, pb[0], pb[1], counter);
+  if (pb[2] > pb[1])
+    hipLaunchKernelGGL(k_batch_persistent<kPartLdMfma>, dim3((unsigned)plan->grid[kPartLdMfma]),
+                       dim3(256), 0, st, items, n_items, pb[1], pb[2], counter + 1);
+  if (pb[3] > pb[2])
+    hipLaunchKernelGGL(k_batch_persistent<kPartLdPopc>, dim3((unsigned)plan->grid[kPartLdPopc]),
+                       dim3(256), 0, st, items, n_items, pb[2], pb[3], counter + 2);
   rc = check_launch("batch_persistent");
   mark_stage(2, st);
   if (rc != PG_OK) return rc;
