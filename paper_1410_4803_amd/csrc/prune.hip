@@ -154,18 +154,23 @@ __device__ __forceinline__ int block_scan(int v, int* wsum, int* total) {
   return base + x - v;
 }
 
+constexpr int kClaim = 1024;               // slots of the per-batch claim table (8 KB)
+
 // Applies staged pairs buf[0, n) in order to the keep ring; wave 0 only.
 // 64 pairs at a time.  One LDS round trip reads both keep bits of every
 // pair (the snapshot).  A pair whose snapshot is live acts -- drops its
 // variant x -- unless an earlier pair of the batch that acted dropped one of
-// its two variants.  Each lane collects the mask K of earlier live pairs
-// whose x is one of its variants (every lane's x is broadcast through LDS).
-// Live pairs with K = 0 act whatever else happens; only the others are taken
-// one by one in pair order, acting when K misses every pair that acted.  The
-// batch's drops are written before the next batch reads the ring (LDS
-// operations of one wave complete in order).
+// its two variants.  Each lane needs the mask K of earlier live pairs whose
+// x is one of its variants: every live lane sets its bit in claim[x mod
+// kClaim], a lane ORs the slots of its two variants and keeps only the
+// earlier pairs whose x (broadcast through xs) really is one of them, then
+// every live lane clears its slot again.  Live pairs with K = 0 act whatever
+// else happens; the others act when K misses every earlier pair that acted,
+// settled in rounds over the whole wave.  The batch's drops are written before
+// the next batch reads the ring (LDS operations of one wave complete in
+// order, which also orders the claim writes, reads and clears).
 __device__ __forceinline__ void apply_pairs(const uint2* buf, int n, uint32_t* ring, uint32_t* xs,
-                                            int lane) {
+                                            unsigned long long* claim, int lane) {
   for (int p0 = 0; p0 < n; p0 += 64) {
     const int np = n - p0 < 64 ? n - p0 : 64;
     // variants are below 2^31: 0xfffffffe / 0xffffffff never match
@@ -180,33 +185,38 @@ __device__ __forceinline__ void apply_pairs(const uint2* buf, int n, uint32_t* r
       x = live ? ((e.y >> 31) ? ea : eb) : 0xffffffffu;
     }
     xs[lane] = x;
-    uint32_t klo = 0, khi = 0;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      uint32_t kk = 0;
-#pragma unroll
-      for (int q4 = 0; q4 < 8; ++q4) {
-        const uint4 v = *reinterpret_cast<const uint4*>(xs + h * 32 + q4 * 4);
-        const uint32_t vs[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (ea == vs[e] || eb == vs[e]) kk |= 1u << (q4 * 4 + e);
+    if (live) atomicOr(&claim[x & (kClaim - 1)], 1ull << lane);
+    uint64_t k = 0;
+    if (live) {
+      // earlier pairs whose x falls in the slots of ea or eb, then exactly
+      k = (claim[ea & (kClaim - 1)] | claim[eb & (kClaim - 1)]) & ((1ull << lane) - 1ull);
+      for (uint64_t c = k; c; c &= c - 1) {
+        const int p = __builtin_ctzll(c);
+        const uint32_t xp = xs[p];
+        if (xp != ea && xp != eb) k &= ~(1ull << p);
       }
-      // only earlier pairs count
-      const int below = lane - h * 32;
-      kk &= below >= 32 ? 0xffffffffu : below <= 0 ? 0u : (1u << below) - 1u;
-      if (h == 0) klo = kk;
-      else khi = kk;
     }
-    const bool free_pair = live && (klo | khi) == 0;
+    if (live) claim[x & (kClaim - 1)] = 0ull;
+    const bool free_pair = live && k == 0;
     uint64_t acted = __ballot(free_pair);
     const uint64_t conflicted = __ballot(live && !free_pair);
-    for (uint64_t rest = conflicted; rest; rest &= rest - 1) {
-      const int p = __builtin_ctzll(rest);
-      // readlane yields int: widen through uint32_t so bit 31 does not spread
-      const uint64_t kp = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(khi, p) << 32) |
-                          (uint64_t)(uint32_t)__builtin_amdgcn_readlane(klo, p);
-      if (!(kp & acted)) acted |= 1ull << p;
+    // Conflicted pairs settle in rounds: a pair is decided once an earlier
+    // pair of its K acted (it does not act) or every pair of its K is decided
+    // and none acted (it acts) -- the same outcome as taking them one by one
+    // in order.  The lowest undecided pair always settles, so this ends.
+    uint64_t decided = ~conflicted;
+    while (conflicted & ~decided) {
+      bool now = false, act = false;
+      if ((conflicted & ~decided) >> lane & 1ull) {
+        if (k & acted) {
+          now = true;
+        } else if ((k & ~decided) == 0) {
+          now = true;
+          act = true;
+        }
+      }
+      decided |= __ballot(now);
+      acted |= __ballot(act);
     }
     if ((acted >> lane) & 1ull) {
       const uint32_t ix = x & (kRingBits - 1);
@@ -250,10 +260,12 @@ __global__ __launch_bounds__(kPT) void k_prune_greedy(const uint32_t* __restrict
   __shared__ uint2 buf[kPBuf];
   __shared__ int wsum[kPT / 64];
   __shared__ __attribute__((aligned(16))) uint32_t xs[64];
+  __shared__ unsigned long long claim[kClaim];
   __shared__ uint16_t s_cc[kPCells * kPT];   // per-cell counts, [cell][thread]
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   for (int i = tid; i < kRingBits / 32; i += kPT) ring[i] = ~0u;
+  for (int i = tid; i < kClaim; i += kPT) claim[i] = 0ull;
   __syncthreads();
   int64_t flushed = 0;
   int64_t kept = 0;
@@ -368,7 +380,7 @@ __global__ __launch_bounds__(kPT) void k_prune_greedy(const uint32_t* __restrict
         }
       }
       __syncthreads();
-      if (tid < 64) apply_pairs(buf, s1 - s0, ring, xs, lane);
+      if (tid < 64) apply_pairs(buf, s1 - s0, ring, xs, claim, lane);
       __syncthreads();
     }
   }
