@@ -222,7 +222,7 @@ int ld_pairs(const Sel& s, const LdPlan& p, char* ws, int32_t window, double r2_
 
 struct PrunePlan {
   LdPlan ld;
-  int64_t off_stats, off_drop, bytes;
+  int64_t off_stats, off_drop, count_cells, off_cc, bytes;
 };
 
 // The LD plan for the pair kernel (largest distance window - 1) plus the
@@ -237,6 +237,8 @@ int plan_prune(const Sel& s, int32_t window, int32_t step, int path_arg, PrunePl
   c.off = p.ld.bytes;
   p.off_stats = c.take(p.ld.rows_pad * (int64_t)sizeof(int2));
   p.off_drop = c.take(p.ld.rows_pad * p.ld.bm_words * 4);
+  p.count_cells = prune_count_capacity(s.nv, window);   // independent of step
+  p.off_cc = c.take(p.count_cells * 2);
   p.bytes = c.off;
   return PG_OK;
 }
@@ -485,8 +487,8 @@ int pg_ld_prune(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_sel,
   if (rc == PG_OK) rc = launch_variant_stats(D, planes, q.words, q.rows_pad, s.nv, stats, st);
   mark_stage(3, st);
   if (rc == PG_OK)
-    rc = launch_prune_greedy(sc, stats, (uint32_t*)(ws + p.off_drop), s.nv, window, step, keep,
-                             n_kept, st);
+    rc = launch_prune_greedy(sc, stats, (uint32_t*)(ws + p.off_drop), (uint16_t*)(ws + p.off_cc),
+                             p.count_cells, s.nv, window, step, keep, n_kept, st);
   mark_stage(4, st);
   return rc;
 }

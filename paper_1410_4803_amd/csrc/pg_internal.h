@@ -241,10 +241,18 @@ int launch_variant_stats(const uint32_t* X, bool planes, int64_t words, int64_t 
 // The greedy pass over the windows, from the pair kernel's bitmap of pairs
 // with r^2 above the threshold (bitmap window = window - 1); `drop` is
 // scratch of the bitmap's size for the drop side of every marked pair.
-int launch_prune_greedy(const LdScratch& sc, const int2* stats, uint32_t* drop, int64_t nv,
-                        int64_t window, int64_t step, uint8_t* keep, int64_t* n_kept,
-                        hipStream_t st);
+// `cc`: scratch for cc_capacity uint16 per-cell counts.  When the call's
+// (window, row) cells, padded to whole passes, fit, they are counted
+// grid-wide first; otherwise (or with cc NULL) the pass counts in its own
+// block.
+int launch_prune_greedy(const LdScratch& sc, const int2* stats, uint32_t* drop, uint16_t* cc,
+                        int64_t cc_capacity, int64_t nv, int64_t window, int64_t step,
+                        uint8_t* keep, int64_t* n_kept, hipStream_t st);
 constexpr int64_t kPruneMaxWindow = 1 << 16;
+// Most per-cell counts kept in scratch (128 MiB of uint16).
+constexpr int64_t kPruneCountCellsMax = (int64_t)1 << 26;
+// Count scratch a pruning plan reserves: enough for any step, capped.
+int64_t prune_count_capacity(int64_t nv, int64_t window);
 
 // ---- relationship matrix (grm.hip) -------------------------------------------
 // Per-marker z tables and the fp64 matrix-core Gram over the sample-major

@@ -250,10 +250,34 @@ __global__ __launch_bounds__(256) void k_prune_dropbits(const uint32_t* __restri
   }
 }
 
+// Marked bits of every (window, row) cell's segment, for the greedy pass's
+// count phase; zero past the last cell (the array is padded to whole passes).
+__global__ __launch_bounds__(256) void k_prune_cellcount(const uint32_t* __restrict__ bitmap,
+                                                         int64_t bm_words, PruneGeom g,
+                                                         int64_t n_windows, int64_t n_pad,
+                                                         uint16_t* __restrict__ cc) {
+  const int64_t n_cells = n_windows * g.W;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_pad;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    int cnt = 0;
+    if (c < n_cells) {
+      int a, j0, j1;
+      cell_bits(g, c / g.W, (int)(c % g.W), a, j0, j1);
+      if (j0 < j1) {
+        const uint32_t* row = bitmap + (int64_t)a * bm_words;
+        for (int q = j0 >> 5; q <= (j1 - 1) >> 5; ++q)
+          cnt += __builtin_popcount(seg_word(row, q, j0, j1));
+      }
+    }
+    cc[c] = (uint16_t)cnt;
+  }
+}
+
 __global__ __launch_bounds__(kPT) void k_prune_greedy(const uint32_t* __restrict__ bitmap,
                                                       int64_t bm_words,
                                                       const uint32_t* __restrict__ drop,
                                                       PruneGeom g, int64_t n_windows,
+                                                      const uint16_t* __restrict__ cc,
                                                       uint8_t* __restrict__ keep,
                                                       int64_t* __restrict__ n_kept) {
   __shared__ uint32_t ring[kRingBits / 32];
@@ -295,7 +319,19 @@ __global__ __launch_bounds__(kPT) void k_prune_greedy(const uint32_t* __restrict
     // segment are loaded together (one memory latency per group); the
     // per-cell counts are kept in LDS for the write phase
     int cnt = 0;
-    {
+    if (cc) {
+      // counts from k_prune_cellcount: this thread's kPCells consecutive cells
+      const uint4* src = reinterpret_cast<const uint4*>(cc + c0 + (int64_t)tid * kPCells);
+      static_assert(kPCells == 16, "two 16-byte loads of eight counts");
+      const uint4 v0 = src[0], v1 = src[1];
+      const uint32_t ws[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+      for (int k = 0; k < kPCells; ++k) {
+        const int c = (int)((ws[k >> 1] >> (16 * (k & 1))) & 0xFFFFu);
+        cnt += c;
+        s_cc[k * kPT + tid] = (uint16_t)c;
+      }
+    } else {
       int64_t w = w_start;
       int r = r_start;
 #pragma unroll
@@ -391,9 +427,20 @@ __global__ __launch_bounds__(kPT) void k_prune_greedy(const uint32_t* __restrict
   if (tid == 0 && n_kept) *n_kept = total;
 }
 
-int launch_prune_greedy(const LdScratch& sc, const int2* stats, uint32_t* drop, int64_t nv,
-                        int64_t window, int64_t step, uint8_t* keep, int64_t* n_kept,
-                        hipStream_t st) {
+int64_t prune_cells_padded(int64_t nv, int64_t window, int64_t step) {
+  const int64_t n_windows = nv <= window ? 1 : ceil_div(nv - window, step) + 1;
+  return round_up(n_windows * window, kPPass);
+}
+
+int64_t prune_count_capacity(int64_t nv, int64_t window) {
+  // step 1 has the most windows, at most nv of them
+  const int64_t worst = round_up(nv * window, kPPass);
+  return worst < kPruneCountCellsMax ? worst : kPruneCountCellsMax;
+}
+
+int launch_prune_greedy(const LdScratch& sc, const int2* stats, uint32_t* drop, uint16_t* cc,
+                        int64_t cc_capacity, int64_t nv, int64_t window, int64_t step,
+                        uint8_t* keep, int64_t* n_kept, hipStream_t st) {
   const int64_t words = nv * sc.bm_words;
   const int64_t blocks = ceil_div(words, 256) < 65536 ? ceil_div(words, 256) : 65536;
   hipLaunchKernelGGL(k_prune_dropbits, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(256), 0, st,
@@ -402,8 +449,17 @@ int launch_prune_greedy(const LdScratch& sc, const int2* stats, uint32_t* drop, 
   if (rc != PG_OK) return rc;
   const int64_t n_windows = nv <= window ? 1 : ceil_div(nv - window, step) + 1;
   const PruneGeom g{nv, window, step};
+  int64_t n_pad = prune_cells_padded(nv, window, step);
+  if (!cc || n_pad > cc_capacity) n_pad = 0;
+  if (n_pad > 0) {
+    const int64_t cb = ceil_div(n_pad, 256) < 65536 ? ceil_div(n_pad, 256) : 65536;
+    hipLaunchKernelGGL(k_prune_cellcount, dim3((unsigned)cb), dim3(256), 0, st, sc.bitmap,
+                       sc.bm_words, g, n_windows, n_pad, cc);
+    rc = check_launch("prune_cellcount");
+    if (rc != PG_OK) return rc;
+  }
   hipLaunchKernelGGL(k_prune_greedy, dim3(1), dim3(kPT), 0, st, sc.bitmap, sc.bm_words, drop, g,
-                     n_windows, keep, n_kept);
+                     n_windows, n_pad > 0 ? cc : nullptr, keep, n_kept);
   return check_launch("prune_greedy");
 }
 

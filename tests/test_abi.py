@@ -183,9 +183,16 @@ def test_prune_workspace_and_validation():
     rc, b = _prune_ws(g, 50)
     _, ld = _ld_ws(g, 49)
     # the LD scratch of the pair kernel (largest distance window - 1), one
-    # int2 of allele counts per padded variant, and a drop-side bitmap of the
-    # pair kernel's bitmap size (2 words per row for window 50)
-    assert rc == 0 and b == ld + 100032 * 8 + 100032 * 2 * 4
+    # int2 of allele counts per padded variant, a drop-side bitmap of the
+    # pair kernel's bitmap size (2 words per row for window 50), and uint16
+    # counts of the (window, row) cells for the smallest step (at most one
+    # window per variant: 100,000 x 50 cells), rounded up to passes of 16,384
+    cells = -(-100000 * 50 // 16384) * 16384
+    assert rc == 0 and b == ld + 100032 * 8 + 100032 * 2 * 4 + cells * 2
+    # capped at 2^26 cells
+    rc, b2 = _prune_ws(_g(1000, 2000000), 1000)
+    _, ld2 = _ld_ws(_g(1000, 2000000), 999)
+    assert rc == 0 and b2 == ld2 + 2000000 * 8 + 2000000 * 32 * 4 + (1 << 26) * 2
     assert _prune_ws(g, 1)[0] == N.PG_EINVAL
     assert _prune_ws(g, (1 << 16) + 1)[0] == N.PG_EINVAL
     assert _prune_ws(g, 1 << 16)[0] == 0

@@ -74,6 +74,26 @@ def test_prune_ring_wraps():
     assert 0 < ref.sum() < V
 
 
+@pytest.mark.parametrize("path", ["mfma", "sparse"])
+def test_prune_step_one(path):
+    """Step 1: the most (window, row) cells a window allows, all counted
+    grid-wide in the workspace the step-free size query reserves."""
+    n, V = 64, 3000
+    bed = synth.mosaic(n, V, 4, 0.01, 0.001, 0.0, 0.01, seed=31)
+    ref = _check(bed, n, V, 100, 1, 0.4, path)
+    assert 0 < ref.sum() < V
+
+
+def test_prune_cells_beyond_the_count_scratch():
+    """More than 2^26 (window, row) cells: the greedy pass counts its cells
+    in its own block instead."""
+    n, V = 16, 300000
+    assert (V - 300 + 1) * 300 > 1 << 26
+    bed = synth.mosaic(n, V, 3, 0.05, 0.001, 0.0, 0.0, seed=32)
+    ref = _check(bed, n, V, 300, 1, 0.5, "mfma")
+    assert 0 < ref.sum() < V
+
+
 def test_prune_no_threshold_crossing():
     n, V = 100, 400
     bed = synth.mosaic(n, V, 3, 0.01, 0.001, 0.0, 0.0, seed=24)
