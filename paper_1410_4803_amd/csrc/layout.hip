@@ -25,9 +25,19 @@ __device__ __forceinline__ uint32_t row_word16(const Sel& s, int64_t v, int64_t 
   const int64_t row = s.v0 + v;
   const uint8_t* p = s.bed + row * s.bpv + 4 * g;
   const int64_t avail = s.bpv - 4 * g;          // bytes of this row from byte 4g on
+  // a row that does not start on a dword: two aligned dwords, shifted, as
+  // long as both lie inside the selected rows of the caller's buffer
+  const uintptr_t pa = reinterpret_cast<uintptr_t>(p) & ~(uintptr_t)3;
+  const uintptr_t first = reinterpret_cast<uintptr_t>(s.bed + s.v0 * s.bpv);
+  const uintptr_t end = reinterpret_cast<uintptr_t>(s.bed + (s.v0 + s.nv) * s.bpv);
   uint32_t w;
   if (aligned && avail >= 4) {
     w = *reinterpret_cast<const uint32_t*>(p);
+  } else if (avail >= 4 && pa >= first && pa + 8 <= end) {
+    const uint32_t lo = *reinterpret_cast<const uint32_t*>(pa);
+    const uint32_t hi = *reinterpret_cast<const uint32_t*>(pa + 4);
+    const int sh = 8 * (int)(reinterpret_cast<uintptr_t>(p) & 3);
+    w = (uint32_t)((((uint64_t)hi << 32) | lo) >> sh);
   } else {
     w = 0;
     for (int b = 0; b < 4; ++b)
