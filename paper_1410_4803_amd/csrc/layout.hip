@@ -7,9 +7,6 @@
 namespace pg {
 
 // ---- helpers for whole-matrix selections (no sample list) -------------------
-// Sixteen consecutive samples of one variant row as a 2-bit word (sample
-// 16g + k at bits 2k), with the missing mask applied and samples >= m forced
-// to missing.  Reads one dword when the row layout allows it, else bytes.
 __device__ __forceinline__ uint32_t spread16(uint32_t x) {
   // bit k -> bit 2k, for the low 16 bits
   x &= 0xFFFFu;
@@ -20,71 +17,120 @@ __device__ __forceinline__ uint32_t spread16(uint32_t x) {
   return x;
 }
 
-__device__ __forceinline__ uint32_t row_word16(const Sel& s, int64_t v, int64_t g, bool aligned) {
-  if (v >= s.nv) return kAllMissing16;
-  const int64_t row = s.v0 + v;
-  const uint8_t* p = s.bed + row * s.bpv + 4 * g;
-  const int64_t avail = s.bpv - 4 * g;          // bytes of this row from byte 4g on
-  // a row that does not start on a dword: two aligned dwords, shifted, as
-  // long as both lie inside the selected rows of the caller's buffer
-  const uintptr_t pa = reinterpret_cast<uintptr_t>(p) & ~(uintptr_t)3;
-  const uintptr_t first = reinterpret_cast<uintptr_t>(s.bed + s.v0 * s.bpv);
-  const uintptr_t end = reinterpret_cast<uintptr_t>(s.bed + (s.v0 + s.nv) * s.bpv);
-  uint32_t w;
-  if (aligned && avail >= 4) {
-    w = *reinterpret_cast<const uint32_t*>(p);
-  } else if (avail >= 4 && pa >= first && pa + 8 <= end) {
-    const uint32_t lo = *reinterpret_cast<const uint32_t*>(pa);
-    const uint32_t hi = *reinterpret_cast<const uint32_t*>(pa + 4);
-    const int sh = 8 * (int)(reinterpret_cast<uintptr_t>(p) & 3);
-    w = (uint32_t)((((uint64_t)hi << 32) | lo) >> sh);
+// Word g of selected variant v: sixteen consecutive samples of the row as a
+// 2-bit word (sample 16g + k at bits 2k), with the missing mask applied and
+// samples >= m (and variants >= nv) forced to missing.  This reads the words
+// of N (v, g) pairs and issues every load before any result is used (a reader
+// that branches per word waits on each load in turn).  Dword-aligned rows take
+// one dword per word, other rows two aligned dwords, shifted; a word whose
+// dwords would leave the selected rows (a row's last partial dword, the edges
+// of the selection) is read byte by byte afterwards.  Words read in place of
+// those come from the first dwords of the selection and are discarded.
+template <int N>
+__device__ __forceinline__ void row_words16(const Sel& s, const int64_t (&v)[N],
+                                            const int64_t (&g)[N], bool aligned,
+                                            uint32_t (&w)[N]) {
+  const uint8_t* first = s.bed + s.v0 * s.bpv;
+  const uint8_t* end = first + s.nv * s.bpv;
+  const uint8_t* safe =
+      reinterpret_cast<const uint8_t*>((reinterpret_cast<uintptr_t>(first) + 3) & ~(uintptr_t)3);
+  const bool loads = aligned ? s.nv > 0 && s.bpv >= 4 : safe + 8 <= end;   // same for all lanes
+  bool fast[N];
+  uint32_t lo[N], hi[N];
+  if (loads && aligned) {
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      const uint8_t* p = first + v[r] * s.bpv + 4 * g[r];
+      fast[r] = v[r] < s.nv && s.bpv - 4 * g[r] >= 4;
+      lo[r] = *reinterpret_cast<const uint32_t*>(fast[r] ? p : first);
+      hi[r] = 0;
+    }
+  } else if (loads) {
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      const uint8_t* p = first + v[r] * s.bpv + 4 * g[r];
+      const uint8_t* pa =
+          reinterpret_cast<const uint8_t*>(reinterpret_cast<uintptr_t>(p) & ~(uintptr_t)3);
+      fast[r] = v[r] < s.nv && s.bpv - 4 * g[r] >= 4 && pa >= first && pa + 8 <= end;
+      const uint32_t* q = reinterpret_cast<const uint32_t*>(fast[r] ? pa : safe);
+      lo[r] = q[0];
+      hi[r] = q[1];
+    }
   } else {
-    w = 0;
-    for (int b = 0; b < 4; ++b)
-      if (b < avail) w |= (uint32_t)p[b] << (8 * b);
+#pragma unroll
+    for (int r = 0; r < N; ++r) { fast[r] = false; lo[r] = hi[r] = 0; }
   }
-  const int64_t valid = s.m - 16 * g;           // samples of this group inside the matrix
-  if (valid < 16) {
-    const uint32_t keep = valid <= 0 ? 0u : ((1u << (2 * valid)) - 1u);
-    w = (w & keep) | (kAllMissing16 & ~keep);
-  }
+  uint64_t mw[N];
   if (s.mask) {
-    const uint64_t mw = s.mask[row * s.wpm + ((16 * g) >> 6)];
-    const uint32_t lanes = spread16((uint32_t)(mw >> ((16 * g) & 63)));
-    w = (w & ~(lanes | (lanes << 1))) | lanes;  // masked calls -> code 01
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      const bool in = v[r] < s.nv && s.m - 16 * g[r] > 0;
+      mw[r] = s.mask[in ? (s.v0 + v[r]) * s.wpm + ((16 * g[r]) >> 6) : 0];
+    }
   }
-  return w;
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+    uint32_t x;
+    if (fast[r]) {
+      const uintptr_t p = reinterpret_cast<uintptr_t>(first + v[r] * s.bpv + 4 * g[r]);
+      x = aligned ? lo[r] : (uint32_t)((((uint64_t)hi[r] << 32) | lo[r]) >> (8 * (p & 3)));
+    } else if (v[r] >= s.nv) {
+      x = kAllMissing16;
+    } else {
+      const uint8_t* p = first + v[r] * s.bpv + 4 * g[r];
+      const int64_t avail = s.bpv - 4 * g[r];
+      x = 0;
+      for (int b = 0; b < 4; ++b)
+        if (b < avail) x |= (uint32_t)p[b] << (8 * b);
+    }
+    const int64_t valid = s.m - 16 * g[r];
+    if (valid < 16) {
+      const uint32_t keep = valid <= 0 ? 0u : ((1u << (2 * valid)) - 1u);
+      x = (x & keep) | (kAllMissing16 & ~keep);
+    }
+    if (s.mask && valid > 0 && v[r] < s.nv) {
+      const uint32_t lanes = spread16((uint32_t)(mw[r] >> ((16 * g[r]) & 63)));
+      x = (x & ~(lanes | (lanes << 1))) | lanes;  // masked calls -> code 01
+    }
+    w[r] = x;
+  }
 }
 
-// Sample-major 2-bit words without a sample list: a thread owns 16 samples x
-// 64 variants (four 16x16 transposes) and writes four consecutive words per
-// sample row.  Lanes take consecutive sample groups, so the row reads
-// coalesce.
-__global__ __launch_bounds__(256) void k_sample_major_fast(Sel s, uint32_t* __restrict__ T,
-                                                           int64_t rows_pad, int64_t wp,
-                                                           int aligned,
-                                                           const uint32_t* __restrict__ gate,
-                                                           uint32_t gate_min) {
-  if (gate && *gate < gate_min) return;
-  const int64_t groups = rows_pad / 16;
-  const int64_t quads = wp / 4;
-  const int64_t total = groups * quads;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t g = e % groups;
-    const int64_t q = e / groups;
-    uint32_t out[4][16];
+// Sample-major 2-bit words without a sample list, 512 samples x 512 variants
+// per block: lanes read consecutive words of one .bed row (whole lines), the
+// 16x16 transposes land in LDS, and the block writes 128-byte runs of T rows.
+// Samples past the matrix and variants past the selection are missing calls.
+constexpr int kSmTW = 32;            // T words (16 variants) and sample groups per block
+constexpr int kSmTS = kSmTW + 1;     // LDS row stride (words)
+
+__global__ __launch_bounds__(256) void k_sample_major_tiled(Sel s, uint32_t* __restrict__ T,
+                                                            int64_t rows_pad, int64_t wp,
+                                                            int aligned) {
+  __shared__ uint32_t s_out[16 * kSmTW * kSmTS];
+  const int64_t nb_a = ceil_div(wp, kSmTW);
+  const int64_t a0 = ((int64_t)blockIdx.x % nb_a) * kSmTW;   // T word (16 variants)
+  const int64_t g0 = ((int64_t)blockIdx.x / nb_a) * kSmTW;   // sample group (16 samples)
+  const int t = threadIdx.x;
+  const int gl = t % kSmTW;
+#pragma unroll 1
+  for (int i = 0; i < 4; ++i) {
+    const int al = t / kSmTW + 8 * i;
+    const int64_t a = a0 + al, g = g0 + gl;
+    int64_t vr[16], gr[16];
 #pragma unroll
-    for (int ww = 0; ww < 4; ++ww) {
-      const int64_t w = 4 * q + ww;
+    for (int r = 0; r < 16; ++r) { vr[r] = 16 * a + r; gr[r] = g; }   // (16 wp >= nv)
+    uint32_t x[16];
+    row_words16(s, vr, gr, aligned != 0, x);
+    transpose16_2bit(x);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) out[ww][r] = row_word16(s, 16 * w + r, g, aligned != 0);
-      transpose16_2bit(out[ww]);
-    }
-#pragma unroll
-    for (int c = 0; c < 16; ++c)
-      *reinterpret_cast<uint4*>(T + (16 * g + c) * wp + 4 * q) =
-          make_uint4(out[0][c], out[1][c], out[2][c], out[3][c]);
+    for (int c = 0; c < 16; ++c) s_out[(c * kSmTW + gl) * kSmTS + al] = x[c];
+  }
+  __syncthreads();
+  const int lane = t & 63, wave = t >> 6;
+  for (int row = 2 * wave + (lane >> 5); row < 16 * kSmTW; row += 8) {
+    const int64_t k = 16 * g0 + row, a = a0 + (lane & 31);
+    if (k < rows_pad && a < wp)   // T row 16 gl + c is LDS row c * kSmTW + gl
+      T[k * wp + a] = s_out[((row & 15) * kSmTW + (row >> 4)) * kSmTS + (lane & 31)];
   }
 }
 
@@ -112,10 +158,13 @@ __global__ __launch_bounds__(256) void k_ibs_planes_fast(Sel s, uint32_t* __rest
     const int64_t g = e % groups;
     const int64_t w = e / groups;
     uint32_t lo16[16], hi16[16];
+    int64_t vr[16], gr[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) lo16[r] = row_word16(s, 32 * w + r, g, aligned != 0);
+    for (int r = 0; r < 16; ++r) { vr[r] = 32 * w + r; gr[r] = g; }
+    row_words16(s, vr, gr, aligned != 0, lo16);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) hi16[r] = row_word16(s, 32 * w + 16 + r, g, aligned != 0);
+    for (int r = 0; r < 16; ++r) vr[r] += 16;
+    row_words16(s, vr, gr, aligned != 0, hi16);
     transpose16_2bit(lo16);
     transpose16_2bit(hi16);
     uint32_t H[16], L[16], M[16];
@@ -152,22 +201,16 @@ __device__ __forceinline__ void ld_planes_of(uint32_t x, uint32_t& hom2, uint32_
 }
 
 __global__ __launch_bounds__(256) void k_ld_planes(Sel s, uint32_t* __restrict__ P, int64_t rows_pad,
-                                                   int64_t words_pad, int aligned) {
+                                                   int64_t words_pad) {
   const int64_t total = rows_pad * words_pad;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t v = e % rows_pad;
     const int64_t w = e / rows_pad;
-    uint32_t x0, x1;
-    if (!s.idx) {
-      x0 = row_word16(s, v, 2 * w, aligned != 0);
-      x1 = row_word16(s, v, 2 * w + 1, aligned != 0);
-    } else {
-      x0 = 0; x1 = 0;
-      for (int b = 0; b < 16; ++b) {
-        x0 |= code_at(s, v, 32 * w + b) << (2 * b);
-        x1 |= code_at(s, v, 32 * w + 16 + b) << (2 * b);
-      }
+    uint32_t x0 = 0, x1 = 0;
+    for (int b = 0; b < 16; ++b) {
+      x0 |= code_at(s, v, 32 * w + b) << (2 * b);
+      x1 |= code_at(s, v, 32 * w + 16 + b) << (2 * b);
     }
     uint32_t p0, q0, m0, p1, q1, m1;
     ld_planes_of(x0, p0, q0, m0);
@@ -210,8 +253,10 @@ __global__ __launch_bounds__(256) void k_sample_major_rep(Sel s, uint32_t* __res
 #pragma unroll
     for (int ww = 0; ww < 4; ++ww) {
       const int64_t w = 4 * q + ww;
+      int64_t vr[16], gr[16];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) out[ww][r] = row_word16(s, 16 * w + r, g, aligned != 0);
+      for (int r = 0; r < 16; ++r) { vr[r] = 16 * w + r; gr[r] = g; }
+      row_words16(s, vr, gr, aligned != 0, out[ww]);
       transpose16_2bit(out[ww]);
     }
 #pragma unroll
@@ -247,16 +292,35 @@ __global__ __launch_bounds__(256) void k_sample_major_rep_gather(Sel s, uint32_t
   }
 }
 
-// Variant-major 2-bit words without a sample list: one word per thread.
+// Variant-major 2-bit words without a sample list: a wave owns 64 * kVmU
+// consecutive words of D (rows run on into each other), with their loads in
+// flight together.
+constexpr int kVmU = 8;
+
 __global__ __launch_bounds__(256) void k_variant_major_fast(Sel s, uint32_t* __restrict__ D,
                                                             int64_t rows_pad, int64_t wn,
                                                             int aligned) {
+  const int lane = threadIdx.x & 63;
   const int64_t total = rows_pad * wn;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t w = e % wn;
-    const int64_t v = e / wn;
-    D[e] = row_word16(s, v, w, aligned != 0);
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t e0 = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * (64 * kVmU);
+       e0 < total; e0 += waves * (64 * kVmU)) {
+    int64_t vr[kVmU], gr[kVmU];
+    int64_t v = (e0 + lane) / wn, g = (e0 + lane) % wn;
+#pragma unroll
+    for (int u = 0; u < kVmU; ++u) {
+      vr[u] = v;
+      gr[u] = g;
+      g += 64;
+      while (g >= wn) { g -= wn; ++v; }
+    }
+    uint32_t x[kVmU];
+    row_words16(s, vr, gr, aligned != 0, x);
+#pragma unroll
+    for (int u = 0; u < kVmU; ++u) {
+      const int64_t e = e0 + 64 * u + lane;
+      if (e < total) D[e] = x[u];
+    }
   }
 }
 
@@ -278,10 +342,7 @@ constexpr int kSmSamples = 64;
 constexpr int kSmWords = 64;
 
 __global__ __launch_bounds__(256) void k_sample_major_2bit(Sel s, uint32_t* __restrict__ T,
-                                                           int64_t rows_pad, int64_t wp,
-                                                           const uint32_t* __restrict__ gate,
-                                                           uint32_t gate_min) {
-  if (gate && *gate < gate_min) return;
+                                                           int64_t rows_pad, int64_t wp) {
   __shared__ uint32_t tile[kSmSamples][kSmWords + 1];
   const int t = threadIdx.x;
   const int64_t nbi = ceil_div(rows_pad, kSmSamples);
@@ -313,15 +374,15 @@ __global__ __launch_bounds__(256) void k_sample_major_2bit(Sel s, uint32_t* __re
 }
 
 int launch_sample_major_2bit(const Sel& s, uint32_t* T, int64_t rows_pad, int64_t wp,
-                             hipStream_t st, const uint32_t* gate, uint32_t gate_min) {
-  if (!s.idx && (wp % 4) == 0) {
-    hipLaunchKernelGGL(k_sample_major_fast, dim3(stride_grid(rows_pad / 16 * (wp / 4))), dim3(256),
-                       0, st, s, T, rows_pad, wp, (int)rows_dword_aligned(s), gate, gate_min);
-    return check_launch("sample_major_fast");
+                             hipStream_t st) {
+  if (!s.idx) {
+    const int64_t blocks = ceil_div(wp, kSmTW) * ceil_div(rows_pad, 16 * kSmTW);
+    hipLaunchKernelGGL(k_sample_major_tiled, dim3((unsigned)blocks), dim3(256), 0, st, s, T,
+                       rows_pad, wp, (int)rows_dword_aligned(s));
+    return check_launch("sample_major_tiled");
   }
   dim3 grid((unsigned)(ceil_div(rows_pad, kSmSamples) * ceil_div(wp, kSmWords)));
-  hipLaunchKernelGGL(k_sample_major_2bit, grid, dim3(256), 0, st, s, T, rows_pad, wp, gate,
-                     gate_min);
+  hipLaunchKernelGGL(k_sample_major_2bit, grid, dim3(256), 0, st, s, T, rows_pad, wp);
   return check_launch("sample_major_2bit");
 }
 
@@ -371,8 +432,8 @@ __global__ __launch_bounds__(256) void k_variant_major_2bit(Sel s, uint32_t* __r
 int launch_variant_major_2bit(const Sel& s, uint32_t* D, int64_t rows_pad, int64_t wn,
                               hipStream_t st) {
   if (!s.idx) {
-    hipLaunchKernelGGL(k_variant_major_fast, dim3(stride_grid(rows_pad * wn)), dim3(256), 0, st, s,
-                       D, rows_pad, wn, (int)rows_dword_aligned(s));
+    hipLaunchKernelGGL(k_variant_major_fast, dim3(stride_grid(ceil_div(rows_pad * wn, kVmU))),
+                       dim3(256), 0, st, s, D, rows_pad, wn, (int)rows_dword_aligned(s));
     return check_launch("variant_major_fast");
   }
   dim3 grid((unsigned)ceil_div(rows_pad * wn, 256));
@@ -393,15 +454,22 @@ __global__ __launch_bounds__(256) void k_ld_planes_tiled(Sel s, uint32_t* __rest
   const int64_t nrb = rows_pad / 64;
   const int64_t v0 = ((int64_t)blockIdx.x % nrb) * 64;
   const int64_t w0 = ((int64_t)blockIdx.x / nrb) * 32;      // first plane word
-#pragma unroll 4
-  for (int k = 0; k < 16; ++k) {
-    const int row = (t >> 6) + 4 * k;
-    const int d = t & 63;                                    // 16-sample group in the block
-    const uint32_t x = row_word16(s, v0 + row, 2 * w0 + d, aligned != 0);
-    const uint32_t lo = x & 0x55555555u, hi = (x >> 1) & 0x55555555u;
-    half[0][row][d] = (uint16_t)compact_even_bits(lo & hi);
-    half[1][row][d] = (uint16_t)compact_even_bits(~(lo | hi) & 0x55555555u);
-    half[2][row][d] = (uint16_t)compact_even_bits(~(lo & ~hi) & 0x55555555u);
+  const int d = t & 63;                                      // 16-sample group in the block
+#pragma unroll 1
+  for (int k0 = 0; k0 < 16; k0 += 8) {
+    int64_t vr[8], gr[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) { vr[k] = v0 + (t >> 6) + 4 * (k0 + k); gr[k] = 2 * w0 + d; }
+    uint32_t xs[8];
+    row_words16(s, vr, gr, aligned != 0, xs);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int row = (t >> 6) + 4 * (k0 + k);
+      const uint32_t lo = xs[k] & 0x55555555u, hi = (xs[k] >> 1) & 0x55555555u;
+      half[0][row][d] = (uint16_t)compact_even_bits(lo & hi);
+      half[1][row][d] = (uint16_t)compact_even_bits(~(lo | hi) & 0x55555555u);
+      half[2][row][d] = (uint16_t)compact_even_bits(~(lo & ~hi) & 0x55555555u);
+    }
   }
   __syncthreads();
 #pragma unroll 4
@@ -424,7 +492,7 @@ int launch_ld_planes(const Sel& s, uint32_t* P, int64_t rows_pad, int64_t words_
                        words_pad, (int)rows_dword_aligned(s));
   } else {
     hipLaunchKernelGGL(k_ld_planes, dim3(stride_grid(rows_pad * words_pad)), dim3(256), 0, st, s,
-                       P, rows_pad, words_pad, (int)rows_dword_aligned(s));
+                       P, rows_pad, words_pad);
   }
   return check_launch("ld_planes");
 }

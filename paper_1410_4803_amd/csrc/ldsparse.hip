@@ -460,13 +460,14 @@ __global__ __launch_bounds__(256) void k_ld_transpose(const uint32_t* __restrict
     }
     transpose16_2bit(x);
 #pragma unroll
-    for (int c = 0; c < 16; ++c) s_out[(16 * gl + c) * kTrS + al] = x[c];
+    for (int c = 0; c < 16; ++c) s_out[(c * kTrW + gl) * kTrS + al] = x[c];
   }
   __syncthreads();
   const int lane = t & 63, wave = t >> 6;
   for (int row = 2 * wave + (lane >> 5); row < 16 * kTrW; row += 8) {
     const int64_t k = 16 * g0 + row, a = a0 + (lane & 31);
-    if (k < t_rows && a < tw) T[k * tw + a] = s_out[row * kTrS + (lane & 31)];
+    if (k < t_rows && a < tw)   // T row 16 gl + c is LDS row c * kTrW + gl
+      T[k * tw + a] = s_out[((row & 15) * kTrW + (row >> 4)) * kTrS + (lane & 31)];
   }
 }
 

@@ -93,11 +93,8 @@ __device__ __forceinline__ void transpose16_2bit(uint32_t x[16]) {
 // ---- layout kernels (layout.hip) -------------------------------------------
 // Sample-major 2-bit words: T[i*wp + w] holds codes of variants 16w..16w+15
 // of selected sample i (code of variant 16w+t at bits 2t); rows_pad x wp.
-// With `gate`, the kernel does nothing while the device word *gate is below
-// gate_min.
 int launch_sample_major_2bit(const Sel& s, uint32_t* T, int64_t rows_pad, int64_t wp,
-                             hipStream_t st, const uint32_t* gate = nullptr,
-                             uint32_t gate_min = 0);
+                             hipStream_t st);
 // Replicated fp4 operand (matrix-core variant 4): per sample, per group of 8
 // variants, words HR (high code bits at nibble bits 1 and 3) and LR (low code
 // bits at nibble bits 1 and 3, ones at bits 0 and 2); rp words per row.
