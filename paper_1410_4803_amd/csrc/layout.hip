@@ -2,7 +2,7 @@
 // operand layouts of the pair kernels.  All are single passes over the input,
 // bound by HBM traffic.  Padding positions are written as missing calls, so
 // they contribute nothing to any count.
-#include "pg_internal.h"
+#include "tiles.h"
 
 namespace pg {
 
@@ -107,9 +107,12 @@ __global__ __launch_bounds__(256) void k_sample_major_tiled(Sel s, uint32_t* __r
                                                             int64_t rows_pad, int64_t wp,
                                                             int aligned) {
   __shared__ uint32_t s_out[16 * kSmTW * kSmTS];
-  const int64_t nb_a = ceil_div(wp, kSmTW);
-  const int64_t a0 = ((int64_t)blockIdx.x % nb_a) * kSmTW;   // T word (16 variants)
-  const int64_t g0 = ((int64_t)blockIdx.x / nb_a) * kSmTW;   // sample group (16 samples)
+  // blocks of one XCD take consecutive sample groups of the same variants, so
+  // the row pieces that straddle two blocks' reads meet in that XCD's L2
+  const int64_t bid = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int64_t nb_g = ceil_div(rows_pad / 16, kSmTW);
+  const int64_t g0 = (bid % nb_g) * kSmTW;   // sample group (16 samples)
+  const int64_t a0 = (bid / nb_g) * kSmTW;   // T word (16 variants)
   const int t = threadIdx.x;
   const int gl = t % kSmTW;
 #pragma unroll 1

@@ -71,13 +71,19 @@ __global__ __launch_bounds__(256) void k_ld_vstats(const uint32_t* __restrict__ 
       uint32_t miss = lo & ~hi;
       const int64_t valid = m - 16 * w;   // selected samples in this word
       if (valid < 16) miss &= valid <= 0 ? 0u : ((1u << (2 * valid)) - 1u);
+      if (__ballot(miss != 0) == 0) continue;   // (the same for the whole wave)
+      // exclusive prefix sum of the per-lane counts (at most 16) over the
+      // wave, one bit of the count at a time, with no cross-lane data moves
       const int k = __popc(miss);
-      int incl = k;
-      for (int d = 1; d < 64; d <<= 1) {
-        const int y = __shfl_up(incl, d, 64);
-        if (lane >= d) incl += y;
+      int excl = 0, total = 0;
+#pragma unroll
+      for (int b = 0; b < 5; ++b) {
+        const uint64_t bb = __ballot((k >> b) & 1);
+        excl += (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bb >> 32),
+                                               __builtin_amdgcn_mbcnt_lo((uint32_t)bb, 0u)) << b;
+        total += __popcll(bb) << b;
       }
-      int64_t pos = c + incl - k;
+      int64_t pos = c + excl;
       while (miss) {
         const int bit = __ffs(miss) - 1;
         const int64_t smp = 16 * w + (bit >> 1);
@@ -85,7 +91,7 @@ __global__ __launch_bounds__(256) void k_ld_vstats(const uint32_t* __restrict__ 
         ++pos;
         miss &= miss - 1;
       }
-      c += __shfl(incl, 63, 64);
+      c += total;
     }
   }
   for (int d = 32; d > 0; d >>= 1) {

@@ -171,3 +171,33 @@ def test_ibs_mask_and_row_stride(path, n, extra):
         if path == "mfma":
             got = pg.ibs_matrix(_cohort(bed, n, mask), layout="full", path=2 | (variant << 8))
             _check_full(got, ref)
+
+
+def _offset_cohort(bed, n, mask, shift):
+    """A cohort whose .bed buffer starts `shift` bytes past an allocation's
+    start (so its rows need not start on a dword boundary)."""
+    flat = np.concatenate([np.full(shift, 0xA5, np.uint8), bed.ravel()])
+    t = torch.from_numpy(flat).cuda()[shift:]
+    m = None if mask is None else torch.from_numpy(np.ascontiguousarray(mask).view(np.int64)).cuda()
+    return pg.Cohort(t, n, bed.shape[0], bed.shape[1], m)
+
+
+@pytest.mark.parametrize("path", ["popc", "mfma", "fp4rep"])
+@pytest.mark.parametrize("n,V,vb,ve,shift,masked", [
+    (97, 300, 7, 251, 1, True),      # 25-byte rows, the range starts inside a dword
+    (1000, 200, 3, 200, 2, True),    # 250-byte rows, the range ends at the buffer's end
+    (160, 90, 0, 90, 0, False),      # 40-byte rows, dword-aligned
+    (160, 90, 5, 61, 3, False),      # the same rows off a dword boundary
+    (5, 4, 2, 3, 3, True),           # one 2-byte row: too small for dword reads
+    (2, 9, 0, 9, 1, False),          # nine 1-byte rows
+])
+def test_ibs_variant_range_without_sample_list(path, n, V, vb, ve, shift, masked):
+    """Variant ranges over all samples: the whole-row reader's edge cases."""
+    bed = synth.hwe(n, V, (0.05, 0.5), 0.02, seed=n + V + vb)
+    mask = synth.missing_mask(n, V, 0.04, seed=n + 3) if masked else None
+    codes = oracle.select(oracle.unpack(bed, n, V, mask), None, vb, ve)
+    c = _offset_cohort(bed, n, mask, shift)
+    for layout in ("full", "tri"):
+        ref = oracle.ibs_matrix(codes, full=layout == "full")
+        got = pg.ibs_matrix(c, v_range=(vb, ve), layout=layout, path=CODES[path])
+        _check_full(got, ref)

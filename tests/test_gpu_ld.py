@@ -173,3 +173,28 @@ def test_ld_threshold_exactly_at_pair_values(path):
         key_g = got["a"].astype(np.int64) * V + got["b"]
         key_w = a[want].astype(np.int64) * V + b[want]
         assert np.array_equal(np.sort(key_g), np.sort(key_w)), t
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("n,V,vb,ve,shift,masked", [
+    (97, 400, 7, 351, 1, True),      # 25-byte rows, the range starts inside a dword
+    (1000, 150, 3, 150, 2, True),    # 250-byte rows, the range ends at the buffer's end
+    (160, 120, 5, 101, 3, False),    # 40-byte rows off a dword boundary
+    (5, 6, 2, 4, 3, True),           # two 2-byte rows: too small for dword reads
+])
+def test_ld_variant_range_without_sample_list(path, n, V, vb, ve, shift, masked):
+    """Variant ranges over all samples: the whole-row reader's edge cases."""
+    W = 60
+    bed = synth.mosaic(n, V, switch=0.01, miss=0.02, seed=n + V + vb)
+    mask = synth.missing_mask(n, V, 0.03, seed=n + 5) if masked else None
+    codes = oracle.select(oracle.unpack(bed, n, V, mask), None, vb, ve)
+    ref = oracle.ld_window(codes, W, -np.inf)
+    ref["a"] += vb
+    ref["b"] += vb
+    flat = np.concatenate([np.full(shift, 0x5A, np.uint8), bed.ravel()])
+    t = torch.from_numpy(flat).cuda()[shift:]
+    m = None if mask is None else torch.from_numpy(mask.view(np.int64)).cuda()
+    c = pg.Cohort(t, n, V, bed.shape[1], m)
+    got = pg.ld_records(c, W, -np.inf, v_range=(vb, ve), path=path)
+    assert len(got) == len(ref)
+    _compare(got, ref, -np.inf)
