@@ -179,6 +179,8 @@ __device__ __forceinline__ void add_plane_sums(Sums6& z, uint32_t pa, uint32_t q
   z.sxy += __builtin_popcount((pa & pb) | (qa & qb)) - __builtin_popcount((pa & qb) | (qa & pb));
 }
 
+constexpr int kEmitU = 4;
+
 template <bool kPlanes>
 __global__ __launch_bounds__(256) void k_ld_emit(const uint32_t* __restrict__ X, int64_t words,
                                                  int64_t rows_pad, int64_t nv, int64_t v0,
@@ -206,9 +208,24 @@ __global__ __launch_bounds__(256) void k_ld_emit(const uint32_t* __restrict__ X,
       k -= pc;
     }
     if (b < 0) continue;   // unreachable when counts and bitmap agree
+    // the row loops load kEmitU steps ahead, so a thread has that many
+    // loads in flight instead of waiting on each
     Sums6 z{0, 0, 0, 0, 0, 0};
     if constexpr (kPlanes) {
-      for (int64_t w = 0; w < words; ++w) {
+      int64_t w = 0;
+      for (; w + kEmitU <= words; w += kEmitU) {
+        uint32_t v[kEmitU][6];
+#pragma unroll
+        for (int u = 0; u < kEmitU; ++u) {
+          const uint32_t* pw = X + (w + u) * 3 * rows_pad;
+          v[u][0] = pw[a]; v[u][1] = pw[rows_pad + a]; v[u][2] = pw[2 * rows_pad + a];
+          v[u][3] = pw[b]; v[u][4] = pw[rows_pad + b]; v[u][5] = pw[2 * rows_pad + b];
+        }
+#pragma unroll
+        for (int u = 0; u < kEmitU; ++u)
+          add_plane_sums(z, v[u][0], v[u][1], v[u][2], v[u][3], v[u][4], v[u][5]);
+      }
+      for (; w < words; ++w) {
         const uint32_t* pw = X + w * 3 * rows_pad;
         add_plane_sums(z, pw[a], pw[rows_pad + a], pw[2 * rows_pad + a], pw[b],
                        pw[rows_pad + b], pw[2 * rows_pad + b]);
@@ -216,8 +233,7 @@ __global__ __launch_bounds__(256) void k_ld_emit(const uint32_t* __restrict__ X,
     } else {
       const uint4* ra = reinterpret_cast<const uint4*>(X + a * words);
       const uint4* rb = reinterpret_cast<const uint4*>(X + b * words);
-      for (int64_t w4 = 0; w4 < words / 4; ++w4) {
-        const uint4 A = ra[w4], B = rb[w4];
+      auto add4 = [&z](const uint4& A, const uint4& B) {
         const uint32_t xs[4] = {A.x, A.y, A.z, A.w}, ys[4] = {B.x, B.y, B.z, B.w};
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -226,7 +242,17 @@ __global__ __launch_bounds__(256) void k_ld_emit(const uint32_t* __restrict__ X,
           masks_of_word(ys[e], pb, qb, mb);
           add_plane_sums(z, pa, qa, ma, pb, qb, mb);
         }
+      };
+      const int64_t n4 = words / 4;
+      int64_t w4 = 0;
+      for (; w4 + kEmitU <= n4; w4 += kEmitU) {
+        uint4 A[kEmitU], B[kEmitU];
+#pragma unroll
+        for (int u = 0; u < kEmitU; ++u) { A[u] = ra[w4 + u]; B[u] = rb[w4 + u]; }
+#pragma unroll
+        for (int u = 0; u < kEmitU; ++u) add4(A[u], B[u]);
       }
+      for (; w4 < n4; ++w4) add4(ra[w4], rb[w4]);
     }
     pg_ld_pair rec;
     rec.a = (int32_t)(v0 + a);
