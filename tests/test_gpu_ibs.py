@@ -121,6 +121,17 @@ def large():
     return w, c
 
 
+def test_ibs_large_default_matches_variant_one(large):
+    """At 10,000 x 100,000 the whole matrix of the default matrix-core kernel
+    equals that of variant 1 (the same tile body without scheduling hints),
+    every entry, not just the sampled pairs below."""
+    w, c = large
+    a = pg.ibs_matrix(c, layout="full", path=CODES["mfma"])
+    b = pg.ibs_matrix(c, layout="full", path=CODES["mfma"] | (1 << 8))
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+
+
 @pytest.mark.parametrize("path", PATHS)
 def test_ibs_large_workload_sampled(large, path):
     """10,000 x 100,000 mosaic, full matrix, in the benchmark's launch
