@@ -260,12 +260,13 @@ int64_t prune_count_capacity(int64_t nv, int64_t window);
 int launch_grm(const Sel& s, const uint32_t* T, int64_t rows_pad, int64_t wp, double* ztab,
                uint32_t* used2, double* part, double* grm, uint32_t* n_used, int full,
                int waves, hipStream_t st);
-// K split of the relationship-matrix kernel: with fewer than 512
+// K split of the relationship-matrix kernel: with fewer than 128
 // upper-triangle tiles of 128 samples, each tile's K chunks of 128 variants
-// are split into up to 16 ranges of at least 8 chunks.
+// are split into up to 16 ranges of at least 8 chunks, as many as keep the
+// whole grid within one round of the 256 CUs (one block per CU).
 inline void grm_split(int64_t rows_pad, int64_t wp, int64_t& n_split, int64_t& cps) {
   const int64_t nt = rows_pad / 128, tiles = nt * (nt + 1) / 2, chunks = wp / 8;
-  int64_t want = ceil_div(512, tiles);
+  int64_t want = 256 / tiles;
   if (want > 16) want = 16;
   if (want > chunks / 8) want = chunks / 8;
   if (want < 1) want = 1;
