@@ -116,6 +116,13 @@ int plan_ibs(const Sel& s, int path_arg, IbsPlan& p) {
   }
   const int64_t nt = p.rows_pad / (path == PG_PATH_MFMA ? kIbsMfmaTile : kIbsPopcTile);
   if (nt * (nt + 1) / 2 + 2 * nt >= kMaxIndex) return fail(PG_EUNSUPPORTED, "too many samples for one call");
+  p.off_part = -1;
+  const bool default_kernel = path == PG_PATH_MFMA &&
+      !(p.variant >= 1 && p.variant <= kIbsVariantW8 + 1);
+  if (default_kernel && ibs_part_bytes(p.rows_pad, p.words) > 0) {
+    p.off_part = round_up(p.bytes, 256);
+    p.bytes = p.off_part + ibs_part_bytes(p.rows_pad, p.words);
+  }
   return PG_OK;
 }
 
@@ -376,7 +383,8 @@ int pg_ibs_matrix(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_se
   } else if (p.path == PG_PATH_MFMA) {
     rc = launch_sample_major_2bit(s, ws, p.rows_pad, p.words, st);
     mark_stage(1, st);
-    if (rc == PG_OK) rc = launch_ibs_mfma(ws, p.words, o, p.variant, st);
+    int32_t* part = p.off_part >= 0 ? (int32_t*)((char*)workspace + p.off_part) : nullptr;
+    if (rc == PG_OK) rc = launch_ibs_mfma(ws, p.words, o, p.variant, st, part);
   } else {
     rc = launch_ibs_planes(s, ws, p.rows_pad, p.words, st);
     mark_stage(1, st);

@@ -34,6 +34,53 @@ __global__ __launch_bounds__(256, 1) void k_ibs_mfma(const uint32_t* __restrict_
   ibs_mfma_tile<kHints>(T, wp, I, J, o, (lds_t*)smem);
 }
 
+// Small cohorts: block b runs K range b / tiles of tile b % tiles and parks
+// its raw sums; k_ibs_split_reduce adds the ranges in order and stores.
+__global__ __launch_bounds__(256, 1) void k_ibs_mfma_split(const uint32_t* __restrict__ T,
+                                                           int64_t wp, int64_t nt, IbsOut o,
+                                                           int64_t cps, int32_t* __restrict__ part) {
+  __shared__ __attribute__((aligned(16))) uint32_t smem[kIbsMfmaSmem];
+  const int64_t tiles = nt * (nt + 1) / 2;
+  const int64_t tile = blockIdx.x % tiles, split = blockIdx.x / tiles;
+  const int64_t chunks = wp / kKW;
+  const int64_t c0 = split * cps, c1 = c0 + cps < chunks ? c0 + cps : chunks;
+  int64_t I, J;
+  tri_tile(tile, nt, I, J);
+  ibs_mfma_tile<true>(T, wp, I, J, o, (lds_t*)smem, c0, c1,
+                      part + (split * tiles + tile) * (192 * 256));
+}
+
+// One thread per (tile, accumulator register, tile thread): the three sums
+// over the K ranges, then the counts as the tile epilogue derives them, at
+// the entry that register holds (32x32 block layout: register v of lane l is
+// row 8*(v/4) + 4*(l/32) + v%4 and column l%32; wave w covers rows 64*(w/2)
+// and columns 64*(w%2) of the tile).
+__global__ __launch_bounds__(256) void k_ibs_split_reduce(int64_t nt, int64_t n_split,
+                                                          const int32_t* __restrict__ part,
+                                                          IbsOut o) {
+  const int64_t tiles = nt * (nt + 1) / 2;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= tiles * 64 * 256) return;
+  const int t = (int)(e % 256);
+  const int k = (int)((e / 256) % 64);    // (a, b) block and register
+  const int64_t tile = e / (256 * 64);
+  const int ab = k / 16, v = k % 16;
+  int32_t m = 0, w = 0, hc = 0;
+  for (int64_t sp = 0; sp < n_split; ++sp) {
+    const int32_t* q = part + (sp * tiles + tile) * (192 * 256) + (ab * 48 + v) * 256 + t;
+    m += q[0];
+    w += q[16 * 256];
+    hc += q[32 * 256];
+  }
+  const uint32_t n = (uint32_t)m, z = (uint32_t)hc >> 1, one = (n - (uint32_t)w) >> 1;
+  const int wid = t >> 6, lane = t & 63;
+  const int row = (wid >> 1) * 64 + (ab >> 1) * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+  const int col = (wid & 1) * 64 + (ab & 1) * 32 + (lane & 31);
+  int64_t I, J;
+  tri_tile(tile, nt, I, J);
+  store_counts(o, I * kT + row, J * kT + col, I != J, n, z, one);
+}
+
 template <bool kHints>
 __global__ __launch_bounds__(512, 1) void k_ibs_mfma_w8(const uint32_t* __restrict__ T, int64_t wp,
                                                         int64_t nt, IbsOut o) {
@@ -75,9 +122,23 @@ __global__ __launch_bounds__(256) void k_ibs_popc(const uint32_t* __restrict__ P
   ibs_popc_tile(P, rows_pad, words_pad, I, J, o, (lds_t*)smem);
 }
 
-int launch_ibs_mfma(const uint32_t* T, int64_t wp, const IbsOut& o, int variant, hipStream_t st) {
+int launch_ibs_mfma(const uint32_t* T, int64_t wp, const IbsOut& o, int variant, hipStream_t st,
+                    int32_t* part) {
   const int64_t nt = ceil_div(o.m, kT);
   const int64_t blocks = variant == 2 ? nt * (nt + 1) / 2 : band_start((nt + 3) / 4, nt);
+  const bool default_kernel = !(variant >= 1 && variant <= kIbsVariantW8 + 1);
+  int64_t n_split = 1, cps = 0;
+  if (default_kernel && part) ibs_split(nt * kT, wp, n_split, cps);
+  if (n_split > 1) {
+    const int64_t tiles = nt * (nt + 1) / 2;
+    hipLaunchKernelGGL(k_ibs_mfma_split, dim3((unsigned)(tiles * n_split)), dim3(256), 0, st, T,
+                       wp, nt, o, cps, part);
+    int rc = check_launch("ibs_mfma_split");
+    if (rc != PG_OK) return rc;
+    hipLaunchKernelGGL(k_ibs_split_reduce, dim3((unsigned)ceil_div(tiles * 64 * 256, 256)),
+                       dim3(256), 0, st, nt, n_split, part, o);
+    return check_launch("ibs_split_reduce");
+  }
   if (variant == 1)
     hipLaunchKernelGGL(k_ibs_mfma<false>, dim3((unsigned)blocks), dim3(256), 0, st, T, wp, nt, o);
   else if (variant == 2)

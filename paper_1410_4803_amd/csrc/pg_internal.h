@@ -141,12 +141,43 @@ struct IbsPlan {
   int path;
   int variant;
   int64_t rows_pad, words;
+  int64_t off_part;   // K-split sums of the default matrix-core kernel (-1: none)
   int64_t bytes;
 };
 // The plan of the default matrix-core kernel for a selection (abi.hip).
 int plan_ibs_default(const Sel& s, IbsPlan& p);
 
-int launch_ibs_mfma(const uint32_t* T, int64_t wp, const IbsOut& o, int variant, hipStream_t st);
+// `part`: workspace of ibs_part_bytes() for the default kernel's K split
+// (nullptr: never split).
+int launch_ibs_mfma(const uint32_t* T, int64_t wp, const IbsOut& o, int variant, hipStream_t st,
+                    int32_t* part = nullptr);
+// K split of the default IBS matrix-core kernel: with fewer than 128
+// upper-triangle tiles of 128 samples, each tile's K chunks of 256 variants
+// are split into ranges of at least two chunks (at most 32 ranges), as many
+// as keep the grid within one round of the 256 CUs (one block per CU).  The
+// ranges park their raw sums (192 int32 per thread of the 256) in the
+// workspace and a second kernel adds them in range order.  n_split == 1: no
+// split.
+inline void ibs_split(int64_t rows_pad, int64_t wp, int64_t& n_split, int64_t& cps) {
+  const int64_t nt = rows_pad / kIbsMfmaTile, tiles = nt * (nt + 1) / 2;
+  const int64_t chunks = wp / kIbsMfmaKWords;
+  int64_t want = tiles < 128 ? 256 / tiles : 1;
+  if (want > 32) want = 32;
+  if (want > chunks / 2) want = chunks / 2;
+  if (want < 2) {
+    n_split = 1;
+    cps = chunks;
+    return;
+  }
+  cps = ceil_div(chunks, want);
+  n_split = ceil_div(chunks, cps);
+}
+inline int64_t ibs_part_bytes(int64_t rows_pad, int64_t wp) {
+  int64_t n_split, cps;
+  ibs_split(rows_pad, wp, n_split, cps);
+  const int64_t nt = rows_pad / kIbsMfmaTile;
+  return n_split > 1 ? n_split * (nt * (nt + 1) / 2) * 192 * 256 * 4 : 0;
+}
 int launch_ibs_fp4rep(const uint32_t* R, int64_t rp, const IbsOut& o, hipStream_t st);
 int launch_ibs_popc(const uint32_t* P, int64_t rows_pad, int64_t words_pad, const IbsOut& o,
                     hipStream_t st);

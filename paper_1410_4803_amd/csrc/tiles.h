@@ -267,10 +267,15 @@ __device__ __forceinline__ void zero_acc(IbsAcc& acc) {
 }
 
 
+// Chunks [c0, c1) of the tile's variants (c1 < 0: all of them).  With
+// `part`, the raw sums go there instead of the counts: 12 accumulator sets x
+// 16 registers per thread, stored [set * 16 + register][thread] with the sets
+// in the order (a, b) = (0,0), (0,1), (1,0), (1,1), each as m, w, hc.
 template <bool kHints>
 __device__ __forceinline__ void ibs_mfma_tile(const uint32_t* __restrict__ T, int64_t wp,
                                               int64_t I, int64_t J, const IbsOut& o,
-                                              lds_t* smem) {
+                                              lds_t* smem, int64_t c0 = 0, int64_t c1 = -1,
+                                              int32_t* __restrict__ part = nullptr) {
   constexpr int kBuf = kT * kLdsStride;
   lds_t* const sA = smem;
   lds_t* const sB = smem + 2 * kBuf;
@@ -303,12 +308,12 @@ __device__ __forceinline__ void ibs_mfma_tile(const uint32_t* __restrict__ T, in
 
   IbsAcc acc;
   zero_acc(acc);
-  const int64_t nchunks = wp / kKW;
-  gload(0);
+  const int64_t nchunks = c1 < 0 ? wp / kKW : c1;
+  gload(c0 * kKW);
   lstore(0);
   __syncthreads();
-  for (int64_t k = 0; k < nchunks; ++k) {
-    const int buf = (int)(k & 1);
+  for (int64_t k = c0; k < nchunks; ++k) {
+    const int buf = (int)((k - c0) & 1);
     if (k + 1 < nchunks) gload((k + 1) * kKW);
     // this lane's 8 words of each of its two A rows and two B rows
     uint32_t wa[2][8], wb[2][8];
@@ -351,6 +356,20 @@ __device__ __forceinline__ void ibs_mfma_tile(const uint32_t* __restrict__ T, in
     }
     if (k + 1 < nchunks) lstore(buf ^ 1);
     __syncthreads();
+  }
+  if (part) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          int32_t* q = part + ((a * 2 + b) * 48 + v) * 256 + t;
+          q[0] = acc.m[a][b][v];
+          q[16 * 256] = acc.w[a][b][v];
+          q[32 * 256] = acc.hc[a][b][v];
+        }
+    return;
   }
   ibs_epilogue(acc, o, I, J, wr, wc, lane);
 }

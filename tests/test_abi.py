@@ -56,6 +56,14 @@ def test_workspace_sizes():
     assert rc == 0 and b == 3 * 10048 * 3136 * 4
     rc, b = _ibs_ws(_g(100, 50), n_sel=7)
     assert rc == 0 and b == 128 * 16 * 4
+    # small cohorts: the default matrix-core kernel splits each tile's chunks
+    # of 256 variants into ranges (500 x 5,000: 10 tiles, 20 chunks, 10 ranges
+    # of 2) whose raw sums (192 x 256 int32 per tile and range) follow the
+    # operand, 256-byte aligned
+    rc, b = _ibs_ws(_g(500, 5000), path=N.PG_PATH_MFMA)
+    assert rc == 0 and b == 512 * 320 * 4 + 10 * 10 * 192 * 256 * 4
+    rc, b = _ibs_ws(_g(500, 5000), path=N.PG_PATH_MFMA | (1 << 8))   # variant 1: no split
+    assert rc == 0 and b == 512 * 320 * 4
     rc, b = _ld_ws(_g(5000, 500000), 1000)
     assert rc == 0 and b > 500000 * 320 * 4
     # correction path: + sample-major operand (5120 x 31264 words), lists of
