@@ -151,26 +151,43 @@ int plan_ibs_default(const Sel& s, IbsPlan& p);
 // (nullptr: never split).
 int launch_ibs_mfma(const uint32_t* T, int64_t wp, const IbsOut& o, int variant, hipStream_t st,
                     int32_t* part = nullptr);
-// K split of the default IBS matrix-core kernel: with fewer than 128
-// upper-triangle tiles of 128 samples, each tile's K chunks of 256 variants
-// are split into ranges of at least two chunks (at most 32 ranges), as many
-// as keep the grid within one round of the 256 CUs (one block per CU).  The
-// ranges park their raw sums (192 int32 per thread of the 256) in the
-// workspace and a second kernel adds them in range order.  n_split == 1: no
-// split.
-inline void ibs_split(int64_t rows_pad, int64_t wp, int64_t& n_split, int64_t& cps) {
-  const int64_t nt = rows_pad / kIbsMfmaTile, tiles = nt * (nt + 1) / 2;
-  const int64_t chunks = wp / kIbsMfmaKWords;
-  int64_t want = tiles < 128 ? 256 / tiles : 1;
-  if (want > 32) want = 32;
-  if (want > chunks / 2) want = chunks / 2;
-  if (want < 2) {
-    n_split = 1;
-    cps = chunks;
-    return;
+// K split of a tile kernel that runs one block per CU on the 256 CUs: each
+// of `tiles` tiles has `chunks` K chunks, split into n_split ranges of cps
+// chunks (cps >= min_cps, n_split <= max_split, tiles * n_split <= 2,048).
+// The time in chunk units is ceil(tiles * n_split / 256) * cps (rounds of the
+// CUs times the chunks per block) plus, when split, reduce_cost per tile and
+// range (reading its partial sums back); the split steps to more ranges only
+// where that saves 5%.  Grids of 512 tiles or more (two rounds and up) are
+// not split: their last round is already a small part, and a measured split
+// of it gained nothing.
+inline void split_ranges(int64_t tiles, int64_t chunks, int64_t min_cps, int64_t max_split,
+                         double reduce_cost, int64_t& n_split, int64_t& cps) {
+  n_split = 1;
+  cps = chunks;
+  if (tiles < 1 || tiles >= 512 || chunks < 2 * min_cps) return;
+  double best = (double)ceil_div(tiles, 256) * (double)chunks;
+  for (int64_t want = 2; want <= max_split && want * tiles <= 2048; ++want) {
+    const int64_t c = ceil_div(chunks, want);
+    if (c < min_cps) break;
+    const int64_t n = ceil_div(chunks, c);
+    const double cost = (double)ceil_div(tiles * n, 256) * (double)c + reduce_cost * tiles * n;
+    if (cost < 0.95 * best) {
+      best = cost;
+      n_split = n;
+      cps = c;
+    }
   }
-  cps = ceil_div(chunks, want);
-  n_split = ceil_div(chunks, cps);
+}
+
+// K split of the default IBS matrix-core kernel (chunks of 256 variants, at
+// least two per range, at most 32 ranges).  The ranges park their raw sums
+// (192 int32 per thread of the 256) in the workspace and a second kernel
+// adds them in range order.  n_split == 1: no split.  A block takes about
+// 2.5 us per chunk and reading one range's 196,608 bytes back about 0.05 us
+// of the whole chip's time: 0.02 chunks.
+inline void ibs_split(int64_t rows_pad, int64_t wp, int64_t& n_split, int64_t& cps) {
+  const int64_t nt = rows_pad / kIbsMfmaTile;
+  split_ranges(nt * (nt + 1) / 2, wp / kIbsMfmaKWords, 2, 32, 0.02, n_split, cps);
 }
 inline int64_t ibs_part_bytes(int64_t rows_pad, int64_t wp) {
   int64_t n_split, cps;
@@ -291,18 +308,12 @@ int64_t prune_count_capacity(int64_t nv, int64_t window);
 int launch_grm(const Sel& s, const uint32_t* T, int64_t rows_pad, int64_t wp, double* ztab,
                uint32_t* used2, double* part, double* grm, uint32_t* n_used, int full,
                int waves, hipStream_t st);
-// K split of the relationship-matrix kernel: with fewer than 128
-// upper-triangle tiles of 128 samples, each tile's K chunks of 128 variants
-// are split into up to 16 ranges of at least 8 chunks, as many as keep the
-// whole grid within one round of the 256 CUs (one block per CU).
+// K split of the relationship-matrix kernel (chunks of 128 variants, at
+// least eight per range, at most 16 ranges; about 19 us per chunk, so a
+// range's 196,608 bytes of partial sums cost 0.003 chunks to read back).
 inline void grm_split(int64_t rows_pad, int64_t wp, int64_t& n_split, int64_t& cps) {
-  const int64_t nt = rows_pad / 128, tiles = nt * (nt + 1) / 2, chunks = wp / 8;
-  int64_t want = 256 / tiles;
-  if (want > 16) want = 16;
-  if (want > chunks / 8) want = chunks / 8;
-  if (want < 1) want = 1;
-  cps = ceil_div(chunks, want);
-  n_split = chunks > 0 ? ceil_div(chunks, cps) : 1;
+  const int64_t nt = rows_pad / 128;
+  split_ranges(nt * (nt + 1) / 2, wp / 8, 8, 16, 0.003, n_split, cps);
 }
 inline int64_t grm_part_bytes(int64_t rows_pad, int64_t wp) {
   int64_t n_split, cps;

@@ -103,3 +103,14 @@ def test_grm_full_size_sampled(variant):
     pj = np.concatenate([rng.integers(0, n, 3000), np.arange(n), np.arange(n)])
     Ar, Nr, Sr = oracle.grm_pairs(codes_sm, pi, pj)
     _compare(A[pi, pj], N[pi, pj], Ar, Nr, Sr, V)
+
+
+def test_grm_medium_cohort_k_split():
+    """2,000 samples (136 tiles of 128, more than half a round of the CUs):
+    the default kernel splits each tile's variants into three ranges."""
+    n, V = 2000, 4096
+    bed = synth.hwe(n, V, (0.01, 0.5), 0.02, seed=2024)
+    codes = oracle.unpack(bed, n, V)
+    Ar, Nr, Sr = oracle.grm(codes, full=False)
+    A, N = _gpu(bed, n, "tri")
+    _compare(A.reshape(Ar.shape), N.reshape(Nr.shape), Ar, Nr, Sr, V)

@@ -212,3 +212,15 @@ def test_ibs_variant_range_without_sample_list(path, n, V, vb, ve, shift, masked
         ref = oracle.ibs_matrix(codes, full=layout == "full")
         got = pg.ibs_matrix(c, v_range=(vb, ve), layout=layout, path=CODES[path])
         _check_full(got, ref)
+
+
+def test_ibs_medium_cohort_k_split():
+    """1,800 samples (120 tiles of 128): the default matrix-core kernel splits
+    each tile's 32 chunks of 256 variants into two ranges; every pair against
+    the oracle."""
+    n, V = 1800, 8000
+    bed = synth.hwe(n, V, (0.05, 0.5), 0.02, seed=1800)
+    codes = oracle.unpack(bed, n, V)
+    ref = oracle.ibs_matrix(codes, full=False)
+    got = pg.ibs_matrix(_cohort(bed, n), layout="tri", path=CODES["mfma"])
+    _check_full(got, ref)
