@@ -146,7 +146,10 @@ enum pg_path {
  *   v_begin, v_end  variant range [v_begin, v_end); 0, 0 selects all.
  */
 
-/* Workspace bytes pg_ibs_matrix needs for this shape and path. */
+/* Workspace bytes pg_ibs_matrix needs for this shape and path: the operand
+ * layout, plus, for the default matrix-core kernel on cohorts of fewer than
+ * 512 tiles of 128 samples, the raw sums of the variant ranges each tile is
+ * split into (196,608 bytes per tile and range, at most 2,048 of them). */
 int pg_ibs_workspace_bytes(const pg_genotypes* g, int64_t n_sel, int64_t v_begin, int64_t v_end,
                            int path, size_t* bytes);
 
@@ -263,7 +266,10 @@ int pg_ld_prune(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_sel,
  * double dot product (about V * 2^-53 times the sum of |increments|).
  */
 
-/* Workspace bytes pg_grm_matrix needs for this shape. */
+/* Workspace bytes pg_grm_matrix needs for this shape: the operand, the
+ * per-marker tables, and, on cohorts of fewer than 512 tiles of 128 samples,
+ * the partial sums and counts of the variant ranges each tile is split into
+ * (196,608 bytes per tile and range). */
 int pg_grm_workspace_bytes(const pg_genotypes* g, int64_t n_sel, int64_t v_begin,
                            int64_t v_end, size_t* bytes);
 
