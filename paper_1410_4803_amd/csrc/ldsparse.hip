@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void k_ld_vstats(const uint32_t* __restrict__ 
   uint32_t* list = lists + v * (int64_t)cap;
   int64_t c = 0;
   int n3 = 0, n0 = 0;
-  constexpr int kU = 4;   // 64-word slices loaded ahead of the scan
+  constexpr int kU = 8;   // 64-word slices loaded ahead of the scan
   for (int64_t w0 = 0; w0 < wn; w0 += 64 * kU) {
     uint32_t x[kU];
 #pragma unroll
