@@ -34,8 +34,9 @@ __global__ __launch_bounds__(256, 1) void k_ibs_mfma(const uint32_t* __restrict_
   ibs_mfma_tile<kHints>(T, wp, I, J, o, (lds_t*)smem);
 }
 
-// Small cohorts: block b runs K range b / tiles of tile b % tiles and parks
-// its raw sums; k_ibs_split_reduce adds the ranges in order and stores.
+// Cohorts of fewer than 512 tiles (ibs_split): block b runs K range
+// b / tiles of tile b % tiles and parks its raw sums; k_ibs_split_reduce
+// adds the ranges in order and stores.
 __global__ __launch_bounds__(256, 1) void k_ibs_mfma_split(const uint32_t* __restrict__ T,
                                                            int64_t wp, int64_t nt, IbsOut o,
                                                            int64_t cps, int32_t* __restrict__ part) {
