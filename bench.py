@@ -35,7 +35,7 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6         # MI355X dense fp64 MFMA
 # algorithmic work per unique genotype-pair comparison (one pair, one variant)
 IBS_MFMA_OPS = 4 * 2          # four int8 contractions: 4 MACs = 8 ops
-IBS_POPC_OPS = 10 / 32        # 10 VALU ops per 32-variant word
+IBS_POPC_OPS = 8 / 32         # per 32-variant word: AND, 2 XOR, 2 bitop3, 3 popcount-adds
 LD_MFMA_OPS = 6 * 2           # six int8 contractions
 LD_POPC_OPS = 16 / 32         # 16 VALU ops per 32-sample word
 
@@ -128,6 +128,17 @@ def traffic_from_profile(kernel: str):
     return rec.get("hbm_bytes_per_launch")
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline_ibs(bed, n, V, budget_s: float):
     """Times the CPU oracle on the first s samples (all variants, strict upper
     triangle), s chosen for about `budget_s` seconds of host work."""
@@ -149,7 +160,7 @@ def cpu_baseline_ibs(bed, n, V, budget_s: float):
     t = run(s)
     comps = s * (s - 1) / 2 * V
     return {"value": round(comps / t / 1e9, 3), "unit": "G/s", "cores": oracle.threads(),
-            "kind": "oracle",
+            "kind": "oracle", "cpu": cpu_model(),
             "sample": f"first {s} samples x all {V} variants of the workload, strict upper "
                       f"triangle ({comps:.3e} comparisons, {t:.1f} s)"}
 
@@ -248,7 +259,7 @@ def cpu_baseline_cluster(wc):
     t0 = time.perf_counter()
     oracle.cluster_complete(d)
     dt = time.perf_counter() - t0
-    return {"value": round(dt * 1e3, 1), "unit": "ms", "cores": 1, "kind": "oracle",
+    return {"value": round(dt * 1e3, 1), "unit": "ms", "cores": 1, "kind": "oracle", "cpu": cpu_model(),
             "sample": "clustering of the whole workload (distances given)"}
 
 
@@ -260,7 +271,7 @@ def cpu_baseline_prune(wp):
     t0 = time.perf_counter()
     keep = oracle.ld_prune(codes, wp["window"], wp["step"], wp["r2_max"])
     dt = time.perf_counter() - t0
-    return {"value": round(dt * 1e3, 1), "unit": "ms", "cores": oracle.threads(),
+    return {"value": round(dt * 1e3, 1), "unit": "ms", "cores": oracle.threads(), "cpu": cpu_model(),
             "kind": "oracle", "sample": "whole workload", "kept": int(keep.sum())}
 
 
@@ -291,31 +302,44 @@ def bench_batch(torch, lib, hip, pg, synth, dev, steps):
     t_tune = time.perf_counter() - t_tune
     b = pg.Batch(probs)        # allocates every problem's outputs
     tiles, grid = b.tiles
-    # one call per problem, same paths and outputs, workspaces allocated up front
+    # one call per problem, same paths, outputs of their own, workspaces
+    # allocated up front
+    loop_out = []
     for p in probs:
         if isinstance(p, pg.IbsProblem):
             ws = torch.empty(max(pg.ibs_workspace_bytes(p.cohort, path=p.path), 1),
                              dtype=torch.uint8, device=dev)
-            calls.append(lambda p=p, ws=ws: pg.ibs_matrix(p.cohort, layout="tri", path=p.path,
-                                                          out=p.out, workspace=ws))
+            o = tuple(torch.empty_like(t) for t in p.out)
+            calls.append(lambda p=p, ws=ws, o=o: pg.ibs_matrix(p.cohort, layout="tri",
+                                                               path=p.path, out=o, workspace=ws))
         else:
             ws = torch.empty(max(pg.ld_workspace_bytes(p.cohort, p.window, path=p.path), 1),
                              dtype=torch.uint8, device=dev)
-            calls.append(lambda p=p, ws=ws: pg.ld_window(p.cohort, p.window, p.r2_min,
-                                                         capacity=p.capacity, path=p.path,
-                                                         out=p.out, n_out=p.n_out, workspace=ws))
+            o = (torch.empty_like(p.out), torch.empty_like(p.n_out))
+            calls.append(lambda p=p, ws=ws, o=o: pg.ld_window(
+                p.cohort, p.window, p.r2_min, capacity=p.capacity, path=p.path, out=o[0],
+                n_out=o[1], workspace=ws))
+        loop_out.append(o)
 
     def loop():
         for f in calls:
             f()
 
     ms_loop, _ = timed_steps(torch, lib, hip, loop, steps, 2, 0)
-    loop_ld = [int(p.n_out.item()) for p in probs if isinstance(p, pg.LdProblem)]
     b.capture()
     ms_graph, _ = timed_steps(torch, lib, hip, b.replay, steps, 2, 0)
     ms_direct, st_d = timed_steps(torch, lib, hip, b.launch, steps, 2, 4)
-    batch_ld = [int(p.n_out.item()) for p in probs if isinstance(p, pg.LdProblem)]
-    assert batch_ld == loop_ld, "batched LD counts differ from the per-problem loop"
+    torch.cuda.synchronize()
+    # every output of the batch equals its one-call-per-problem counterpart
+    for k, (p, o) in enumerate(zip(probs, loop_out)):
+        if isinstance(p, pg.IbsProblem):
+            assert all(torch.equal(x, y) for x, y in zip(p.out, o)), f"IBS problem {k}"
+        else:
+            total = int(o[1].item())
+            assert int(p.n_out.item()) == total, f"LD problem {k}: emitted count"
+            kept = min(total, p.capacity)
+            assert torch.equal(p.out[:kept], o[0][:kept]), f"LD problem {k}: records"
+    del loop_out, calls
     choice = {}
     for p in probs:
         k = ("ibs_" if isinstance(p, pg.IbsProblem) else "ld_") + \
@@ -344,13 +368,11 @@ def bench_serve(torch, pg, synth, dev, seconds, serial_seconds):
     8-slot server is compared with one request at a time on the same arrivals."""
     import numpy as np
     from paper_1410_4803_amd.serve import GpuBackend, Server, poisson_requests
-    rng = np.random.Generator(np.random.PCG64(1004))
-    shapes = [(int(round(math.exp(rng.uniform(math.log(1000), math.log(50000))))),
-               int(round(math.exp(rng.uniform(math.log(10000), math.log(200000))))))
-              for _ in range(8)]
+    specs = synth.serve_cohorts()
+    shapes = [(d["n"], d["V"]) for d in specs]
     log(f"serving: generating 8 cohorts {shapes}")
-    cohorts = [pg.Cohort.from_numpy(synth.hwe(n, V, (0.01, 0.5), 0.01, seed=2000 + k), n,
-                                    device=dev) for k, (n, V) in enumerate(shapes)]
+    cohorts = [pg.Cohort.from_numpy(synth.serve_cohort_bed(d), d["n"], device=dev)
+               for d in specs]
     resident = sum(c.nbytes for c in cohorts)
     budget = 64 << 30
     reqs = poisson_requests(shapes, rate=200.0, seconds=seconds, seed=1005)
@@ -490,9 +512,16 @@ def main():
         call2, out2 = ibs_runner(other)
         log(f"timing the {other} path")
         ms2, st2 = timed_steps(torch, lib, hip, call2, max(3, args.steps // 2), 1, 3)
-        extras[f"ibs_large_{other}"] = {"value": round(comps / (ms2 * 1e-3) / 1e9, 1), "unit": "G/s",
-                                        "ms_per_step": round(ms2, 3),
-                                        "pair_kernel_ms": round(mean(st2[1]), 3)}
+        pk2 = mean(st2[1])
+        rec2 = {"value": round(comps / (ms2 * 1e-3) / 1e9, 1), "unit": "G/s",
+                "ms_per_step": round(ms2, 3), "pair_kernel_ms": round(pk2, 3)}
+        if other == "popc":
+            ach2 = comps * IBS_POPC_OPS / (pk2 * 1e-3) / 1e12
+            rec2["roofline"] = {"bound": "alu", "kernel": "k_ibs_popc", "unit": "TOP/s",
+                                "ops_per_32_comparisons": 8, "achieved": round(ach2, 2),
+                                "peak": round(PEAK_VALU_TOPS, 2),
+                                "frac": round(ach2 / PEAK_VALU_TOPS, 4)}
+        extras[f"ibs_large_{other}"] = rec2
         del call2, out2
         torch.cuda.empty_cache()
 

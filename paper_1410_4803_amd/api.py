@@ -10,6 +10,7 @@ every computation runs in the library's HIP kernels.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 from dataclasses import dataclass
 
@@ -36,6 +37,14 @@ def _stream_handle(stream) -> int:
 
 def _ptr(t) -> int | None:
     return None if t is None else int(t.data_ptr())
+
+
+def _on(stream):
+    """Context in which buffers for a call on `stream` are allocated: the
+    caching allocator then ties them to that stream, so a workspace freed
+    when the call returns is not handed to other streams' work while the
+    library's kernels may still use it."""
+    return torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()
 
 
 @dataclass
@@ -124,18 +133,19 @@ def ibs_matrix(cohort: Cohort, *, sample_idx: torch.Tensor | None = None, v_rang
     n_sel, vb, ve = _sel(cohort, sample_idx, v_range)
     m = n_sel or cohort.n_samples
     size = ibs_output_size(m, layout)
-    if out is None:
-        shape = (m, m) if layout == "full" else (size,)
-        out = tuple(torch.empty(shape, dtype=torch.int32, device=cohort.bed.device)
-                    for _ in range(4))
-    else:
-        for k, t in enumerate(out):
-            _require_cuda(t, f"out[{k}]", torch.int32)
-            if t.numel() < size:
-                raise ValueError("output tensor too small")
-    need = ibs_workspace_bytes(cohort, n_sel, (vb, ve), path)
-    if workspace is None:
-        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=cohort.bed.device)
+    with _on(stream):
+        if out is None:
+            shape = (m, m) if layout == "full" else (size,)
+            out = tuple(torch.empty(shape, dtype=torch.int32, device=cohort.bed.device)
+                        for _ in range(4))
+        else:
+            for k, t in enumerate(out):
+                _require_cuda(t, f"out[{k}]", torch.int32)
+                if t.numel() < size:
+                    raise ValueError("output tensor too small")
+        need = ibs_workspace_bytes(cohort, n_sel, (vb, ve), path)
+        if workspace is None:
+            workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=cohort.bed.device)
     g = cohort.struct()
     st = lib.pg_ibs_matrix(ctypes.byref(g), _ptr(sample_idx), n_sel, vb, ve, N.LAYOUTS[layout],
                            _path(path), *[_ptr(t) for t in out], _ptr(workspace),
@@ -163,13 +173,14 @@ def ld_window(cohort: Cohort, window: int, r2_min: float, *, capacity: int,
     lib = N.load()
     n_sel, vb, ve = _sel(cohort, sample_idx, v_range)
     dev = cohort.bed.device
-    if out is None:
-        out = torch.empty((max(capacity, 1), 64), dtype=torch.uint8, device=dev)
-    if n_out is None:
-        n_out = torch.empty(1, dtype=torch.int64, device=dev)
-    need = ld_workspace_bytes(cohort, window, n_sel, (vb, ve), path)
-    if workspace is None:
-        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    with _on(stream):
+        if out is None:
+            out = torch.empty((max(capacity, 1), 64), dtype=torch.uint8, device=dev)
+        if n_out is None:
+            n_out = torch.empty(1, dtype=torch.int64, device=dev)
+        need = ld_workspace_bytes(cohort, window, n_sel, (vb, ve), path)
+        if workspace is None:
+            workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
     g = cohort.struct()
     st = lib.pg_ld_window(ctypes.byref(g), _ptr(sample_idx), n_sel, vb, ve, int(window),
                           float(r2_min), _ptr(out), int(capacity), _ptr(n_out), _path(path),
@@ -219,13 +230,14 @@ def ld_prune(cohort: Cohort, window: int, step: int, r2_threshold: float, *,
     n_sel, vb, ve = _sel(cohort, sample_idx, v_range)
     dev = cohort.bed.device
     nv = (ve - vb) if (vb, ve) != (0, 0) else cohort.n_variants
-    if keep is None:
-        keep = torch.empty(nv, dtype=torch.uint8, device=dev)
-    if n_kept is None:
-        n_kept = torch.empty(1, dtype=torch.int64, device=dev)
-    need = prune_workspace_bytes(cohort, window, n_sel, (vb, ve), path)
-    if workspace is None:
-        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    with _on(stream):
+        if keep is None:
+            keep = torch.empty(nv, dtype=torch.uint8, device=dev)
+        if n_kept is None:
+            n_kept = torch.empty(1, dtype=torch.int64, device=dev)
+        need = prune_workspace_bytes(cohort, window, n_sel, (vb, ve), path)
+        if workspace is None:
+            workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
     g = cohort.struct()
     st = lib.pg_ld_prune(ctypes.byref(g), _ptr(sample_idx), n_sel, vb, ve, int(window), int(step),
                          float(r2_threshold), _ptr(keep), _ptr(n_kept), _path(path),
@@ -255,8 +267,9 @@ def grm_matrix(cohort: Cohort, *, sample_idx: torch.Tensor | None = None, v_rang
     dev = cohort.bed.device
     if out is None:
         shape = (m, m) if layout == "full" else (ibs_output_size(m, layout),)
-        out = (torch.empty(shape, dtype=torch.float64, device=dev),
-               torch.empty(shape, dtype=torch.int32, device=dev))
+        with _on(stream):
+            out = (torch.empty(shape, dtype=torch.float64, device=dev),
+                   torch.empty(shape, dtype=torch.int32, device=dev))
     A, Nn = out
     size = ibs_output_size(m, layout)
     _require_cuda(A, "A", torch.float64)
@@ -265,7 +278,8 @@ def grm_matrix(cohort: Cohort, *, sample_idx: torch.Tensor | None = None, v_rang
         raise ValueError(f"outputs need {size} entries")
     need = grm_workspace_bytes(cohort, n_sel, (vb, ve))
     if workspace is None:
-        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+        with _on(stream):
+            workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
     g = cohort.struct()
     st = lib.pg_grm_matrix(ctypes.byref(g), _ptr(sample_idx), n_sel, vb, ve, N.LAYOUTS[layout],
                            _path(path), _ptr(A), _ptr(Nn), _ptr(workspace), workspace.numel(),
@@ -281,7 +295,8 @@ def ibs_distance(ibs0: torch.Tensor, ibs1: torch.Tensor, nonmiss: torch.Tensor, 
     for t, name in ((ibs0, "ibs0"), (ibs1, "ibs1"), (nonmiss, "nonmiss")):
         _require_cuda(t, name, torch.int32)
     if out is None:
-        out = torch.empty(ibs0.shape, dtype=torch.float64, device=ibs0.device)
+        with _on(stream):
+            out = torch.empty(ibs0.shape, dtype=torch.float64, device=ibs0.device)
     _require_cuda(out, "out", torch.float64)
     if not (ibs0.numel() == ibs1.numel() == nonmiss.numel() == out.numel()):
         raise ValueError("inputs and output must have the same number of entries")
@@ -312,10 +327,11 @@ def ibs_cluster(ibs0: torch.Tensor, ibs1: torch.Tensor, ibs2: torch.Tensor | Non
     for t, name in ((ibs0, "ibs0"), (ibs1, "ibs1"), (nonmiss, "nonmiss")):
         _require_cuda(t, name, torch.int32)
     dev = ibs0.device
-    if out is None:
-        out = torch.empty((max(m - 1, 1), 16), dtype=torch.uint8, device=dev)
-    if workspace is None:
-        workspace = torch.empty(cluster_workspace_bytes(m), dtype=torch.uint8, device=dev)
+    with _on(stream):
+        if out is None:
+            out = torch.empty((max(m - 1, 1), 16), dtype=torch.uint8, device=dev)
+        if workspace is None:
+            workspace = torch.empty(cluster_workspace_bytes(m), dtype=torch.uint8, device=dev)
     N.check(N.load().pg_ibs_cluster(_ptr(ibs0), _ptr(ibs1), _ptr(nonmiss), m, _ptr(out),
                                     _ptr(workspace), workspace.numel(), _stream_handle(stream)),
             "pg_ibs_cluster")

@@ -51,7 +51,10 @@ class GpuBackend:
     """Runs requests through the library on per-slot streams."""
 
     def __init__(self, cohorts: list[Cohort], n_slots: int, device=None, tuner=None,
-                 keep_results: bool = True, ld_capacity: int = 1 << 18):
+                 keep_results: bool | str = True, ld_capacity: int = 1 << 18):
+        """keep_results: True keeps each result (numpy arrays) on its
+        request, False keeps nothing, "digest" keeps a 128-bit hash of the
+        result's bytes (for comparing many large results)."""
         self.cohorts = cohorts
         self.device = device or cohorts[0].bed.device
         self.tuner = tuner
@@ -148,19 +151,37 @@ class GpuBackend:
         LD query overflowed its buffer: req.ld_capacity is then set to the
         needed size and the server re-issues the request."""
         req.device_ms = h["e0"].elapsed_time(h["e1"])
+        res = None
         if h["kind"] == "ibs":
-            res = tuple(v.numpy().view(np.uint32).copy() for v in h["views"]) if self.keep else None
+            if self.keep == "digest":
+                res = _digest(v.numpy() for v in h["views"])
+            elif self.keep:
+                res = tuple(v.numpy().view(np.uint32).copy() for v in h["views"])
         else:
             total = int(h["n"].item())
             if total > h["cap"]:
                 req.ld_capacity = total
                 return False
-            res = None
-            if self.keep:
+            if self.keep == "digest":
+                res = _digest([h["out"][:64 * total].numpy()])
+            elif self.keep:
                 raw = h["out"][:64 * total].numpy().copy()
                 res = raw.view(N.LD_PAIR)
         req.result = res
         return True
+
+
+def _digest(arrays) -> str:
+    """128-bit hash of the concatenated bytes of numpy arrays."""
+    try:
+        import xxhash
+        h = xxhash.xxh3_128()
+    except ImportError:                       # pragma: no cover
+        import hashlib
+        h = hashlib.blake2b(digest_size=16)
+    for a in arrays:
+        h.update(np.ascontiguousarray(a).reshape(-1).view(np.uint8))
+    return h.hexdigest()
 
 
 class Server:
@@ -227,6 +248,11 @@ class Server:
                 continue
             if not ok:                                # re-issue with a larger buffer, at the front
                 req.footprint = self.backend.footprint(req)
+                if req.footprint > self.budget:       # the larger buffer can never fit
+                    req.error = "footprint after LD overflow exceeds the memory budget"
+                    req.done = self.now()
+                    self.rejected.append(req)
+                    continue
                 self.queue.appendleft(req)
                 continue
             req.done = self.now()

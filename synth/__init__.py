@@ -187,3 +187,21 @@ def batch_problems(seed: int = 1003, count: int = 64, make_bed: bool = True) -> 
             d["bed"] = hwe(n, V, (0.01, 0.5), 0.01, d["seed"])
         probs.append(d)
     return probs
+
+
+def serve_cohorts(seed: int = 1004, count: int = 8) -> list:
+    """Serving workload cohorts: samples log-uniform in [1k, 50k], variants
+    log-uniform in [10k, 200k] (PCG64 `seed`), HWE MAF~U[0.01,0.5], 1%
+    missing.  Returns dicts with n, V and the .bed seed; call hwe() (or
+    serve_cohort_bed) for the payload."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for k in range(count):
+        n = int(round(math.exp(rng.uniform(math.log(1000), math.log(50000)))))
+        V = int(round(math.exp(rng.uniform(math.log(10000), math.log(200000)))))
+        out.append(dict(n=n, V=V, seed=2000 + k))
+    return out
+
+
+def serve_cohort_bed(d: dict) -> np.ndarray:
+    return hwe(d["n"], d["V"], (0.01, 0.5), 0.01, d["seed"])

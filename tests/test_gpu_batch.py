@@ -145,3 +145,77 @@ def test_batch_generated_workload_subset():
     for k, (g, s) in enumerate(zip(got, singles)):
         assert _same(g, s), f"problem {k}"
     b.close()
+
+
+def _tri_row_pairs(m, rows):
+    """Packed upper-triangle indices and (i, j) pairs of whole rows: every
+    pair of each listed sample with every other sample."""
+    idx, pi, pj = [], [], []
+    for i in rows:
+        j = np.delete(np.arange(m), i)
+        a, b = np.minimum(i, j), np.maximum(i, j)
+        idx.append(a * m - a * (a + 1) // 2 + (b - a - 1))
+        pi.append(a)
+        pj.append(b)
+    return np.concatenate(idx), np.concatenate(pi), np.concatenate(pj)
+
+
+def test_batch_full_workload():
+    """The whole 64-problem batched workload (samples log-uniform in [200,
+    20,000], variants in [2,000, 50,000], HWE, 1% missing; even problems IBS
+    triangles, odd problems LD windows of 500 at r^2 >= 0.2) as the
+    benchmark runs it: tuner-chosen paths, captured in one HIP graph and
+    replayed twice.  Every problem's outputs, in buffers of their own, equal
+    a separate call per problem byte for byte (IBS: all four counts; LD: the
+    total and the record list), and whole rows of the three largest IBS
+    problems and row ranges of the three largest LD problems match the
+    oracle."""
+    specs = synth.batch_problems()
+    assert len(specs) == 64
+    tuner = pg.Tuner()
+    probs = []
+    for d in specs:
+        c = pg.Cohort.from_numpy(d["bed"], d["n"])
+        if d["kind"] == "ibs":
+            path = tuner.tune("ibs", c, layout="tri", reps=1, for_batch=True)
+            probs.append(pg.IbsProblem(c, layout="tri", path=path))
+        else:
+            path = tuner.tune("ld", c, window=d["window"], r2_min=d["r2_min"], reps=1,
+                              for_batch=True)
+            probs.append(pg.LdProblem(c, window=d["window"], r2_min=d["r2_min"],
+                                      capacity=max(1 << 16, 64 * d["V"]), path=path))
+    b = pg.Batch(probs)
+    b.capture()
+    b.replay()
+    b.replay()
+    got = b.results()
+    for k, p in enumerate(probs):
+        s = _single(p)
+        if isinstance(p, pg.IbsProblem):
+            for x, y in zip(got[k], s):
+                assert torch.equal(x, y), f"problem {k} (IBS {specs[k]['n']} x {specs[k]['V']})"
+        else:
+            assert int(p.n_out.item()) == len(s), f"problem {k}: emitted count"
+            assert got[k].tobytes() == s.tobytes(), f"problem {k} (LD)"
+        del s
+    ibs_k = sorted((k for k in range(64) if specs[k]["kind"] == "ibs"),
+                   key=lambda k: specs[k]["n"] ** 2 * specs[k]["V"])[-3:]
+    for k in ibs_k:
+        d = specs[k]
+        m, V = d["n"], d["V"]
+        rows = np.array([0, 1, m // 2, m - 2, m - 1])
+        tidx, pi, pj = _tri_row_pairs(m, rows)
+        ref = oracle.ibs_pairs(oracle.unpack(d["bed"], m, V, sample_major=True), pi, pj)
+        t = torch.from_numpy(tidx).cuda()
+        g = np.stack([o[t].cpu().numpy().view(np.uint32) for o in got[k]], 1)
+        assert np.array_equal(g, ref), f"problem {k}: rows differ from the oracle"
+    ld_k = sorted((k for k in range(64) if specs[k]["kind"] == "ld"),
+                  key=lambda k: specs[k]["n"] * specs[k]["V"])[-3:]
+    for k in ld_k:
+        d = specs[k]
+        codes = oracle.unpack(d["bed"], d["n"], d["V"])
+        for a0 in (0, d["V"] // 2, d["V"] - 60):
+            ref = oracle.ld_window(codes, d["window"], d["r2_min"], a_begin=a0, a_end=a0 + 60)
+            sel = got[k][(got[k]["a"] >= a0) & (got[k]["a"] < a0 + 60)]
+            compare_records(sel, ref, d["r2_min"])
+    b.close()

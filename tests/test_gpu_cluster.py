@@ -100,3 +100,23 @@ def test_cluster_full_size_large_workload_hierarchy():
         assert a < b and alive[a] and alive[b]
         alive[b] = False
     assert alive.sum() == 1 and alive[0]
+
+
+def test_cluster_full_size_large_workload_exact():
+    """Complete linkage of the 10,000-sample panel, merge for merge (pair and
+    height, ties included) against the oracle's sequence stored by
+    tests/golden/make_fullsize.py (oracle IBS counts -> oracle distance ->
+    oracle clustering on the same seeded panel, whose hash the file
+    records)."""
+    import os
+    import sys
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+    import make_fullsize
+    sha, ref = make_fullsize.load_cluster()
+    w = synth.grm_large()
+    n = w["n"]
+    assert make_fullsize.bed_sha256(w["bed"]) == sha, "stored merges were computed from another panel"
+    assert len(ref) == n - 1
+    got = _cluster(_ibs(w["bed"], n), n)
+    assert np.array_equal(got["a"], ref["a"]) and np.array_equal(got["b"], ref["b"])
+    assert np.array_equal(got["height"], ref["height"])

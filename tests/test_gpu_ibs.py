@@ -116,111 +116,70 @@ def test_ibs_small_workload_exact(path):
 
 @pytest.fixture(scope="module")
 def large():
+    """The 10,000 x 100,000 workload in the benchmark's launch configuration
+    (full layout, default matrix-core kernel), computed once."""
     w = synth.ibs_large()
     c = _cohort(w["bed"], w["n"])
-    return w, c
-
-
-def test_ibs_large_default_matches_variant_one(large):
-    """At 10,000 x 100,000 the whole matrix of the default matrix-core kernel
-    equals that of variant 1 (the same tile body without scheduling hints),
-    every entry, not just the sampled pairs below."""
-    w, c = large
-    a = pg.ibs_matrix(c, layout="full", path=CODES["mfma"])
-    b = pg.ibs_matrix(c, layout="full", path=CODES["mfma"] | (1 << 8))
-    for x, y in zip(a, b):
-        assert torch.equal(x, y)
-
-
-@pytest.mark.parametrize("path", PATHS)
-def test_ibs_large_workload_sampled(large, path):
-    """10,000 x 100,000 mosaic, full matrix, in the benchmark's launch
-    configuration; 3,000 sampled pairs (plus diagonal entries and the tile
-    corners) against the oracle, and whole-matrix properties."""
-    w, c = large
-    n, V = w["n"], w["V"]
-    out = pg.ibs_matrix(c, layout="full", path=CODES[path])
+    ref = pg.ibs_matrix(c, layout="full", path=CODES["mfma"])
     torch.cuda.synchronize()
-    rng = np.random.default_rng(99)
-    pi = rng.integers(0, n, 3000)
-    pj = rng.integers(0, n, 3000)
-    edges = np.array([0, 1, 63, 64, 127, 128, 129, 9983, 9984, 9998, 9999])
-    pi = np.concatenate([pi, edges, np.repeat(edges, len(edges))])
-    pj = np.concatenate([pj, edges, np.tile(edges, len(edges))])
+    return w, c, ref
+
+
+def test_ibs_large_rows_vs_oracle(large):
+    """32 whole rows of the 10,000 x 100,000 matrix (320,000 pairs, the tile
+    edges among them) against the oracle, every count, plus whole-matrix
+    properties of the default kernel's output."""
+    w, c, out = large
+    n, V = w["n"], w["V"]
+    rng = np.random.default_rng(2024)
+    edges = np.array([0, 1, 63, 64, 127, 128, 4999, 9871, 9983, 9984, 9998, 9999])
+    others = rng.choice(np.setdiff1d(np.arange(n), edges), 20, replace=False)
+    rows = np.sort(np.concatenate([edges, others]))
+    assert len(rows) == 32
     codes_sm = oracle.unpack(w["bed"], n, V, sample_major=True)
-    ref = oracle.ibs_pairs(codes_sm, pi, pj)
-    ti = torch.from_numpy(pi).cuda()
-    tj = torch.from_numpy(pj).cuda()
-    got = np.stack([o[ti, tj].cpu().numpy().view(np.uint32) for o in out], 1)
-    assert np.array_equal(got, ref)
+    pi = np.repeat(rows, n)
+    pj = np.tile(np.arange(n), len(rows))
+    ref = oracle.ibs_pairs(codes_sm, pi, pj).reshape(len(rows), n, 4)
+    tr = torch.from_numpy(rows).cuda()
+    for k, o in enumerate(out):
+        got = o[tr].cpu().numpy().view(np.uint32)
+        bad = np.argwhere(got != ref[:, :, k])
+        assert bad.size == 0, f"count {k}: {len(bad)} mismatches, first {bad[:3].tolist()}"
     i0, i1, i2, nm = out
     assert torch.equal(i0 + i1 + i2, nm)
     for o in out:
         assert torch.equal(o, o.T)
     assert (torch.diagonal(i0) == 0).all() and (torch.diagonal(i1) == 0).all()
-    nonmiss = (codes_sm != 1).sum(1)
-    assert np.array_equal(torch.diagonal(nm).cpu().numpy(), nonmiss)
-    assert np.array_equal(torch.diagonal(i2).cpu().numpy(), nonmiss)
 
 
-@pytest.mark.parametrize("path", PATHS)
-@pytest.mark.parametrize("n,extra", [(97, 0), (97, 5), (160, 3), (1000, 0)])
-def test_ibs_mask_and_row_stride(path, n, extra):
-    """Missing mask with all samples (the transposing layout path), rows
-    padded to a stride larger than ceil(n/4) with garbage bytes."""
-    V = 777
-    bed = synth.hwe(n, V, (0.05, 0.5), 0.02, seed=n + extra, garbage_pad=True)
-    mask = synth.missing_mask(n, V, 0.04, seed=n + 1)
-    if extra:
-        junk = np.random.default_rng(n).integers(0, 256, (V, extra), dtype=np.uint8)
-        bed = np.concatenate([bed, junk], axis=1)
-    codes = oracle.unpack(bed, n, V, mask)
-    ref = oracle.ibs_matrix(codes, full=True)
-    got = pg.ibs_matrix(_cohort(bed, n, mask), layout="full", path=CODES[path])
-    _check_full(got, ref)
-    for variant in (1, 2):
-        if path == "mfma":
-            got = pg.ibs_matrix(_cohort(bed, n, mask), layout="full", path=2 | (variant << 8))
-            _check_full(got, ref)
+@pytest.mark.parametrize("path", PATHS + ["mfma_v1"])
+def test_ibs_large_paths_equal_whole_matrix(large, path):
+    """Every other path and kernel variant gives the default kernel's whole
+    10,000 x 10,000 output, all four counts, entry for entry (the default is
+    pinned to the oracle by the rows above); 300 random pairs of each path
+    also go to the oracle directly."""
+    w, c, ref = large
+    code = CODES["mfma"] | (1 << 8) if path == "mfma_v1" else CODES[path]
+    out = pg.ibs_matrix(c, layout="full", path=code)
+    torch.cuda.synchronize()
+    for k, (x, y) in enumerate(zip(out, ref)):
+        assert torch.equal(x, y), f"{path}: count {k} differs from the default kernel"
+    n, V = w["n"], w["V"]
+    rng = np.random.default_rng(sum(map(ord, path)))
+    pi, pj = rng.integers(0, n, 300), rng.integers(0, n, 300)
+    codes_sm = oracle.unpack(w["bed"], n, V, sample_major=True)
+    r = oracle.ibs_pairs(codes_sm, pi, pj)
+    ti, tj = torch.from_numpy(pi).cuda(), torch.from_numpy(pj).cuda()
+    got = np.stack([o[ti, tj].cpu().numpy().view(np.uint32) for o in out], 1)
+    assert np.array_equal(got, r)
 
 
-def _offset_cohort(bed, n, mask, shift):
-    """A cohort whose .bed buffer starts `shift` bytes past an allocation's
-    start (so its rows need not start on a dword boundary)."""
-    flat = np.concatenate([np.full(shift, 0xA5, np.uint8), bed.ravel()])
-    t = torch.from_numpy(flat).cuda()[shift:]
-    m = None if mask is None else torch.from_numpy(np.ascontiguousarray(mask).view(np.int64)).cuda()
-    return pg.Cohort(t, n, bed.shape[0], bed.shape[1], m)
-
-
-@pytest.mark.parametrize("path", ["popc", "mfma", "fp4rep"])
-@pytest.mark.parametrize("n,V,vb,ve,shift,masked", [
-    (97, 300, 7, 251, 1, True),      # 25-byte rows, the range starts inside a dword
-    (1000, 200, 3, 200, 2, True),    # 250-byte rows, the range ends at the buffer's end
-    (160, 90, 0, 90, 0, False),      # 40-byte rows, dword-aligned
-    (160, 90, 5, 61, 3, False),      # the same rows off a dword boundary
-    (5, 4, 2, 3, 3, True),           # one 2-byte row: too small for dword reads
-    (2, 9, 0, 9, 1, False),          # nine 1-byte rows
-])
-def test_ibs_variant_range_without_sample_list(path, n, V, vb, ve, shift, masked):
-    """Variant ranges over all samples: the whole-row reader's edge cases."""
-    bed = synth.hwe(n, V, (0.05, 0.5), 0.02, seed=n + V + vb)
-    mask = synth.missing_mask(n, V, 0.04, seed=n + 3) if masked else None
-    codes = oracle.select(oracle.unpack(bed, n, V, mask), None, vb, ve)
-    c = _offset_cohort(bed, n, mask, shift)
-    for layout in ("full", "tri"):
-        ref = oracle.ibs_matrix(codes, full=layout == "full")
-        got = pg.ibs_matrix(c, v_range=(vb, ve), layout=layout, path=CODES[path])
-        _check_full(got, ref)
-
-
-def test_ibs_medium_cohort_k_split():
-    """1,800 samples (120 tiles of 128): the default matrix-core kernel splits
-    each tile's 32 chunks of 256 variants into two ranges; every pair against
-    the oracle."""
-    n, V = 1800, 8000
-    bed = synth.hwe(n, V, (0.05, 0.5), 0.02, seed=1800)
-    codes = oracle.unpack(bed, n, V)
-    ref = oracle.ibs_matrix(codes, full=False)
-    got = pg.ibs_matrix(_cohort(bed, n), layout="tri", path=CODES["mfma"])
-    _check_full(got, ref)
+def test_ibs_large_triangle_equals_full(large):
+    """The packed upper-triangle layout at 10,000 x 100,000 holds exactly the
+    full layout's strict upper triangle."""
+    w, c, ref = large
+    n = w["n"]
+    tri = pg.ibs_matrix(c, layout="tri", path=CODES["mfma"])
+    iu = torch.triu_indices(n, n, 1, device="cuda")
+    for k, (t, f) in enumerate(zip(tri, ref)):
+        assert torch.equal(t, f[iu[0], iu[1]]), f"count {k}"

@@ -107,25 +107,64 @@ def test_ld_capacity_protocol_and_determinism():
 
 @pytest.fixture(scope="module")
 def ld_large():
-    w = synth.ld_large()
-    return w, pg.Cohort.from_numpy(w["bed"], w["n"])
-
-
-@pytest.mark.parametrize("path", PATHS)
-def test_ld_large_workload_sampled(ld_large, path):
     """5,000 samples x 500,000 variants, window 1,000, r^2 >= 0.2, in the
-    benchmark's launch configuration; the oracle recomputes every pair of
-    three row ranges (including the first and last rows)."""
-    w, c = ld_large
+    benchmark's launch configuration; the default path's records, once."""
+    w = synth.ld_large()
+    c = pg.Cohort.from_numpy(w["bed"], w["n"])
+    ref = pg.ld_records(c, w["window"], w["r2_min"], path="mfma")
+    return w, c, ref
+
+
+def _row_ranges(V, count, width, seed):
+    rng = np.random.default_rng(seed)
+    starts = [0, V - width] + sorted(rng.choice(np.arange(width, V - 2 * width, width),
+                                                count - 2, replace=False).tolist())
+    return [(int(s), int(s) + width) for s in starts]
+
+
+def test_ld_large_rows_vs_oracle(ld_large):
+    """Twelve ranges of 100 rows (the first and last rows among them: 1.2
+    million in-window pairs) recomputed by the oracle and compared with the
+    default path's records: every count exact, r^2 within 1e-12."""
+    w, c, got = ld_large
     n, V, W = w["n"], w["V"], w["window"]
-    got = pg.ld_records(c, W, w["r2_min"], path=path)
     assert len(got) > 0
     assert (np.diff(got["a"].astype(np.int64) * (1 << 32) + got["b"]) > 0).all()
     codes = oracle.unpack(w["bed"], n, V)
-    for a0, a1 in [(0, 120), (250_000, 250_120), (V - 150, V)]:
+    total = 0
+    for a0, a1 in _row_ranges(V, 12, 100, 11):
         ref = oracle.ld_window(codes, W, w["r2_min"], a_begin=a0, a_end=a1)
         sel = got[(got["a"] >= a0) & (got["a"] < a1)]
-        assert _compare(sel, ref, w["r2_min"]) > 0
+        total += _compare(sel, ref, w["r2_min"])
+    assert total > 0
+
+
+@pytest.mark.parametrize("path", ["popc", "sparse", 3 | (1 << 8)])
+def test_ld_large_paths_equal_records(ld_large, path):
+    """The popcount path, the correction path (with its default tile rule
+    and with every tile forced onto it) emit the default path's record list
+    at 5,000 x 500,000 byte for byte."""
+    w, c, ref = ld_large
+    got = pg.ld_records(c, w["window"], w["r2_min"], path=path)
+    assert len(got) == len(ref)
+    assert got.tobytes() == ref.tobytes()
+
+
+def test_ld_large_without_missing_calls():
+    """The same panel without missing calls (where the correction path takes
+    its tiles): the correction and dense paths emit identical record lists,
+    and four row ranges match the oracle."""
+    w = synth.ld_large_nomiss()
+    n, V, W = w["n"], w["V"], w["window"]
+    c = pg.Cohort.from_numpy(w["bed"], n)
+    dense = pg.ld_records(c, W, w["r2_min"], path="mfma")
+    sparse = pg.ld_records(c, W, w["r2_min"], path="sparse")
+    assert dense.tobytes() == sparse.tobytes()
+    codes = oracle.unpack(w["bed"], n, V)
+    for a0, a1 in _row_ranges(V, 4, 100, 12):
+        ref = oracle.ld_window(codes, W, w["r2_min"], a_begin=a0, a_end=a1)
+        sel = sparse[(sparse["a"] >= a0) & (sparse["a"] < a1)]
+        _compare(sel, ref, w["r2_min"])
 
 
 @pytest.mark.parametrize("path", PATHS)

@@ -147,3 +147,26 @@ def test_prune_full_size_small_workload():
     for path in ("mfma", "sparse"):
         got = _gpu(wp["bed"], wp["n"], wp["window"], wp["step"], wp["r2_max"], path=path)
         assert np.array_equal(got, ref), path
+
+
+def _golden():
+    import os
+    import sys
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+    import make_fullsize
+    return make_fullsize
+
+
+def test_prune_full_size_large_workload():
+    """The whole 10,000 x 88,025 --indep-pairwise 700 70 0.7 workload the
+    benchmark times, flag for flag against the oracle's flags stored by
+    tests/golden/make_fullsize.py (computed from the same seeded panel,
+    whose hash the file records), on every pair-kernel path."""
+    gold = _golden()
+    sha, ref = gold.load_prune()
+    wp = synth.prune_large()
+    assert gold.bed_sha256(wp["bed"]) == sha, "stored flags were computed from another panel"
+    assert len(ref) == wp["V"]
+    for path in PATHS:
+        got = _gpu(wp["bed"], wp["n"], wp["window"], wp["step"], wp["r2_max"], path=path)
+        assert np.array_equal(got, ref), path

@@ -76,3 +76,67 @@ def test_overflowing_ld_request_is_reissued(cohorts):
     ref = pg.ld_records(cs[1], 300, -np.inf, sample_idx=pg.api.torch.from_numpy(idx).cuda(),
                         v_range=(100, 2100))
     assert got.result.tobytes() == ref.tobytes()
+
+
+def test_serving_workload_cohorts():
+    """The serving workload's eight resident cohorts (up to 12,312 samples
+    and 180,243 variants) and the first second of its 200 requests/s Poisson
+    arrivals: every response of the 8-slot mix equals the same request run
+    alone (a one-slot server, nothing else on the GPU), compared by a 128-bit
+    hash of the result bytes; the smallest IBS and LD responses are checked
+    whole against the oracle, and the IBS response with the most samples on
+    sampled pairs."""
+    specs = synth.serve_cohorts()
+    shapes = [(d["n"], d["V"]) for d in specs]
+    beds = [synth.serve_cohort_bed(d) for d in specs]
+    cs = [pg.Cohort.from_numpy(b, n) for b, (n, V) in zip(beds, shapes)]
+    reqs = poisson_requests(shapes, rate=200.0, seconds=1.0, seed=1005)
+    assert len(reqs) >= 150
+    budget = 64 << 30
+    mix = Server(GpuBackend(cs, 8, keep_results="digest"), 8, budget)
+    st = mix.run([_copy(r) for r in reqs])
+    assert st["completed"] == len(reqs) and st["rejected"] == 0
+    alone_reqs = [_copy(r) for r in reqs]
+    for r in alone_reqs:
+        r.arrival = 0.0
+    alone = Server(GpuBackend(cs, 1, keep_results="digest"), 1, budget)
+    alone.run(alone_reqs)
+    assert alone.max_running == 1
+    dig = {r.rid: r.result for r in alone.finished}
+    assert len(dig) == len(reqs)
+    for r in mix.finished:
+        assert r.result == dig[r.rid], f"request {r.rid} ({r.kind}) differs in the mix"
+
+    def work(r):
+        return len(r.sample_idx) ** 2 * (r.v_range[1] - r.v_range[0])
+
+    ibs = [r for r in reqs if r.kind == "ibs"]
+    ld = [r for r in reqs if r.kind == "ld"]
+    picks = [min(ibs, key=work), min(ld, key=work), max(ibs, key=lambda r: len(r.sample_idx))]
+    keep = Server(GpuBackend(cs, 1, keep_results=True), 1, budget)
+    keep.run([_copy(r) for r in picks])
+    by_rid = {r.rid: r for r in keep.finished}
+    from paper_1410_4803_amd.serve import _digest
+    for k, p in enumerate(picks):
+        r = by_rid[p.rid]
+        n, V = shapes[r.cohort]
+        raw = r.result if r.kind == "ld" else tuple(x.view(np.int32) for x in r.result)
+        assert _digest(raw if isinstance(raw, tuple) else [raw]) == dig[r.rid]
+        codes = oracle.select(oracle.unpack(beds[r.cohort], n, V), r.sample_idx, *r.v_range)
+        if r.kind == "ld":
+            ref = oracle.ld_window(codes, r.window, r.r2_min)
+            ref["a"] += r.v_range[0]
+            ref["b"] += r.v_range[0]
+            compare_records(r.result, ref, r.r2_min)
+        elif k == 0:
+            for g, e in zip(r.result, oracle.ibs_matrix(codes, full=False)):
+                assert np.array_equal(g, e)
+        else:
+            m = len(r.sample_idx)
+            rng = np.random.default_rng(8)
+            pi = rng.integers(0, m - 1, 4000)
+            pj = pi + 1 + (rng.integers(0, 1 << 30, 4000) % (m - 1 - pi))
+            ref = oracle.ibs_pairs(np.ascontiguousarray(codes.T), pi, pj)
+            t = pi * m - pi * (pi + 1) // 2 + (pj - pi - 1)
+            got = np.stack([x[t] for x in r.result], 1)
+            assert np.array_equal(got, ref)

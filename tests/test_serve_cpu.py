@@ -103,3 +103,20 @@ def test_poisson_workload_shape():
     assert 0.65 < frac_ibs < 0.75
     arr = np.array([r.arrival for r in reqs])
     assert (np.diff(arr) > 0).all() and arr[-1] <= 5
+
+
+class GrowingOverflowBackend(FakeBackend):
+    """An LD request whose overflow size makes its footprint exceed the budget."""
+
+    def footprint(self, req):
+        return 1000 if not req.ld_capacity else 10 ** 7
+
+
+def test_overflow_beyond_budget_is_rejected():
+    be = GrowingOverflowBackend(overflow_once={1})
+    srv = Server(be, n_slots=2, memory_budget=100_000)
+    stats = srv.run(_reqs([10] * 4))            # run() must return
+    assert sorted(r.rid for r in srv.finished) == [0, 2, 3]
+    errs = {r.rid: r.error for r in srv.rejected}
+    assert list(errs) == [1] and "budget" in errs[1]
+    assert stats["completed"] == 3 and stats["rejected"] == 1 and srv.idle()
