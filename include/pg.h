@@ -172,6 +172,26 @@ int pg_ibs_matrix(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_se
                   uint32_t* ibs1, uint32_t* ibs2, uint32_t* nonmiss, void* workspace,
                   size_t workspace_bytes, void* stream);
 
+/*
+ * pg_ibs_matrix without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Arguments, outputs and results are those
+ * of pg_ibs_matrix; the scratch space is instead a static device array of
+ * PG_NOALLOC_SCRATCH_BYTES (64 MiB) that the library holds on every device it
+ * runs on until the process ends, so the call allocates nothing.  A call
+ * whose workspace would exceed it (pg_ibs_workspace_bytes) returns
+ * PG_EUNSUPPORTED before enqueueing anything.  Every call on one device uses
+ * the same array: calls that overlap on one device (other streams, other
+ * threads) race and must be serialised by the caller.
+ */
+#define PG_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int pg_ibs_matrix_noalloc(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_sel,
+                          int64_t v_begin, int64_t v_end, int out_layout, int path,
+                          uint32_t* ibs0, uint32_t* ibs1, uint32_t* ibs2, uint32_t* nonmiss,
+                          void* stream);
+/* The static scratch size of pg_ibs_matrix_noalloc, in bytes. */
+int pg_noalloc_scratch_bytes(size_t* bytes);
+
 /* One emitted LD pair: 64 bytes. a < b are absolute variant indices. */
 typedef struct pg_ld_pair {
   int32_t a, b;

@@ -154,6 +154,34 @@ def ibs_matrix(cohort: Cohort, *, sample_idx: torch.Tensor | None = None, v_rang
     return out
 
 
+def noalloc_scratch_bytes() -> int:
+    """Size of the static scratch array pg_ibs_matrix_noalloc works in."""
+    out = ctypes.c_size_t(0)
+    N.check(N.load().pg_noalloc_scratch_bytes(ctypes.byref(out)), "pg_noalloc_scratch_bytes")
+    return out.value
+
+
+def ibs_matrix_noalloc(cohort: Cohort, out, *, sample_idx: torch.Tensor | None = None,
+                       v_range=None, layout: str = "full", path="auto", stream=None):
+    """pg_ibs_matrix_noalloc: the IBS matrix into the caller's four int32
+    tensors `out`, with the library's static scratch array as workspace (no
+    allocation anywhere in the call).  Calls that overlap on one GPU race."""
+    lib = N.load()
+    n_sel, vb, ve = _sel(cohort, sample_idx, v_range)
+    m = n_sel or cohort.n_samples
+    size = ibs_output_size(m, layout)
+    for k, t in enumerate(out):
+        _require_cuda(t, f"out[{k}]", torch.int32)
+        if t.numel() < size:
+            raise ValueError("output tensor too small")
+    g = cohort.struct()
+    st = lib.pg_ibs_matrix_noalloc(ctypes.byref(g), _ptr(sample_idx), n_sel, vb, ve,
+                                   N.LAYOUTS[layout], _path(path), *[_ptr(t) for t in out],
+                                   _stream_handle(stream))
+    N.check(st, "pg_ibs_matrix_noalloc")
+    return out
+
+
 def ld_workspace_bytes(cohort: Cohort, window: int, n_sel: int = 0, v_range=None,
                        path="auto") -> int:
     vb, ve = (0, 0) if v_range is None else v_range

@@ -6,6 +6,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "pg_internal.h"
 
 namespace pg {
@@ -30,6 +32,33 @@ void mark_stage(int k, hipStream_t st) {
 int check_launch(const char* what) {
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(PG_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+  return PG_OK;
+}
+
+// ---- static scratch of pg_ibs_matrix_noalloc ----------------------------------
+// One array per device, held until the process ends.  In host code its name
+// is only a stand-in: kernels get the device address hipGetSymbolAddress
+// returns for the current device, looked up once per device.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+int noalloc_scratch(void** ptr) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(PG_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(PG_EUNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(PG_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                  hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
   return PG_OK;
 }
 
@@ -353,10 +382,16 @@ int pg_ibs_workspace_bytes(const pg_genotypes* g, int64_t n_sel, int64_t v_begin
   return PG_OK;
 }
 
-int pg_ibs_matrix(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_sel,
-                  int64_t v_begin, int64_t v_end, int out_layout, int path, uint32_t* ibs0,
-                  uint32_t* ibs1, uint32_t* ibs2, uint32_t* nonmiss, void* workspace,
-                  size_t workspace_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Body of pg_ibs_matrix and pg_ibs_matrix_noalloc: `workspace` is the
+// caller's buffer or the library's static scratch array.
+int ibs_matrix_run(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_sel,
+                   int64_t v_begin, int64_t v_end, int out_layout, int path, uint32_t* ibs0,
+                   uint32_t* ibs1, uint32_t* ibs2, uint32_t* nonmiss, void* workspace,
+                   size_t workspace_bytes, void* stream, bool noalloc) {
   g_last_error[0] = 0;
   Sel s;
   int rc = make_sel(g, sample_idx != nullptr, sample_idx, n_sel, v_begin, v_end, s);
@@ -369,6 +404,23 @@ int pg_ibs_matrix(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_se
   IbsPlan p;
   rc = plan_ibs(s, path, p);
   if (rc != PG_OK) return rc;
+  if (noalloc) {
+    // without room for the K split's sums, the unsplit kernel (same sums)
+    if (p.bytes > kNoAllocScratchBytes && p.off_part >= 0 && p.off_part <= kNoAllocScratchBytes) {
+      p.bytes = p.off_part;
+      p.off_part = -1;
+    }
+    if (p.bytes > kNoAllocScratchBytes)
+      return fail(PG_EUNSUPPORTED,
+                  "pg_ibs_matrix_noalloc: %lld scratch bytes needed for %lld samples x %lld "
+                  "variants, more than the static array's %lld; call pg_ibs_matrix with a "
+                  "workspace instead",
+                  (long long)p.bytes, (long long)s.m, (long long)s.nv,
+                  (long long)kNoAllocScratchBytes);
+    rc = noalloc_scratch(&workspace);
+    if (rc != PG_OK) return rc;
+    workspace_bytes = (size_t)kNoAllocScratchBytes;
+  }
   if ((int64_t)workspace_bytes < p.bytes || (!workspace && p.bytes > 0))
     return fail(PG_ENOMEM, "workspace of %llu bytes < %lld required",
                 (unsigned long long)workspace_bytes, (long long)p.bytes);
@@ -392,6 +444,32 @@ int pg_ibs_matrix(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_se
   }
   mark_stage(2, st);
   return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pg_ibs_matrix(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_sel,
+                  int64_t v_begin, int64_t v_end, int out_layout, int path, uint32_t* ibs0,
+                  uint32_t* ibs1, uint32_t* ibs2, uint32_t* nonmiss, void* workspace,
+                  size_t workspace_bytes, void* stream) {
+  return ibs_matrix_run(g, sample_idx, n_sel, v_begin, v_end, out_layout, path, ibs0, ibs1, ibs2,
+                        nonmiss, workspace, workspace_bytes, stream, false);
+}
+
+int pg_ibs_matrix_noalloc(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_sel,
+                          int64_t v_begin, int64_t v_end, int out_layout, int path,
+                          uint32_t* ibs0, uint32_t* ibs1, uint32_t* ibs2, uint32_t* nonmiss,
+                          void* stream) {
+  return ibs_matrix_run(g, sample_idx, n_sel, v_begin, v_end, out_layout, path, ibs0, ibs1, ibs2,
+                        nonmiss, nullptr, 0, stream, true);
+}
+
+int pg_noalloc_scratch_bytes(size_t* bytes) {
+  if (!bytes) return fail(PG_EINVAL, "bytes is NULL");
+  *bytes = (size_t)kNoAllocScratchBytes;
+  return PG_OK;
 }
 
 int pg_ld_workspace_bytes(const pg_genotypes* g, int64_t n_sel, int64_t v_begin, int64_t v_end,

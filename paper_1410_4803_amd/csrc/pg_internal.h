@@ -147,6 +147,12 @@ struct IbsPlan {
 // The plan of the default matrix-core kernel for a selection (abi.hip).
 int plan_ibs_default(const Sel& s, IbsPlan& p);
 
+// Static scratch of pg_ibs_matrix_noalloc (abi.hip): its size, and its
+// device address on the current device (looked up once per device).
+constexpr int64_t kNoAllocScratchBytes = (int64_t)64 << 20;
+constexpr int kMaxDevices = 64;
+int noalloc_scratch(void** ptr);
+
 // `part`: workspace of ibs_part_bytes() for the default kernel's K split
 // (nullptr: never split).
 int launch_ibs_mfma(const uint32_t* T, int64_t wp, const IbsOut& o, int variant, hipStream_t st,

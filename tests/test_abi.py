@@ -267,3 +267,20 @@ def test_peak_rates_validation():
     assert lib.pg_peak_rates(0x2000, 1 << 30, None) == N.PG_EINVAL
     assert lib.pg_peak_rates(0x2000, 1 << 20, out) == N.PG_ENOMEM
     assert lib.pg_peak_rates(None, 1 << 30, out) == N.PG_ENOMEM
+
+
+def test_noalloc_rejects_oversized_before_the_device():
+    """pg_ibs_matrix_noalloc refuses, on the host and before any HIP call, a
+    call whose scratch would exceed the static array; the size query reports
+    the array's size."""
+    lib = N.load()
+    b = ctypes.c_size_t(0)
+    assert lib.pg_noalloc_scratch_bytes(ctypes.byref(b)) == 0 and b.value == 64 << 20
+    g = _g(10000, 40000)
+    fake = ctypes.c_void_p(0x1000)
+    rc = lib.pg_ibs_matrix_noalloc(ctypes.byref(g), None, 0, 0, 0, N.PG_TRI_UPPER, N.PG_PATH_MFMA,
+                                   fake, fake, fake, fake, None)
+    assert rc == N.PG_EUNSUPPORTED
+    assert "static array" in N.last_error()
+    assert lib.pg_ibs_matrix_noalloc(None, None, 0, 0, 0, 0, 0, fake, fake, fake, fake,
+                                     None) == N.PG_EINVAL
