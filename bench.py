@@ -30,11 +30,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_INT8_TOPS = 5000.0        # MI355X dense int8 MFMA, 5.0 POP/s
+PEAK_FP4_TFLOPS = 10100.0      # MI355X dense fp4 MFMA, 10.1 PFLOP/s
 PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12   # 32-bit integer VALU lane-ops/s, 39.3 T
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6         # MI355X dense fp64 MFMA
 # algorithmic work per unique genotype-pair comparison (one pair, one variant)
-IBS_MFMA_OPS = 4 * 2          # four int8 contractions: 4 MACs = 8 ops
+IBS_MFMA_OPS = 4 * 2          # four contractions: 4 multiply-adds = 8 ops (int8 or fp4)
+IBS_FP4_VARIANTS = (0, 8)      # the default kernel: pipelined, fp4 operands
 IBS_POPC_OPS = 8 / 32         # per 32-variant word: AND, 2 XOR, 2 bitop3, 3 popcount-adds
 LD_MFMA_OPS = 6 * 2           # six int8 contractions
 LD_POPC_OPS = 16 / 32         # 16 VALU ops per 32-sample word
@@ -418,7 +420,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--quick", action="store_true", help="default workload only, no extras")
     ap.add_argument("--extras", default="all",
-                    help="comma list of extras: other,small,ld,prune,grm,cluster,peaks,batch,serve "
+                    help="comma list of extras: other,int8,small,ld,prune,grm,cluster,peaks,batch,serve "
                          "(or all / none)")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--serve-seconds", type=float, default=60.0)
@@ -463,7 +465,12 @@ def main():
     log(f"timing {args.steps} steps ({args.warmup} warmup), path {path}")
     ms, stages = timed_steps(torch, lib, hip, call, args.steps, args.warmup, 3)
     layout_ms, pair_ms = mean(stages[0]), mean(stages[1])
-    if path == "mfma":
+    fp4 = path == "mfma" and args.variant in IBS_FP4_VARIANTS
+    if fp4:
+        ops = comps * IBS_MFMA_OPS
+        roof = {"bound": "mfma", "achieved": ops / (pair_ms * 1e-3) / 1e12,
+                "peak": PEAK_FP4_TFLOPS, "unit": "TFLOP/s", "kernel": "k_ibs_fp4_pipe"}
+    elif path == "mfma":
         ops = comps * IBS_MFMA_OPS
         roof = {"bound": "mfma", "achieved": ops / (pair_ms * 1e-3) / 1e12, "peak": PEAK_INT8_TOPS,
                 "unit": "TOP/s", "kernel": "k_ibs_mfma"}
@@ -488,7 +495,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int8" if path == "mfma" else "u32",
+        "dtype": "fp4" if fp4 else "int8" if path == "mfma" else "u32",
         "data": "synthetic",
         "config": {"workload": w["name"], "n_samples": n, "n_variants": V, "layout": "full",
                    "path": path, "variant": args.variant, "comparisons_per_step": comps},
@@ -504,7 +511,8 @@ def main():
     extras = {}
     want = set()
     if not args.quick:
-        everything = {"other", "small", "ld", "prune", "grm", "cluster", "peaks", "batch", "serve"}
+        everything = {"other", "int8", "small", "ld", "prune", "grm", "cluster", "peaks", "batch",
+                      "serve"}
         want = everything if args.extras == "all" else \
             set(x for x in args.extras.split(",") if x and x != "none")
     if "other" in want:
@@ -523,6 +531,22 @@ def main():
                                 "frac": round(ach2 / PEAK_VALU_TOPS, 4)}
         extras[f"ibs_large_{other}"] = rec2
         del call2, out2
+        torch.cuda.empty_cache()
+
+    if "int8" in want and path == "mfma":
+        # the same tile schedule with int8 operands, against the int8 peak
+        call3, out3 = ibs_runner("mfma", 7)
+        log("timing the int8 matrix-core kernel (variant 7)")
+        ms3, st3 = timed_steps(torch, lib, hip, call3, max(3, args.steps // 2), 1, 3)
+        pk3 = mean(st3[1])
+        ach3 = comps * IBS_MFMA_OPS / (pk3 * 1e-3) / 1e12
+        extras["ibs_large_int8"] = {
+            "value": round(comps / (ms3 * 1e-3) / 1e9, 1), "unit": "G/s", "variant": 7,
+            "ms_per_step": round(ms3, 3), "pair_kernel_ms": round(pk3, 3),
+            "roofline": {"bound": "mfma", "kernel": "k_ibs_mfma_pipe", "unit": "TOP/s",
+                         "achieved": round(ach3, 2), "peak": PEAK_INT8_TOPS,
+                         "frac": round(ach3 / PEAK_INT8_TOPS, 4)}}
+        del call3, out3
         torch.cuda.empty_cache()
 
     if "small" in want:
@@ -618,8 +642,9 @@ def main():
         pk = {k: round(v, 1) for k, v in pk.items()}
         pk["published"] = {"int8_mfma_tops": PEAK_INT8_TOPS, "fp64_mfma_tflops": PEAK_FP64_TFLOPS,
                            "valu_bcnt_tops": round(PEAK_VALU_TOPS, 1), "hbm_copy_gbs": PEAK_HBM_GBS}
-        pk["ibs_pair_kernel_frac_of_measured_int8"] = round(
-            roof["achieved"] / pk["int8_mfma_tops"], 4) if path == "mfma" else None
+        pk["ibs_int8_kernel_frac_of_measured_int8"] = round(
+            extras["ibs_large_int8"]["roofline"]["achieved"] / pk["int8_mfma_tops"], 4) \
+            if "ibs_large_int8" in extras else None
         extras["peaks"] = pk
 
     if "batch" in want:

@@ -118,18 +118,32 @@ int make_sel(const pg_genotypes* g, bool list, const int32_t* idx, int64_t n_sel
 }
 
 
+int ibs_auto_path(int64_t m, int64_t nv) {
+  (void)m;
+  (void)nv;
+  return PG_PATH_MFMA;
+}
+
+// Resolves the kernel variant: 0 (or an undefined code) is the default, the
+// pipelined fp4 kernel; fp4 variants fall back to the pipelined int8 kernel
+// when a sum could reach 2^24.
+int resolve_ibs_variant(int variant, int64_t nv) {
+  if (variant <= 0 || variant >= kIbsVariants) variant = kIbsVariantFp4Pipe;
+  const bool fp4 = variant == kIbsVariantFp4 || variant == kIbsVariantFp4Rep ||
+                   variant == kIbsVariantFp4Pipe;
+  if (fp4 && nv >= kFp4MaxVariants) variant = kIbsVariantPipe;
+  return variant;
+}
+
 int plan_ibs(const Sel& s, int path_arg, IbsPlan& p) {
   int path = path_arg & 0xFF;
-  p.variant = (path_arg >> 8) & 0xFF;
   if (path_arg < 0 || (path_arg >> 16) != 0) return fail(PG_EINVAL, "bad path argument %d", path_arg);
-  if (path == PG_PATH_AUTO) path = PG_PATH_MFMA;
+  if (path == PG_PATH_AUTO) path = ibs_auto_path(s.m, s.nv);
   if (path != PG_PATH_MFMA && path != PG_PATH_POPC)
     return fail(PG_EINVAL, "unknown path %d", path);
   p.path = path;
-  // fp4 operands accumulate in fp32: exact only while every sum stays below 2^24
-  if (path == PG_PATH_MFMA && (p.variant == kIbsVariantFp4 || p.variant == kIbsVariantFp4Rep) &&
-      s.nv >= ((int64_t)1 << 24))
-    p.variant = 0;
+  p.variant = path == PG_PATH_MFMA ? resolve_ibs_variant((path_arg >> 8) & 0xFF, s.nv)
+                                   : (path_arg >> 8) & 0xFF;
   if (path == PG_PATH_MFMA && p.variant == kIbsVariantFp4Rep) {
     p.rows_pad = round_up(s.m, kIbsMfmaTile);
     p.words = round_up(s.nv, 4 * kIbsRepChunk) / 4;     // 2 words per 8 variants
@@ -146,9 +160,10 @@ int plan_ibs(const Sel& s, int path_arg, IbsPlan& p) {
   const int64_t nt = p.rows_pad / (path == PG_PATH_MFMA ? kIbsMfmaTile : kIbsPopcTile);
   if (nt * (nt + 1) / 2 + 2 * nt >= kMaxIndex) return fail(PG_EUNSUPPORTED, "too many samples for one call");
   p.off_part = -1;
-  const bool default_kernel = path == PG_PATH_MFMA &&
-      !(p.variant >= 1 && p.variant <= kIbsVariantW8 + 1);
-  if (default_kernel && ibs_part_bytes(p.rows_pad, p.words) > 0) {
+  // the pipelined kernels split small cohorts' K range (ibs_split)
+  const bool pipelined = path == PG_PATH_MFMA &&
+      (p.variant == kIbsVariantPipe || p.variant == kIbsVariantFp4Pipe);
+  if (pipelined && ibs_part_bytes(p.rows_pad, p.words) > 0) {
     p.off_part = round_up(p.bytes, 256);
     p.bytes = p.off_part + ibs_part_bytes(p.rows_pad, p.words);
   }

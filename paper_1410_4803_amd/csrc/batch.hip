@@ -78,7 +78,10 @@ __global__ __launch_bounds__(256, kPart == kPartIbs ? 1 : 2) void k_batch_persis
       int64_t I, J;
       tri_tile(local, it.nt, I, J);
       if (it.path == PG_PATH_MFMA) {
-        ibs_mfma_tile<true>(it.X, it.words, I, J, it.o, (lds_t*)smem);
+        if (it.variant == kIbsVariantFp4Pipe)
+          ibs_fp4_tile_pipe(it.X, it.words, I, J, it.o, (lds_t*)smem);
+        else
+          ibs_mfma_tile_pipe<true>(it.X, it.words, I, J, it.o, (lds_t*)smem);
       } else {
         ibs_popc_tile(it.X, it.rows_pad, it.words, I, J, it.o, (lds_t*)smem);
       }
@@ -158,13 +161,14 @@ int pg_batch_plan(const pg_problem* probs, int n_probs, pg_plan** out) {
     int rc;
     if (q.p.kind == PG_KIND_IBS) {
       rc = batch_validate_ibs(q.p, q.s, q.path, q.variant, q.rows_pad, q.words);
-      // the persistent kernel hosts one matrix-core body (the int8 default):
-      // every matrix-core variant gives the same counts, and hosting more bodies
+      // the persistent kernel hosts the default matrix-core body (pipelined
+      // fp4, or pipelined int8 where fp4 sums could reach 2^24): every
+      // matrix-core variant gives the same counts, and hosting more bodies
       // would raise the kernel's register and LDS budget for every tile
-      if (rc == PG_OK && q.path == PG_PATH_MFMA && q.variant != 0) {
-        q.variant = 0;
+      if (rc == PG_OK && q.path == PG_PATH_MFMA) {
         IbsPlan dflt;
         rc = plan_ibs_default(q.s, dflt);
+        q.variant = dflt.variant;
         q.rows_pad = dflt.rows_pad;
         q.words = dflt.words;
       }
@@ -176,7 +180,8 @@ int pg_batch_plan(const pg_problem* probs, int n_probs, pg_plan** out) {
                                                      : 3 * q.rows_pad * q.words * 4;
         q.off_x = take(off, bytes);
         // rough cycles per tile, for longest-first ordering
-        q.tile_cost = q.path == PG_PATH_MFMA ? (double)q.words * 460.0 : (double)q.words * 520.0;
+        q.tile_cost = q.path != PG_PATH_MFMA ? (double)q.words * 520.0
+                      : (double)q.words * (q.variant == kIbsVariantFp4Pipe ? 310.0 : 440.0);
       }
     } else if (q.p.kind == PG_KIND_LD) {
       rc = batch_validate_ld(q.p, q.s, q.path, q.variant, q.rows_pad, q.words, q.bm_words);

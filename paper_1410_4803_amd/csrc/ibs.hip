@@ -34,9 +34,19 @@ __global__ __launch_bounds__(256, 1) void k_ibs_mfma(const uint32_t* __restrict_
   ibs_mfma_tile<kHints>(T, wp, I, J, o, (lds_t*)smem);
 }
 
+template <bool kHints>
+__global__ __launch_bounds__(256, 1) void k_ibs_mfma_pipe(const uint32_t* __restrict__ T,
+                                                          int64_t wp, int64_t nt, IbsOut o) {
+  __shared__ __attribute__((aligned(16))) uint32_t smem[kIbsMfmaSmem];
+  int64_t I, J;
+  if (!band_tile(xcd_swizzle(blockIdx.x, gridDim.x), nt, I, J)) return;
+  ibs_mfma_tile_pipe<kHints>(T, wp, I, J, o, (lds_t*)smem);
+}
+
 // Cohorts of fewer than 512 tiles (ibs_split): block b runs K range
 // b / tiles of tile b % tiles and parks its raw sums; k_ibs_split_reduce
 // adds the ranges in order and stores.
+template <bool kFp4>
 __global__ __launch_bounds__(256, 1) void k_ibs_mfma_split(const uint32_t* __restrict__ T,
                                                            int64_t wp, int64_t nt, IbsOut o,
                                                            int64_t cps, int32_t* __restrict__ part) {
@@ -47,8 +57,11 @@ __global__ __launch_bounds__(256, 1) void k_ibs_mfma_split(const uint32_t* __res
   const int64_t c0 = split * cps, c1 = c0 + cps < chunks ? c0 + cps : chunks;
   int64_t I, J;
   tri_tile(tile, nt, I, J);
-  ibs_mfma_tile<true>(T, wp, I, J, o, (lds_t*)smem, c0, c1,
-                      part + (split * tiles + tile) * (192 * 256));
+  int32_t* const q = part + (split * tiles + tile) * (192 * 256);
+  if constexpr (kFp4)
+    ibs_fp4_tile_pipe(T, wp, I, J, o, (lds_t*)smem, c0, c1, q);
+  else
+    ibs_mfma_tile_pipe<true>(T, wp, I, J, o, (lds_t*)smem, c0, c1, q);
 }
 
 // One thread per (tile, accumulator register, tile thread): the three sums
@@ -107,6 +120,14 @@ __global__ __launch_bounds__(256, 1) void k_ibs_fp4(const uint32_t* __restrict__
   ibs_fp4_tile(T, wp, I, J, o, (lds_t*)smem);
 }
 
+__global__ __launch_bounds__(256, 1) void k_ibs_fp4_pipe(const uint32_t* __restrict__ T,
+                                                         int64_t wp, int64_t nt, IbsOut o) {
+  __shared__ __attribute__((aligned(16))) uint32_t smem[kIbsMfmaSmem];
+  int64_t I, J;
+  if (!band_tile(xcd_swizzle(blockIdx.x, gridDim.x), nt, I, J)) return;
+  ibs_fp4_tile_pipe(T, wp, I, J, o, (lds_t*)smem);
+}
+
 __global__ __launch_bounds__(256, 1) void k_ibs_fp4rep(const uint32_t* __restrict__ R, int64_t rp,
                                                        int64_t nt, IbsOut o) {
   __shared__ __attribute__((aligned(16))) uint32_t smem[kIbsRepSmem];
@@ -123,36 +144,47 @@ __global__ __launch_bounds__(256) void k_ibs_popc(const uint32_t* __restrict__ P
   ibs_popc_tile(P, rows_pad, words_pad, I, J, o, (lds_t*)smem);
 }
 
+// `variant` is resolved (resolve_ibs_variant): 1 .. kIbsVariants - 1.
 int launch_ibs_mfma(const uint32_t* T, int64_t wp, const IbsOut& o, int variant, hipStream_t st,
                     int32_t* part) {
   const int64_t nt = ceil_div(o.m, kT);
   const int64_t blocks = variant == 2 ? nt * (nt + 1) / 2 : band_start((nt + 3) / 4, nt);
-  const bool default_kernel = !(variant >= 1 && variant <= kIbsVariantW8 + 1);
+  const bool fp4 = variant == kIbsVariantFp4Pipe;
   int64_t n_split = 1, cps = 0;
-  if (default_kernel && part) ibs_split(nt * kT, wp, n_split, cps);
+  if ((variant == kIbsVariantPipe || fp4) && part) ibs_split(nt * kT, wp, n_split, cps);
   if (n_split > 1) {
     const int64_t tiles = nt * (nt + 1) / 2;
-    hipLaunchKernelGGL(k_ibs_mfma_split, dim3((unsigned)(tiles * n_split)), dim3(256), 0, st, T,
-                       wp, nt, o, cps, part);
+    hipLaunchKernelGGL(fp4 ? k_ibs_mfma_split<true> : k_ibs_mfma_split<false>,
+                       dim3((unsigned)(tiles * n_split)), dim3(256), 0, st, T, wp, nt, o, cps, part);
     int rc = check_launch("ibs_mfma_split");
     if (rc != PG_OK) return rc;
     hipLaunchKernelGGL(k_ibs_split_reduce, dim3((unsigned)ceil_div(tiles * 64 * 256, 256)),
                        dim3(256), 0, st, nt, n_split, part, o);
     return check_launch("ibs_split_reduce");
   }
-  if (variant == 1)
-    hipLaunchKernelGGL(k_ibs_mfma<false>, dim3((unsigned)blocks), dim3(256), 0, st, T, wp, nt, o);
-  else if (variant == 2)
-    hipLaunchKernelGGL(k_ibs_mfma_simple, dim3((unsigned)blocks), dim3(256), 0, st, T, wp, nt, o);
-  else if (variant == 3)
-    hipLaunchKernelGGL(k_ibs_fp4, dim3((unsigned)blocks), dim3(256), 0, st, T, wp, nt, o);
-  else if (variant == kIbsVariantW8)
-    hipLaunchKernelGGL(k_ibs_mfma_w8<true>, dim3((unsigned)blocks), dim3(512), 0, st, T, wp, nt, o);
-  else if (variant == kIbsVariantW8 + 1)
-    hipLaunchKernelGGL(k_ibs_mfma_w8<false>, dim3((unsigned)blocks), dim3(512), 0, st, T, wp, nt,
-                       o);
-  else
-    hipLaunchKernelGGL(k_ibs_mfma<true>, dim3((unsigned)blocks), dim3(256), 0, st, T, wp, nt, o);
+  const dim3 grid((unsigned)blocks);
+  switch (variant) {
+    case 1: hipLaunchKernelGGL(k_ibs_mfma<false>, grid, dim3(256), 0, st, T, wp, nt, o); break;
+    case 2: hipLaunchKernelGGL(k_ibs_mfma_simple, grid, dim3(256), 0, st, T, wp, nt, o); break;
+    case kIbsVariantFp4:
+      hipLaunchKernelGGL(k_ibs_fp4, grid, dim3(256), 0, st, T, wp, nt, o);
+      break;
+    case kIbsVariantW8:
+      hipLaunchKernelGGL(k_ibs_mfma_w8<true>, grid, dim3(512), 0, st, T, wp, nt, o);
+      break;
+    case kIbsVariantW8 + 1:
+      hipLaunchKernelGGL(k_ibs_mfma_w8<false>, grid, dim3(512), 0, st, T, wp, nt, o);
+      break;
+    case kIbsVariantPipe:
+      hipLaunchKernelGGL(k_ibs_mfma_pipe<true>, grid, dim3(256), 0, st, T, wp, nt, o);
+      break;
+    case kIbsVariantR1:
+      hipLaunchKernelGGL(k_ibs_mfma<true>, grid, dim3(256), 0, st, T, wp, nt, o);
+      break;
+    default:
+      hipLaunchKernelGGL(k_ibs_fp4_pipe, grid, dim3(256), 0, st, T, wp, nt, o);
+      break;
+  }
   return check_launch("ibs_mfma");
 }
 

@@ -131,6 +131,12 @@ constexpr int kIbsMfmaKWords = 16;    // 2-bit words per K chunk (256 variants)
 constexpr int kIbsVariantFp4 = 3;     // matrix-core variant with fp4 operands
 constexpr int kIbsVariantFp4Rep = 4;  // fp4 operands from the replicated layout
 constexpr int kIbsVariantW8 = 5;      // eight waves of 64x32 (6: without scheduling hints)
+constexpr int kIbsVariantPipe = 7;    // int8, chunk boundaries pipelined
+constexpr int kIbsVariantFp4Pipe = 8; // fp4 operands, chunk boundaries pipelined (the default)
+constexpr int kIbsVariantR1 = 9;      // int8, unpipelined, scheduling hints
+constexpr int kIbsVariants = 10;      // variant codes 1 .. kIbsVariants - 1 are defined
+// fp4 operands accumulate in fp32, exact while every sum stays below 2^24
+constexpr int64_t kFp4MaxVariants = (int64_t)1 << 24;
 constexpr int kIbsRepChunk = 64;      // replicated words per K chunk (256 variants)
 constexpr int kIbsPopcTile = 64;
 constexpr int kIbsPopcKWords = 16;    // 32-bit plane words per K chunk
@@ -146,6 +152,10 @@ struct IbsPlan {
 };
 // The plan of the default matrix-core kernel for a selection (abi.hip).
 int plan_ibs_default(const Sel& s, IbsPlan& p);
+
+// The path PG_PATH_AUTO resolves to for an IBS matrix of m samples and nv
+// variants (abi.hip).
+int ibs_auto_path(int64_t m, int64_t nv);
 
 // Static scratch of pg_ibs_matrix_noalloc (abi.hip): its size, and its
 // device address on the current device (looked up once per device).

@@ -375,6 +375,140 @@ __device__ __forceinline__ void ibs_mfma_tile(const uint32_t* __restrict__ T, in
 }
 
 
+// Pipelined form: the same tile, Grams, K order and arithmetic as
+// ibs_mfma_tile, with the chunk boundary taken out of the critical path.
+// ibs_mfma_tile reads a chunk's words from LDS and expands its first step
+// after the chunk barrier, with no MFMA in flight; here every stage of chunk
+// k + 1 happens while the MFMAs of chunk k run:
+//   - chunk c is fetched from global memory two chunks ahead (in the middle
+//     of chunk c - 2, right after the previous fetch was stored) and stored
+//     to LDS buffer c % 2 in the middle of chunk c - 2;
+//   - one barrier at the start of each chunk orders those stores before the
+//     reads of the next chunk, and the reads of a buffer before it is
+//     overwritten two chunks later;
+//   - a lane reads the next chunk's words in two halves, words 0-3 during
+//     step 4 (words 0-3 of the current chunk are expanded by then) and words
+//     4-7 during step 7, into the same registers, and the first step of the
+//     next chunk is expanded during the last step of the current one.
+// Variant 7 of the matrix-core path.
+template <bool kHints>
+__device__ __forceinline__ void ibs_mfma_tile_pipe(const uint32_t* __restrict__ T, int64_t wp,
+                                                   int64_t I, int64_t J, const IbsOut& o,
+                                                   lds_t* smem, int64_t c0 = 0, int64_t c1 = -1,
+                                                   int32_t* __restrict__ part = nullptr) {
+  constexpr int kBuf = kT * kLdsStride;
+  lds_t* const sA = smem;
+  lds_t* const sB = smem + 2 * kBuf;
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int wid = t >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  const int g = lane >> 5;
+  const int rl = lane & 31;
+
+  const int lrow = t >> 2;
+  const int lq = (t & 3) * 4;
+  const uint32_t* pa = T + (I * kT + lrow) * wp + lq;
+  const uint32_t* pb = T + (J * kT + lrow) * wp + lq;
+  const int64_t half = 64 * wp;
+  uint4 ga0, ga1, gb0, gb1;
+  auto gload = [&](int64_t kc) {
+    ga0 = *reinterpret_cast<const uint4*>(pa + kc);
+    ga1 = *reinterpret_cast<const uint4*>(pa + half + kc);
+    gb0 = *reinterpret_cast<const uint4*>(pb + kc);
+    gb1 = *reinterpret_cast<const uint4*>(pb + half + kc);
+  };
+  auto lstore = [&](int buf) {
+    lds_st4(&(sA + buf * kBuf)[lrow * kLdsStride + lq], ga0);
+    lds_st4(&(sA + buf * kBuf)[(lrow + 64) * kLdsStride + lq], ga1);
+    lds_st4(&(sB + buf * kBuf)[lrow * kLdsStride + lq], gb0);
+    lds_st4(&(sB + buf * kBuf)[(lrow + 64) * kLdsStride + lq], gb1);
+  };
+  uint32_t wa[2][8], wb[2][8];
+  // words 4*h .. 4*h + 3 of this lane's two A rows and two B rows
+  auto lread = [&](int buf, int h) {
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      const lds_t* ra = &(sA + buf * kBuf)[(wr * 64 + x * 32 + rl) * kLdsStride + g * 8 + 4 * h];
+      const lds_t* rb = &(sB + buf * kBuf)[(wc * 64 + x * 32 + rl) * kLdsStride + g * 8 + 4 * h];
+      const uint4 a = lds_ld4(ra);
+      const uint4 b = lds_ld4(rb);
+      wa[x][4 * h] = a.x; wa[x][4 * h + 1] = a.y; wa[x][4 * h + 2] = a.z; wa[x][4 * h + 3] = a.w;
+      wb[x][4 * h] = b.x; wb[x][4 * h + 1] = b.y; wb[x][4 * h + 2] = b.z; wb[x][4 * h + 3] = b.w;
+    }
+  };
+
+  IbsAcc acc;
+  zero_acc(acc);
+  // The loop body has no branches, so the scheduler can interleave every
+  // stage with the MFMAs: fetches past the last chunk re-read the last chunk
+  // (in bounds), and the stores, reads and expansions past it fill buffers
+  // and registers nothing reads afterwards.
+  const int64_t nch = (c1 < 0 ? wp / kKW : c1) - c0;
+  auto fetch = [&](int64_t c) { gload((c0 + (c < nch ? c : nch - 1)) * kKW); };
+  fetch(0);
+  lstore(0);
+  fetch(1);
+  lstore(1);
+  fetch(2);
+  __syncthreads();
+  lread(0, 0);
+  lread(0, 1);
+  Feat4 fa[2], fb[2];
+  fa[0] = expand_a(wa[0][0]); fa[1] = expand_a(wa[1][0]);
+  fb[0] = expand_b(wb[0][0]); fb[1] = expand_b(wb[1][0]);
+  for (int64_t k = 0; k < nch; ++k) {
+    const int buf = (int)(k & 1);
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < kKW / 2; ++s) {
+      if (s == 3) {
+        lstore(buf);                                  // chunk k + 2
+        fetch(k + 3);
+      }
+      if (s == 4) lread(buf ^ 1, 0);                  // words 0-3 of chunk k + 1
+      if (s == 7) lread(buf ^ 1, 1);                  // words 4-7
+      Feat4 na[2], nb[2];
+      const int sn = (s + 1) & 7;                     // next step's word (chunk k + 1 at s = 7)
+      na[0] = expand_a(wa[0][sn]); na[1] = expand_a(wa[1][sn]);
+      nb[0] = expand_b(wb[0][sn]); nb[1] = expand_b(wb[1][sn]);
+      mfma_step(acc, fa, fb);
+      if constexpr (kHints) {
+        // the step's memory operations first (LDS stores and global fetches
+        // at step 3, LDS reads at steps 4 and 7), then one MFMA and up to six
+        // VALU instructions, sixteen times
+        if (s == 3) {
+          __builtin_amdgcn_sched_group_barrier(0x200, 4, 0);
+          __builtin_amdgcn_sched_group_barrier(0x020, 4, 0);
+        }
+        if (s == 4 || s == 7) __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);
+        }
+      }
+      fa[0] = na[0]; fa[1] = na[1];
+      fb[0] = nb[0]; fb[1] = nb[1];
+    }
+  }
+  if (part) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          int32_t* q = part + ((a * 2 + b) * 48 + v) * 256 + t;
+          q[0] = acc.m[a][b][v];
+          q[16 * 256] = acc.w[a][b][v];
+          q[32 * 256] = acc.hc[a][b][v];
+        }
+    return;
+  }
+  ibs_epilogue(acc, o, I, J, wr, wc, lane);
+}
+
 // Eight-wave form (variant 5): 512 threads = 8 waves in a 2x4 grid over the
 // same 128x128 tile, each wave 64x32 = 2x1 blocks and three accumulator sets
 // (96 accumulator registers), so two waves share each SIMD and one wave's
@@ -784,6 +918,172 @@ __device__ __forceinline__ void ibs_fp4_tile(const uint32_t* __restrict__ T, int
     }
     if (k + 1 < nchunks) lstore(buf ^ 1);
     __syncthreads();
+  }
+  fp4_epilogue(acc, o, I, J, wr, wc, lane);
+}
+
+// Pipelined fp4 tile (variant 8): ibs_mfma_tile_pipe's schedule with the
+// fp4 Grams of ibs_fp4_tile.  One MFMA lane takes two 2-bit words (32
+// variants) per step, so a chunk is four steps; the fetch and LDS store of
+// chunk k + 2 happen at step 1, the reads of chunk k + 1 at steps 2 (words
+// 0-3) and 3 (words 4-7).
+//
+// Expansion of one word w (code j at bits 2j, 2j + 1) into the nibbles of
+// its even codes (nibble n = code 2n) and of its odd codes (nibble n = code
+// 2n + 1): with X holding each code's high bit and Y its low bit at bit 1 of
+// the code's nibble (even: X = w, Y = w << 1; odd: X = w >> 2, Y = w >> 1)
+// and K = bit 1 of every nibble,
+//   m = K & (X | ~Y),  w = m | (K & X & ~Y) << 2,  h = K & ~(X ^ Y),
+//   c = h | (K & ~X & ~Y) << 2  (A side),  -c = h | (K & X & Y) << 2  (B side);
+// bits 0, 2 of every nibble stay 0 and bit 3 is the sign, so every value is
+// 0 or +-1.0 in e2m1.  The even nibbles of a word fill one dword of a
+// feature and the odd nibbles the next; A and B use the same order.
+constexpr uint32_t kNibK = 0x22222222u;
+constexpr int kB3Mx = 0xa2;   // K & (X | ~Y): S0 = X, S1 = Y, S2 = K
+constexpr int kB3Het = 0x20;  // K & X & ~Y
+constexpr int kB3Hom = 0x82;  // K & ~(X ^ Y)
+constexpr int kB3Neg0 = 0x02; // K & ~X & ~Y
+constexpr int kB3Neg3 = 0x80; // K & X & Y
+
+__device__ __forceinline__ void fp4_parity(uint32_t X, uint32_t Y, bool b_side, uint32_t& m,
+                                           uint32_t& w, uint32_t& h, uint32_t& c) {
+  m = __builtin_amdgcn_bitop3_b32(X, Y, kNibK, kB3Mx);
+  const uint32_t het = __builtin_amdgcn_bitop3_b32(X, Y, kNibK, kB3Het);
+  w = (het << 2) | m;
+  h = __builtin_amdgcn_bitop3_b32(X, Y, kNibK, kB3Hom);
+  const uint32_t neg = b_side ? __builtin_amdgcn_bitop3_b32(X, Y, kNibK, kB3Neg3)
+                              : __builtin_amdgcn_bitop3_b32(X, Y, kNibK, kB3Neg0);
+  c = (neg << 2) | h;
+}
+
+__device__ __forceinline__ Fp4Feat fp4_expand2(uint32_t w0, uint32_t w1, bool b_side) {
+  Fp4Feat f;
+  f.m = (v8i){0}; f.w = (v8i){0}; f.h = (v8i){0}; f.c = (v8i){0};
+  const uint32_t ws[2] = {w0, w1};
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    uint32_t m, w, h, c;
+    fp4_parity(ws[q], ws[q] << 1, b_side, m, w, h, c);
+    f.m[2 * q] = (int)m; f.w[2 * q] = (int)w; f.h[2 * q] = (int)h; f.c[2 * q] = (int)c;
+    fp4_parity(ws[q] >> 2, ws[q] >> 1, b_side, m, w, h, c);
+    f.m[2 * q + 1] = (int)m; f.w[2 * q + 1] = (int)w; f.h[2 * q + 1] = (int)h;
+    f.c[2 * q + 1] = (int)c;
+  }
+  return f;
+}
+
+__device__ __forceinline__ void ibs_fp4_tile_pipe(const uint32_t* __restrict__ T, int64_t wp,
+                                                  int64_t I, int64_t J, const IbsOut& o,
+                                                  lds_t* smem, int64_t c0 = 0, int64_t c1 = -1,
+                                                  int32_t* __restrict__ part = nullptr) {
+  constexpr int kBuf = kT * kLdsStride;
+  lds_t* const sA = smem;
+  lds_t* const sB = smem + 2 * kBuf;
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int wid = t >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  const int g = lane >> 5;
+  const int rl = lane & 31;
+  const int lrow = t >> 2;
+  const int lq = (t & 3) * 4;
+  const uint32_t* pa = T + (I * kT + lrow) * wp + lq;
+  const uint32_t* pb = T + (J * kT + lrow) * wp + lq;
+  const int64_t half = 64 * wp;
+  uint4 ga0, ga1, gb0, gb1;
+  auto gload = [&](int64_t kc) {
+    ga0 = *reinterpret_cast<const uint4*>(pa + kc);
+    ga1 = *reinterpret_cast<const uint4*>(pa + half + kc);
+    gb0 = *reinterpret_cast<const uint4*>(pb + kc);
+    gb1 = *reinterpret_cast<const uint4*>(pb + half + kc);
+  };
+  auto lstore = [&](int buf) {
+    lds_st4(&(sA + buf * kBuf)[lrow * kLdsStride + lq], ga0);
+    lds_st4(&(sA + buf * kBuf)[(lrow + 64) * kLdsStride + lq], ga1);
+    lds_st4(&(sB + buf * kBuf)[lrow * kLdsStride + lq], gb0);
+    lds_st4(&(sB + buf * kBuf)[(lrow + 64) * kLdsStride + lq], gb1);
+  };
+  uint32_t wa[2][8], wb[2][8];
+  auto lread = [&](int buf, int h) {
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      const lds_t* ra = &(sA + buf * kBuf)[(wr * 64 + x * 32 + rl) * kLdsStride + g * 8 + 4 * h];
+      const lds_t* rb = &(sB + buf * kBuf)[(wc * 64 + x * 32 + rl) * kLdsStride + g * 8 + 4 * h];
+      const uint4 a = lds_ld4(ra);
+      const uint4 b = lds_ld4(rb);
+      wa[x][4 * h] = a.x; wa[x][4 * h + 1] = a.y; wa[x][4 * h + 2] = a.z; wa[x][4 * h + 3] = a.w;
+      wb[x][4 * h] = b.x; wb[x][4 * h + 1] = b.y; wb[x][4 * h + 2] = b.z; wb[x][4 * h + 3] = b.w;
+    }
+  };
+  Fp4Acc acc;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      acc.m[a][b] = (v16f){0};
+      acc.w[a][b] = (v16f){0};
+      acc.hc[a][b] = (v16f){0};
+    }
+  const int64_t nch = (c1 < 0 ? wp / kKW : c1) - c0;
+  auto fetch = [&](int64_t c) { gload((c0 + (c < nch ? c : nch - 1)) * kKW); };
+  fetch(0);
+  lstore(0);
+  fetch(1);
+  lstore(1);
+  fetch(2);
+  __syncthreads();
+  lread(0, 0);
+  lread(0, 1);
+  Fp4Feat fa[2], fb[2];
+  fa[0] = fp4_expand2(wa[0][0], wa[0][1], false);
+  fa[1] = fp4_expand2(wa[1][0], wa[1][1], false);
+  fb[0] = fp4_expand2(wb[0][0], wb[0][1], true);
+  fb[1] = fp4_expand2(wb[1][0], wb[1][1], true);
+  for (int64_t k = 0; k < nch; ++k) {
+    const int buf = (int)(k & 1);
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < kKW / 4; ++s) {
+      if (s == 1) {
+        lstore(buf);                                  // chunk k + 2
+        fetch(k + 3);
+      }
+      if (s == 2) lread(buf ^ 1, 0);                  // words 0-3 of chunk k + 1
+      if (s == 3) lread(buf ^ 1, 1);                  // words 4-7
+      const int sn = 2 * ((s + 1) & 3);               // next step's first word
+      Fp4Feat na[2], nb[2];
+      na[0] = fp4_expand2(wa[0][sn], wa[0][sn + 1], false);
+      na[1] = fp4_expand2(wa[1][sn], wa[1][sn + 1], false);
+      nb[0] = fp4_expand2(wb[0][sn], wb[0][sn + 1], true);
+      nb[1] = fp4_expand2(wb[1][sn], wb[1][sn + 1], true);
+      fp4_step(acc, fa, fb);
+      if (s == 1) {
+        __builtin_amdgcn_sched_group_barrier(0x200, 4, 0);
+        __builtin_amdgcn_sched_group_barrier(0x020, 4, 0);
+      }
+      if (s >= 2) __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x002, 8, 0);
+      }
+      fa[0] = na[0]; fa[1] = na[1];
+      fb[0] = nb[0]; fb[1] = nb[1];
+    }
+  }
+  if (part) {   // the raw sums as int32 (exact integers), laid out as ibs_mfma_tile's
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          int32_t* q = part + ((a * 2 + b) * 48 + v) * 256 + t;
+          q[0] = (int32_t)acc.m[a][b][v];
+          q[16 * 256] = (int32_t)acc.w[a][b][v];
+          q[32 * 256] = (int32_t)acc.hc[a][b][v];
+        }
+    return;
   }
   fp4_epilogue(acc, o, I, J, wr, wc, lane);
 }

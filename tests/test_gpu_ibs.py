@@ -16,12 +16,16 @@ pytestmark = pytest.mark.gpu
 
 pg = pytest.importorskip("paper_1410_4803_amd")
 
-PATHS = ["popc", "mfma", "fp4", "fp4rep", "w8", "w8nh"]
+PATHS = ["popc", "mfma", "fp4", "fp4rep", "w8", "w8nh", "pipe", "fp4pipe", "r1"]
 # path codes: "fp4" / "fp4rep" are matrix-core variants 3 and 4 (fp4 operands,
 # from the 2-bit and from the replicated layout); "w8" / "w8nh" are variants
-# 5 and 6 (eight waves of 64x32, with and without scheduling hints)
+# 5 and 6 (eight waves of 64x32, with and without scheduling hints); "pipe" is
+# variant 7 (int8, the chunk boundaries pipelined), "fp4pipe" variant 8 (the
+# same with fp4 operands: the default kernel, "mfma"), "r1" variant 9 (int8,
+# unpipelined)
 CODES = {"popc": 1, "mfma": 2, "fp4": 2 | (3 << 8), "fp4rep": 2 | (4 << 8), "w8": 2 | (5 << 8),
-         "w8nh": 2 | (6 << 8)}
+         "w8nh": 2 | (6 << 8), "pipe": 2 | (7 << 8),
+         "fp4pipe": 2 | (8 << 8), "r1": 2 | (9 << 8)}
 
 
 def _cohort(bed, n, mask=None):
