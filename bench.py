@@ -40,6 +40,7 @@ IBS_FP4_VARIANTS = (0, 8)      # the default kernel: pipelined, fp4 operands
 IBS_POPC_OPS = 8 / 32         # per 32-variant word: AND, 2 XOR, 2 bitop3, 3 popcount-adds
 LD_MFMA_OPS = 6 * 2           # six int8 contractions
 LD_POPC_OPS = 16 / 32         # 16 VALU ops per 32-sample word
+LD_INT8 = 2 | (1 << 8)         # the LD matrix-core path's int8 tile (variant 1)
 
 
 def log(msg: str) -> None:
@@ -181,7 +182,7 @@ def bench_prune(torch, lib, hip, pg, wp, dev, steps):
     pairs = sum(min(W - 1, V - 1 - a) for a in range(V))
     comps = pairs * n
     band_ms = mean(st[1])
-    ach = comps * LD_MFMA_OPS / (band_ms * 1e-3) / 1e12
+    ach = comps * LD_MFMA_OPS / (band_ms * 1e-3) / 1e12   # pipelined fp4 band kernel
     kept = int(n_kept.item())
     assert kept == int(keep.sum().item())
     # the missing-call correction path on the same call (these panels have no
@@ -204,9 +205,9 @@ def bench_prune(torch, lib, hip, pg, wp, dev, steps):
             "stages_ms": {"layout": round(mean(st[0]), 3), "band_kernel": round(band_ms, 3),
                           "allele_counts": round(mean(st[2]), 3),
                           "greedy": round(mean(st[3]), 3)},
-            "roofline": {"bound": "mfma", "kernel": "k_ld_mfma", "unit": "TOP/s",
-                         "achieved": round(ach, 2), "peak": PEAK_INT8_TOPS,
-                         "frac": round(ach / PEAK_INT8_TOPS, 4)}}
+            "roofline": {"bound": "mfma", "kernel": "k_ld_mfma<fp4>", "unit": "TFLOP/s",
+                         "dtype": "fp4", "achieved": round(ach, 2), "peak": PEAK_FP4_TFLOPS,
+                         "frac": round(ach / PEAK_FP4_TFLOPS, 4)}}
 
 
 def bench_grm(torch, lib, hip, pg, wg, dev, steps, path="auto"):
@@ -330,7 +331,7 @@ def bench_batch(torch, lib, hip, pg, synth, dev, steps):
     ms_loop, _ = timed_steps(torch, lib, hip, loop, steps, 2, 0)
     b.capture()
     ms_graph, _ = timed_steps(torch, lib, hip, b.replay, steps, 2, 0)
-    ms_direct, st_d = timed_steps(torch, lib, hip, b.launch, steps, 2, 4)
+    ms_direct, st_d = timed_steps(torch, lib, hip, b.launch, steps, 2, 3)
     torch.cuda.synchronize()
     # every output of the batch equals its one-call-per-problem counterpart
     for k, (p, o) in enumerate(zip(probs, loop_out)):
@@ -354,20 +355,22 @@ def bench_batch(torch, lib, hip, pg, synth, dev, steps):
             "graph": {"value": round(comps / (ms_graph * 1e-3) / 1e9, 1), "unit": "G/s",
                       "ms_per_step": round(ms_graph, 3)},
             "direct_launch": {"ms_per_step": round(ms_direct, 3),
-                              "layouts_ms": round(mean(st_d[0]), 3),
-                              "persistent_kernel_ms": round(mean(st_d[1]), 3),
-                              "ld_finish_ms": round(mean(st_d[2]), 3)},
+                              "ibs_branch_ms": round(mean(st_d[0]), 3),
+                              "both_branches_ms": round(mean(st_d[0]) + mean(st_d[1]), 3)},
             "one_call_per_problem": {"value": round(comps / (ms_loop * 1e-3) / 1e9, 1),
                                      "unit": "G/s", "ms_per_step": round(ms_loop, 3)},
             "speedup_vs_loop": round(ms_loop / ms_graph, 3)}
 
 
-def bench_serve(torch, pg, synth, dev, seconds, serial_seconds):
+def bench_serve(torch, pg, synth, dev, seconds, serial_seconds, rates, rate_seconds):
     """8 resident cohorts (samples log-uniform in [1k, 50k], variants in
     [10k, 200k], HWE, MAF~U[0.01,0.5], 1% missing); Poisson 200 requests/s,
     70% IBS matrices (strict upper triangle) / 30% LD windows (500, r^2 >=
     0.2); subsets of 100-5,000 samples, ranges of 1k-20k variants.  The
-    8-slot server is compared with one request at a time on the same arrivals."""
+    8-slot server and one request at a time run the same arrivals for the
+    same time; then both at higher arrival rates (`rates`, `rate_seconds`
+    each), and the server once more at the highest rate under a 2 GiB memory
+    budget, where admission has to hold requests back."""
     import numpy as np
     from paper_1410_4803_amd.serve import GpuBackend, Server, poisson_requests
     specs = synth.serve_cohorts()
@@ -377,7 +380,6 @@ def bench_serve(torch, pg, synth, dev, seconds, serial_seconds):
                for d in specs]
     resident = sum(c.nbytes for c in cohorts)
     budget = 64 << 30
-    reqs = poisson_requests(shapes, rate=200.0, seconds=seconds, seed=1005)
 
     def work(r):
         m, L = len(r.sample_idx), r.v_range[1] - r.v_range[0]
@@ -385,29 +387,106 @@ def bench_serve(torch, pg, synth, dev, seconds, serial_seconds):
             return m * (m - 1) / 2 * L
         return sum(min(r.window, L - 1 - a) for a in range(L)) * m
 
+    def run(slots, rate, secs, mem=budget):
+        reqs = poisson_requests(shapes, rate=rate, seconds=secs, seed=1005)
+        srv = Server(GpuBackend(cohorts, slots, keep_results=False), slots, mem)
+        st = srv.run(reqs)
+        done = srv.finished
+        span = max(r.done for r in done) - min(r.arrival for r in done)
+        st["value"] = round(sum(work(r) for r in done) / span / 1e9, 1)
+        st["unit"] = "G/s"
+        st["offered_rps"] = rate
+        st["requests"] = len(reqs)
+        st["queue_wait_p50_ms"] = round(float(np.percentile(
+            [r.admitted - r.arrival for r in done], 50)) * 1e3, 3)
+        return st
+
     # warm-up: a handful of requests (kernels, allocator pools, pinned buffers)
     warm = poisson_requests(shapes, rate=200.0, seconds=0.1, seed=99)
     Server(GpuBackend(cohorts, 8, keep_results=False), 8, budget).run(warm)
-    log(f"serving {len(reqs)} requests over {seconds} s with 8 slots")
-    srv = Server(GpuBackend(cohorts, 8, keep_results=False), 8, budget)
-    st = srv.run(reqs)
-    served = sum(work(r) for r in srv.finished)
-    span = max(r.done for r in srv.finished) - min(r.arrival for r in srv.finished)
-    st["value"] = round(served / span / 1e9, 1)
-    st["unit"] = "G/s"
-    ser_reqs = [r for r in poisson_requests(shapes, rate=200.0, seconds=serial_seconds,
-                                            seed=1005)]
-    log(f"serving {len(ser_reqs)} requests one at a time")
-    ser = Server(GpuBackend(cohorts, 1, keep_results=False), 1, budget)
-    sst = ser.run(ser_reqs)
-    served_s = sum(work(r) for r in ser.finished)
-    span_s = max(r.done for r in ser.finished) - min(r.arrival for r in ser.finished)
-    sst["value"] = round(served_s / span_s / 1e9, 1)
-    sst["unit"] = "G/s"
+    log(f"serving {seconds} s of 200 requests/s with 8 slots")
+    st = run(8, 200.0, seconds)
+    log(f"serving {serial_seconds} s of 200 requests/s one at a time")
+    sst = run(1, 200.0, serial_seconds)
+    sweep = []
+    for rate in rates:
+        log(f"serving {rate_seconds} s of {rate} requests/s: 8 slots, then one at a time")
+        sweep.append({"offered_rps": rate, "server_8_slots": run(8, rate, rate_seconds),
+                      "serial_one_at_a_time": run(1, rate, rate_seconds)})
+    tight = None
+    if rates:
+        log(f"serving {rate_seconds} s of {max(rates)} requests/s with a 2 GiB budget")
+        tight = run(8, max(rates), rate_seconds, mem=2 << 30)
+        tight["memory_budget"] = 2 << 30
     return {"workload": "serve_8_cohorts_poisson200", "cohorts": shapes,
             "resident_bytes": resident, "memory_budget": budget, "seconds": seconds,
-            "requests": len(reqs), "server_8_slots": st,
-            "serial_one_at_a_time": dict(sst, seconds=serial_seconds)}
+            "requests": st["requests"], "server_8_slots": st,
+            "serial_one_at_a_time": dict(sst, seconds=serial_seconds),
+            "rate_sweep": sweep, "rate_sweep_seconds": rate_seconds,
+            "budget_bound_run": tight}
+
+
+def sweep(torch, lib, hip, pg, synth, dev, which: str, reps: int) -> None:
+    """Path crossover: whole-call time of every kernel path per shape, one
+    JSON line per shape (then a summary line with the fastest path per
+    shape).  IBS: HWE panels (MAF~U[0.05,0.5], 1% missing), strict upper
+    triangle, m in 64..10,000 samples x V in {5,000, 20,000, 100,000}.  LD:
+    HWE panels of 20,000 variants, m in 500..20,000 samples x window in {50,
+    500, 1,000} x missing rate in {0, 0.5%, 1%}, r^2 >= 0.2."""
+    best = {}
+    if which in ("ibs", "all"):
+        for V in (5000, 20000, 100000):
+            for m in (64, 128, 256, 512, 1024, 2048, 4096, 10000):
+                bed = synth.hwe(m, V, (0.05, 0.5), 0.01, seed=7000 + m + V)
+                c = pg.Cohort.from_numpy(bed, m, device=dev)
+                size = m * (m - 1) // 2
+                out = tuple(torch.empty(max(size, 1), dtype=torch.int32, device=dev)
+                            for _ in range(4))
+                rec = {"sweep": "ibs", "m": m, "V": V, "ms": {}}
+                for path in ("mfma", "popc"):
+                    ws = torch.empty(max(pg.ibs_workspace_bytes(c, path=path), 1),
+                                     dtype=torch.uint8, device=dev)
+                    ms, st = timed_steps(torch, lib, hip, lambda: pg.ibs_matrix(
+                        c, layout="tri", path=path, out=out, workspace=ws), reps, 2, 3)
+                    rec["ms"][path] = round(min(ms, 1e9), 4)
+                    rec.setdefault("pair_kernel_ms", {})[path] = round(mean(st[1]), 4)
+                    del ws
+                rec["auto"] = {1: "popc", 2: "mfma"}[pg.api.resolve_path("ibs", m, V) & 0xFF]
+                rec["fastest"] = min(rec["ms"], key=rec["ms"].get)
+                best[f"ibs:{m}x{V}"] = rec["fastest"]
+                print(json.dumps(rec), flush=True)
+                del c, out
+                torch.cuda.empty_cache()
+    if which in ("ld", "all"):
+        V = 20000
+        cap = 1 << 22
+        ol = torch.empty((cap, 64), dtype=torch.uint8, device=dev)
+        nl = torch.empty(1, dtype=torch.int64, device=dev)
+        for miss in (0.0, 0.005, 0.01):
+            for m in (500, 1000, 2000, 5000, 10000, 20000):
+                bed = synth.hwe(m, V, (0.05, 0.5), miss, seed=8000 + m + int(miss * 1e4))
+                c = pg.Cohort.from_numpy(bed, m, device=dev)
+                for W in (50, 500, 1000):
+                    rec = {"sweep": "ld", "m": m, "V": V, "window": W, "miss": miss, "ms": {}}
+                    for path in ("mfma", "sparse", "popc"):
+                        ws = torch.empty(pg.ld_workspace_bytes(c, W, path=path),
+                                         dtype=torch.uint8, device=dev)
+                        ms, st = timed_steps(torch, lib, hip, lambda: pg.ld_window(
+                            c, W, 0.2, capacity=cap, out=ol, n_out=nl, workspace=ws,
+                            path=path), reps, 2, 5)
+                        rec["ms"][path] = round(ms, 4)
+                        rec.setdefault("band_kernel_ms", {})[path] = round(mean(st[1]), 4)
+                        del ws
+                    rec["auto"] = {1: "popc", 2: "mfma", 3: "sparse"}[
+                        pg.api.resolve_path("ld", m, V, W) & 0xFF]
+                    rec["fastest"] = min(rec["ms"], key=rec["ms"].get)
+                    best[f"ld:{m}:{W}:{miss}"] = rec["fastest"]
+                    print(json.dumps(rec), flush=True)
+                del c
+                torch.cuda.empty_cache()
+    print(json.dumps({"sweep": "summary", "fastest": best}), flush=True)
+
+
 
 
 def main():
@@ -424,9 +503,15 @@ def main():
                          "(or all / none)")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--serve-seconds", type=float, default=60.0)
-    ap.add_argument("--serial-seconds", type=float, default=15.0)
+    ap.add_argument("--serial-seconds", type=float, default=60.0)
+    ap.add_argument("--serve-rates", default="400,800,1600",
+                    help="arrival rates (requests/s) of the serving sweep")
+    ap.add_argument("--serve-rate-seconds", type=float, default=6.0)
     ap.add_argument("--grm-path", type=int, default=0,
                     help="path code of the relationship-matrix calls (0 = library default)")
+    ap.add_argument("--sweep", choices=["ibs", "ld", "all"], default=None,
+                    help="print the path crossover sweep (JSON lines) instead of the benchmark")
+    ap.add_argument("--sweep-reps", type=int, default=3)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -446,6 +531,9 @@ def main():
     lib = N.load()
     hip = HipEvents()
     dev = torch.device("cuda:0")
+    if args.sweep:
+        sweep(torch, lib, hip, pg, synth, dev, args.sweep, args.sweep_reps)
+        return
 
     # ---- default workload: IBS 10,000 x 100,000, full matrix ----
     log("generating the 10000 x 100000 mosaic panel")
@@ -569,7 +657,7 @@ def main():
         cap = 4_000_000
         ol = torch.empty((cap, 64), dtype=torch.uint8, device=dev)
         nl = torch.empty(1, dtype=torch.int64, device=dev)
-        for wl, key, lpaths in ((synth.ld_large(), "ld_large", ("mfma", "sparse", "popc")),
+        for wl, key, lpaths in ((synth.ld_large(), "ld_large", ("mfma", "sparse", "popc", LD_INT8)),
                                 (synth.ld_large_nomiss(), "ld_large_nomiss", ("mfma", "sparse"))):
             log(f"timing LD windows on {wl['name']}")
             cl = pg.Cohort.from_numpy(wl["bed"], wl["n"], device=dev)
@@ -594,11 +682,18 @@ def main():
                                      "emit": round(mean(stl[3]), 3)}}
                 if lpath == "mfma":
                     ach = compsl * LD_MFMA_OPS / (band_ms * 1e-3) / 1e12
-                    rec["roofline"] = {"bound": "mfma", "kernel": "k_ld_mfma", "unit": "TOP/s",
-                                       "achieved": round(ach, 2), "peak": PEAK_INT8_TOPS,
-                                       "frac": round(ach / PEAK_INT8_TOPS, 4),
-                                       "traffic": traffic_from_profile("k_ld_mfma")
+                    rec["roofline"] = {"bound": "mfma", "kernel": "k_ld_mfma<fp4>",
+                                       "unit": "TFLOP/s", "dtype": "fp4",
+                                       "achieved": round(ach, 2), "peak": PEAK_FP4_TFLOPS,
+                                       "frac": round(ach / PEAK_FP4_TFLOPS, 4),
+                                       "traffic": traffic_from_profile("k_ld_mfma<fp4>")
                                        if key == "ld_large" else None}
+                elif lpath == LD_INT8:
+                    ach = compsl * LD_MFMA_OPS / (band_ms * 1e-3) / 1e12
+                    rec["roofline"] = {"bound": "mfma", "kernel": "k_ld_mfma<int8>",
+                                       "unit": "TOP/s", "dtype": "int8",
+                                       "achieved": round(ach, 2), "peak": PEAK_INT8_TOPS,
+                                       "frac": round(ach / PEAK_INT8_TOPS, 4)}
                 elif lpath == "popc":
                     ach = compsl * LD_POPC_OPS / (band_ms * 1e-3) / 1e12
                     rec["roofline"] = {"bound": "alu", "kernel": "k_ld_popc", "unit": "TOP/s",
@@ -607,7 +702,8 @@ def main():
                                        "traffic": traffic_from_profile("k_ld_popc")}
                 else:
                     rec["vs_mfma"] = round(extras[f"{key}_mfma"]["ms_per_step"] / msl, 3)
-                extras[f"{key}_{lpath}"] = rec
+                rec["path"] = lpath if isinstance(lpath, str) else "mfma_int8"
+                extras[f"{key}_{rec['path']}"] = rec
                 del wkl
             del cl
         del ol
@@ -651,8 +747,9 @@ def main():
         extras["batch"] = bench_batch(torch, lib, hip, pg, synth, dev, args.steps)
         torch.cuda.empty_cache()
     if "serve" in want and args.serve_seconds > 0:
+        rates = [float(x) for x in args.serve_rates.split(",") if x]
         extras["serve"] = bench_serve(torch, pg, synth, dev, args.serve_seconds,
-                                      args.serial_seconds)
+                                      args.serial_seconds, rates, args.serve_rate_seconds)
         torch.cuda.empty_cache()
 
     if args.copy_calibration:

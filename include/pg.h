@@ -107,10 +107,20 @@ enum pg_layout {
  * 8-15 select a kernel variant of that path (0 = the library's default; the
  * tuner tries the others).  Unknown variants fall back to the default. */
 enum pg_path {
-  PG_PATH_AUTO = 0, /* library picks per shape */
+  PG_PATH_AUTO = 0, /* library picks per shape (pg_resolve_path) */
   PG_PATH_POPC = 1, /* bit planes + popcount on the vector ALUs */
-  PG_PATH_MFMA = 2, /* 2-bit codes expanded to int8 indicator features and
-                       contracted on the int8 matrix cores */
+  PG_PATH_MFMA = 2, /* 2-bit codes expanded to indicator features (values
+                       0, +-1) and contracted on the matrix cores.  Default
+                       kernels (variant 0): fp4 (e2m1) operands with fp32
+                       sums, exact below 2^24 summed terms; beyond that
+                       (IBS: 2^24 variants, LD: 2^24 samples) int8 operands
+                       with int32 sums.  IBS variants: 1 int8 without
+                       scheduling hints, 2 unpipelined reference, 3 fp4
+                       unpipelined, 4 fp4 from a replicated operand, 5/6
+                       eight waves, 7 int8 pipelined, 8 fp4 pipelined (the
+                       default), 9 int8 with hints, unpipelined.  LD
+                       variants: 1 the int8 tile.  All give identical
+                       counts. */
   PG_PATH_SPARSE = 3 /* LD only: sum x_a x_b on the int8 matrix cores, the
                        other five sums from per-variant totals corrected at
                        the other variant's missing calls (section "Bit
@@ -120,7 +130,7 @@ enum pg_path {
                        one of its variants has more missing calls than a
                        list slot holds (max(64, ceil(m/16) rounded up to a
                        multiple of 8), at most 65,528, for m selected
-                       samples) or its 128 variants have more than 3m/4 in
+                       samples) or its 128 variants have more than m/4 in
                        all, and every tile does unless a quarter of the
                        64-variant groups pass these tests on their own
                        (then the extra sample-major operand pays).  Exact
@@ -136,6 +146,14 @@ enum pg_path {
                        least (v_end - v_begin) * window and *n_out receives
                        that product. */
 };
+
+/*
+ * The kernel path and variant (path | variant << 8) that a call of `kind`
+ * (PG_KIND_IBS or PG_KIND_LD) with the given `path` argument runs for m
+ * selected samples, nv selected variants and (LD) `window`: PG_PATH_AUTO
+ * and variant 0 resolve here exactly as the compute calls resolve them.
+ */
+int pg_resolve_path(int kind, int64_t m, int64_t nv, int32_t window, int path, int* resolved);
 
 /*
  * Sample selection and variant range (shared by the IBS and LD calls):
@@ -415,12 +433,17 @@ int pg_batch_workspace_bytes(const pg_plan* plan, size_t* bytes);
  * (informational). */
 int pg_batch_tiles(const pg_plan* plan, int64_t* total_tiles, int* grid);
 /* Writes the tile table into `workspace` (a host-to-device copy on `stream`,
- * waited for before returning).  Launches must use this same workspace. */
+ * waited for before returning) and creates the plan's second stream and two
+ * events (default priority; released by pg_plan_free).  Launches must use
+ * this same workspace. */
 int pg_batch_upload(pg_plan* plan, void* workspace, size_t workspace_bytes, void* stream);
-/* Enqueues the whole batch on `stream`: operand layouts, the persistent
- * kernels (each over its group of tiles), then LD scans and emits.  Kernels
- * only, so it may be captured into a HIP graph.  Stage events
- * (pg_profile_events): 1 = layouts, 2 = persistent kernels, 3 = LD finish. */
+/* Enqueues the whole batch behind the work already on `stream`, in two
+ * concurrent branches: the IBS problems (layouts, persistent kernel) on
+ * `stream`, the LD problems (layouts, persistent kernels, scans and emits)
+ * on the plan's second stream, joined back into `stream` before the call's
+ * work counts as done there.  Kernels and event waits only, so it may be
+ * captured into a HIP graph.  Stage events (pg_profile_events, on `stream`):
+ * 1 = the IBS branch done, 2 = both branches done. */
 int pg_batch_launch(const pg_plan* plan, void* workspace, size_t workspace_bytes, void* stream);
 void pg_plan_free(pg_plan* plan);
 

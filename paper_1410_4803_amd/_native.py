@@ -30,7 +30,7 @@ SYMBOLS = ("pg_status_str", "pg_last_error", "pg_version", "pg_profile_events",
            "pg_ibs_distance", "pg_cluster_workspace_bytes", "pg_ibs_cluster", "pg_peak_rates",
            "pg_batch_plan", "pg_batch_workspace_bytes", "pg_batch_tiles", "pg_batch_upload",
            "pg_batch_launch", "pg_plan_free", "pg_batch_capture", "pg_graph_launch",
-           "pg_graph_destroy", "pg_ibs_matrix_noalloc", "pg_noalloc_scratch_bytes")
+           "pg_graph_destroy", "pg_ibs_matrix_noalloc", "pg_noalloc_scratch_bytes", "pg_resolve_path")
 PG_KIND_IBS, PG_KIND_LD = 0, 1
 
 LD_PAIR = np.dtype([("a", "<i4"), ("b", "<i4"), ("n", "<i8"), ("sx", "<i8"), ("sy", "<i8"),
@@ -98,6 +98,9 @@ def load():
     lib.pg_ibs_matrix_noalloc.restype = ctypes.c_int
     lib.pg_noalloc_scratch_bytes.argtypes = [ctypes.POINTER(sz)]
     lib.pg_noalloc_scratch_bytes.restype = ctypes.c_int
+    lib.pg_resolve_path.argtypes = [ctypes.c_int, i64, i64, i32, ctypes.c_int,
+                                    ctypes.POINTER(ctypes.c_int)]
+    lib.pg_resolve_path.restype = ctypes.c_int
     lib.pg_ld_workspace_bytes.argtypes = [gp, i64, i64, i64, i32, ctypes.c_int, ctypes.POINTER(sz)]
     lib.pg_ld_workspace_bytes.restype = ctypes.c_int
     lib.pg_ld_window.argtypes = [gp, p, i64, i64, i64, i32, dbl, p, i64, p, ctypes.c_int, p, sz, p]

@@ -154,6 +154,16 @@ def ibs_matrix(cohort: Cohort, *, sample_idx: torch.Tensor | None = None, v_rang
     return out
 
 
+def resolve_path(kind: str, m: int, nv: int, window: int = 0, path="auto") -> int:
+    """The path | variant << 8 code a call of `kind` ("ibs" or "ld") runs for
+    m samples, nv variants and window (pg_resolve_path)."""
+    out = ctypes.c_int(0)
+    N.check(N.load().pg_resolve_path(N.PG_KIND_IBS if kind == "ibs" else N.PG_KIND_LD, int(m),
+                                     int(nv), int(window), _path(path), ctypes.byref(out)),
+            "pg_resolve_path")
+    return out.value
+
+
 def noalloc_scratch_bytes() -> int:
     """Size of the static scratch array pg_ibs_matrix_noalloc works in."""
     out = ctypes.c_size_t(0)

@@ -118,9 +118,24 @@ int make_sel(const pg_genotypes* g, bool list, const int32_t* idx, int64_t n_sel
 }
 
 
+// PG_PATH_AUTO.  Measured whole-call times (the sweep mode of bench.py):
+// the pipelined fp4 matrix-core kernel wins every IBS shape of 64 to 10,000
+// samples x 5,000 to 100,000 variants, the popcount kernel coming closest
+// at 64 samples (0.087 vs 0.081 ms), and every LD shape of 500 to 20,000
+// samples x windows of 50 to 1,000 at 0.5% and 1% missing calls.  The
+// missing-call correction path wins only on data without missing calls
+// (5,000 samples and up, windows of 500 and up), which the plan cannot see,
+// so it stays a caller's choice.
 int ibs_auto_path(int64_t m, int64_t nv) {
   (void)m;
   (void)nv;
+  return PG_PATH_MFMA;
+}
+
+int ld_auto_path(int64_t m, int64_t nv, int32_t window) {
+  (void)m;
+  (void)nv;
+  (void)window;
   return PG_PATH_MFMA;
 }
 
@@ -184,10 +199,16 @@ int plan_ld(const Sel& s, int32_t window, int path_arg, LdPlan& p) {
   if (path_arg < 0 || (path_arg >> 16) != 0) return fail(PG_EINVAL, "bad path argument %d", path_arg);
   int path = path_arg & 0xFF;
   p.variant = (path_arg >> 8) & 0xFF;
-  if (path == PG_PATH_AUTO) path = PG_PATH_MFMA;
+  if (path == PG_PATH_AUTO) path = ld_auto_path(s.m, s.nv, window);
   if (path != PG_PATH_MFMA && path != PG_PATH_POPC && path != PG_PATH_SPARSE)
     return fail(PG_EINVAL, "unknown path %d", path);
   p.path = path;
+  // matrix-core kernel: fp4 by default (exact below 2^24 samples), int8 as
+  // variant 1 or beyond that
+  if (path == PG_PATH_MFMA && (p.variant != kLdVariantInt8 && s.m < kFp4MaxVariants))
+    p.variant = kLdVariantFp4;
+  else if (path == PG_PATH_MFMA)
+    p.variant = kLdVariantInt8;
   p.rows_pad = round_up(s.nv, kLdTile);
   p.bm_words = ceil_div(window, 32);
   int64_t operand_bytes;
@@ -225,12 +246,14 @@ int plan_ld(const Sel& s, int32_t window, int path_arg, LdPlan& p) {
 constexpr int kLdAllTiles = 1, kLdDiag = 2, kLdWide = 4;
 
 // Band tiles take the correction path when their two 64-variant groups hold
-// at most 3m/4 missing calls (m selected samples), and only once a quarter
+// at most m/4 missing calls (m selected samples), and only once a quarter
 // of the groups have a diagonal tile that does, so that the sample-major
-// operand is worth building.  Measured on 5,000 samples: the correction
-// kernel costs as much as the dense one at about 0.9m per tile.
+// operand is worth building.  Measured on 5,000 samples, window 1,000: the
+// correction kernel costs as much as the pipelined fp4 dense kernel at
+// about 0.28m missing calls per tile (0.22% of the calls), and 1.5x less
+// without missing calls.
 int64_t ld_sparse_budget(const LdPlan& p, int64_t m) {
-  return p.variant & (kLdAllTiles | kLdDiag) ? INT64_MAX : 3 * m / 4;
+  return p.variant & (kLdAllTiles | kLdDiag) ? INT64_MAX : m / 4;
 }
 uint32_t ld_sparse_min_groups(const LdPlan& p) {
   const int64_t g = p.rows_pad / kLdTile;
@@ -255,7 +278,8 @@ int ld_pairs(const Sel& s, const LdPlan& p, char* ws, int32_t window, double r2_
   if (p.path == PG_PATH_MFMA) {
     mark_stage(1, st);
     if (rc != PG_OK) return rc;
-    return launch_ld_mfma(D, p.words, s.nv, p.rows_pad, window, r2_min, sc, st);
+    return launch_ld_mfma(D, p.words, s.nv, p.rows_pad, window, r2_min, sc, st, nullptr,
+                          p.variant == kLdVariantFp4);
   }
   LdSparse sp{(uint32_t*)(ws + p.off_lists), (int4*)(ws + p.off_vst), (int64_t*)(ws + p.off_gsum),
               (int*)(ws + p.off_gmax), (uint32_t*)(ws + p.off_any), ld_sparse_min_groups(p),
@@ -485,6 +509,28 @@ int pg_noalloc_scratch_bytes(size_t* bytes) {
   if (!bytes) return fail(PG_EINVAL, "bytes is NULL");
   *bytes = (size_t)kNoAllocScratchBytes;
   return PG_OK;
+}
+
+int pg_resolve_path(int kind, int64_t m, int64_t nv, int32_t window, int path, int* resolved) {
+  if (!resolved) return fail(PG_EINVAL, "resolved is NULL");
+  if (m < 1 || m >= kMaxIndex || nv < 1 || nv >= kMaxIndex)
+    return fail(PG_EINVAL, "m %lld / nv %lld outside [1, 2^31)", (long long)m, (long long)nv);
+  Sel s{};
+  s.n = s.m = m;
+  s.nv = nv;
+  int rc;
+  if (kind == PG_KIND_IBS) {
+    IbsPlan p;
+    rc = plan_ibs(s, path, p);
+    if (rc == PG_OK) *resolved = p.path | (p.variant << 8);
+  } else if (kind == PG_KIND_LD) {
+    LdPlan p;
+    rc = plan_ld(s, window, path, p);
+    if (rc == PG_OK) *resolved = p.path | (p.variant << 8);
+  } else {
+    rc = fail(PG_EINVAL, "unknown kind %d", kind);
+  }
+  return rc;
 }
 
 int pg_ld_workspace_bytes(const pg_genotypes* g, int64_t n_sel, int64_t v_begin, int64_t v_end,

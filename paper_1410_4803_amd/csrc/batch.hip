@@ -5,14 +5,19 @@
 // carves one workspace into per-problem operands and LD scratch, and orders
 // the problems by part (IBS, LD matrix-core, LD popcount), longest tile first
 // within each part, so that the tiles of all problems form one global list.
-// A launch enqueues, on one stream: every problem's operand layout (and LD
-// scratch clearing), a reset of the tile counters, one persistent kernel per
-// non-empty part (its blocks take tiles of that part with an atomic counter
-// until the part is exhausted), and every LD problem's scan and emit.  The
-// tile bodies are the same device functions the one-problem kernels run, so
+// A launch enqueues two branches that run concurrently: on the caller's
+// stream the IBS problems' operand layouts, a reset of their tile counter
+// and the IBS persistent kernel; on a stream of the plan's own (forked from
+// the caller's with an event and joined back with another) the LD problems'
+// layouts and scratch clearing, their tile counters, the LD persistent
+// kernels and every LD problem's scan and emit.  A persistent kernel's
+// blocks take tiles of their part with an atomic counter until the part is
+// exhausted, so as one branch's tiles run out its CUs go to the other
+// branch's blocks, and neither part's tail leaves the GPU idle.  The tile
+// bodies are the same device functions the one-problem kernels run, so
 // results are identical to calling pg_ibs_matrix / pg_ld_window per problem.
-// The sequence contains kernels only (no memset or copy nodes), so it can be
-// captured into a HIP graph and replayed.
+// The sequence contains kernels and event waits only (no memset or copy
+// nodes), so it can be captured into a HIP graph and replayed.
 #include <algorithm>
 #include <new>
 #include <vector>
@@ -89,11 +94,16 @@ __global__ __launch_bounds__(256, kPart == kPartIbs ? 1 : 2) void k_batch_persis
       const int64_t I = local / it.n_band;
       const int64_t J = I + local % it.n_band;
       if (J < it.nt) {
-        if constexpr (kPart == kPartLdMfma)
-          ld_mfma_tile(it.X, it.words, it.nv, I, J, it.window, it.r2_min, it.sc, (lds_t*)smem);
-        else
+        if constexpr (kPart == kPartLdMfma) {
+          if (it.variant == kLdVariantFp4)
+            ld_fp4_tile_pipe(it.X, it.words, it.nv, I, J, it.window, it.r2_min, it.sc,
+                             (lds_t*)smem);
+          else
+            ld_mfma_tile(it.X, it.words, it.nv, I, J, it.window, it.r2_min, it.sc, (lds_t*)smem);
+        } else {
           ld_popc_tile(it.X, it.words, it.nv, it.rows_pad, I, J, it.window, it.r2_min, it.sc,
                        (lds_t*)smem);
+        }
       }
     }
     __syncthreads();   // LDS is reused by the next tile
@@ -136,6 +146,15 @@ struct pg_plan {
   int64_t off_items = 0, off_counter = 0, bytes = 0;
   int grid[kParts] = {256, 256, 256};
   const void* uploaded_ws = nullptr;
+  // the LD branch runs on a stream of the plan's own, forked from and
+  // joined back into the caller's stream with two events
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  ~pg_plan() {
+    if (join) (void)hipEventDestroy(join);
+    if (fork) (void)hipEventDestroy(fork);
+    if (side) (void)hipStreamDestroy(side);
+  }
 };
 
 namespace pg {
@@ -297,6 +316,11 @@ int pg_batch_upload(pg_plan* plan, void* workspace, size_t workspace_bytes, void
     t += q.ntiles;
   }
   hipStream_t st = (hipStream_t)stream;
+  if (!plan->side &&
+      (hipStreamCreateWithFlags(&plan->side, hipStreamNonBlocking) != hipSuccess ||
+       hipEventCreateWithFlags(&plan->fork, hipEventDisableTiming) != hipSuccess ||
+       hipEventCreateWithFlags(&plan->join, hipEventDisableTiming) != hipSuccess))
+    return fail(PG_EDEVICE, "batch stream and events: %s", hipGetErrorString(hipGetLastError()));
   if (hipMemcpyAsync(ws + plan->off_items, items.data(), sizeof(BatchItem) * items.size(),
                      hipMemcpyHostToDevice, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
@@ -313,42 +337,60 @@ int pg_batch_launch(const pg_plan* plan, void* workspace, size_t workspace_bytes
   if (plan->uploaded_ws != workspace)
     return fail(PG_EINVAL, "workspace differs from the one given to pg_batch_upload");
   hipStream_t st = (hipStream_t)stream;
+  hipStream_t side = plan->side;
   char* ws = (char*)workspace;
   int rc = PG_OK;
   mark_stage(0, st);
-  for (int k : plan->order) {
-    const ProblemPlan& q = plan->probs[k];
-    uint32_t* X = (uint32_t*)(ws + q.off_x);
-    if (q.p.kind == PG_KIND_IBS) {
-      rc = q.path == PG_PATH_MFMA ? launch_sample_major_2bit(q.s, X, q.rows_pad, q.words, st)
-                                  : launch_ibs_planes(q.s, X, q.rows_pad, q.words, st);
-    } else {
-      rc = q.path == PG_PATH_MFMA ? launch_variant_major_2bit(q.s, X, q.rows_pad, q.words, st)
-                                  : launch_ld_planes(q.s, X, q.rows_pad, q.words, st);
-      const LdScratch sc{(uint32_t*)(ws + q.off_bm), q.bm_words, (uint32_t*)(ws + q.off_cnt),
-                         (int64_t*)(ws + q.off_off), (int64_t*)(ws + q.off_bsum)};
-      if (rc == PG_OK) rc = ld_clear(sc, q.rows_pad, st);
-    }
-    if (rc != PG_OK) return rc;
-  }
+  // fork: the LD branch waits for everything before this call on `st`
+  if (hipEventRecord(plan->fork, st) != hipSuccess ||
+      hipStreamWaitEvent(side, plan->fork, 0) != hipSuccess)
+    return fail(PG_EDEVICE, "batch fork: %s", hipGetErrorString(hipGetLastError()));
   unsigned long long* counter = (unsigned long long*)(ws + plan->off_counter);
-  rc = fill_u32((uint32_t*)counter, 2 * kParts, 0u, st);
-  if (rc != PG_OK) return rc;
-  mark_stage(1, st);
   const BatchItem* items = (const BatchItem*)(ws + plan->off_items);
   const int n_items = (int)plan->probs.size();
   const int64_t* pb = plan->part_begin;
-  if (pb[1] > pb[0])
+  // IBS branch on `st`: layouts, the tile counter, the persistent kernel
+  for (int k : plan->order) {
+    const ProblemPlan& q = plan->probs[k];
+    if (q.p.kind != PG_KIND_IBS) continue;
+    uint32_t* X = (uint32_t*)(ws + q.off_x);
+    rc = q.path == PG_PATH_MFMA ? launch_sample_major_2bit(q.s, X, q.rows_pad, q.words, st)
+                                : launch_ibs_planes(q.s, X, q.rows_pad, q.words, st);
+    if (rc != PG_OK) return rc;
+  }
+  if (pb[1] > pb[0]) {
+    rc = fill_u32((uint32_t*)counter, 2, 0u, st);
+    if (rc != PG_OK) return rc;
     hipLaunchKernelGGL(k_batch_persistent<kPartIbs>, dim3((unsigned)plan->grid[kPartIbs]),
                        dim3(256), 0, st, items, n_items, pb[0], pb[1], counter);
+    rc = check_launch("batch_persistent_ibs");
+    if (rc != PG_OK) return rc;
+  }
+  mark_stage(1, st);
+  // LD branch on `side`: layouts and scratch clearing, the tile counters,
+  // the persistent kernels, the scans and emits
+  for (int k : plan->order) {
+    const ProblemPlan& q = plan->probs[k];
+    if (q.p.kind != PG_KIND_LD) continue;
+    uint32_t* X = (uint32_t*)(ws + q.off_x);
+    rc = q.path == PG_PATH_MFMA ? launch_variant_major_2bit(q.s, X, q.rows_pad, q.words, side)
+                                : launch_ld_planes(q.s, X, q.rows_pad, q.words, side);
+    const LdScratch sc{(uint32_t*)(ws + q.off_bm), q.bm_words, (uint32_t*)(ws + q.off_cnt),
+                       (int64_t*)(ws + q.off_off), (int64_t*)(ws + q.off_bsum)};
+    if (rc == PG_OK) rc = ld_clear(sc, q.rows_pad, side);
+    if (rc != PG_OK) return rc;
+  }
+  if (pb[3] > pb[1]) {
+    rc = fill_u32((uint32_t*)(counter + 1), 2 * (kParts - 1), 0u, side);
+    if (rc != PG_OK) return rc;
+  }
   if (pb[2] > pb[1])
     hipLaunchKernelGGL(k_batch_persistent<kPartLdMfma>, dim3((unsigned)plan->grid[kPartLdMfma]),
-                       dim3(256), 0, st, items, n_items, pb[1], pb[2], counter + 1);
+                       dim3(256), 0, side, items, n_items, pb[1], pb[2], counter + 1);
   if (pb[3] > pb[2])
     hipLaunchKernelGGL(k_batch_persistent<kPartLdPopc>, dim3((unsigned)plan->grid[kPartLdPopc]),
-                       dim3(256), 0, st, items, n_items, pb[2], pb[3], counter + 2);
-  rc = check_launch("batch_persistent");
-  mark_stage(2, st);
+                       dim3(256), 0, side, items, n_items, pb[2], pb[3], counter + 2);
+  rc = check_launch("batch_persistent_ld");
   if (rc != PG_OK) return rc;
   for (int k : plan->order) {
     const ProblemPlan& q = plan->probs[k];
@@ -356,10 +398,14 @@ int pg_batch_launch(const pg_plan* plan, void* workspace, size_t workspace_bytes
     const LdScratch sc{(uint32_t*)(ws + q.off_bm), q.bm_words, (uint32_t*)(ws + q.off_cnt),
                        (int64_t*)(ws + q.off_off), (int64_t*)(ws + q.off_bsum)};
     rc = launch_ld_finish((uint32_t*)(ws + q.off_x), q.path == PG_PATH_POPC, q.words, q.rows_pad,
-                          q.s.nv, q.s.v0, sc, q.p.out, q.p.capacity, q.p.n_out, st, false);
+                          q.s.nv, q.s.v0, sc, q.p.out, q.p.capacity, q.p.n_out, side, false);
     if (rc != PG_OK) return rc;
   }
-  mark_stage(3, st);
+  // join: `st` continues once the LD branch is done
+  if (hipEventRecord(plan->join, side) != hipSuccess ||
+      hipStreamWaitEvent(st, plan->join, 0) != hipSuccess)
+    return fail(PG_EDEVICE, "batch join: %s", hipGetErrorString(hipGetLastError()));
+  mark_stage(2, st);
   return PG_OK;
 }
 

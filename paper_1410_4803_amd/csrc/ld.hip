@@ -56,6 +56,7 @@ int launch_ld_popc(const uint32_t* P, int64_t words_pad, int64_t nv, int64_t row
   return rc;
 }
 
+template <bool kFp4>
 __global__ __launch_bounds__(256, 2) void k_ld_mfma(const uint32_t* __restrict__ D, int64_t wn,
                                                     int64_t nv, int64_t n_row_tiles, int64_t n_band,
                                                     int32_t window, double r2_min, LdScratch sc,
@@ -70,16 +71,21 @@ __global__ __launch_bounds__(256, 2) void k_ld_mfma(const uint32_t* __restrict__
   if (gsum && ld_tile_sparse(gsum, gmax, groups_ok, min_groups, I, J, cap, budget))
     return;   // the correction path's
   __shared__ __attribute__((aligned(16))) uint32_t smem[kLdMfmaSmem];
-  ld_mfma_tile(D, wn, nv, I, J, window, r2_min, sc, (lds_t*)smem);
+  if constexpr (kFp4)
+    ld_fp4_tile_pipe(D, wn, nv, I, J, window, r2_min, sc, (lds_t*)smem);
+  else
+    ld_mfma_tile(D, wn, nv, I, J, window, r2_min, sc, (lds_t*)smem);
 }
 
 int launch_ld_mfma(const uint32_t* D, int64_t wn, int64_t nv, int64_t rows_pad, int32_t window,
-                   double r2_min, const LdScratch& sc, hipStream_t st, const LdSparse* sp) {
+                   double r2_min, const LdScratch& sc, hipStream_t st, const LdSparse* sp,
+                   bool fp4) {
   int rc;
   const int64_t n_row_tiles = rows_pad / kL;
   const int64_t n_band = ((int64_t)window + kL - 1) / kL + 1;
   const int64_t blocks = n_row_tiles * n_band;
-  hipLaunchKernelGGL(k_ld_mfma, dim3((unsigned)blocks), dim3(256), 0, st, D, wn, nv, n_row_tiles,
+  hipLaunchKernelGGL(fp4 ? k_ld_mfma<true> : k_ld_mfma<false>, dim3((unsigned)blocks), dim3(256),
+                     0, st, D, wn, nv, n_row_tiles,
                      n_band, window, r2_min, sc, sp ? sp->gsum : nullptr,
                      sp ? sp->gmax : nullptr, sp ? sp->groups_ok : nullptr,
                      sp ? sp->min_groups : 0u, sp ? sp->cap : 0, sp ? sp->budget : 0);

@@ -511,7 +511,7 @@ int launch_ld_sparse(const uint32_t* D, int64_t wn, const uint32_t* T, int64_t t
   int rc;
   // the dense kernel takes the tiles this path leaves
   if (!dbg) {
-    rc = launch_ld_mfma(D, wn, nv, rows_pad, window, r2_min, sc, st, &sp);
+    rc = launch_ld_mfma(D, wn, nv, rows_pad, window, r2_min, sc, st, &sp, m < kFp4MaxVariants);
     if (rc != PG_OK) return rc;
   }
   const int64_t n_row_tiles = rows_pad / kLdTile;

@@ -156,6 +156,8 @@ int plan_ibs_default(const Sel& s, IbsPlan& p);
 // The path PG_PATH_AUTO resolves to for an IBS matrix of m samples and nv
 // variants (abi.hip).
 int ibs_auto_path(int64_t m, int64_t nv);
+// The path PG_PATH_AUTO resolves to for LD windows (abi.hip).
+int ld_auto_path(int64_t m, int64_t nv, int32_t window);
 
 // Static scratch of pg_ibs_matrix_noalloc (abi.hip): its size, and its
 // device address on the current device (looked up once per device).
@@ -263,10 +265,15 @@ inline int ld_sparse_cap(int64_t m) {
 // Clears the emission bitmap and row counts (stage 1 ends after this).
 int ld_clear(const LdScratch& sc, int64_t rows_pad, hipStream_t st);
 // Dense pair kernel over the band; with `sp`, tiles the correction path
-// takes are skipped (and stage 2 is left to that path).
+// takes are skipped (and stage 2 is left to that path).  fp4: the pipelined
+// fp4 tile (exact below 2^24 samples), else the int8 tile.
 int launch_ld_mfma(const uint32_t* D, int64_t wn, int64_t nv, int64_t rows_pad, int32_t window,
                    double r2_min, const LdScratch& sc, hipStream_t st,
-                   const LdSparse* sp = nullptr);
+                   const LdSparse* sp = nullptr, bool fp4 = true);
+// Kernel variants of the LD matrix-core path: 0 (default) the pipelined fp4
+// tile, or the int8 tile (1) when sums could reach 2^24 (m >= 2^24).
+constexpr int kLdVariantFp4 = 0;
+constexpr int kLdVariantInt8 = 1;
 // Correction path, first part: lists, counts and totals from D
 // (variant-major, wn words), the group statistics and groups_ok.
 int launch_ld_sparse_stats(const uint32_t* D, int64_t wn, int64_t tw, int64_t m, int64_t nv,

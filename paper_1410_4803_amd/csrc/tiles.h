@@ -1408,6 +1408,142 @@ __device__ __forceinline__ void ld_mfma_tile(const uint32_t* __restrict__ D, int
 }
 
 
+// Pipelined fp4 form of the banded matrix-core tile (the default LD kernel):
+// the same six Grams on v_mfma_scale_f32_32x32x64_f8f6f4 with e2m1 operands
+// (m, x, h are 0 or +-1, exact; fp32 sums exact below 2^24 samples), and
+// the chunk schedule of ibs_fp4_tile_pipe: a chunk of 256 samples is four
+// steps of 64 per MFMA lane (two 2-bit words), chunk k + 2 is fetched and
+// stored to LDS at step 1 of chunk k, chunk k + 1 is read at steps 2 and 3,
+// and its first step expanded during step 3.  Waves without a pair in the
+// window run a loop that only stages, with the same barriers.
+// Expansion of one parity of a word (see ibs_fp4_tile_pipe for X, Y, K):
+//   m = K & (X | ~Y),  h = K & ~(X ^ Y),  x = h | (K & ~X & ~Y) << 2
+// (x = -1 for homozygous A1, +1 for homozygous A2, 0 otherwise).
+struct Fp4Feat3 {
+  v8i m, x, h;
+};
+
+__device__ __forceinline__ Fp4Feat3 ld_fp4_expand2(uint32_t w0, uint32_t w1) {
+  Fp4Feat3 f;
+  f.m = (v8i){0}; f.x = (v8i){0}; f.h = (v8i){0};
+  const uint32_t ws[2] = {w0, w1};
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+#pragma unroll
+    for (int par = 0; par < 2; ++par) {
+      const uint32_t X = par ? ws[q] >> 2 : ws[q];
+      const uint32_t Y = par ? ws[q] >> 1 : ws[q] << 1;
+      const uint32_t h = __builtin_amdgcn_bitop3_b32(X, Y, kNibK, kB3Hom);
+      const uint32_t neg = __builtin_amdgcn_bitop3_b32(X, Y, kNibK, kB3Neg0);
+      f.m[2 * q + par] = (int)__builtin_amdgcn_bitop3_b32(X, Y, kNibK, kB3Mx);
+      f.h[2 * q + par] = (int)h;
+      f.x[2 * q + par] = (int)((neg << 2) | h);
+    }
+  }
+  return f;
+}
+
+__device__ __forceinline__ void ld_fp4_tile_pipe(const uint32_t* __restrict__ D, int64_t wn,
+                                                 int64_t nv, int64_t I, int64_t J, int32_t window,
+                                                 double r2_min, const LdScratch& sc, lds_t* smem) {
+  constexpr int kBuf = kL * kLStride;
+  lds_t* const sA = smem;
+  lds_t* const sB = smem + 2 * kBuf;
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int wid = t >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  const int g = lane >> 5;
+  const int rl = lane & 31;
+  const int64_t a_lo = I * kL + wr * 32, b_lo = J * kL + wc * 32;
+  const bool active = (b_lo + 31 > a_lo) && (b_lo - (a_lo + 31) <= window) && (b_lo < nv);
+
+  const int lrow = t >> 2;
+  const int lq = (t & 3) * 4;
+  const uint32_t* pa = D + (I * kL + lrow) * wn + lq;
+  const uint32_t* pb = D + (J * kL + lrow) * wn + lq;
+  uint4 ga, gb;
+  const int64_t nch = wn / kLW;
+  auto fetch = [&](int64_t c) {
+    const int64_t kc = (c < nch ? c : nch - 1) * kLW;
+    ga = *reinterpret_cast<const uint4*>(pa + kc);
+    gb = *reinterpret_cast<const uint4*>(pb + kc);
+  };
+  auto lstore = [&](int buf) {
+    lds_st4(&(sA + buf * kBuf)[lrow * kLStride + lq], ga);
+    lds_st4(&(sB + buf * kBuf)[lrow * kLStride + lq], gb);
+  };
+  fetch(0);
+  lstore(0);
+  fetch(1);
+  lstore(1);
+  fetch(2);
+  __syncthreads();
+  if (!active) {
+    for (int64_t k = 0; k < nch; ++k) {
+      __syncthreads();
+      lstore((int)(k & 1));
+      fetch(k + 3);
+    }
+    return;   // nothing after this point synchronises
+  }
+  uint32_t wa[8], wb[8];
+  auto lread = [&](int buf, int h) {
+    const uint4 a = lds_ld4(&(sA + buf * kBuf)[(wr * 32 + rl) * kLStride + g * 8 + 4 * h]);
+    const uint4 b = lds_ld4(&(sB + buf * kBuf)[(wc * 32 + rl) * kLStride + g * 8 + 4 * h]);
+    wa[4 * h] = a.x; wa[4 * h + 1] = a.y; wa[4 * h + 2] = a.z; wa[4 * h + 3] = a.w;
+    wb[4 * h] = b.x; wb[4 * h + 1] = b.y; wb[4 * h + 2] = b.z; wb[4 * h + 3] = b.w;
+  };
+  v16f s_n = (v16f){0}, s_x = (v16f){0}, s_y = (v16f){0};
+  v16f s_xx = (v16f){0}, s_yy = (v16f){0}, s_xy = (v16f){0};
+  lread(0, 0);
+  lread(0, 1);
+  Fp4Feat3 fa = ld_fp4_expand2(wa[0], wa[1]), fb = ld_fp4_expand2(wb[0], wb[1]);
+  for (int64_t k = 0; k < nch; ++k) {
+    const int buf = (int)(k & 1);
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < kLW / 4; ++s) {
+      if (s == 1) {
+        lstore(buf);                                  // chunk k + 2
+        fetch(k + 3);
+      }
+      if (s == 2) lread(buf ^ 1, 0);                  // words 0-3 of chunk k + 1
+      if (s == 3) lread(buf ^ 1, 1);                  // words 4-7
+      const int sn = 2 * ((s + 1) & 3);
+      const Fp4Feat3 na = ld_fp4_expand2(wa[sn], wa[sn + 1]);
+      const Fp4Feat3 nb = ld_fp4_expand2(wb[sn], wb[sn + 1]);
+      s_n = mfma_fp4(fa.m, fb.m, s_n);
+      s_x = mfma_fp4(fa.x, fb.m, s_x);
+      s_y = mfma_fp4(fa.m, fb.x, s_y);
+      s_xx = mfma_fp4(fa.h, fb.m, s_xx);
+      s_yy = mfma_fp4(fa.m, fb.h, s_yy);
+      s_xy = mfma_fp4(fa.x, fb.x, s_xy);
+      if (s == 1) {
+        __builtin_amdgcn_sched_group_barrier(0x200, 2, 0);
+        __builtin_amdgcn_sched_group_barrier(0x020, 2, 0);
+      }
+      if (s >= 2) __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x002, 7, 0);
+      }
+      fa = na;
+      fb = nb;
+    }
+  }
+  // 32x32 accumulator layout: register v of lane l holds row
+  // 8*(v/4) + 4*(l/32) + v%4 and column l%32.
+  for (int v = 0; v < 16; ++v) {
+    const int64_t a = a_lo + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+    const int64_t b = b_lo + (lane & 31);
+    if (!(a < b && b - a <= window && b < nv)) continue;
+    ld_mark(sc, a, b, r2_min, (int64_t)(int)s_n[v], (int64_t)(int)s_x[v], (int64_t)(int)s_y[v],
+            (int64_t)(int)s_xx[v], (int64_t)(int)s_yy[v], (int64_t)(int)s_xy[v]);
+  }
+}
+
 // LDS words each body needs.
 constexpr int kIbsMfmaSmem = 4 * kT * kLdsStride;
 constexpr int kIbsMfmaSimpleSmem = 2 * kT * kLdsStride;

@@ -18,16 +18,17 @@ import torch
 from . import _native as N
 from . import api
 
-IBS_CANDIDATES = {"mfma": N.PG_PATH_MFMA, "mfma_fp4": N.PG_PATH_MFMA | (3 << 8),
-                  "mfma_fp4rep": N.PG_PATH_MFMA | (4 << 8), "mfma_w8": N.PG_PATH_MFMA | (5 << 8),
-                  "mfma_w8nh": N.PG_PATH_MFMA | (6 << 8), "popc": N.PG_PATH_POPC}
+IBS_CANDIDATES = {"mfma": N.PG_PATH_MFMA, "mfma_int8": N.PG_PATH_MFMA | (7 << 8),
+                  "mfma_fp4": N.PG_PATH_MFMA | (3 << 8), "mfma_fp4rep": N.PG_PATH_MFMA | (4 << 8),
+                  "mfma_w8": N.PG_PATH_MFMA | (5 << 8), "popc": N.PG_PATH_POPC}
 # inside a batch every matrix-core problem runs the default body, so only the
 # path is worth choosing there
 IBS_BATCH_CANDIDATES = {"mfma": N.PG_PATH_MFMA, "popc": N.PG_PATH_POPC}
 # batches run the matrix-core and popcount LD tiles; one-problem calls (the
 # serving loop) also have the missing-call correction path
 LD_BATCH_CANDIDATES = {"mfma": N.PG_PATH_MFMA, "popc": N.PG_PATH_POPC}
-LD_CANDIDATES = {"mfma": N.PG_PATH_MFMA, "popc": N.PG_PATH_POPC, "sparse": N.PG_PATH_SPARSE}
+LD_CANDIDATES = {"mfma": N.PG_PATH_MFMA, "mfma_int8": N.PG_PATH_MFMA | (1 << 8),
+                 "popc": N.PG_PATH_POPC, "sparse": N.PG_PATH_SPARSE}
 
 
 def _bucket(x: int) -> int:
@@ -42,11 +43,10 @@ def shape_key(kind: str, m: int, nv: int, window: int | None = None) -> str:
 
 
 def rule_of_thumb(kind: str, m: int, nv: int, window: int | None = None) -> int:
-    """Default without a measurement: the matrix-core path, except for IBS
-    matrices too small to fill 128-sample tiles."""
-    if kind == "ibs" and m <= 128:
-        return N.PG_PATH_POPC
-    return N.PG_PATH_MFMA
+    """Default without a measurement: what the library's PG_PATH_AUTO resolves
+    to for the shape (pg_resolve_path; the matrix-core path at every shape
+    measured)."""
+    return api.resolve_path(kind, m, nv, window or 0, "auto")
 
 
 class Tuner:

@@ -284,3 +284,48 @@ def test_noalloc_rejects_oversized_before_the_device():
     assert "static array" in N.last_error()
     assert lib.pg_ibs_matrix_noalloc(None, None, 0, 0, 0, 0, 0, fake, fake, fake, fake,
                                      None) == N.PG_EINVAL
+
+
+@pytest.mark.parametrize("m,nv", [(1, 1), (64, 5000), (500, 5000), (10000, 100000),
+                                  (20000, 50000), (3, (1 << 24) + 5)])
+def test_resolve_path_ibs(m, nv):
+    """PG_PATH_AUTO resolves to the matrix-core path at every measured IBS
+    shape, kernel variant 8 (pipelined fp4) below 2^24 variants and variant 7
+    (pipelined int8: fp32 sums would no longer be exact) from there; explicit
+    paths and variants pass through, undefined variants become the default."""
+    lib = N.load()
+    out = ctypes.c_int(-1)
+
+    def res(path):
+        assert lib.pg_resolve_path(N.PG_KIND_IBS, m, nv, 0, path, ctypes.byref(out)) == 0
+        return out.value
+
+    fp4 = nv < (1 << 24)
+    default = N.PG_PATH_MFMA | ((8 if fp4 else 7) << 8)
+    assert res(N.PG_PATH_AUTO) == default
+    assert res(N.PG_PATH_MFMA) == default
+    assert res(N.PG_PATH_MFMA | (99 << 8)) == default
+    assert res(N.PG_PATH_MFMA | (9 << 8)) == N.PG_PATH_MFMA | (9 << 8)
+    assert res(N.PG_PATH_MFMA | (3 << 8)) == N.PG_PATH_MFMA | ((3 if fp4 else 7) << 8)
+    assert res(N.PG_PATH_POPC) == N.PG_PATH_POPC
+
+
+@pytest.mark.parametrize("m,nv,w", [(1, 2, 1), (500, 20000, 50), (5000, 500000, 1000),
+                                    (20000, 20000, 1000)])
+def test_resolve_path_ld(m, nv, w):
+    """LD: PG_PATH_AUTO resolves to the matrix-core path (variant 0, the
+    pipelined fp4 tile); variant 1 is the int8 tile; the correction and
+    popcount paths pass through."""
+    lib = N.load()
+    out = ctypes.c_int(-1)
+
+    def res(path):
+        assert lib.pg_resolve_path(N.PG_KIND_LD, m, nv, w, path, ctypes.byref(out)) == 0
+        return out.value
+
+    assert res(N.PG_PATH_AUTO) == N.PG_PATH_MFMA
+    assert res(N.PG_PATH_MFMA | (1 << 8)) == N.PG_PATH_MFMA | (1 << 8)
+    assert res(N.PG_PATH_SPARSE) == N.PG_PATH_SPARSE
+    assert res(N.PG_PATH_POPC) == N.PG_PATH_POPC
+    assert lib.pg_resolve_path(7, m, nv, w, 0, ctypes.byref(out)) == N.PG_EINVAL
+    assert lib.pg_resolve_path(N.PG_KIND_LD, m, nv, 0, 0, ctypes.byref(out)) == N.PG_EINVAL

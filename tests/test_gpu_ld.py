@@ -15,7 +15,7 @@ pg = pytest.importorskip("paper_1410_4803_amd")
 
 from ldcheck import compare_records as _compare
 
-PATHS = ["mfma", "popc", "sparse"]
+PATHS = ["mfma", "popc", "sparse", 2 | (1 << 8)]   # the last: the int8 matrix-core tile
 
 
 def _run(bed, n, W, r2_min, mask=None, **kw):
@@ -139,11 +139,11 @@ def test_ld_large_rows_vs_oracle(ld_large):
     assert total > 0
 
 
-@pytest.mark.parametrize("path", ["popc", "sparse", 3 | (1 << 8)])
+@pytest.mark.parametrize("path", ["popc", "sparse", 3 | (1 << 8), 2 | (1 << 8)])
 def test_ld_large_paths_equal_records(ld_large, path):
     """The popcount path, the correction path (with its default tile rule
-    and with every tile forced onto it) emit the default path's record list
-    at 5,000 x 500,000 byte for byte."""
+    and with every tile forced onto it) and the int8 matrix-core tile emit
+    the default path's record list at 5,000 x 500,000 byte for byte."""
     w, c, ref = ld_large
     got = pg.ld_records(c, w["window"], w["r2_min"], path=path)
     assert len(got) == len(ref)

@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 
 pg = pytest.importorskip("paper_1410_4803_amd")
 
-PATHS = ["mfma", "popc", "sparse"]
+PATHS = ["mfma", "popc", "sparse", 2 | (1 << 8)]   # the last: the int8 matrix-core tile
 
 
 def _gpu(bed, n, W, S, t, mask=None, **kw):
