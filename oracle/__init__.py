@@ -75,6 +75,12 @@ def _load():
         lib.oracle_grm_pairs.restype = None
         lib.oracle_ibs_distance.argtypes = [p, p, p, i64, p]
         lib.oracle_ibs_distance.restype = None
+        lib.oracle_ibs_similarity.argtypes = [p, p, p, i64, p]
+        lib.oracle_ibs_similarity.restype = None
+        lib.oracle_genome_terms.argtypes = [i64, i64, p]
+        lib.oracle_genome_terms.restype = None
+        lib.oracle_genome.argtypes = [p, i64, i64, p, p, p, i64, p, p, p, p]
+        lib.oracle_genome.restype = None
         lib.oracle_cluster_complete.argtypes = [p, i64, p]
         lib.oracle_cluster_complete.restype = i32
         lib.oracle_threads.argtypes = []
@@ -242,6 +248,37 @@ def ibs_distance(ibs0, ibs1, nonmiss) -> np.ndarray:
     _load().oracle_ibs_distance(i0.ctypes.data, i1.ctypes.data, nm.ctypes.data, i0.size,
                                 out.ctypes.data)
     return out
+
+
+def ibs_similarity(ibs1, ibs2, nonmiss) -> np.ndarray:
+    """(2*IBS2 + IBS1) / (2*N) elementwise (NaN where N = 0), same shape."""
+    i1, i2, nm = (_c(x, np.uint32) for x in (ibs1, ibs2, nonmiss))
+    out = np.zeros(i1.shape, dtype=np.float64)
+    _load().oracle_ibs_similarity(i1.ctypes.data, i2.ctypes.data, nm.ctypes.data, i1.size,
+                                  out.ctypes.data)
+    return out
+
+
+def genome_terms(x: int, y: int) -> np.ndarray:
+    """The five expected-IBS-given-IBD terms of one marker with x A2 and y A1
+    alleles observed: P(IBS0|IBD0), P(IBS1|IBD0), P(IBS2|IBD0), P(IBS1|IBD1),
+    P(IBS2|IBD1)."""
+    t = np.zeros(5, dtype=np.float64)
+    _load().oracle_genome_terms(int(x), int(y), t.ctypes.data)
+    return t
+
+
+def genome(codes_vm: np.ndarray, ibs0, ibs1, nonmiss):
+    """(Z0, Z1, Z2, PI_HAT) float64 arrays shaped like the counts: the IBD
+    report for IBS counts computed over the samples and variants of
+    codes_vm."""
+    V, n = codes_vm.shape
+    codes_vm = _c(codes_vm, np.int8)
+    i0, i1, nm = (_c(x, np.uint32) for x in (ibs0, ibs1, nonmiss))
+    outs = [np.zeros(i0.shape, dtype=np.float64) for _ in range(4)]
+    _load().oracle_genome(codes_vm.ctypes.data, n, V, i0.ctypes.data, i1.ctypes.data,
+                          nm.ctypes.data, i0.size, *[o.ctypes.data for o in outs])
+    return tuple(outs)
 
 
 def cluster_complete(dist: np.ndarray) -> np.ndarray:

@@ -454,6 +454,111 @@ void oracle_ibs_distance(const uint32_t* ibs0, const uint32_t* ibs1, const uint3
 }
 
 /*
+ * IBS similarity, the value --distance ibs reports (section "Identity-by-state
+ * matrices, complete linkage clustering" names it without a formula).
+ * Reading: the proportion of alleles shared identical by state over the
+ * jointly non-missing markers, s = (IBS2 + IBS1/2) / N = (2*IBS2 + IBS1) /
+ * (2*N), the correctly rounded quotient of the two integers; NaN when N = 0.
+ */
+void oracle_ibs_similarity(const uint32_t* ibs1, const uint32_t* ibs2, const uint32_t* nonmiss,
+                           int64_t count, double* s) {
+#pragma omp parallel for schedule(static)
+  for (int64_t e = 0; e < count; ++e)
+    s[e] = nonmiss[e] ? (double)(2 * (int64_t)ibs2[e] + ibs1[e]) / (double)(2 * (int64_t)nonmiss[e])
+                      : NAN;
+}
+
+/*
+ * Expected IBS given IBD at one marker (the IBD report, --genome /
+ * --Z-genome, that Table 2 times after the IBS matrix; the paper gives no
+ * formulas, so this is the method-of-moments reading stated here).  The
+ * marker's observed alleles are x copies of A2 and y of A1 (n = x + y >= 4).
+ * Two samples that share no allele IBD carry four alleles drawn without
+ * replacement from these n; with one allele IBD, three (the shared one and
+ * one more each).  Counting the ordered draws:
+ *   t[0] = P(IBS0 | IBD0) = 2 x(x-1) y(y-1) / n(n-1)(n-2)(n-3)
+ *          (opposite homozygotes);
+ *   t[1] = P(IBS1 | IBD0) = 4 [x(x-1)(x-2) y + x y(y-1)(y-2)] / n(n-1)(n-2)(n-3)
+ *          (a homozygote and a heterozygote);
+ *   t[2] = P(IBS2 | IBD0) = [x(x-1)(x-2)(x-3) + y(y-1)(y-2)(y-3)
+ *          + 4 x(x-1) y(y-1)] / n(n-1)(n-2)(n-3)  (the same genotype);
+ *   t[3] = P(IBS1 | IBD1) = 2 [x(x-1) y + x y(y-1)] / n(n-1)(n-2)
+ *          (the two non-shared alleles differ);
+ *   t[4] = P(IBS2 | IBD1) = [x(x-1)(x-2) + y(y-1)(y-2) + x(x-1) y
+ *          + x y(y-1)] / n(n-1)(n-2);
+ * and P(IBS2 | IBD2) = 1.  Evaluated in double exactly as written (products
+ * left to right, the sums in the order shown, then one division).
+ */
+void oracle_genome_terms(int64_t x, int64_t y, double t[5]) {
+  const double X = (double)x, Y = (double)y, n = (double)(x + y);
+  const double d4 = n * (n - 1.0) * (n - 2.0) * (n - 3.0);
+  const double d3 = n * (n - 1.0) * (n - 2.0);
+  const double x2 = X * (X - 1.0), y2 = Y * (Y - 1.0);
+  const double x3 = x2 * (X - 2.0), y3 = y2 * (Y - 2.0);
+  t[0] = 2.0 * x2 * y2 / d4;
+  t[1] = 4.0 * (x3 * Y + X * y3) / d4;
+  t[2] = (x3 * (X - 3.0) + y3 * (Y - 3.0) + 4.0 * x2 * y2) / d4;
+  t[3] = 2.0 * (x2 * Y + X * y2) / d3;
+  t[4] = (x3 + y3 + x2 * Y + X * y2) / d3;
+}
+
+/*
+ * The IBD report for IBS counts over the samples and variants of codes_vm
+ * (variant-major, V rows of n codes): per marker with at least 4 observed
+ * alleles among these samples, the five terms above, summed in increasing
+ * marker order and divided by the number K of such markers (E00, E10, E20,
+ * E11, E21).  For each of `count` pairs with jointly non-missing count N:
+ *   P0 = IBS0 / N,  P1 = IBS1 / N,
+ *   Z0 = min(P0 / E00, 1),
+ *   Z1 = (P1 - Z0 E10) / E11, clamped to [0, 1 - Z0],
+ *   Z2 = (1 - Z0) - Z1,   PI_HAT = 0.5 Z1 + Z2
+ * (the IBS0 and IBS1 moment equations; Z0 + Z1 + Z2 = 1).  All four are NaN
+ * when N = 0, K = 0, E00 = 0 or E11 = 0.
+ */
+void oracle_genome(const int8_t* codes_vm, int64_t n, int64_t V, const uint32_t* ibs0,
+                   const uint32_t* ibs1, const uint32_t* nonmiss, int64_t count, double* z0,
+                   double* z1, double* z2, double* pi_hat) {
+  double S[5] = {0, 0, 0, 0, 0};
+  int64_t K = 0;
+  for (int64_t v = 0; v < V; ++v) {
+    int64_t calls = 0, a2 = 0;
+    for (int64_t k = 0; k < n; ++k) {
+      const int8_t c = codes_vm[v * n + k];
+      if (c == MISSING) continue;
+      calls += 1;
+      a2 += dosage(c);
+    }
+    if (2 * calls < 4) continue;
+    double t[5];
+    oracle_genome_terms(a2, 2 * calls - a2, t);
+    for (int q = 0; q < 5; ++q) S[q] += t[q];
+    K += 1;
+  }
+  const double E00 = S[0] / (double)K, E10 = S[1] / (double)K;
+  const double E11 = S[3] / (double)K;
+  const int ok = K > 0 && E00 != 0.0 && E11 != 0.0;
+#pragma omp parallel for schedule(static)
+  for (int64_t e = 0; e < count; ++e) {
+    if (!ok || nonmiss[e] == 0) {
+      z0[e] = z1[e] = z2[e] = pi_hat[e] = NAN;
+      continue;
+    }
+    const double N = (double)nonmiss[e];
+    const double p0 = (double)ibs0[e] / N, p1 = (double)ibs1[e] / N;
+    double a = p0 / E00;
+    if (a > 1.0) a = 1.0;
+    double b = (p1 - a * E10) / E11;
+    if (b < 0.0) b = 0.0;
+    if (b > 1.0 - a) b = 1.0 - a;
+    const double c = (1.0 - a) - b;
+    z0[e] = a;
+    z1[e] = b;
+    z2[e] = c;
+    pi_hat[e] = 0.5 * b + c;
+  }
+}
+
+/*
  * Complete-linkage agglomerative clustering of m samples from their m x m
  * distance matrix (section "Identity-by-state matrices, complete linkage
  * clustering").  Plain definition: while more than one cluster remains,

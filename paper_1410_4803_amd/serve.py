@@ -197,6 +197,8 @@ class Server:
         self.t0 = time.perf_counter()
         self.peak_used = 0
         self.max_running = 0
+        self.memory_holds = 0               # admissions deferred for memory
+        self._held: Request | None = None
 
     def now(self) -> float:
         return time.perf_counter() - self.t0
@@ -215,6 +217,9 @@ class Server:
         while self.queue and free:
             req = self.queue[0]
             if self.used + req.footprint > self.budget:
+                if self._held is not req:            # count each deferred request once
+                    self.memory_holds += 1
+                    self._held = req
                 break                                # wait for memory (arrival order)
             self.queue.popleft()
             slot = free.pop(0)
@@ -288,7 +293,8 @@ class Server:
             min((r.arrival for r in self.finished), default=0.0)
         out = {"completed": len(self.finished), "rejected": len(self.rejected),
                "throughput_rps": round(len(self.finished) / span, 2) if span > 0 else 0.0,
-               "max_concurrent": self.max_running, "peak_device_bytes": self.peak_used}
+               "max_concurrent": self.max_running, "peak_device_bytes": self.peak_used,
+               "memory_holds": self.memory_holds}
         if len(lat):
             out.update(p50_ms=round(float(np.percentile(lat, 50)) * 1e3, 3),
                        p99_ms=round(float(np.percentile(lat, 99)) * 1e3, 3),

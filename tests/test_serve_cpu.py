@@ -56,6 +56,7 @@ def test_admission_respects_budget_and_slots():
     assert srv.peak_used <= 250_000
     assert be.max_concurrent == 2
     assert be.started == list(range(10))       # arrival order
+    assert stats["memory_holds"] >= 1          # the budget, not the slots, held requests
     assert all(r.result == int(np.arange(100).sum()) + r.rid for r in srv.finished)
     for key in ("p50_ms", "p99_ms", "throughput_rps", "queue_wait_p99_ms"):
         assert key in stats
