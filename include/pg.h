@@ -370,6 +370,55 @@ int pg_ibs_cluster(const uint32_t* ibs0, const uint32_t* ibs1, const uint32_t* n
                    int64_t m, pg_merge* merges, void* workspace, size_t workspace_bytes,
                    void* stream);
 
+/*
+ * IBS similarity and the IBD report (--distance ibs and --Z-genome; the
+ * paper times the IBD report in Table 2 without giving its formulas).
+ *
+ * Similarity, elementwise over `count` entries of pg_ibs_matrix output (any
+ * layout): sim[e] = (2*IBS2 + IBS1) / (2*N), the correctly rounded quotient
+ * of the two integers; NaN when N = 0.  Device arrays.
+ */
+int pg_ibs_similarity(const uint32_t* ibs1, const uint32_t* ibs2, const uint32_t* nonmiss,
+                      int64_t count, double* sim, void* stream);
+
+/* Workspace bytes pg_ibs_genome needs for this selection (sample_idx is not
+ * read: only n_sel matters, 0 = all samples). */
+int pg_genome_workspace_bytes(const pg_genotypes* g, int64_t n_sel, int64_t v_begin,
+                              int64_t v_end, size_t* bytes);
+
+/*
+ * IBD estimates by the method of moments, from IBS counts over the same
+ * samples and variant range (g, sample_idx, n_sel, v_begin, v_end mean what
+ * they mean for pg_ibs_matrix and must be the ones the counts came from).
+ * Reading:
+ *   per marker with n = 2 * (called samples) >= 4 observed alleles, x of
+ *   them A2 and y = n - x A1, the IBS probabilities of two samples that
+ *   share no allele IBD (four alleles drawn without replacement) or one
+ *   (three drawn):
+ *     P(IBS0|IBD0) = 2 x(x-1) y(y-1) / [n(n-1)(n-2)(n-3)]
+ *     P(IBS1|IBD0) = 4 [x(x-1)(x-2) y + x y(y-1)(y-2)] / [n(n-1)(n-2)(n-3)]
+ *     P(IBS1|IBD1) = 2 [x(x-1) y + x y(y-1)] / [n(n-1)(n-2)]
+ *   averaged over those markers (E00, E10, E11; the mean is the sum in
+ *   increasing marker order divided by their number);
+ *   per entry e with N = nonmiss[e] > 0, P0 = ibs0[e]/N, P1 = ibs1[e]/N:
+ *     z0 = min(P0 / E00, 1)
+ *     z1 = (P1 - z0 E10) / E11, clamped to [0, 1 - z0]
+ *     z2 = (1 - z0) - z1,   pi_hat = 0.5 z1 + z2
+ *   NaN in all four outputs when N = 0, when no marker has n >= 4, or when
+ *   E00 or E11 is zero.
+ * Every operation is an IEEE double operation in the order written, so the
+ * results are exactly determined by the counts and the genotypes.
+ * ibs0, ibs1, nonmiss: `count` entries of pg_ibs_matrix output (any layout);
+ * z0, z1, z2, pi_hat: `count` doubles each (device).  Errors: PG_EINVAL for
+ * a bad selection or NULL pointer, PG_ENOMEM for a short workspace.
+ * Stages for pg_profile_events: 1 = per-marker terms and their averages,
+ * 2 = per-pair estimates.
+ */
+int pg_ibs_genome(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_sel,
+                  int64_t v_begin, int64_t v_end, const uint32_t* ibs0, const uint32_t* ibs1,
+                  const uint32_t* nonmiss, int64_t count, double* z0, double* z1, double* z2,
+                  double* pi_hat, void* workspace, size_t workspace_bytes, void* stream);
+
 /* ---- diagnostics -----------------------------------------------------------
  *
  * Measured throughput of the units the kernels are bound by, on the current

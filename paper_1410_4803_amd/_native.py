@@ -30,7 +30,8 @@ SYMBOLS = ("pg_status_str", "pg_last_error", "pg_version", "pg_profile_events",
            "pg_ibs_distance", "pg_cluster_workspace_bytes", "pg_ibs_cluster", "pg_peak_rates",
            "pg_batch_plan", "pg_batch_workspace_bytes", "pg_batch_tiles", "pg_batch_upload",
            "pg_batch_launch", "pg_plan_free", "pg_batch_capture", "pg_graph_launch",
-           "pg_graph_destroy", "pg_ibs_matrix_noalloc", "pg_noalloc_scratch_bytes", "pg_resolve_path")
+           "pg_graph_destroy", "pg_ibs_matrix_noalloc", "pg_noalloc_scratch_bytes", "pg_resolve_path",
+           "pg_ibs_similarity", "pg_genome_workspace_bytes", "pg_ibs_genome")
 PG_KIND_IBS, PG_KIND_LD = 0, 1
 
 LD_PAIR = np.dtype([("a", "<i4"), ("b", "<i4"), ("n", "<i8"), ("sx", "<i8"), ("sy", "<i8"),
@@ -121,6 +122,12 @@ def load():
     lib.pg_cluster_workspace_bytes.restype = ctypes.c_int
     lib.pg_ibs_cluster.argtypes = [p, p, p, i64, p, p, sz, p]
     lib.pg_ibs_cluster.restype = ctypes.c_int
+    lib.pg_ibs_similarity.argtypes = [p, p, p, i64, p, p]
+    lib.pg_ibs_similarity.restype = ctypes.c_int
+    lib.pg_genome_workspace_bytes.argtypes = [gp, i64, i64, i64, ctypes.POINTER(sz)]
+    lib.pg_genome_workspace_bytes.restype = ctypes.c_int
+    lib.pg_ibs_genome.argtypes = [gp, p, i64, i64, i64, p, p, p, i64, p, p, p, p, p, sz, p]
+    lib.pg_ibs_genome.restype = ctypes.c_int
     lib.pg_peak_rates.argtypes = [p, sz, p]
     lib.pg_peak_rates.restype = ctypes.c_int
     pp = ctypes.POINTER(ctypes.c_void_p)

@@ -343,6 +343,65 @@ def ibs_distance(ibs0: torch.Tensor, ibs1: torch.Tensor, nonmiss: torch.Tensor, 
     return out
 
 
+def ibs_similarity(ibs1: torch.Tensor, ibs2: torch.Tensor, nonmiss: torch.Tensor, *,
+                   out=None, stream=None) -> torch.Tensor:
+    """(2*IBS2 + IBS1) / (2*N) elementwise (NaN where N = 0), float64, the
+    shape of the inputs (any pg_ibs_matrix layout)."""
+    for t, name in ((ibs1, "ibs1"), (ibs2, "ibs2"), (nonmiss, "nonmiss")):
+        _require_cuda(t, name, torch.int32)
+    if out is None:
+        with _on(stream):
+            out = torch.empty(ibs1.shape, dtype=torch.float64, device=ibs1.device)
+    _require_cuda(out, "out", torch.float64)
+    if not (ibs1.numel() == ibs2.numel() == nonmiss.numel() == out.numel()):
+        raise ValueError("inputs and output must have the same number of entries")
+    N.check(N.load().pg_ibs_similarity(_ptr(ibs1), _ptr(ibs2), _ptr(nonmiss), ibs1.numel(),
+                                       _ptr(out), _stream_handle(stream)), "pg_ibs_similarity")
+    return out
+
+
+def genome_workspace_bytes(cohort: Cohort, n_sel: int = 0, v_range=None) -> int:
+    vb, ve = (0, 0) if v_range is None else v_range
+    out = ctypes.c_size_t(0)
+    g = cohort.struct()
+    N.check(N.load().pg_genome_workspace_bytes(ctypes.byref(g), n_sel, vb, ve,
+                                               ctypes.byref(out)), "pg_genome_workspace_bytes")
+    return out.value
+
+
+def ibs_genome(cohort: Cohort, ibs0: torch.Tensor, ibs1: torch.Tensor, nonmiss: torch.Tensor,
+               *, sample_idx: torch.Tensor | None = None, v_range=None, out=None,
+               workspace: torch.Tensor | None = None, stream=None):
+    """IBD report (Z0, Z1, Z2, PI_HAT) by the method of moments from the IBS
+    counts of the same selection (pass the sample_idx and v_range the counts
+    were computed with).  Returns four float64 CUDA tensors shaped like ibs0
+    (any pg_ibs_matrix layout)."""
+    lib = N.load()
+    for t, name in ((ibs0, "ibs0"), (ibs1, "ibs1"), (nonmiss, "nonmiss")):
+        _require_cuda(t, name, torch.int32)
+    if not (ibs0.numel() == ibs1.numel() == nonmiss.numel()):
+        raise ValueError("inputs must have the same number of entries")
+    n_sel, vb, ve = _sel(cohort, sample_idx, v_range)
+    dev = cohort.bed.device
+    with _on(stream):
+        if out is None:
+            out = tuple(torch.empty(ibs0.shape, dtype=torch.float64, device=dev)
+                        for _ in range(4))
+        if workspace is None:
+            workspace = torch.empty(max(genome_workspace_bytes(cohort, n_sel, (vb, ve)), 1),
+                                    dtype=torch.uint8, device=dev)
+    for t in out:
+        _require_cuda(t, "out", torch.float64)
+        if t.numel() != ibs0.numel():
+            raise ValueError("outputs must have as many entries as the inputs")
+    g = cohort.struct()
+    N.check(lib.pg_ibs_genome(ctypes.byref(g), _ptr(sample_idx), n_sel, vb, ve, _ptr(ibs0),
+                              _ptr(ibs1), _ptr(nonmiss), ibs0.numel(), *(_ptr(t) for t in out),
+                              _ptr(workspace), workspace.numel(), _stream_handle(stream)),
+            "pg_ibs_genome")
+    return out
+
+
 def cluster_workspace_bytes(m: int) -> int:
     out = ctypes.c_size_t(0)
     N.check(N.load().pg_cluster_workspace_bytes(int(m), ctypes.byref(out)),

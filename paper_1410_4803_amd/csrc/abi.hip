@@ -697,6 +697,75 @@ int pg_ibs_distance(const uint32_t* ibs0, const uint32_t* ibs1, const uint32_t* 
   return launch_ibs_distance(ibs0, ibs1, nonmiss, count, dist, (hipStream_t)stream);
 }
 
+int pg_ibs_similarity(const uint32_t* ibs1, const uint32_t* ibs2, const uint32_t* nonmiss,
+                      int64_t count, double* sim, void* stream) {
+  g_last_error[0] = 0;
+  if (count < 0) return fail(PG_EINVAL, "count < 0");
+  if (count > 0 && (!ibs1 || !ibs2 || !nonmiss || !sim))
+    return fail(PG_EINVAL, "an input or output pointer is NULL");
+  return launch_ibs_similarity(ibs1, ibs2, nonmiss, count, sim, (hipStream_t)stream);
+}
+
+namespace {
+// Variant-major operand of the selection (rows_pad x wn words), the five
+// per-marker term columns, the per-marker flags and the six sums.
+struct GenomePlan {
+  int64_t rows_pad, wn, off_D, off_terms, off_used, off_sums, bytes;
+};
+void plan_genome(const Sel& s, GenomePlan& p) {
+  p.rows_pad = round_up(s.nv, 64);
+  p.wn = ceil_div(s.m, 16);
+  Carve c;
+  p.off_D = c.take(p.rows_pad * p.wn * 4);
+  p.off_terms = c.take(5 * p.rows_pad * 8);
+  p.off_used = c.take(p.rows_pad * 4);
+  p.off_sums = c.take(8 * 8);
+  p.bytes = c.off;
+}
+}  // namespace
+
+int pg_genome_workspace_bytes(const pg_genotypes* g, int64_t n_sel, int64_t v_begin,
+                              int64_t v_end, size_t* bytes) {
+  g_last_error[0] = 0;
+  if (!bytes) return fail(PG_EINVAL, "bytes is NULL");
+  Sel s;
+  const int rc = make_sel(g, n_sel > 0, nullptr, n_sel, v_begin, v_end, s);
+  if (rc != PG_OK) return rc;
+  GenomePlan p;
+  plan_genome(s, p);
+  *bytes = (size_t)p.bytes;
+  return PG_OK;
+}
+
+int pg_ibs_genome(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_sel,
+                  int64_t v_begin, int64_t v_end, const uint32_t* ibs0, const uint32_t* ibs1,
+                  const uint32_t* nonmiss, int64_t count, double* z0, double* z1, double* z2,
+                  double* pi_hat, void* workspace, size_t workspace_bytes, void* stream) {
+  g_last_error[0] = 0;
+  Sel s;
+  int rc = make_sel(g, sample_idx != nullptr, sample_idx, n_sel, v_begin, v_end, s);
+  if (rc != PG_OK) return rc;
+  if (count < 0) return fail(PG_EINVAL, "count < 0");
+  if (count > 0 && (!ibs0 || !ibs1 || !nonmiss || !z0 || !z1 || !z2 || !pi_hat))
+    return fail(PG_EINVAL, "an input or output pointer is NULL");
+  GenomePlan p;
+  plan_genome(s, p);
+  if ((int64_t)workspace_bytes < p.bytes || !workspace)
+    return fail(PG_ENOMEM, "workspace of %llu bytes < %lld required",
+                (unsigned long long)workspace_bytes, (long long)p.bytes);
+  char* ws = (char*)workspace;
+  hipStream_t st = (hipStream_t)stream;
+  mark_stage(0, st);
+  uint32_t* D = (uint32_t*)(ws + p.off_D);
+  rc = launch_variant_major_2bit(s, D, p.rows_pad, p.wn, st);
+  if (rc != PG_OK) return rc;
+  rc = launch_genome(D, p.wn, s.nv, p.rows_pad, (double*)(ws + p.off_terms),
+                     (uint32_t*)(ws + p.off_used), (double*)(ws + p.off_sums), ibs0, ibs1,
+                     nonmiss, count, z0, z1, z2, pi_hat, st);
+  if (rc == PG_OK) mark_stage(2, st);
+  return rc;
+}
+
 namespace {
 struct ClusterPlan {
   int64_t off_D, off_nnd, off_nnj, bytes;

@@ -52,6 +52,176 @@ int launch_ibs_distance(const uint32_t* i0, const uint32_t* i1, const uint32_t* 
   return check_launch("ibs_distance");
 }
 
+// ---- IBS similarity and the IBD report ---------------------------------------
+// Similarity (the --distance ibs value; reading): s = (2 IBS2 + IBS1) / (2 N),
+// the correctly rounded quotient of two integers, NaN when N = 0.
+__global__ __launch_bounds__(256) void k_ibs_similarity(const uint32_t* __restrict__ i1,
+                                                        const uint32_t* __restrict__ i2,
+                                                        const uint32_t* __restrict__ nm,
+                                                        int64_t count, double* __restrict__ s) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t n = nm[e];
+    s[e] = n ? __ddiv_rn((double)(2 * (int64_t)i2[e] + i1[e]), (double)(2 * (int64_t)n))
+             : __longlong_as_double(0x7ff8000000000000ll);
+  }
+}
+
+int launch_ibs_similarity(const uint32_t* i1, const uint32_t* i2, const uint32_t* nm,
+                          int64_t count, double* s, hipStream_t st) {
+  if (count <= 0) return PG_OK;
+  const int64_t blocks = ceil_div(count, 256) < 65536 ? ceil_div(count, 256) : 65536;
+  hipLaunchKernelGGL(k_ibs_similarity, dim3((unsigned)blocks), dim3(256), 0, st, i1, i2, nm,
+                     count, s);
+  return check_launch("ibs_similarity");
+}
+
+// IBD report (reading; the paper times it but gives no formulas).  A marker
+// whose observed alleles among the selected samples are x copies of A2 and y
+// of A1 (n = x + y >= 4) expects, for two samples sharing no allele IBD (four
+// alleles drawn without replacement from those n) or one (three drawn),
+//   P(IBS0|IBD0) = 2 x(x-1) y(y-1) / n(n-1)(n-2)(n-3),
+//   P(IBS1|IBD0) = 4 [x(x-1)(x-2) y + x y(y-1)(y-2)] / n(n-1)(n-2)(n-3),
+//   P(IBS2|IBD0) = [x(x-1)(x-2)(x-3) + y(y-1)(y-2)(y-3) + 4 x(x-1) y(y-1)] / n(n-1)(n-2)(n-3),
+//   P(IBS1|IBD1) = 2 [x(x-1) y + x y(y-1)] / n(n-1)(n-2),
+//   P(IBS2|IBD1) = [x(x-1)(x-2) + y(y-1)(y-2) + x(x-1) y + x y(y-1)] / n(n-1)(n-2).
+// These are averaged over the markers with n >= 4 (E00, E10, E20, E11, E21),
+// and per pair the IBS0 and IBS1 moment equations give
+//   Z0 = min(P0 / E00, 1),  Z1 = (P1 - Z0 E10) / E11 clamped to [0, 1 - Z0],
+//   Z2 = (1 - Z0) - Z1,  PI_HAT = 0.5 Z1 + Z2,  with P0 = IBS0 / N, P1 = IBS1 / N.
+// Every term is evaluated in IEEE double in the order written (explicit
+// round-to-nearest operations, no contraction) and the averages are sums in
+// increasing marker order, so the results are the same doubles any
+// implementation of these formulas in that order gets.
+
+// One wave per marker row of the variant-major operand D (rows_pad x wn
+// words of 16 codes, padding codes missing): counts the calls and A2 alleles,
+// then writes the five terms (0 when n < 4) to terms[q * rows_pad + v] and
+// whether the marker counts to used[v].
+__global__ __launch_bounds__(256) void k_genome_terms(const uint32_t* __restrict__ D, int64_t wn,
+                                                      int64_t nv, int64_t rows_pad,
+                                                      double* __restrict__ terms,
+                                                      uint32_t* __restrict__ used) {
+  const int lane = threadIdx.x & 63;
+  const int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (v >= nv) return;
+  const uint32_t* row = D + v * wn;
+  int64_t calls = 0, a2 = 0;
+  for (int64_t w = lane; w < wn; w += 64) {
+    const uint32_t x = row[w];
+    const uint32_t lo = x & 0x55555555u, hi = (x >> 1) & 0x55555555u;
+    calls += __popc((hi | ~lo) & 0x55555555u);          // codes 00, 10, 11
+    a2 += 2 * __popc(hi & lo) + __popc(hi & ~lo);       // 11 twice, 10 once
+  }
+  for (int d = 32; d > 0; d >>= 1) {
+    calls += __shfl_xor(calls, d, 64);
+    a2 += __shfl_xor(a2, d, 64);
+  }
+  if (lane != 0) return;
+  double t[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const bool ok = 2 * calls >= 4;
+  if (ok) {
+    const double X = (double)a2, Y = (double)(2 * calls - a2), n = (double)(2 * calls);
+    const double d4 = __dmul_rn(__dmul_rn(__dmul_rn(n, __dsub_rn(n, 1.0)), __dsub_rn(n, 2.0)),
+                                __dsub_rn(n, 3.0));
+    const double d3 = __dmul_rn(__dmul_rn(n, __dsub_rn(n, 1.0)), __dsub_rn(n, 2.0));
+    const double x2 = __dmul_rn(X, __dsub_rn(X, 1.0)), y2 = __dmul_rn(Y, __dsub_rn(Y, 1.0));
+    const double x3 = __dmul_rn(x2, __dsub_rn(X, 2.0)), y3 = __dmul_rn(y2, __dsub_rn(Y, 2.0));
+    t[0] = __ddiv_rn(__dmul_rn(__dmul_rn(2.0, x2), y2), d4);
+    t[1] = __ddiv_rn(__dmul_rn(4.0, __dadd_rn(__dmul_rn(x3, Y), __dmul_rn(X, y3))), d4);
+    t[2] = __ddiv_rn(__dadd_rn(__dadd_rn(__dmul_rn(x3, __dsub_rn(X, 3.0)),
+                                         __dmul_rn(y3, __dsub_rn(Y, 3.0))),
+                               __dmul_rn(__dmul_rn(4.0, x2), y2)),
+                     d4);
+    t[3] = __ddiv_rn(__dmul_rn(2.0, __dadd_rn(__dmul_rn(x2, Y), __dmul_rn(X, y2))), d3);
+    t[4] = __ddiv_rn(__dadd_rn(__dadd_rn(__dadd_rn(x3, y3), __dmul_rn(x2, Y)), __dmul_rn(X, y2)),
+                     d3);
+  }
+#pragma unroll
+  for (int q = 0; q < 5; ++q) terms[q * rows_pad + v] = t[q];
+  used[v] = ok ? 1u : 0u;
+}
+
+// The five sums in increasing marker order (thread q sums term q; a marker
+// that does not count adds +0.0, which leaves a non-negative sum unchanged)
+// and the count K of markers that count; out = {S00, S10, S20, S11, S21, K}.
+__global__ __launch_bounds__(64) void k_genome_sums(const double* __restrict__ terms,
+                                                    const uint32_t* __restrict__ used, int64_t nv,
+                                                    int64_t rows_pad, double* __restrict__ out) {
+  const int q = threadIdx.x;
+  if (q > 5) return;
+  if (q == 5) {
+    int64_t K = 0;
+    for (int64_t v = 0; v < nv; ++v) K += used[v];
+    out[5] = (double)K;
+    return;
+  }
+  const double* t = terms + q * rows_pad;
+  double S = 0.0;
+  int64_t v = 0;
+  for (; v + 8 <= nv; v += 8) {
+    double b[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) b[u] = t[v + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) S = __dadd_rn(S, b[u]);
+  }
+  for (; v < nv; ++v) S = __dadd_rn(S, t[v]);
+  out[q] = S;
+}
+
+__global__ __launch_bounds__(256) void k_genome_pairs(const double* __restrict__ sums,
+                                                      const uint32_t* __restrict__ i0,
+                                                      const uint32_t* __restrict__ i1,
+                                                      const uint32_t* __restrict__ nm,
+                                                      int64_t count, double* __restrict__ z0,
+                                                      double* __restrict__ z1,
+                                                      double* __restrict__ z2,
+                                                      double* __restrict__ pi) {
+  const double K = sums[5];
+  const double E00 = __ddiv_rn(sums[0], K), E10 = __ddiv_rn(sums[1], K);
+  const double E11 = __ddiv_rn(sums[3], K);
+  const bool ok = K > 0.0 && E00 != 0.0 && E11 != 0.0;
+  const double nan = __longlong_as_double(0x7ff8000000000000ll);
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    if (!ok || nm[e] == 0) {
+      z0[e] = z1[e] = z2[e] = pi[e] = nan;
+      continue;
+    }
+    const double N = (double)nm[e];
+    const double p0 = __ddiv_rn((double)i0[e], N), p1 = __ddiv_rn((double)i1[e], N);
+    double a = __ddiv_rn(p0, E00);
+    if (a > 1.0) a = 1.0;
+    double b = __ddiv_rn(__dsub_rn(p1, __dmul_rn(a, E10)), E11);
+    if (b < 0.0) b = 0.0;
+    if (b > __dsub_rn(1.0, a)) b = __dsub_rn(1.0, a);
+    const double c = __dsub_rn(__dsub_rn(1.0, a), b);
+    z0[e] = a;
+    z1[e] = b;
+    z2[e] = c;
+    pi[e] = __dadd_rn(__dmul_rn(0.5, b), c);
+  }
+}
+
+int launch_genome(const uint32_t* D, int64_t wn, int64_t nv, int64_t rows_pad, double* terms,
+                  uint32_t* used, double* sums, const uint32_t* i0, const uint32_t* i1,
+                  const uint32_t* nm, int64_t count, double* z0, double* z1, double* z2,
+                  double* pi, hipStream_t st) {
+  hipLaunchKernelGGL(k_genome_terms, dim3((unsigned)ceil_div(nv, 4)), dim3(256), 0, st, D, wn, nv,
+                     rows_pad, terms, used);
+  int rc = check_launch("genome_terms");
+  if (rc != PG_OK) return rc;
+  hipLaunchKernelGGL(k_genome_sums, dim3(1), dim3(64), 0, st, terms, used, nv, rows_pad, sums);
+  rc = check_launch("genome_sums");
+  mark_stage(1, st);
+  if (rc != PG_OK || count <= 0) return rc;
+  const int64_t blocks = ceil_div(count, 256) < 65536 ? ceil_div(count, 256) : 65536;
+  hipLaunchKernelGGL(k_genome_pairs, dim3((unsigned)blocks), dim3(256), 0, st, sums, i0, i1, nm,
+                     count, z0, z1, z2, pi);
+  return check_launch("genome_pairs");
+}
+
 // (value, index) minimum with the smaller index on equal values.
 __device__ __forceinline__ void take_min(double& bv, int& bi, double v, int i) {
   if (v < bv || (v == bv && (unsigned)i < (unsigned)bi)) {

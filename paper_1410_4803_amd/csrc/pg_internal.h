@@ -348,6 +348,16 @@ inline int64_t grm_part_bytes(int64_t rows_pad, int64_t wp) {
 // ---- IBS distance and clustering (cluster.hip) ------------------------------
 int launch_ibs_distance(const uint32_t* i0, const uint32_t* i1, const uint32_t* nm, int64_t count,
                         double* d, hipStream_t st);
+int launch_ibs_similarity(const uint32_t* i1, const uint32_t* i2, const uint32_t* nm,
+                          int64_t count, double* s, hipStream_t st);
+// IBD report from the variant-major operand D of the selection (rows_pad x
+// wn words): terms 5 x rows_pad doubles, used rows_pad words, sums 6 doubles
+// of workspace; then `count` pairs of IBS counts.  Stage 1 ends after the
+// per-marker averages.
+int launch_genome(const uint32_t* D, int64_t wn, int64_t nv, int64_t rows_pad, double* terms,
+                  uint32_t* used, double* sums, const uint32_t* i0, const uint32_t* i1,
+                  const uint32_t* nm, int64_t count, double* z0, double* z1, double* z2,
+                  double* pi, hipStream_t st);
 // D: m x m doubles; nn_d: m doubles; nn_j: m ints.
 int launch_ibs_cluster(const uint32_t* i0, const uint32_t* i1, const uint32_t* nm, int64_t m,
                        double* D, double* nn_d, int* nn_j, pg_merge* merges, hipStream_t st);
