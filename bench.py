@@ -253,6 +253,36 @@ def bench_cluster(torch, lib, hip, pg, wc, dev, steps):
                           "merge_loop": round(mean(st[1]), 3)}}
 
 
+def bench_genome(torch, lib, hip, pg, cohort, counts, dev, steps):
+    """IBS similarity and the IBD report over the default workload's full
+    10,000 x 10,000 counts.  The report's per-pair kernel is bound by HBM:
+    per entry it reads three uint32 counts and writes four doubles (44 B);
+    the similarity reads three counts and writes one double (20 B)."""
+    i0, i1, i2, nm = counts
+    n = i0.shape[0]
+    z = tuple(torch.empty((n, n), dtype=torch.float64, device=dev) for _ in range(4))
+    ws = torch.empty(pg.genome_workspace_bytes(cohort), dtype=torch.uint8, device=dev)
+    ms, st = timed_steps(torch, lib, hip, lambda: pg.ibs_genome(
+        cohort, i0, i1, nm, out=z, workspace=ws), steps, 2, 3)
+    pairs_ms = mean(st[1])
+    gbs = 44.0 * n * n / (pairs_ms * 1e-3) / 1e9
+    sim = z[0]
+    ms_s, _ = timed_steps(torch, lib, hip, lambda: pg.ibs_similarity(i1, i2, nm, out=sim),
+                          steps, 2, 0)
+    gbs_s = 20.0 * n * n / (ms_s * 1e-3) / 1e9
+    torch.cuda.synchronize()
+    assert bool((torch.diagonal(z[2]) == 1.0).all())
+    return {"samples": n, "ms_per_call": round(ms, 3), "unit": "ms",
+            "stages_ms": {"layout_terms_and_averages": round(mean(st[0]), 3),
+                          "pair_estimates": round(pairs_ms, 3)},
+            "roofline": {"bound": "hbm", "kernel": "k_genome_pairs", "unit": "GB/s",
+                         "bytes_per_entry": 44, "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                         "frac": round(gbs / PEAK_HBM_GBS, 4)},
+            "similarity": {"ms_per_call": round(ms_s, 3), "bytes_per_entry": 20,
+                           "achieved_gbs": round(gbs_s, 1),
+                           "frac": round(gbs_s / PEAK_HBM_GBS, 4)}}
+
+
 def cpu_baseline_cluster(wc):
     """The oracle's O(m^3) complete linkage on the same distances."""
     import oracle
@@ -499,7 +529,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--quick", action="store_true", help="default workload only, no extras")
     ap.add_argument("--extras", default="all",
-                    help="comma list of extras: other,int8,small,ld,prune,grm,cluster,peaks,batch,serve "
+                    help="comma list of extras: other,int8,small,ld,prune,grm,cluster,genome,peaks,batch,"
+                         "serve "
                          "(or all / none)")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--serve-seconds", type=float, default=60.0)
@@ -594,15 +625,21 @@ def main():
     torch.cuda.synchronize()
     i0, i1, i2, nm = out
     assert torch.equal(i0 + i1 + i2, nm) and torch.equal(nm, nm.T)
-    del out, call
+    del i0, i1, i2, nm, call
 
     extras = {}
     want = set()
     if not args.quick:
-        everything = {"other", "int8", "small", "ld", "prune", "grm", "cluster", "peaks", "batch",
-                      "serve"}
+        everything = {"other", "int8", "small", "ld", "prune", "grm", "cluster", "genome", "peaks",
+                      "batch", "serve"}
         want = everything if args.extras == "all" else \
             set(x for x in args.extras.split(",") if x and x != "none")
+    if "genome" in want:
+        log("timing the IBD report and the similarity on the full counts")
+        extras["genome_" + w["name"]] = bench_genome(torch, lib, hip, pg, cohort, out, dev,
+                                                     max(3, args.steps // 2))
+    del out
+    torch.cuda.empty_cache()
     if "other" in want:
         other = "popc" if path == "mfma" else "mfma"
         call2, out2 = ibs_runner(other)
@@ -753,11 +790,13 @@ def main():
         torch.cuda.empty_cache()
 
     if args.copy_calibration:
-        # plain device copy of exactly 1 GiB, for the HBM byte counters
-        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        # an elementwise kernel that reads exactly 1 GiB and writes 1 GiB, for the
+        # HBM byte counters (a plain tensor copy may go to the DMA engines,
+        # which the kernel counters do not see)
+        src = torch.zeros(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
 

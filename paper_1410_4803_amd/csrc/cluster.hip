@@ -142,32 +142,60 @@ __global__ __launch_bounds__(256) void k_genome_terms(const uint32_t* __restrict
   used[v] = ok ? 1u : 0u;
 }
 
-// The five sums in increasing marker order (thread q sums term q; a marker
-// that does not count adds +0.0, which leaves a non-negative sum unchanged)
-// and the count K of markers that count; out = {S00, S10, S20, S11, S21, K}.
-__global__ __launch_bounds__(64) void k_genome_sums(const double* __restrict__ terms,
+// The five sums in increasing marker order and the count K of markers that
+// count; out = {S00, S10, S20, S11, S21, K}.  One block: all threads stage a
+// chunk of the five term columns in LDS (coalesced loads, many in flight),
+// then threads 0..4 each add their column's chunk in order; a marker that
+// does not count, and the padding past the last marker, add +0.0, which
+// leaves a non-negative sum unchanged.  K is an integer count, summed in any
+// order.
+constexpr int kSumChunk = 1024;
+constexpr int kSumPer = 5 * kSumChunk / 256;      // staged values per thread
+__global__ __launch_bounds__(256) void k_genome_sums(const double* __restrict__ terms,
                                                     const uint32_t* __restrict__ used, int64_t nv,
                                                     int64_t rows_pad, double* __restrict__ out) {
-  const int q = threadIdx.x;
-  if (q > 5) return;
-  if (q == 5) {
-    int64_t K = 0;
-    for (int64_t v = 0; v < nv; ++v) K += used[v];
-    out[5] = (double)K;
-    return;
-  }
-  const double* t = terms + q * rows_pad;
+  __shared__ double buf[5][kSumChunk + 1];
+  __shared__ unsigned long long kcount;
+  const int t = threadIdx.x;
+  if (t == 0) kcount = 0;
   double S = 0.0;
-  int64_t v = 0;
-  for (; v + 8 <= nv; v += 8) {
-    double b[8];
+  unsigned long long K = 0;
+  // the next chunk is loaded into registers while the current one is summed
+  double nxt[kSumPer];
+  auto fetch = [&](int64_t c0) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) b[u] = t[v + u];
+    for (int r = 0; r < kSumPer; ++r) {
+      const int i = t + 256 * r, q = i / kSumChunk, j = i % kSumChunk;
+      nxt[r] = c0 + j < nv ? terms[q * rows_pad + c0 + j] : 0.0;
+    }
+  };
+  fetch(0);
+  for (int64_t c0 = 0; c0 < nv; c0 += kSumChunk) {
+    const int64_t len = nv - c0 < kSumChunk ? nv - c0 : kSumChunk;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) S = __dadd_rn(S, b[u]);
+    for (int r = 0; r < kSumPer; ++r) {
+      const int i = t + 256 * r;
+      buf[i / kSumChunk][i % kSumChunk] = nxt[r];
+    }
+    for (int64_t j = t; j < len; j += 256) K += used[c0 + j];
+    __syncthreads();
+    if (c0 + kSumChunk < nv) fetch(c0 + kSumChunk);
+    if (t < 5) {
+      const double* col = buf[t];
+      for (int j = 0; j < len; j += 32) {
+        double b[32];
+#pragma unroll
+        for (int u = 0; u < 32; ++u) b[u] = col[j + u];
+#pragma unroll
+        for (int u = 0; u < 32; ++u) S = __dadd_rn(S, b[u]);
+      }
+    }
+    __syncthreads();
   }
-  for (; v < nv; ++v) S = __dadd_rn(S, t[v]);
-  out[q] = S;
+  atomicAdd(&kcount, K);
+  __syncthreads();
+  if (t < 5) out[t] = S;
+  if (t == 5) out[5] = (double)kcount;
 }
 
 __global__ __launch_bounds__(256) void k_genome_pairs(const double* __restrict__ sums,
@@ -212,7 +240,7 @@ int launch_genome(const uint32_t* D, int64_t wn, int64_t nv, int64_t rows_pad, d
                      rows_pad, terms, used);
   int rc = check_launch("genome_terms");
   if (rc != PG_OK) return rc;
-  hipLaunchKernelGGL(k_genome_sums, dim3(1), dim3(64), 0, st, terms, used, nv, rows_pad, sums);
+  hipLaunchKernelGGL(k_genome_sums, dim3(1), dim3(256), 0, st, terms, used, nv, rows_pad, sums);
   rc = check_launch("genome_sums");
   mark_stage(1, st);
   if (rc != PG_OK || count <= 0) return rc;

@@ -812,8 +812,11 @@ __device__ __forceinline__ void fp4_step(Fp4Acc& acc, const Fp4Feat (&fa)[2],
     for (int b = 0; b < 2; ++b) acc.hc[a][b] = mfma_fp4(fa[a].c, fb[b].c, acc.hc[a][b]);
 }
 
+// zshift: 1 when the hc accumulator holds 2 IBS0 (G_h - G_c), 0 when it
+// holds IBS0 (the opposite-homozygote Gram set).
 __device__ __forceinline__ void fp4_epilogue(const Fp4Acc& acc, const IbsOut& o, int64_t I,
-                                             int64_t J, int wr, int wc, int lane) {
+                                             int64_t J, int wr, int wc, int lane,
+                                             int zshift = 1) {
   const bool mirror = (I != J);
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -823,7 +826,7 @@ __device__ __forceinline__ void fp4_epilogue(const Fp4Acc& acc, const IbsOut& o,
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         n[v] = (uint32_t)(int)acc.m[a][b][v];
-        z[v] = (uint32_t)(int)acc.hc[a][b][v] >> 1;
+        z[v] = (uint32_t)(int)acc.hc[a][b][v] >> zshift;
         one[v] = (n[v] - (uint32_t)(int)acc.w[a][b][v]) >> 1;
       }
       store_block(o, I * kT + wr * 64 + a * 32, J * kT + wc * 64 + b * 32 + (lane & 31), mirror,
@@ -922,54 +925,83 @@ __device__ __forceinline__ void ibs_fp4_tile(const uint32_t* __restrict__ T, int
   fp4_epilogue(acc, o, I, J, wr, wc, lane);
 }
 
-// Pipelined fp4 tile (variant 8): ibs_mfma_tile_pipe's schedule with the
-// fp4 Grams of ibs_fp4_tile.  One MFMA lane takes two 2-bit words (32
-// variants) per step, so a chunk is four steps; the fetch and LDS store of
-// chunk k + 2 happen at step 1, the reads of chunk k + 1 at steps 2 (words
-// 0-3) and 3 (words 4-7).
+// Pipelined fp4 tile (variant 8, the default): ibs_mfma_tile_pipe's
+// schedule on the fp4 matrix cores, with a cheaper Gram set than
+// ibs_fp4_tile.  One MFMA lane takes two 2-bit words (32 variants) per step,
+// so a chunk is four steps; the fetch and LDS store of chunk k + 2 happen at
+// step 1, the reads of chunk k + 1 at steps 2 (words 0-3) and 3 (words 4-7).
+//
+// Grams: features m = [called], w = +1 homozygote / -1 heterozygote,
+// a1 = [homozygous A1], a2 = [homozygous A2] (all 0 when missing), the same
+// on both sides:
+//   N = G(m, m),  IBS1 = (N - G(w, w)) / 2,  IBS0 = G(a2, a1) + G(a1, a2),
+// the two products of IBS0 sharing one accumulator.  Of the four-product
+// sets that fit three accumulators this one needs the fewest bit operations:
+// only w carries a sign.
 //
 // Expansion of one word w (code j at bits 2j, 2j + 1) into the nibbles of
 // its even codes (nibble n = code 2n) and of its odd codes (nibble n = code
 // 2n + 1): with X holding each code's high bit and Y its low bit at bit 1 of
 // the code's nibble (even: X = w, Y = w << 1; odd: X = w >> 2, Y = w >> 1)
 // and K = bit 1 of every nibble,
-//   m = K & (X | ~Y),  w = m | (K & X & ~Y) << 2,  h = K & ~(X ^ Y),
-//   c = h | (K & ~X & ~Y) << 2  (A side),  -c = h | (K & X & Y) << 2  (B side);
+//   m = K & (X | ~Y),  w = m | (K & X & ~Y) << 2,  a1 = K & ~X & ~Y,
+//   a2 = K & X & Y;
 // bits 0, 2 of every nibble stay 0 and bit 3 is the sign, so every value is
-// 0 or +-1.0 in e2m1.  The even nibbles of a word fill one dword of a
-// feature and the odd nibbles the next; A and B use the same order.
+// 0 or +-1.0 in e2m1: four v_bitop3 and one shift-or per parity of a word.
+// The even nibbles of a word fill one dword of a feature and the odd nibbles
+// the next; A and B use the same order.
 constexpr uint32_t kNibK = 0x22222222u;
 constexpr int kB3Mx = 0xa2;   // K & (X | ~Y): S0 = X, S1 = Y, S2 = K
 constexpr int kB3Het = 0x20;  // K & X & ~Y
 constexpr int kB3Hom = 0x82;  // K & ~(X ^ Y)
-constexpr int kB3Neg0 = 0x02; // K & ~X & ~Y
-constexpr int kB3Neg3 = 0x80; // K & X & Y
+constexpr int kB3A1 = 0x02;   // K & ~X & ~Y
+constexpr int kB3A2 = 0x80;   // K & X & Y
 
-__device__ __forceinline__ void fp4_parity(uint32_t X, uint32_t Y, bool b_side, uint32_t& m,
-                                           uint32_t& w, uint32_t& h, uint32_t& c) {
+__device__ __forceinline__ void fp4_parity(uint32_t X, uint32_t Y, uint32_t& m, uint32_t& w,
+                                           uint32_t& a1, uint32_t& a2) {
   m = __builtin_amdgcn_bitop3_b32(X, Y, kNibK, kB3Mx);
   const uint32_t het = __builtin_amdgcn_bitop3_b32(X, Y, kNibK, kB3Het);
   w = (het << 2) | m;
-  h = __builtin_amdgcn_bitop3_b32(X, Y, kNibK, kB3Hom);
-  const uint32_t neg = b_side ? __builtin_amdgcn_bitop3_b32(X, Y, kNibK, kB3Neg3)
-                              : __builtin_amdgcn_bitop3_b32(X, Y, kNibK, kB3Neg0);
-  c = (neg << 2) | h;
+  a1 = __builtin_amdgcn_bitop3_b32(X, Y, kNibK, kB3A1);
+  a2 = __builtin_amdgcn_bitop3_b32(X, Y, kNibK, kB3A2);
 }
 
-__device__ __forceinline__ Fp4Feat fp4_expand2(uint32_t w0, uint32_t w1, bool b_side) {
+// Features of two words, stored in Fp4Feat as m, w, h = a1, c = a2.
+__device__ __forceinline__ Fp4Feat fp4_expand2(uint32_t w0, uint32_t w1) {
   Fp4Feat f;
   f.m = (v8i){0}; f.w = (v8i){0}; f.h = (v8i){0}; f.c = (v8i){0};
   const uint32_t ws[2] = {w0, w1};
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
-    uint32_t m, w, h, c;
-    fp4_parity(ws[q], ws[q] << 1, b_side, m, w, h, c);
-    f.m[2 * q] = (int)m; f.w[2 * q] = (int)w; f.h[2 * q] = (int)h; f.c[2 * q] = (int)c;
-    fp4_parity(ws[q] >> 2, ws[q] >> 1, b_side, m, w, h, c);
-    f.m[2 * q + 1] = (int)m; f.w[2 * q + 1] = (int)w; f.h[2 * q + 1] = (int)h;
-    f.c[2 * q + 1] = (int)c;
+    uint32_t m, w, a1, a2;
+    fp4_parity(ws[q], ws[q] << 1, m, w, a1, a2);
+    f.m[2 * q] = (int)m; f.w[2 * q] = (int)w; f.h[2 * q] = (int)a1; f.c[2 * q] = (int)a2;
+    fp4_parity(ws[q] >> 2, ws[q] >> 1, m, w, a1, a2);
+    f.m[2 * q + 1] = (int)m; f.w[2 * q + 1] = (int)w; f.h[2 * q + 1] = (int)a1;
+    f.c[2 * q + 1] = (int)a2;
   }
   return f;
+}
+
+// acc.hc accumulates IBS0 itself here.
+__device__ __forceinline__ void fp4_step_opp(Fp4Acc& acc, const Fp4Feat (&fa)[2],
+                                             const Fp4Feat (&fb)[2]) {
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc.m[a][b] = mfma_fp4(fa[a].m, fb[b].m, acc.m[a][b]);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc.w[a][b] = mfma_fp4(fa[a].w, fb[b].w, acc.w[a][b]);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc.hc[a][b] = mfma_fp4(fa[a].c, fb[b].h, acc.hc[a][b]);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc.hc[a][b] = mfma_fp4(fa[a].h, fb[b].c, acc.hc[a][b]);
 }
 
 __device__ __forceinline__ void ibs_fp4_tile_pipe(const uint32_t* __restrict__ T, int64_t wp,
@@ -1035,10 +1067,10 @@ __device__ __forceinline__ void ibs_fp4_tile_pipe(const uint32_t* __restrict__ T
   lread(0, 0);
   lread(0, 1);
   Fp4Feat fa[2], fb[2];
-  fa[0] = fp4_expand2(wa[0][0], wa[0][1], false);
-  fa[1] = fp4_expand2(wa[1][0], wa[1][1], false);
-  fb[0] = fp4_expand2(wb[0][0], wb[0][1], true);
-  fb[1] = fp4_expand2(wb[1][0], wb[1][1], true);
+  fa[0] = fp4_expand2(wa[0][0], wa[0][1]);
+  fa[1] = fp4_expand2(wa[1][0], wa[1][1]);
+  fb[0] = fp4_expand2(wb[0][0], wb[0][1]);
+  fb[1] = fp4_expand2(wb[1][0], wb[1][1]);
   for (int64_t k = 0; k < nch; ++k) {
     const int buf = (int)(k & 1);
     __syncthreads();
@@ -1052,11 +1084,11 @@ __device__ __forceinline__ void ibs_fp4_tile_pipe(const uint32_t* __restrict__ T
       if (s == 3) lread(buf ^ 1, 1);                  // words 4-7
       const int sn = 2 * ((s + 1) & 3);               // next step's first word
       Fp4Feat na[2], nb[2];
-      na[0] = fp4_expand2(wa[0][sn], wa[0][sn + 1], false);
-      na[1] = fp4_expand2(wa[1][sn], wa[1][sn + 1], false);
-      nb[0] = fp4_expand2(wb[0][sn], wb[0][sn + 1], true);
-      nb[1] = fp4_expand2(wb[1][sn], wb[1][sn + 1], true);
-      fp4_step(acc, fa, fb);
+      na[0] = fp4_expand2(wa[0][sn], wa[0][sn + 1]);
+      na[1] = fp4_expand2(wa[1][sn], wa[1][sn + 1]);
+      nb[0] = fp4_expand2(wb[0][sn], wb[0][sn + 1]);
+      nb[1] = fp4_expand2(wb[1][sn], wb[1][sn + 1]);
+      fp4_step_opp(acc, fa, fb);
       if (s == 1) {
         __builtin_amdgcn_sched_group_barrier(0x200, 4, 0);
         __builtin_amdgcn_sched_group_barrier(0x020, 4, 0);
@@ -1081,11 +1113,11 @@ __device__ __forceinline__ void ibs_fp4_tile_pipe(const uint32_t* __restrict__ T
           int32_t* q = part + ((a * 2 + b) * 48 + v) * 256 + t;
           q[0] = (int32_t)acc.m[a][b][v];
           q[16 * 256] = (int32_t)acc.w[a][b][v];
-          q[32 * 256] = (int32_t)acc.hc[a][b][v];
+          q[32 * 256] = 2 * (int32_t)acc.hc[a][b][v];   // 2 IBS0, as G_h - G_c
         }
     return;
   }
-  fp4_epilogue(acc, o, I, J, wr, wc, lane);
+  fp4_epilogue(acc, o, I, J, wr, wc, lane, 0);
 }
 
 // ---- matrix-core path, fp4 operands from the replicated layout ----------------------
@@ -1434,7 +1466,7 @@ __device__ __forceinline__ Fp4Feat3 ld_fp4_expand2(uint32_t w0, uint32_t w1) {
       const uint32_t X = par ? ws[q] >> 2 : ws[q];
       const uint32_t Y = par ? ws[q] >> 1 : ws[q] << 1;
       const uint32_t h = __builtin_amdgcn_bitop3_b32(X, Y, kNibK, kB3Hom);
-      const uint32_t neg = __builtin_amdgcn_bitop3_b32(X, Y, kNibK, kB3Neg0);
+      const uint32_t neg = __builtin_amdgcn_bitop3_b32(X, Y, kNibK, kB3A1);
       f.m[2 * q + par] = (int)__builtin_amdgcn_bitop3_b32(X, Y, kNibK, kB3Mx);
       f.h[2 * q + par] = (int)h;
       f.x[2 * q + par] = (int)((neg << 2) | h);
