@@ -176,8 +176,7 @@ int launch_ibs_mfma(const uint32_t* T, int64_t wp, const IbsOut& o, int variant,
 // CUs times the chunks per block) plus, when split, reduce_cost per tile and
 // range (reading its partial sums back); the split steps to more ranges only
 // where that saves 5%.  Grids of 512 tiles or more (two rounds and up) are
-// not split: their last round is already a small part, and a measured split
-// of it gained nothing.
+// left to the tail split below.
 inline void split_ranges(int64_t tiles, int64_t chunks, int64_t min_cps, int64_t max_split,
                          double reduce_cost, int64_t& n_split, int64_t& cps) {
   n_split = 1;
@@ -207,11 +206,26 @@ inline void ibs_split(int64_t rows_pad, int64_t wp, int64_t& n_split, int64_t& c
   const int64_t nt = rows_pad / kIbsMfmaTile;
   split_ranges(nt * (nt + 1) / 2, wp / kIbsMfmaKWords, 2, 32, 0.02, n_split, cps);
 }
+// Tail split of the whole-tile launch (grids too large for ibs_split).  The
+// tiles, in the banded order without empty positions, are cut into 8
+// contiguous runs of equal length (+-1), one per XCD; the head of each run
+// -- `head` tiles, whole rounds of the XCD's 32 CUs -- runs whole tiles, and
+// the rest of the run (at most rmax tiles) runs as n_split K ranges of cps
+// chunks each, whose raw sums a reduce kernel adds in range order.
+// tail == false: no tail split.
+struct IbsTail {
+  bool tail = false;
+  int64_t head = 0, rmax = 0, n_split = 1, cps = 0;
+  int64_t start[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // run x = [start[x], start[x + 1])
+};
+IbsTail ibs_tail_plan(int64_t rows_pad, int64_t wp);
 inline int64_t ibs_part_bytes(int64_t rows_pad, int64_t wp) {
   int64_t n_split, cps;
   ibs_split(rows_pad, wp, n_split, cps);
   const int64_t nt = rows_pad / kIbsMfmaTile;
-  return n_split > 1 ? n_split * (nt * (nt + 1) / 2) * 192 * 256 * 4 : 0;
+  if (n_split > 1) return n_split * (nt * (nt + 1) / 2) * 192 * 256 * 4;
+  const IbsTail t = ibs_tail_plan(rows_pad, wp);
+  return t.tail ? 8 * t.rmax * t.n_split * 192 * 256 * 4 : 0;
 }
 int launch_ibs_fp4rep(const uint32_t* R, int64_t rp, const IbsOut& o, hipStream_t st);
 int launch_ibs_popc(const uint32_t* P, int64_t rows_pad, int64_t words_pad, const IbsOut& o,

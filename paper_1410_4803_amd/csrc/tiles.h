@@ -94,6 +94,38 @@ __device__ __forceinline__ bool band_tile(int64_t b, int64_t nt, int64_t& I, int
   return I < nt && J < nt && J >= I;
 }
 
+// The same banded order without the empty positions: valid tile v (0 <=
+// v < nt(nt+1)/2) -> (I, J).  Band P has r = min(4, nt - 4P) rows; its
+// first r columns hold 1, 2, .., r tiles (the diagonal block's upper
+// triangle) and every later column r, so the band holds
+// r(r+1)/2 + r(nt - 4P - r) tiles; within a column the rows ascend.
+__host__ __device__ __forceinline__ void valid_band_tile(int64_t v, int64_t nt, int64_t& I,
+                                                         int64_t& J) {
+  int64_t P = 0, base = 0;
+  for (;;) {
+    const int64_t r = nt - 4 * P < 4 ? nt - 4 * P : 4;
+    const int64_t tri = r * (r + 1) / 2;
+    const int64_t cnt = tri + r * (nt - 4 * P - r);
+    if (v < base + cnt || 4 * (P + 1) >= nt) {
+      int64_t u = v - base, d, row;
+      if (u < tri) {
+        d = 0;
+        while ((d + 1) * (d + 2) / 2 <= u) ++d;
+        row = u - d * (d + 1) / 2;
+      } else {
+        u -= tri;
+        d = r + u / r;
+        row = u % r;
+      }
+      I = 4 * P + row;
+      J = 4 * P + d;
+      return;
+    }
+    base += cnt;
+    ++P;
+  }
+}
+
 // Blocks are handed to the 8 XCDs round-robin (block b runs on XCD b % 8);
 // remap so each XCD takes a contiguous run of the tile order (for the first
 // 8*(B/8) blocks) and its L2 sees neighbouring tiles.
