@@ -41,6 +41,8 @@ IBS_POPC_OPS = 8 / 32         # per 32-variant word: AND, 2 XOR, 2 bitop3, 3 pop
 LD_MFMA_OPS = 6 * 2           # six int8 contractions
 LD_POPC_OPS = 16 / 32         # 16 VALU ops per 32-sample word
 LD_INT8 = 2 | (1 << 8)         # the LD matrix-core path's int8 tile (variant 1)
+IBS_FP4_KERNELS = "k_ibs_head<true>+k_ibs_tail<true>+k_ibs_tail_reduce"
+IBS_INT8_KERNELS = "k_ibs_head<false>+k_ibs_tail<false>+k_ibs_tail_reduce"
 
 
 def log(msg: str) -> None:
@@ -586,9 +588,11 @@ def main():
     layout_ms, pair_ms = mean(stages[0]), mean(stages[1])
     fp4 = path == "mfma" and args.variant in IBS_FP4_VARIANTS
     if fp4:
+        # the pair stage: whole tiles, the last round's tiles in K ranges, and
+        # the reduce of those ranges (one launch each)
         ops = comps * IBS_MFMA_OPS
         roof = {"bound": "mfma", "achieved": ops / (pair_ms * 1e-3) / 1e12,
-                "peak": PEAK_FP4_TFLOPS, "unit": "TFLOP/s", "kernel": "k_ibs_fp4_pipe"}
+                "peak": PEAK_FP4_TFLOPS, "unit": "TFLOP/s", "kernel": IBS_FP4_KERNELS}
     elif path == "mfma":
         ops = comps * IBS_MFMA_OPS
         roof = {"bound": "mfma", "achieved": ops / (pair_ms * 1e-3) / 1e12, "peak": PEAK_INT8_TOPS,
@@ -668,7 +672,7 @@ def main():
         extras["ibs_large_int8"] = {
             "value": round(comps / (ms3 * 1e-3) / 1e9, 1), "unit": "G/s", "variant": 7,
             "ms_per_step": round(ms3, 3), "pair_kernel_ms": round(pk3, 3),
-            "roofline": {"bound": "mfma", "kernel": "k_ibs_mfma_pipe", "unit": "TOP/s",
+            "roofline": {"bound": "mfma", "kernel": IBS_INT8_KERNELS, "unit": "TOP/s",
                          "achieved": round(ach3, 2), "peak": PEAK_INT8_TOPS,
                          "frac": round(ach3 / PEAK_INT8_TOPS, 4)}}
         del call3, out3
