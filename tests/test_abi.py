@@ -50,7 +50,12 @@ def _ld_ws(g, W, n_sel=0, vb=0, ve=0, path=0):
 
 
 def test_workspace_sizes():
+    # 10,000 x 100,000: the operand (10,112 rows x 6,256 words), then the tail
+    # split's sums: 3,160 tiles in 8 runs of 395, 384 whole tiles each
+    # (12 rounds of 32 CUs), 11 tail tiles x 5 K ranges x 196,608 bytes per run
     rc, b = _ibs_ws(_g(10000, 100000), path=N.PG_PATH_MFMA)
+    assert rc == 0 and b == 10112 * 6256 * 4 + 8 * 11 * 5 * 192 * 256 * 4
+    rc, b = _ibs_ws(_g(10000, 100000), path=N.PG_PATH_MFMA | (2 << 8))   # a whole-tile variant
     assert rc == 0 and b == 10112 * 6256 * 4
     rc, b = _ibs_ws(_g(10000, 100000), path=N.PG_PATH_POPC)
     assert rc == 0 and b == 3 * 10048 * 3136 * 4
