@@ -160,14 +160,19 @@ int pg_resolve_path(int kind, int64_t m, int64_t nv, int32_t window, int path, i
  *   sample_idx  optional device int32 array of n_sel indices into
  *               [0, n_samples); output rows/columns follow its order and
  *               duplicates are allowed.  NULL selects all samples in order,
- *               and n_sel must then be 0 or n_samples.
+ *               and n_sel must then be 0 or n_samples.  The array lives in
+ *               device memory and is not read on the host, so its entries
+ *               are not validated: an entry outside [0, n_samples) selects
+ *               a sample whose every call is missing (all its counts are 0).
  *   v_begin, v_end  variant range [v_begin, v_end); 0, 0 selects all.
  */
 
 /* Workspace bytes pg_ibs_matrix needs for this shape and path: the operand
- * layout, plus, for the default matrix-core kernel on cohorts of fewer than
- * 512 tiles of 128 samples, the raw sums of the variant ranges each tile is
- * split into (196,608 bytes per tile and range, at most 2,048 of them). */
+ * layout, plus, for the default matrix-core kernel, the raw sums of the
+ * variant ranges its tiles are split into (196,608 bytes per tile and
+ * range): on cohorts of fewer than 512 tiles of 128 samples every tile is
+ * split (at most 2,048 tile ranges); on larger ones only the tiles of the
+ * last, partial round of the CUs are (at most 8 x 32 tiles x 8 ranges). */
 int pg_ibs_workspace_bytes(const pg_genotypes* g, int64_t n_sel, int64_t v_begin, int64_t v_end,
                            int path, size_t* bytes);
 
