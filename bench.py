@@ -324,12 +324,12 @@ def bench_batch(torch, lib, hip, pg, synth, dev, steps):
         d.pop("bed")
         n, V = d["n"], d["V"]
         if d["kind"] == "ibs":
-            path = tuner.tune("ibs", c, layout="tri", reps=1, for_batch=True)
+            path = tuner.tune("ibs", c, layout="tri", reps=3, for_batch=True)
             p = pg.IbsProblem(c, layout="tri", path=path)
             comps += n * (n - 1) / 2 * V
         else:
             W = d["window"]
-            path = tuner.tune("ld", c, window=W, r2_min=d["r2_min"], reps=1, for_batch=True)
+            path = tuner.tune("ld", c, window=W, r2_min=d["r2_min"], reps=3, for_batch=True)
             cap = max(1 << 16, 64 * V)
             p = pg.LdProblem(c, window=W, r2_min=d["r2_min"], capacity=cap, path=path)
             comps += sum(min(W, V - 1 - a) for a in range(V)) * n

@@ -144,6 +144,10 @@ struct pg_plan {
   int64_t total_tiles = 0;
   int64_t part_begin[kParts + 1] = {0, 0, 0, 0};   // tile range of each part
   int64_t off_items = 0, off_counter = 0, bytes = 0;
+  // the sample-major layouts of the matrix-core IBS problems without a
+  // sample list run as one launch (LayoutJob table at off_jobs)
+  int64_t off_jobs = 0, job_blocks = 0;
+  int n_jobs = 0;
   int grid[kParts] = {256, 256, 256};
   const void* uploaded_ws = nullptr;
   // the LD branch runs on a stream of the plan's own, forked from and
@@ -240,6 +244,14 @@ int pg_batch_plan(const pg_problem* probs, int n_probs, pg_plan** out) {
   const int64_t t = plan->part_begin[kParts];
   plan->total_tiles = t;
   plan->off_items = take(off, (int64_t)sizeof(BatchItem) * n_probs);
+  for (int k : plan->order) {
+    const ProblemPlan& q = plan->probs[k];
+    if (q.p.kind == PG_KIND_IBS && q.path == PG_PATH_MFMA && !q.s.idx) {
+      ++plan->n_jobs;
+      plan->job_blocks += sample_major_job_blocks(q.rows_pad, q.words);
+    }
+  }
+  plan->off_jobs = take(off, (int64_t)sizeof(LayoutJob) * std::max(plan->n_jobs, 1));
   plan->off_counter = take(off, 8 * kParts);   // one tile counter per kernel
   plan->bytes = off;
   // persistent grids: resident blocks of each kernel on this device
@@ -315,6 +327,21 @@ int pg_batch_upload(pg_plan* plan, void* workspace, size_t workspace_bytes, void
     items.push_back(it);
     t += q.ntiles;
   }
+  std::vector<LayoutJob> jobs;
+  int64_t jb = 0;
+  for (int k : plan->order) {
+    const ProblemPlan& q = plan->probs[k];
+    if (!(q.p.kind == PG_KIND_IBS && q.path == PG_PATH_MFMA && !q.s.idx)) continue;
+    LayoutJob j{};
+    j.s = q.s;
+    j.T = (uint32_t*)(ws + q.off_x);
+    j.rows_pad = q.rows_pad;
+    j.wp = q.words;
+    j.block_begin = jb;
+    j.aligned = rows_dword_aligned(q.s) ? 1 : 0;
+    jobs.push_back(j);
+    jb += sample_major_job_blocks(q.rows_pad, q.words);
+  }
   hipStream_t st = (hipStream_t)stream;
   if (!plan->side &&
       (hipStreamCreateWithFlags(&plan->side, hipStreamNonBlocking) != hipSuccess ||
@@ -323,6 +350,9 @@ int pg_batch_upload(pg_plan* plan, void* workspace, size_t workspace_bytes, void
     return fail(PG_EDEVICE, "batch stream and events: %s", hipGetErrorString(hipGetLastError()));
   if (hipMemcpyAsync(ws + plan->off_items, items.data(), sizeof(BatchItem) * items.size(),
                      hipMemcpyHostToDevice, st) != hipSuccess ||
+      (!jobs.empty() &&
+       hipMemcpyAsync(ws + plan->off_jobs, jobs.data(), sizeof(LayoutJob) * jobs.size(),
+                      hipMemcpyHostToDevice, st) != hipSuccess) ||
       hipStreamSynchronize(st) != hipSuccess)
     return fail(PG_EDEVICE, "tile table upload failed: %s", hipGetErrorString(hipGetLastError()));
   plan->uploaded_ws = workspace;
@@ -349,10 +379,15 @@ int pg_batch_launch(const pg_plan* plan, void* workspace, size_t workspace_bytes
   const BatchItem* items = (const BatchItem*)(ws + plan->off_items);
   const int n_items = (int)plan->probs.size();
   const int64_t* pb = plan->part_begin;
-  // IBS branch on `st`: layouts, the tile counter, the persistent kernel
+  // IBS branch on `st`: layouts (one launch for the jobs), the tile counter,
+  // the persistent kernel
+  rc = launch_sample_major_jobs((const LayoutJob*)(ws + plan->off_jobs), plan->n_jobs,
+                                plan->job_blocks, st);
+  if (rc != PG_OK) return rc;
   for (int k : plan->order) {
     const ProblemPlan& q = plan->probs[k];
     if (q.p.kind != PG_KIND_IBS) continue;
+    if (q.path == PG_PATH_MFMA && !q.s.idx) continue;   // a layout job
     uint32_t* X = (uint32_t*)(ws + q.off_x);
     rc = q.path == PG_PATH_MFMA ? launch_sample_major_2bit(q.s, X, q.rows_pad, q.words, st)
                                 : launch_ibs_planes(q.s, X, q.rows_pad, q.words, st);

@@ -103,13 +103,11 @@ __device__ __forceinline__ void row_words16(const Sel& s, const int64_t (&v)[N],
 constexpr int kSmTW = 32;            // T words (16 variants) and sample groups per block
 constexpr int kSmTS = kSmTW + 1;     // LDS row stride (words)
 
-__global__ __launch_bounds__(256) void k_sample_major_tiled(Sel s, uint32_t* __restrict__ T,
-                                                            int64_t rows_pad, int64_t wp,
-                                                            int aligned) {
-  __shared__ uint32_t s_out[16 * kSmTW * kSmTS];
-  // blocks of one XCD take consecutive sample groups of the same variants, so
-  // the row pieces that straddle two blocks' reads meet in that XCD's L2
-  const int64_t bid = xcd_swizzle(blockIdx.x, gridDim.x);
+// Block `bid` of the tiled layout of one operand.
+__device__ __forceinline__ void sample_major_tiled_block(const Sel& s, uint32_t* __restrict__ T,
+                                                         int64_t rows_pad, int64_t wp,
+                                                         int aligned, int64_t bid,
+                                                         uint32_t* s_out) {
   const int64_t nb_g = ceil_div(rows_pad / 16, kSmTW);
   const int64_t g0 = (bid % nb_g) * kSmTW;   // sample group (16 samples)
   const int64_t a0 = (bid / nb_g) * kSmTW;   // T word (16 variants)
@@ -135,6 +133,43 @@ __global__ __launch_bounds__(256) void k_sample_major_tiled(Sel s, uint32_t* __r
     if (k < rows_pad && a < wp)   // T row 16 gl + c is LDS row c * kSmTW + gl
       T[k * wp + a] = s_out[((row & 15) * kSmTW + (row >> 4)) * kSmTS + (lane & 31)];
   }
+}
+
+__global__ __launch_bounds__(256) void k_sample_major_tiled(Sel s, uint32_t* __restrict__ T,
+                                                            int64_t rows_pad, int64_t wp,
+                                                            int aligned) {
+  __shared__ uint32_t s_out[16 * kSmTW * kSmTS];
+  // blocks of one XCD take consecutive sample groups of the same variants, so
+  // the row pieces that straddle two blocks' reads meet in that XCD's L2
+  sample_major_tiled_block(s, T, rows_pad, wp, aligned, xcd_swizzle(blockIdx.x, gridDim.x),
+                           s_out);
+}
+
+// Many operands in one launch: block b lays out block b - block_begin of the
+// job whose block range holds b (jobs in increasing block_begin).
+__global__ __launch_bounds__(256) void k_sample_major_jobs(const LayoutJob* __restrict__ jobs,
+                                                           int n_jobs) {
+  __shared__ uint32_t s_out[16 * kSmTW * kSmTS];
+  const int64_t b = blockIdx.x;
+  int lo = 0, hi = n_jobs - 1;
+  while (lo < hi) {   // the last job with block_begin <= b
+    const int mid = (lo + hi + 1) / 2;
+    if (jobs[mid].block_begin <= b) lo = mid; else hi = mid - 1;
+  }
+  const LayoutJob j = jobs[lo];
+  sample_major_tiled_block(j.s, j.T, j.rows_pad, j.wp, j.aligned, b - j.block_begin, s_out);
+}
+
+int64_t sample_major_job_blocks(int64_t rows_pad, int64_t wp) {
+  return ceil_div(wp, kSmTW) * ceil_div(rows_pad, 16 * kSmTW);
+}
+
+int launch_sample_major_jobs(const LayoutJob* jobs, int n_jobs, int64_t total_blocks,
+                             hipStream_t st) {
+  if (n_jobs <= 0 || total_blocks <= 0) return PG_OK;
+  hipLaunchKernelGGL(k_sample_major_jobs, dim3((unsigned)total_blocks), dim3(256), 0, st, jobs,
+                     n_jobs);
+  return check_launch("sample_major_jobs");
 }
 
 // Every other bit (bits 0, 2, 4, ... of x) packed into the low 16 bits.
@@ -327,7 +362,7 @@ __global__ __launch_bounds__(256) void k_variant_major_fast(Sel s, uint32_t* __r
   }
 }
 
-static bool rows_dword_aligned(const Sel& s) {
+bool rows_dword_aligned(const Sel& s) {
   return (s.bpv % 4) == 0 && (reinterpret_cast<uintptr_t>(s.bed) % 4) == 0;
 }
 
@@ -379,7 +414,7 @@ __global__ __launch_bounds__(256) void k_sample_major_2bit(Sel s, uint32_t* __re
 int launch_sample_major_2bit(const Sel& s, uint32_t* T, int64_t rows_pad, int64_t wp,
                              hipStream_t st) {
   if (!s.idx) {
-    const int64_t blocks = ceil_div(wp, kSmTW) * ceil_div(rows_pad, 16 * kSmTW);
+    const int64_t blocks = sample_major_job_blocks(rows_pad, wp);
     hipLaunchKernelGGL(k_sample_major_tiled, dim3((unsigned)blocks), dim3(256), 0, st, s, T,
                        rows_pad, wp, (int)rows_dword_aligned(s));
     return check_launch("sample_major_tiled");

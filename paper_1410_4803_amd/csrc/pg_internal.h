@@ -105,6 +105,20 @@ int launch_sample_major_rep(const Sel& s, uint32_t* R, int64_t rows_pad, int64_t
 // at P[(w*3 + p)*rows_pad + i]; words_pad words.
 int launch_ibs_planes(const Sel& s, uint32_t* P, int64_t rows_pad, int64_t words_pad,
                       hipStream_t st);
+// The same layout (without a sample list) for several operands in one
+// launch: one job per operand, blocks [block_begin, block_begin +
+// sample_major_job_blocks(rows_pad, wp)) of the launch lay it out.
+struct LayoutJob {
+  Sel s;
+  uint32_t* T;
+  int64_t rows_pad, wp, block_begin;
+  int aligned;   // rows_dword_aligned(s)
+};
+bool rows_dword_aligned(const Sel& s);
+int64_t sample_major_job_blocks(int64_t rows_pad, int64_t wp);
+// jobs: device array of n_jobs jobs in increasing block_begin.
+int launch_sample_major_jobs(const LayoutJob* jobs, int n_jobs, int64_t total_blocks,
+                             hipStream_t st);
 // Variant-major 2-bit words over the selected samples: D[v*wn + w] holds
 // codes of samples 16w..16w+15 of selected variant v; rows_pad x wn.
 int launch_variant_major_2bit(const Sel& s, uint32_t* D, int64_t rows_pad, int64_t wn,
