@@ -102,6 +102,13 @@ enum pg_layout {
                        index i*m - i*(i+1)/2 + (j-i-1); m(m-1)/2 entries */
   PG_FULL = 1       /* m x m row-major, both halves and the diagonal */
 };
+/* Flag OR-ed into the `out_layout` of pg_ibs_matrix (and of an IBS
+ * pg_problem): the four count arrays are uint16 instead of uint32 (pass
+ * uint16_t arrays through the uint32_t* parameters).  Every count is at most
+ * the number of selected variants, so it is allowed only when
+ * v_end - v_begin < 65,536 (PG_EINVAL otherwise).  Halves the output: for
+ * result copies to the host, as a server sends them. */
+#define PG_COUNTS_U16 0x100
 
 /* Kernel path.  The low 8 bits of a `path` argument select the path; bits
  * 8-15 select a kernel variant of that path (0 = the library's default; the
@@ -185,7 +192,9 @@ int pg_ibs_workspace_bytes(const pg_genotypes* g, int64_t n_sel, int64_t v_begin
  * (ibs0 + ibs1 + ibs2 == nonmiss).  The diagonal of PG_FULL holds
  * ibs2 = nonmiss = the sample's non-missing count, ibs0 = ibs1 = 0.
  * Outputs are four caller-owned uint32 device arrays of m*m (PG_FULL) or
- * m(m-1)/2 (PG_TRI_UPPER) entries; counts are exact.  With zero entries
+ * m(m-1)/2 (PG_TRI_UPPER) entries (uint16 with PG_COUNTS_U16); counts are
+ * exact.  The consumers below (distance, similarity, clustering, IBD report)
+ * take the uint32 form.  With zero entries
  * (one sample, PG_TRI_UPPER) the call validates its arguments, enqueues
  * nothing and the output pointers may be NULL.
  * Section "Bitwise parallelism".

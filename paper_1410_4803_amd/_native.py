@@ -33,6 +33,7 @@ SYMBOLS = ("pg_status_str", "pg_last_error", "pg_version", "pg_profile_events",
            "pg_graph_destroy", "pg_ibs_matrix_noalloc", "pg_noalloc_scratch_bytes", "pg_resolve_path",
            "pg_ibs_similarity", "pg_genome_workspace_bytes", "pg_ibs_genome")
 PG_KIND_IBS, PG_KIND_LD = 0, 1
+PG_COUNTS_U16 = 0x100    # out_layout flag: 16-bit IBS counts
 
 LD_PAIR = np.dtype([("a", "<i4"), ("b", "<i4"), ("n", "<i8"), ("sx", "<i8"), ("sy", "<i8"),
                     ("sxx", "<i8"), ("syy", "<i8"), ("sxy", "<i8"), ("r2", "<f8")])

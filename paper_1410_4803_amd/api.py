@@ -125,29 +125,35 @@ def ibs_output_size(m: int, layout: str) -> int:
 
 def ibs_matrix(cohort: Cohort, *, sample_idx: torch.Tensor | None = None, v_range=None,
                layout: str = "full", path="auto", out=None, workspace: torch.Tensor | None = None,
-               stream=None):
-    """IBS0, IBS1, IBS2, N as four CUDA int32 tensors (uint32 counts, all
-    < 2^31): (m, m) for layout "full", m(m-1)/2 packed upper triangle for
-    "tri".  Asynchronous on `stream` (default: the current stream)."""
+               stream=None, counts: str = "u32"):
+    """IBS0, IBS1, IBS2, N as four CUDA tensors: (m, m) for layout "full",
+    m(m-1)/2 packed upper triangle for "tri".  counts "u32": int32 tensors
+    holding uint32 counts (all < 2^31); "u16": int16 tensors holding uint16
+    counts (PG_COUNTS_U16; fewer than 65,536 selected variants), half the
+    bytes.  Asynchronous on `stream` (default: the current stream)."""
     lib = N.load()
+    if counts not in ("u32", "u16"):
+        raise ValueError("counts must be 'u32' or 'u16'")
+    dtype = torch.int16 if counts == "u16" else torch.int32
     n_sel, vb, ve = _sel(cohort, sample_idx, v_range)
     m = n_sel or cohort.n_samples
     size = ibs_output_size(m, layout)
     with _on(stream):
         if out is None:
             shape = (m, m) if layout == "full" else (size,)
-            out = tuple(torch.empty(shape, dtype=torch.int32, device=cohort.bed.device)
+            out = tuple(torch.empty(shape, dtype=dtype, device=cohort.bed.device)
                         for _ in range(4))
         else:
             for k, t in enumerate(out):
-                _require_cuda(t, f"out[{k}]", torch.int32)
+                _require_cuda(t, f"out[{k}]", dtype)
                 if t.numel() < size:
                     raise ValueError("output tensor too small")
         need = ibs_workspace_bytes(cohort, n_sel, (vb, ve), path)
         if workspace is None:
             workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=cohort.bed.device)
     g = cohort.struct()
-    st = lib.pg_ibs_matrix(ctypes.byref(g), _ptr(sample_idx), n_sel, vb, ve, N.LAYOUTS[layout],
+    lay = N.LAYOUTS[layout] | (N.PG_COUNTS_U16 if counts == "u16" else 0)
+    st = lib.pg_ibs_matrix(ctypes.byref(g), _ptr(sample_idx), n_sel, vb, ve, lay,
                            _path(path), *[_ptr(t) for t in out], _ptr(workspace),
                            workspace.numel(), _stream_handle(stream))
     N.check(st, "pg_ibs_matrix")
@@ -172,21 +178,26 @@ def noalloc_scratch_bytes() -> int:
 
 
 def ibs_matrix_noalloc(cohort: Cohort, out, *, sample_idx: torch.Tensor | None = None,
-                       v_range=None, layout: str = "full", path="auto", stream=None):
-    """pg_ibs_matrix_noalloc: the IBS matrix into the caller's four int32
-    tensors `out`, with the library's static scratch array as workspace (no
-    allocation anywhere in the call).  Calls that overlap on one GPU race."""
+                       v_range=None, layout: str = "full", path="auto", stream=None,
+                       counts: str = "u32"):
+    """pg_ibs_matrix_noalloc: the IBS matrix into the caller's four tensors
+    `out` (int32, or int16 with counts "u16"), with the library's static
+    scratch array as workspace (no allocation anywhere in the call).  Calls
+    that overlap on one GPU race."""
     lib = N.load()
+    if counts not in ("u32", "u16"):
+        raise ValueError("counts must be 'u32' or 'u16'")
     n_sel, vb, ve = _sel(cohort, sample_idx, v_range)
     m = n_sel or cohort.n_samples
     size = ibs_output_size(m, layout)
     for k, t in enumerate(out):
-        _require_cuda(t, f"out[{k}]", torch.int32)
+        _require_cuda(t, f"out[{k}]", torch.int16 if counts == "u16" else torch.int32)
         if t.numel() < size:
             raise ValueError("output tensor too small")
     g = cohort.struct()
-    st = lib.pg_ibs_matrix_noalloc(ctypes.byref(g), _ptr(sample_idx), n_sel, vb, ve,
-                                   N.LAYOUTS[layout], _path(path), *[_ptr(t) for t in out],
+    lay = N.LAYOUTS[layout] | (N.PG_COUNTS_U16 if counts == "u16" else 0)
+    st = lib.pg_ibs_matrix_noalloc(ctypes.byref(g), _ptr(sample_idx), n_sel, vb, ve, lay,
+                                   _path(path), *[_ptr(t) for t in out],
                                    _stream_handle(stream))
     N.check(st, "pg_ibs_matrix_noalloc")
     return out

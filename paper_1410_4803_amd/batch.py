@@ -29,7 +29,8 @@ class IbsProblem:
     v_range: tuple | None = None
     layout: str = "tri"
     path: int | str = "auto"
-    out: tuple | None = None          # four int32 tensors; allocated if None
+    out: tuple | None = None          # four int32 tensors (int16 with counts "u16"); allocated if None
+    counts: str = "u32"               # "u16": 16-bit counts (fewer than 65,536 variants)
 
 
 @dataclass
@@ -79,11 +80,16 @@ class Batch:
             if isinstance(p, IbsProblem):
                 q.kind = N.PG_KIND_IBS
                 size = ibs_output_size(m, p.layout)
+                dtype = torch.int16 if p.counts == "u16" else torch.int32
                 if p.out is None:
                     shape = (m, m) if p.layout == "full" else (size,)
-                    p.out = tuple(torch.empty(shape, dtype=torch.int32, device=self.device)
+                    p.out = tuple(torch.empty(shape, dtype=dtype, device=self.device)
                                   for _ in range(4))
-                q.out_layout = N.LAYOUTS[p.layout]
+                for k, t in enumerate(p.out):
+                    _require_cuda(t, f"out[{k}]", dtype)
+                    if t.numel() < size:
+                        raise ValueError("output tensor too small")
+                q.out_layout = N.LAYOUTS[p.layout] | (N.PG_COUNTS_U16 if p.counts == "u16" else 0)
                 q.ibs0, q.ibs1, q.ibs2, q.nonmiss = [_ptr(t) for t in p.out]
             else:
                 q.kind = N.PG_KIND_LD

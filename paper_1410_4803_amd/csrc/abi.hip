@@ -341,13 +341,25 @@ int plan_grm(const Sel& s, GrmPlan& p) {
 
 int plan_ibs_default(const Sel& s, IbsPlan& p) { return plan_ibs(s, PG_PATH_MFMA, p); }
 
+int ibs_out_layout(int out_layout, int64_t nv, int& layout, int& u16) {
+  layout = out_layout & ~PG_COUNTS_U16;
+  u16 = (out_layout & PG_COUNTS_U16) ? 1 : 0;
+  if (layout != PG_FULL && layout != PG_TRI_UPPER)
+    return fail(PG_EINVAL, "unknown layout %d", out_layout);
+  if (u16 && nv >= 65536)
+    return fail(PG_EINVAL, "16-bit counts need fewer than 65,536 variants (%lld selected)",
+                (long long)nv);
+  return PG_OK;
+}
+
 int batch_validate_ibs(const pg_problem& q, Sel& s, int& path, int& variant, int64_t& rows_pad,
                        int64_t& words) {
   int rc = make_sel(&q.g, q.sample_idx != nullptr, q.sample_idx, q.n_sel, q.v_begin, q.v_end, s);
   if (rc != PG_OK) return rc;
-  if (q.out_layout != PG_FULL && q.out_layout != PG_TRI_UPPER)
-    return fail(PG_EINVAL, "unknown layout %d", q.out_layout);
-  const int64_t entries = q.out_layout == PG_FULL ? s.m * s.m : s.m * (s.m - 1) / 2;
+  int layout, u16;
+  rc = ibs_out_layout(q.out_layout, s.nv, layout, u16);
+  if (rc != PG_OK) return rc;
+  const int64_t entries = layout == PG_FULL ? s.m * s.m : s.m * (s.m - 1) / 2;
   if (entries > 0 && (!q.ibs0 || !q.ibs1 || !q.ibs2 || !q.nonmiss))
     return fail(PG_EINVAL, "an output pointer is NULL");
   IbsPlan p;
@@ -435,9 +447,10 @@ int ibs_matrix_run(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_s
   Sel s;
   int rc = make_sel(g, sample_idx != nullptr, sample_idx, n_sel, v_begin, v_end, s);
   if (rc != PG_OK) return rc;
-  if (out_layout != PG_FULL && out_layout != PG_TRI_UPPER)
-    return fail(PG_EINVAL, "unknown layout %d", out_layout);
-  const int64_t entries = out_layout == PG_FULL ? s.m * s.m : s.m * (s.m - 1) / 2;
+  int layout, u16;
+  rc = ibs_out_layout(out_layout, s.nv, layout, u16);
+  if (rc != PG_OK) return rc;
+  const int64_t entries = layout == PG_FULL ? s.m * s.m : s.m * (s.m - 1) / 2;
   if (entries == 0) return PG_OK;  // one sample, triangle layout: nothing to write
   if (!ibs0 || !ibs1 || !ibs2 || !nonmiss) return fail(PG_EINVAL, "an output pointer is NULL");
   IbsPlan p;
@@ -464,7 +477,7 @@ int ibs_matrix_run(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_s
     return fail(PG_ENOMEM, "workspace of %llu bytes < %lld required",
                 (unsigned long long)workspace_bytes, (long long)p.bytes);
   hipStream_t st = (hipStream_t)stream;
-  IbsOut o{ibs0, ibs1, ibs2, nonmiss, s.m, out_layout == PG_FULL};
+  IbsOut o{ibs0, ibs1, ibs2, nonmiss, s.m, layout == PG_FULL, u16};
   uint32_t* ws = (uint32_t*)workspace;
   mark_stage(0, st);
   if (p.path == PG_PATH_MFMA && p.variant == kIbsVariantFp4Rep) {

@@ -315,7 +315,9 @@ int pg_batch_upload(pg_plan* plan, void* workspace, size_t workspace_bytes, void
     it.rows_pad = q.rows_pad;
     it.nt = q.nt;
     if (q.p.kind == PG_KIND_IBS) {
-      it.o = IbsOut{q.p.ibs0, q.p.ibs1, q.p.ibs2, q.p.nonmiss, q.s.m, q.p.out_layout == PG_FULL};
+      it.o = IbsOut{q.p.ibs0, q.p.ibs1, q.p.ibs2, q.p.nonmiss, q.s.m,
+                    (q.p.out_layout & ~PG_COUNTS_U16) == PG_FULL,
+                    (q.p.out_layout & PG_COUNTS_U16) ? 1 : 0};
     } else {
       it.window = q.p.window;
       it.n_band = q.n_band;

@@ -138,7 +138,11 @@ struct IbsOut {
   uint32_t* nonmiss;
   int64_t m;     // matrix order
   int full;      // PG_FULL or PG_TRI_UPPER
+  int u16;       // the arrays hold uint16 counts (PG_COUNTS_U16)
 };
+// out_layout of an IBS call: the layout and the count width; PG_EINVAL for
+// an unknown layout or flag, or 16-bit counts over 65,536 variants or more.
+int ibs_out_layout(int out_layout, int64_t nv, int& layout, int& u16);
 
 constexpr int kIbsMfmaTile = 128;     // samples per tile side
 constexpr int kIbsMfmaKWords = 16;    // 2-bit words per K chunk (256 variants)

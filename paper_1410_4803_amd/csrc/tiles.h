@@ -5,6 +5,8 @@
 // matching k*Smem constant); bodies synchronise internally.
 #pragma once
 
+#include <type_traits>
+
 #include "pg_internal.h"
 
 namespace pg {
@@ -135,21 +137,35 @@ __device__ __forceinline__ int64_t xcd_swizzle(int64_t b, int64_t nblocks) {
   return (b % 8) * (full / 8) + b / 8;
 }
 
-__device__ __forceinline__ void store_counts(const IbsOut& o, int64_t i, int64_t j, bool mirror,
-                                             uint32_t n, uint32_t z, uint32_t one) {
+// kU16: the arrays hold 16-bit counts (o.u16).  The tile epilogues choose
+// the width once, outside their unrolled loops.
+template <bool kU16>
+__device__ __forceinline__ void store_counts_w(const IbsOut& o, int64_t i, int64_t j, bool mirror,
+                                               uint32_t n, uint32_t z, uint32_t one) {
   if (i >= o.m || j >= o.m) return;
   const uint32_t two = n - z - one;
-  if (o.full) {
-    const int64_t a = i * o.m + j;
-    o.ibs0[a] = z; o.ibs1[a] = one; o.ibs2[a] = two; o.nonmiss[a] = n;
-    if (mirror) {
-      const int64_t b = j * o.m + i;
-      o.ibs0[b] = z; o.ibs1[b] = one; o.ibs2[b] = two; o.nonmiss[b] = n;
+  auto put = [&](int64_t a) {
+    if constexpr (kU16) {
+      reinterpret_cast<uint16_t*>(o.ibs0)[a] = (uint16_t)z;
+      reinterpret_cast<uint16_t*>(o.ibs1)[a] = (uint16_t)one;
+      reinterpret_cast<uint16_t*>(o.ibs2)[a] = (uint16_t)two;
+      reinterpret_cast<uint16_t*>(o.nonmiss)[a] = (uint16_t)n;
+    } else {
+      o.ibs0[a] = z; o.ibs1[a] = one; o.ibs2[a] = two; o.nonmiss[a] = n;
     }
+  };
+  if (o.full) {
+    put(i * o.m + j);
+    if (mirror) put(j * o.m + i);
   } else if (i < j) {
-    const int64_t a = i * o.m - i * (i + 1) / 2 + (j - i - 1);
-    o.ibs0[a] = z; o.ibs1[a] = one; o.ibs2[a] = two; o.nonmiss[a] = n;
+    put(i * o.m - i * (i + 1) / 2 + (j - i - 1));
   }
+}
+
+__device__ __forceinline__ void store_counts(const IbsOut& o, int64_t i, int64_t j, bool mirror,
+                                             uint32_t n, uint32_t z, uint32_t one) {
+  if (o.u16) store_counts_w<true>(o, i, j, mirror, n, z, one);
+  else store_counts_w<false>(o, i, j, mirror, n, z, one);
 }
 
 // Stores the counts of one 32x32 accumulator block (register v of lane l is
@@ -158,6 +174,7 @@ __device__ __forceinline__ void store_counts(const IbsOut& o, int64_t i, int64_t
 // (j, i) of an off-diagonal tile go out as one 16-byte store per four
 // consecutive i, so each row receives whole 32-byte pieces (scalar stores at
 // the matrix edge or when rows are not 16-byte aligned).
+template <bool kU16>
 __device__ __forceinline__ void store_block(const IbsOut& o, int64_t i_base, int64_t j,
                                             bool mirror, int lane, const uint32_t (&n)[16],
                                             const uint32_t (&z)[16], const uint32_t (&one)[16]) {
@@ -165,17 +182,17 @@ __device__ __forceinline__ void store_block(const IbsOut& o, int64_t i_base, int
   if (!o.full) {
 #pragma unroll
     for (int v = 0; v < 16; ++v)
-      store_counts(o, ib + 8 * (v >> 2) + (v & 3), j, false, n[v], z[v], one[v]);
+      store_counts_w<kU16>(o, ib + 8 * (v >> 2) + (v & 3), j, false, n[v], z[v], one[v]);
     return;
   }
 #pragma unroll
   for (int v = 0; v < 16; ++v)
-    store_counts(o, ib + 8 * (v >> 2) + (v & 3), j, false, n[v], z[v], one[v]);
+    store_counts_w<kU16>(o, ib + 8 * (v >> 2) + (v & 3), j, false, n[v], z[v], one[v]);
   if (!mirror || j >= o.m) return;
   const bool vec_ok = (o.m & 3) == 0 &&
                       ((reinterpret_cast<uintptr_t>(o.ibs0) | reinterpret_cast<uintptr_t>(o.ibs1) |
                         reinterpret_cast<uintptr_t>(o.ibs2) | reinterpret_cast<uintptr_t>(o.nonmiss)) &
-                       15) == 0;
+                       (kU16 ? 7 : 15)) == 0;
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
     const int64_t i0 = ib + 8 * g;
@@ -188,19 +205,24 @@ __device__ __forceinline__ void store_block(const IbsOut& o, int64_t i_base, int
                       n[4 * g + 2] - z[4 * g + 2] - one[4 * g + 2],
                       n[4 * g + 3] - z[4 * g + 3] - one[4 * g + 3]);
       t3 = make_uint4(n[4 * g], n[4 * g + 1], n[4 * g + 2], n[4 * g + 3]);
-      *reinterpret_cast<uint4*>(o.ibs0 + a) = t0;
-      *reinterpret_cast<uint4*>(o.ibs1 + a) = t1;
-      *reinterpret_cast<uint4*>(o.ibs2 + a) = t2;
-      *reinterpret_cast<uint4*>(o.nonmiss + a) = t3;
+      if constexpr (kU16) {   // four 16-bit counts per 8-byte store
+        auto pack = [](uint4 t) {
+          return make_uint2((t.x & 0xFFFFu) | (t.y << 16), (t.z & 0xFFFFu) | (t.w << 16));
+        };
+        *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(o.ibs0) + a) = pack(t0);
+        *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(o.ibs1) + a) = pack(t1);
+        *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(o.ibs2) + a) = pack(t2);
+        *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(o.nonmiss) + a) = pack(t3);
+      } else {
+        *reinterpret_cast<uint4*>(o.ibs0 + a) = t0;
+        *reinterpret_cast<uint4*>(o.ibs1 + a) = t1;
+        *reinterpret_cast<uint4*>(o.ibs2 + a) = t2;
+        *reinterpret_cast<uint4*>(o.nonmiss + a) = t3;
+      }
     } else {
-#pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int64_t i = i0 + e;
-        if (i < o.m) {
-          const int64_t a = j * o.m + i;
-          const int v = 4 * g + e;
-          o.ibs0[a] = z[v]; o.ibs1[a] = one[v]; o.ibs2[a] = n[v] - z[v] - one[v]; o.nonmiss[a] = n[v];
-        }
+        const int v = 4 * g + e;
+        store_counts_w<kU16>(o, j, i0 + e, false, n[v], z[v], one[v]);
       }
     }
   }
@@ -271,20 +293,25 @@ __device__ __forceinline__ void mfma_step(IbsAcc& acc, const Feat4 (&fa)[2], con
 __device__ __forceinline__ void ibs_epilogue(const IbsAcc& acc, const IbsOut& o, int64_t I,
                                              int64_t J, int wr, int wc, int lane) {
   const bool mirror = (I != J);
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      uint32_t n[16], z[16], one[16];
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        n[v] = (uint32_t)acc.m[a][b][v];
-        z[v] = (uint32_t)acc.hc[a][b][v] >> 1;
-        one[v] = (n[v] - (uint32_t)acc.w[a][b][v]) >> 1;
+  auto stores = [&](auto width) {
+    constexpr bool kU16 = decltype(width)::value;
+  #pragma unroll
+    for (int a = 0; a < 2; ++a)
+  #pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        uint32_t n[16], z[16], one[16];
+  #pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          n[v] = (uint32_t)acc.m[a][b][v];
+          z[v] = (uint32_t)acc.hc[a][b][v] >> 1;
+          one[v] = (n[v] - (uint32_t)acc.w[a][b][v]) >> 1;
+        }
+        store_block<kU16>(o, I * kT + wr * 64 + a * 32, J * kT + wc * 64 + b * 32 + (lane & 31), mirror,
+                    lane, n, z, one);
       }
-      store_block(o, I * kT + wr * 64 + a * 32, J * kT + wc * 64 + b * 32 + (lane & 31), mirror,
-                  lane, n, z, one);
-    }
+  };
+  if (o.u16) stores(std::true_type{});
+  else stores(std::false_type{});
 }
 
 __device__ __forceinline__ void zero_acc(IbsAcc& acc) {
@@ -653,18 +680,23 @@ __device__ __forceinline__ void ibs_mfma_tile_w8(const uint32_t* __restrict__ T,
     __syncthreads();
   }
   const bool mirror = (I != J);
+  auto stores = [&](auto width) {
+    constexpr bool kU16 = decltype(width)::value;
 #pragma unroll
-  for (int a = 0; a < 2; ++a) {
-    uint32_t n[16], z[16], one[16];
+    for (int a = 0; a < 2; ++a) {
+      uint32_t n[16], z[16], one[16];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      n[v] = (uint32_t)acc.m[a][v];
-      z[v] = (uint32_t)acc.hc[a][v] >> 1;
-      one[v] = (n[v] - (uint32_t)acc.w[a][v]) >> 1;
+      for (int v = 0; v < 16; ++v) {
+        n[v] = (uint32_t)acc.m[a][v];
+        z[v] = (uint32_t)acc.hc[a][v] >> 1;
+        one[v] = (n[v] - (uint32_t)acc.w[a][v]) >> 1;
+      }
+      store_block<kU16>(o, I * kT + wr * 64 + a * 32, J * kT + wc * 32 + (lane & 31), mirror,
+                        lane, n, z, one);
     }
-    store_block(o, I * kT + wr * 64 + a * 32, J * kT + wc * 32 + (lane & 31), mirror, lane, n, z,
-                one);
-  }
+  };
+  if (o.u16) stores(std::true_type{});
+  else stores(std::false_type{});
 }
 
 // Unpipelined reference form (variant 2).
@@ -764,10 +796,17 @@ __device__ __forceinline__ void ibs_popc_tile(const uint32_t* __restrict__ P, in
     __syncthreads();
   }
   const bool mirror = (I != J);
-  for (int r = 0; r < 4; ++r)
-    for (int c = 0; c < 4; ++c)
-      store_counts(o, I * kP + ty * 4 + r, J * kP + tx * 4 + c, mirror, cn[r][c], cz[r][c],
-                   co[r][c]);
+  auto stores = [&](auto width) {
+    constexpr bool kU16 = decltype(width)::value;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        store_counts_w<kU16>(o, I * kP + ty * 4 + r, J * kP + tx * 4 + c, mirror, cn[r][c],
+                             cz[r][c], co[r][c]);
+  };
+  if (o.u16) stores(std::true_type{});
+  else stores(std::false_type{});
 }
 
 
@@ -850,20 +889,25 @@ __device__ __forceinline__ void fp4_epilogue(const Fp4Acc& acc, const IbsOut& o,
                                              int64_t J, int wr, int wc, int lane,
                                              int zshift = 1) {
   const bool mirror = (I != J);
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      uint32_t n[16], z[16], one[16];
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        n[v] = (uint32_t)(int)acc.m[a][b][v];
-        z[v] = (uint32_t)(int)acc.hc[a][b][v] >> zshift;
-        one[v] = (n[v] - (uint32_t)(int)acc.w[a][b][v]) >> 1;
+  auto stores = [&](auto width) {
+    constexpr bool kU16 = decltype(width)::value;
+  #pragma unroll
+    for (int a = 0; a < 2; ++a)
+  #pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        uint32_t n[16], z[16], one[16];
+  #pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          n[v] = (uint32_t)(int)acc.m[a][b][v];
+          z[v] = (uint32_t)(int)acc.hc[a][b][v] >> zshift;
+          one[v] = (n[v] - (uint32_t)(int)acc.w[a][b][v]) >> 1;
+        }
+        store_block<kU16>(o, I * kT + wr * 64 + a * 32, J * kT + wc * 64 + b * 32 + (lane & 31), mirror,
+                    lane, n, z, one);
       }
-      store_block(o, I * kT + wr * 64 + a * 32, J * kT + wc * 64 + b * 32 + (lane & 31), mirror,
-                  lane, n, z, one);
-    }
+  };
+  if (o.u16) stores(std::true_type{});
+  else stores(std::false_type{});
 }
 
 __device__ __forceinline__ void ibs_fp4_tile(const uint32_t* __restrict__ T, int64_t wp,

@@ -51,10 +51,17 @@ class GpuBackend:
     """Runs requests through the library on per-slot streams."""
 
     def __init__(self, cohorts: list[Cohort], n_slots: int, device=None, tuner=None,
-                 keep_results: bool | str = True, ld_capacity: int = 1 << 18):
+                 keep_results: bool | str = True, ld_capacity: int = 1 << 18,
+                 ibs_counts: str = "auto"):
         """keep_results: True keeps each result (numpy arrays) on its
         request, False keeps nothing, "digest" keeps a 128-bit hash of the
-        result's bytes (for comparing many large results)."""
+        result's bytes (for comparing many large results).  ibs_counts:
+        "auto" returns IBS counts as uint16 when the request's variant range
+        is shorter than 65,536 (half the device memory and the copy to the
+        host), else uint32; "u32" always uint32."""
+        if ibs_counts not in ("auto", "u32"):
+            raise ValueError("ibs_counts must be 'auto' or 'u32'")
+        self.ibs_counts = ibs_counts
         self.cohorts = cohorts
         self.device = device or cohorts[0].bed.device
         self.tuner = tuner
@@ -76,13 +83,19 @@ class GpuBackend:
             return N.PG_PATH_AUTO
         return self.tuner.choose(req.kind, m, nv, req.window if req.kind == "ld" else None)
 
+    def _counts(self, req: Request) -> str:
+        """Width of an IBS request's counts: "u16" or "u32"."""
+        short = req.v_range[1] - req.v_range[0] < 65536
+        return "u16" if self.ibs_counts == "auto" and short else "u32"
+
     def footprint(self, req: Request) -> int:
         c = self.cohorts[req.cohort]
         m = len(req.sample_idx)
         path = self._path(req)
         if req.kind == "ibs":
             ws = ibs_workspace_bytes(c, m, req.v_range, path)
-            return ws + 4 * 4 * ibs_output_size(m, req.layout) + 4 * m
+            width = 2 if self._counts(req) == "u16" else 4
+            return ws + 4 * width * ibs_output_size(m, req.layout) + 4 * m
         ws = ld_workspace_bytes(c, req.window, m, req.v_range, path)
         return ws + 64 * self._ld_cap(req) + 8 + 4 * m
 
@@ -115,18 +128,21 @@ class GpuBackend:
             e0.record(st)
             if req.kind == "ibs":
                 size = ibs_output_size(m, req.layout)
-                out = tuple(torch.empty(size, dtype=torch.int32, device=self.device)
+                counts = self._counts(req)
+                dtype, width = (torch.int16, 2) if counts == "u16" else (torch.int32, 4)
+                out = tuple(torch.empty(size, dtype=dtype, device=self.device)
                             for _ in range(4))
                 ibs_matrix(c, sample_idx=idx, v_range=req.v_range, layout=req.layout, path=path,
-                           out=out, stream=st)
+                           out=out, stream=st, counts=counts)
                 e1.record(st)
-                host = self._host_buf(slot, 16 * size)
-                views = [host[k * 4 * size:(k + 1) * 4 * size].view(torch.int32)
+                host = self._host_buf(slot, 4 * width * size)
+                views = [host[k * width * size:(k + 1) * width * size].view(dtype)
                          for k in range(4)]
                 for v, o in zip(views, out):
                     v.copy_(o, non_blocking=True)
                 keep = (out, idx)
-                h = {"kind": "ibs", "views": views, "keep": keep}
+                h = {"kind": "ibs", "views": views, "keep": keep,
+                     "np": np.uint16 if counts == "u16" else np.uint32}
             else:
                 cap = self._ld_cap(req)
                 out, n_out = ld_window(c, req.window, req.r2_min, capacity=cap, sample_idx=idx,
@@ -156,7 +172,7 @@ class GpuBackend:
             if self.keep == "digest":
                 res = _digest(v.numpy() for v in h["views"])
             elif self.keep:
-                res = tuple(v.numpy().view(np.uint32).copy() for v in h["views"])
+                res = tuple(v.numpy().view(h["np"]).copy() for v in h["views"])
         else:
             total = int(h["n"].item())
             if total > h["cap"]:

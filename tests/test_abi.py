@@ -125,6 +125,19 @@ def test_calls_reject_before_launch():
     rc = lib.pg_ibs_matrix(ctypes.byref(g), None, 0, 0, 0, 5, 0, fake, fake, fake, fake,
                            fake, 1 << 30, None)
     assert rc == N.PG_EINVAL
+    # 16-bit counts: only for ranges under 65,536 variants; unknown flag bits rejected
+    for lay, V, vb, ve in [(N.PG_FULL | N.PG_COUNTS_U16, 70000, 0, 0),
+                           (N.PG_TRI_UPPER | N.PG_COUNTS_U16, 70000, 1000, 66536),
+                           (N.PG_FULL | 0x200, 50, 0, 0), (5 | N.PG_COUNTS_U16, 50, 0, 0)]:
+        gv = _g(100, V)
+        rc = lib.pg_ibs_matrix(ctypes.byref(gv), None, 0, vb, ve, lay, 0, fake, fake, fake, fake,
+                               fake, 1 << 30, None)
+        assert rc == N.PG_EINVAL, (lay, V)
+        why = "65,536" if V > 65535 else "unknown layout"
+        assert why in N.last_error()
+        rc = lib.pg_ibs_matrix_noalloc(ctypes.byref(gv), None, 0, vb, ve, lay, 0, fake, fake,
+                                       fake, fake, None)
+        assert rc == N.PG_EINVAL and why in N.last_error(), (lay, V)
     # one sample, triangle layout: nothing to do, NULL outputs accepted
     g1 = _g(1, 50)
     rc = lib.pg_ibs_matrix(ctypes.byref(g1), None, 0, 0, 0, N.PG_TRI_UPPER, 0, None, None, None,
@@ -181,6 +194,15 @@ def test_batch_plan_validation_names_problem():
     arr[2].path = N.PG_PATH_SPARSE      # the correction path is for one-problem calls
     rc = lib.pg_batch_plan(arr, 3, ctypes.byref(plan))
     assert rc == N.PG_EUNSUPPORTED and "problem 2" in N.last_error()
+    arr[2].path = 0
+    arr[1].g = _g(100, 65536)          # 16-bit counts need fewer than 65,536 variants
+    arr[1].out_layout = N.PG_TRI_UPPER | N.PG_COUNTS_U16
+    rc = lib.pg_batch_plan(arr, 3, ctypes.byref(plan))
+    assert rc == N.PG_EINVAL and "problem 1" in N.last_error()
+    arr[1].g = _g(100, 65535)
+    rc = lib.pg_batch_plan(arr, 3, ctypes.byref(plan))
+    assert rc == N.PG_OK and plan.value
+    lib.pg_plan_free(plan)
 
 
 def _prune_ws(g, W, n_sel=0, vb=0, ve=0, path=0):

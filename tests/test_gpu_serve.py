@@ -120,7 +120,7 @@ def test_serving_workload_cohorts():
     for k, p in enumerate(picks):
         r = by_rid[p.rid]
         n, V = shapes[r.cohort]
-        raw = r.result if r.kind == "ld" else tuple(x.view(np.int32) for x in r.result)
+        raw = r.result
         assert _digest(raw if isinstance(raw, tuple) else [raw]) == dig[r.rid]
         codes = oracle.select(oracle.unpack(beds[r.cohort], n, V), r.sample_idx, *r.v_range)
         if r.kind == "ld":
