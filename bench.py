@@ -401,7 +401,7 @@ def bench_serve(torch, pg, synth, dev, seconds, serial_seconds, rates, rate_seco
     0.2); subsets of 100-5,000 samples, ranges of 1k-20k variants.  The
     8-slot server and one request at a time run the same arrivals for the
     same time; then both at higher arrival rates (`rates`, `rate_seconds`
-    each), and the server once more at the highest rate under a 512 MiB
+    each), and the server once more at the highest rate under a 384 MiB
     memory budget, where admission has to hold requests back."""
     import numpy as np
     from paper_1410_4803_amd.serve import GpuBackend, Server, poisson_requests
@@ -447,9 +447,9 @@ def bench_serve(torch, pg, synth, dev, seconds, serial_seconds, rates, rate_seco
                       "serial_one_at_a_time": run(1, rate, rate_seconds)})
     tight = None
     if rates:
-        log(f"serving {rate_seconds} s of {max(rates)} requests/s with a 512 MiB budget")
-        tight = run(8, max(rates), rate_seconds, mem=512 << 20)
-        tight["memory_budget"] = 512 << 20
+        log(f"serving {rate_seconds} s of {max(rates)} requests/s with a 384 MiB budget")
+        tight = run(8, max(rates), rate_seconds, mem=384 << 20)
+        tight["memory_budget"] = 384 << 20
     return {"workload": "serve_8_cohorts_poisson200", "cohorts": shapes,
             "resident_bytes": resident, "memory_budget": budget, "seconds": seconds,
             "requests": st["requests"], "server_8_slots": st,
