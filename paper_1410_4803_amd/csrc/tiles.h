@@ -811,8 +811,8 @@ __device__ __forceinline__ void ibs_popc_tile(const uint32_t* __restrict__ P, in
 
 
 // ---- matrix-core path, fp4 operands -----------------------------------------------
-// The same four Grams on the fp4 (e2m1) matrix cores: v_mfma_scale_f32_32x32x64_f8f6f4
-// with both operands in fp4 and unit scales.  Every feature value is -1, 0 or
+// The same four Grams on the fp4 (e2m1) matrix cores: v_mfma_f32_32x32x64_f8f6f4
+// with both operands in fp4, unscaled (mfma_fp4).  Every feature value is -1, 0 or
 // +1, exact in e2m1 (0b0010 = 1.0, 0b1010 = -1.0); every partial sum is an
 // integer of magnitude <= V, exact in the fp32 accumulator while V < 2^24
 // (the caller falls back to the int8 kernel above that).  One MFMA lane holds
@@ -858,9 +858,13 @@ struct Fp4Acc {
   v16f m[2][2], w[2][2], hc[2][2];
 };
 
+// Formats 4/4 = e2m1 for A and B, scale operands 0: the compiler then emits
+// the unscaled v_mfma_f32_32x32x64_f8f6f4 (one 64-bit instruction, no scale
+// register), which computes the plain product.  With unit scales written out
+// (127 in e8m0) it emits the scaled form, a 128-bit instruction pair that
+// issues more slowly: 4% on the IBS tile, the same results.
 __device__ __forceinline__ v16f mfma_fp4(const v8i& a, const v8i& b, const v16f& c) {
-  // formats 4/4 = e2m1 for A and B; scales 127 = 2^0 in e8m0
-  return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 4, 4, 0, 127, 0, 127);
+  return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 4, 4, 0, 0, 0, 0);
 }
 
 __device__ __forceinline__ void fp4_step(Fp4Acc& acc, const Fp4Feat (&fa)[2],
@@ -1517,7 +1521,7 @@ __device__ __forceinline__ void ld_mfma_tile(const uint32_t* __restrict__ D, int
 
 
 // Pipelined fp4 form of the banded matrix-core tile (the default LD kernel):
-// the same six Grams on v_mfma_scale_f32_32x32x64_f8f6f4 with e2m1 operands
+// the same six Grams on v_mfma_f32_32x32x64_f8f6f4 with e2m1 operands
 // (m, x, h are 0 or +-1, exact; fp32 sums exact below 2^24 samples), and
 // the chunk schedule of ibs_fp4_tile_pipe: a chunk of 256 samples is four
 // steps of 64 per MFMA lane (two 2-bit words), chunk k + 2 is fetched and
