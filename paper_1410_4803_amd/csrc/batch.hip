@@ -50,13 +50,20 @@ struct BatchItem {
 // block per CU (the matrix-core tile's register budget), then LD matrix-core
 // tiles, then LD popcount tiles.
 enum { kPartIbs = 0, kPartLdMfma = 1, kPartLdPopc = 2, kParts = 3 };
+constexpr int kCounters = 8 + kParts - 1;   // 8 XCD runs of the IBS part, one per LD part
 
 __host__ __device__ inline int batch_part(int kind, int path) {
   return kind == PG_KIND_IBS ? kPartIbs : path == PG_PATH_MFMA ? kPartLdMfma : kPartLdPopc;
 }
 
 // Persistent loop over the tiles [t_begin, t_end) of the global list: every
-// block takes tiles from `counter` until the range is used up.
+// block takes tiles from `counter` until the range is used up.  The IBS part
+// is XCD-aware, as the one-problem launch is: its range is cut into 8
+// contiguous runs with a counter each (counter[0..7]), block b takes tiles
+// from run b % 8 (the XCD it runs on) and, once that run is used up, from
+// the other runs in turn; within a problem the tiles go in the banded order
+// (valid_band_tile), so the tiles one XCD runs together share operand rows
+// in its L2.
 template <int kPart>
 __global__ __launch_bounds__(256, kPart == kPartIbs ? 1 : 2) void k_batch_persistent(
     const BatchItem* __restrict__ items, int n_items, int64_t t_begin, int64_t t_end,
@@ -66,8 +73,28 @@ __global__ __launch_bounds__(256, kPart == kPartIbs ? 1 : 2) void k_batch_persis
                             : kPart == kPartLdMfma ? kLdMfmaSmem : kLdPopcSmem;
   __shared__ __attribute__((aligned(16))) uint32_t smem[kSmem];
   __shared__ int64_t s_tile;
+  const int xcd = (int)(blockIdx.x % 8);
+  unsigned used = 0;   // IBS: runs found used up (thread 0 only)
   for (;;) {
-    if (threadIdx.x == 0) s_tile = t_begin + (int64_t)atomicAdd(counter, 1ull);
+    if (threadIdx.x == 0) {
+      if constexpr (kPart == kPartIbs) {
+        const int64_t n = t_end - t_begin;
+        int64_t got = t_end;
+        for (int k = 0; k < 8; ++k) {
+          const int y = (xcd + k) & 7;
+          if (used & (1u << y)) continue;
+          const int64_t v = t_begin + n * y / 8 + (int64_t)atomicAdd(&counter[y], 1ull);
+          if (v < t_begin + n * (y + 1) / 8) {
+            got = v;
+            break;
+          }
+          used |= 1u << y;
+        }
+        s_tile = got;
+      } else {
+        s_tile = t_begin + (int64_t)atomicAdd(counter, 1ull);
+      }
+    }
     __syncthreads();
     const int64_t t = s_tile;
     __syncthreads();
@@ -81,7 +108,7 @@ __global__ __launch_bounds__(256, kPart == kPartIbs ? 1 : 2) void k_batch_persis
     const int64_t local = t - it.tile_begin;
     if constexpr (kPart == kPartIbs) {
       int64_t I, J;
-      tri_tile(local, it.nt, I, J);
+      valid_band_tile(local, it.nt, I, J);
       if (it.path == PG_PATH_MFMA) {
         if (it.variant == kIbsVariantFp4Pipe)
           ibs_fp4_tile_pipe(it.X, it.words, I, J, it.o, (lds_t*)smem);
@@ -252,7 +279,7 @@ int pg_batch_plan(const pg_problem* probs, int n_probs, pg_plan** out) {
     }
   }
   plan->off_jobs = take(off, (int64_t)sizeof(LayoutJob) * std::max(plan->n_jobs, 1));
-  plan->off_counter = take(off, 8 * kParts);   // one tile counter per kernel
+  plan->off_counter = take(off, 8 * kCounters);   // tile counters: 8 (IBS) + 2 (LD)
   plan->bytes = off;
   // persistent grids: resident blocks of each kernel on this device
   auto resident = [](const void* kernel, int64_t tiles) {
@@ -396,7 +423,7 @@ int pg_batch_launch(const pg_plan* plan, void* workspace, size_t workspace_bytes
     if (rc != PG_OK) return rc;
   }
   if (pb[1] > pb[0]) {
-    rc = fill_u32((uint32_t*)counter, 2, 0u, st);
+    rc = fill_u32((uint32_t*)counter, 16, 0u, st);
     if (rc != PG_OK) return rc;
     hipLaunchKernelGGL(k_batch_persistent<kPartIbs>, dim3((unsigned)plan->grid[kPartIbs]),
                        dim3(256), 0, st, items, n_items, pb[0], pb[1], counter);
@@ -418,15 +445,15 @@ int pg_batch_launch(const pg_plan* plan, void* workspace, size_t workspace_bytes
     if (rc != PG_OK) return rc;
   }
   if (pb[3] > pb[1]) {
-    rc = fill_u32((uint32_t*)(counter + 1), 2 * (kParts - 1), 0u, side);
+    rc = fill_u32((uint32_t*)(counter + 8), 2 * (kParts - 1), 0u, side);
     if (rc != PG_OK) return rc;
   }
   if (pb[2] > pb[1])
     hipLaunchKernelGGL(k_batch_persistent<kPartLdMfma>, dim3((unsigned)plan->grid[kPartLdMfma]),
-                       dim3(256), 0, side, items, n_items, pb[1], pb[2], counter + 1);
+                       dim3(256), 0, side, items, n_items, pb[1], pb[2], counter + 8);
   if (pb[3] > pb[2])
     hipLaunchKernelGGL(k_batch_persistent<kPartLdPopc>, dim3((unsigned)plan->grid[kPartLdPopc]),
-                       dim3(256), 0, side, items, n_items, pb[2], pb[3], counter + 2);
+                       dim3(256), 0, side, items, n_items, pb[2], pb[3], counter + 9);
   rc = check_launch("batch_persistent_ld");
   if (rc != PG_OK) return rc;
   for (int k : plan->order) {
