@@ -429,8 +429,23 @@ __device__ __forceinline__ double ld_r2(int64_t n, int64_t sx, int64_t sy, int64
 // * (1 - 2^-50)) then c^2 / den < r2_min (1 - 2^-51), whose rounding is still
 // below r2_min, so the test fails exactly as the full evaluation would.
 // NaN r2 (n, va or vb zero) never passes.
+//
+// Before that, a cheaper test rejects most pairs: below 2^15 samples every
+// sum is below 2^15 in magnitude, so c, va and vb are exact in int32 (each
+// product below 2^30).  In float each conversion and product is within
+// 2^-24 relative (nine roundings in all), so fl(c)^2 < fl(fl(r2_min) *
+// fl(va) fl(vb)) (1 - 2^-16) implies c^2 / (va vb) < r2_min (1 - 2^-17),
+// which the double route also rounds below r2_min.  NaN and infinite
+// products compare false and fall through.
 __device__ __forceinline__ bool ld_r2_reaches(int64_t n, int64_t sx, int64_t sy, int64_t sxx,
                                               int64_t syy, int64_t sxy, double r2_min) {
+  if (n < (1 << 15) && r2_min > 0.0) {
+    const int32_t ni = (int32_t)n, x = (int32_t)sx, y = (int32_t)sy;
+    const float c = (float)(ni * (int32_t)sxy - x * y);
+    const float va = (float)(ni * (int32_t)sxx - x * x);
+    const float vb = (float)(ni * (int32_t)syy - y * y);
+    if (c * c < (float)r2_min * (va * vb) * (1.0f - 0x1p-16f)) return false;
+  }
   if (n >= ((int64_t)1 << 26)) return ld_r2_wide(n, sx, sy, sxx, syy, sxy) >= r2_min;
   const double dn = (double)(int)n, dx = (double)(int)sx, dy = (double)(int)sy;
   const double c = __dsub_rn(__dmul_rn(dn, (double)(int)sxy), __dmul_rn(dx, dy));
