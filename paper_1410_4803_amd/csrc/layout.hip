@@ -96,11 +96,14 @@ __device__ __forceinline__ void row_words16(const Sel& s, const int64_t (&v)[N],
   }
 }
 
-// Sample-major 2-bit words without a sample list, 512 samples x 512 variants
+// Sample-major 2-bit words without a sample list, 512 samples x 256 variants
 // per block: lanes read consecutive words of one .bed row (whole lines), the
-// 16x16 transposes land in LDS, and the block writes 128-byte runs of T rows.
+// 16x16 transposes land in LDS, and the block writes 64-byte runs of T rows.
+// The block's 34 KB of LDS let four blocks share a CU (512 x 512 blocks, 68
+// KB: two per CU, 17% slower at 10,000 x 100,000).
 // Samples past the matrix and variants past the selection are missing calls.
-constexpr int kSmTW = 32;            // T words (16 variants) and sample groups per block
+constexpr int kSmTG = 32;            // sample groups (16 samples) per block
+constexpr int kSmTW = 16;            // T words (16 variants) per block
 constexpr int kSmTS = kSmTW + 1;     // LDS row stride (words)
 
 // Block `bid` of the tiled layout of one operand.
@@ -108,14 +111,14 @@ __device__ __forceinline__ void sample_major_tiled_block(const Sel& s, uint32_t*
                                                          int64_t rows_pad, int64_t wp,
                                                          int aligned, int64_t bid,
                                                          uint32_t* s_out) {
-  const int64_t nb_g = ceil_div(rows_pad / 16, kSmTW);
-  const int64_t g0 = (bid % nb_g) * kSmTW;   // sample group (16 samples)
+  const int64_t nb_g = ceil_div(rows_pad / 16, kSmTG);
+  const int64_t g0 = (bid % nb_g) * kSmTG;   // sample group (16 samples)
   const int64_t a0 = (bid / nb_g) * kSmTW;   // T word (16 variants)
   const int t = threadIdx.x;
-  const int gl = t % kSmTW;
+  const int gl = t % kSmTG;
 #pragma unroll 1
-  for (int i = 0; i < 4; ++i) {
-    const int al = t / kSmTW + 8 * i;
+  for (int i = 0; i < kSmTW / 8; ++i) {
+    const int al = t / kSmTG + 8 * i;
     const int64_t a = a0 + al, g = g0 + gl;
     int64_t vr[16], gr[16];
 #pragma unroll
@@ -124,21 +127,21 @@ __device__ __forceinline__ void sample_major_tiled_block(const Sel& s, uint32_t*
     row_words16(s, vr, gr, aligned != 0, x);
     transpose16_2bit(x);
 #pragma unroll
-    for (int c = 0; c < 16; ++c) s_out[(c * kSmTW + gl) * kSmTS + al] = x[c];
+    for (int c = 0; c < 16; ++c) s_out[(c * kSmTG + gl) * kSmTS + al] = x[c];
   }
   __syncthreads();
-  const int lane = t & 63, wave = t >> 6;
-  for (int row = 2 * wave + (lane >> 5); row < 16 * kSmTW; row += 8) {
-    const int64_t k = 16 * g0 + row, a = a0 + (lane & 31);
-    if (k < rows_pad && a < wp)   // T row 16 gl + c is LDS row c * kSmTW + gl
-      T[k * wp + a] = s_out[((row & 15) * kSmTW + (row >> 4)) * kSmTS + (lane & 31)];
+  for (int e = t; e < 16 * kSmTG * kSmTW; e += 256) {
+    const int row = e / kSmTW, col = e % kSmTW;
+    const int64_t k = 16 * g0 + row, a = a0 + col;
+    if (k < rows_pad && a < wp)   // T row 16 gl + c is LDS row c * kSmTG + gl
+      T[k * wp + a] = s_out[((row & 15) * kSmTG + (row >> 4)) * kSmTS + col];
   }
 }
 
 __global__ __launch_bounds__(256) void k_sample_major_tiled(Sel s, uint32_t* __restrict__ T,
                                                             int64_t rows_pad, int64_t wp,
                                                             int aligned) {
-  __shared__ uint32_t s_out[16 * kSmTW * kSmTS];
+  __shared__ uint32_t s_out[16 * kSmTG * kSmTS];
   // blocks of one XCD take consecutive sample groups of the same variants, so
   // the row pieces that straddle two blocks' reads meet in that XCD's L2
   sample_major_tiled_block(s, T, rows_pad, wp, aligned, xcd_swizzle(blockIdx.x, gridDim.x),
@@ -149,7 +152,7 @@ __global__ __launch_bounds__(256) void k_sample_major_tiled(Sel s, uint32_t* __r
 // job whose block range holds b (jobs in increasing block_begin).
 __global__ __launch_bounds__(256) void k_sample_major_jobs(const LayoutJob* __restrict__ jobs,
                                                            int n_jobs) {
-  __shared__ uint32_t s_out[16 * kSmTW * kSmTS];
+  __shared__ uint32_t s_out[16 * kSmTG * kSmTS];
   const int64_t b = blockIdx.x;
   int lo = 0, hi = n_jobs - 1;
   while (lo < hi) {   // the last job with block_begin <= b
@@ -161,7 +164,7 @@ __global__ __launch_bounds__(256) void k_sample_major_jobs(const LayoutJob* __re
 }
 
 int64_t sample_major_job_blocks(int64_t rows_pad, int64_t wp) {
-  return ceil_div(wp, kSmTW) * ceil_div(rows_pad, 16 * kSmTW);
+  return ceil_div(wp, kSmTW) * ceil_div(rows_pad, 16 * kSmTG);
 }
 
 int launch_sample_major_jobs(const LayoutJob* jobs, int n_jobs, int64_t total_blocks,
