@@ -41,6 +41,8 @@ IBS_POPC_OPS = 8 / 32         # per 32-variant word: AND, 2 XOR, 2 bitop3, 3 pop
 LD_MFMA_OPS = 6 * 2           # six int8 contractions
 LD_POPC_OPS = 16 / 32         # 16 VALU ops per 32-sample word
 LD_INT8 = 2 | (1 << 8)         # the LD matrix-core path's int8 tile (variant 1)
+LD_SPARSE_ALL = 3 | (1 << 8)   # the correction path on every tile (variant 1)
+LD_PATH_NAMES = {LD_INT8: "mfma_int8", LD_SPARSE_ALL: "sparse_all_tiles"}
 IBS_FP4_KERNELS = "k_ibs_head<true>+k_ibs_tail<true>+k_ibs_tail_reduce"
 IBS_INT8_KERNELS = "k_ibs_head<false>+k_ibs_tail<false>+k_ibs_tail_reduce"
 
@@ -698,7 +700,8 @@ def main():
         cap = 4_000_000
         ol = torch.empty((cap, 64), dtype=torch.uint8, device=dev)
         nl = torch.empty(1, dtype=torch.int64, device=dev)
-        for wl, key, lpaths in ((synth.ld_large(), "ld_large", ("mfma", "sparse", "popc", LD_INT8)),
+        for wl, key, lpaths in ((synth.ld_large(), "ld_large",
+                                 ("mfma", "sparse", LD_SPARSE_ALL, "popc", LD_INT8)),
                                 (synth.ld_large_nomiss(), "ld_large_nomiss", ("mfma", "sparse"))):
             log(f"timing LD windows on {wl['name']}")
             cl = pg.Cohort.from_numpy(wl["bed"], wl["n"], device=dev)
@@ -743,7 +746,7 @@ def main():
                                        "traffic": traffic_from_profile("k_ld_popc")}
                 else:
                     rec["vs_mfma"] = round(extras[f"{key}_mfma"]["ms_per_step"] / msl, 3)
-                rec["path"] = lpath if isinstance(lpath, str) else "mfma_int8"
+                rec["path"] = lpath if isinstance(lpath, str) else LD_PATH_NAMES[lpath]
                 extras[f"{key}_{rec['path']}"] = rec
                 del wkl
             del cl

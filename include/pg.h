@@ -137,14 +137,13 @@ enum pg_path {
                        one of its variants has more missing calls than a
                        list slot holds (max(64, ceil(m/16) rounded up to a
                        multiple of 8), at most 65,528, for m selected
-                       samples) or its 128 variants have more than m/4 in
+                       samples) or its 128 variants have more than 3m/8 in
                        all, and every tile does unless a quarter of the
                        64-variant groups pass these tests on their own
                        (then the extra sample-major operand pays).  Exact
                        like the other paths; not available in batches.
-                       Variant bits: 1 drops the last two rules; 4 forces
-                       the 64-bit gather addressing that operands above
-                       4 GiB use anyway; 2 (pg_ld_window only) is a
+                       Variant bits: 1 drops the last two rules; 2
+                       (pg_ld_window only) is a
                        diagnostic that implies 1: no
                        emission; every pair (a, b) of a tile the path takes
                        (under variant 1's rule) gets the kernel's own record

@@ -241,19 +241,21 @@ int plan_ld(const Sel& s, int32_t window, int path_arg, LdPlan& p) {
 }
 
 // Variant bits of the correction path: every tile whose lists fit (1), the
-// diagnostic records (2, implies 1), 64-bit gather addressing (4; always on
-// when the sample-major operand exceeds 4 GiB).
-constexpr int kLdAllTiles = 1, kLdDiag = 2, kLdWide = 4;
+// diagnostic records (2, implies 1).
+constexpr int kLdAllTiles = 1, kLdDiag = 2;
 
 // Band tiles take the correction path when their two 64-variant groups hold
-// at most m/4 missing calls (m selected samples), and only once a quarter
+// at most 3m/8 missing calls (m selected samples), and only once a quarter
 // of the groups have a diagonal tile that does, so that the sample-major
-// operand is worth building.  Measured on 5,000 samples, window 1,000: the
-// correction kernel costs as much as the pipelined fp4 dense kernel at
-// about 0.28m missing calls per tile (0.22% of the calls), and 1.5x less
-// without missing calls.
+// operand is worth building.  Measured on 5,000 samples x 500,000 variants,
+// window 1,000, every tile forced onto the correction kernel: 4.1 ms without
+// missing calls, 5.4 ms at 0.25% (0.32m per tile), 6.1 ms at 0.5% (0.64m),
+// 7.3 ms at 1%, against 6.1-6.2 ms for the pipelined fp4 dense kernel.  Per
+// tile the two cost the same near 0.6m; the rule stops at 3m/8 so that the
+// tiles' savings also pay for building T and the longer statistics pass
+// (0.7 ms together at this size).
 int64_t ld_sparse_budget(const LdPlan& p, int64_t m) {
-  return p.variant & (kLdAllTiles | kLdDiag) ? INT64_MAX : m / 4;
+  return p.variant & (kLdAllTiles | kLdDiag) ? INT64_MAX : 3 * m / 8;
 }
 uint32_t ld_sparse_min_groups(const LdPlan& p) {
   const int64_t g = p.rows_pad / kLdTile;
@@ -283,15 +285,14 @@ int ld_pairs(const Sel& s, const LdPlan& p, char* ws, int32_t window, double r2_
   }
   LdSparse sp{(uint32_t*)(ws + p.off_lists), (int4*)(ws + p.off_vst), (int64_t*)(ws + p.off_gsum),
               (int*)(ws + p.off_gmax), (uint32_t*)(ws + p.off_any), ld_sparse_min_groups(p),
-              p.cap, ld_sparse_budget(p, s.m),
-              (p.variant & kLdWide) != 0 || p.t_rows * p.t_words * 4 > (int64_t)UINT32_MAX};
+              p.cap, ld_sparse_budget(p, s.m)};
   uint32_t* T = (uint32_t*)(ws + p.off_T);
-  if (rc == PG_OK) rc = launch_ld_sparse_stats(D, p.words, p.t_words, s.m, s.nv, p.rows_pad, sp, st);
+  if (rc == PG_OK) rc = launch_ld_sparse_stats(D, p.words, s.m, s.nv, p.rows_pad, sp, st);
   // the sample-major operand only when the path is on
   if (rc == PG_OK) rc = launch_ld_transpose(D, p.rows_pad, p.words, T, p.t_rows, p.t_words, sp, st);
   mark_stage(1, st);
   if (rc != PG_OK) return rc;
-  return launch_ld_sparse(D, p.words, T, p.t_words, s.m, s.nv, p.rows_pad, window, r2_min, sc, sp,
+  return launch_ld_sparse(D, p.words, T, p.t_rows, s.m, s.nv, p.rows_pad, window, r2_min, sc, sp,
                           st, dbg, s.v0);
 }
 

@@ -13,10 +13,14 @@
 // and Sxy is one int8 Gram over all samples on the matrix cores.  Every sum
 // stays an exact integer.
 //
-// A correction is one gather per missing call and 16 variants: a word of the
-// sample-major operand T holds the codes of 16 consecutive variants at one
-// sample, and their per-variant counts of homozygous A1, homozygous A2 and
-// missing codes grow as bytes, one byte-permute lookup per four variants.
+// A correction reads one word per missing call and 16 variants: a word of
+// the sample-major operand T holds the codes of 16 consecutive variants at
+// one sample, and their per-variant counts of homozygous A1, homozygous A2
+// and missing codes grow as bytes, one byte-permute lookup per four variants.
+// T is stored in strips of 64 variants (a tile's side), so one tile side at
+// one sample is 16 contiguous bytes and the samples of a strip are adjacent:
+// the missing calls of a tile read from two contiguous runs, and a line
+// fetched for one sample holds the tile's codes at seven neighbouring ones.
 //
 // Tiles are the 64 x 64 variant tiles of the dense kernel.  A tile takes
 // this path when all of its variants have at most `cap` missing calls (the
@@ -36,12 +40,10 @@ namespace pg {
 // Per-variant missing-call list, count and totals: one wave per variant row
 // of the variant-major operand D (padding samples are missing calls and are
 // not listed; padding variants get zero counts and empty lists).  A list
-// entry is the byte offset k * row_bytes of sample k's row of T, or k itself
-// when T is too large for 32-bit offsets (kWide).
-template <bool kWide>
+// entry is the sample index.
 __global__ __launch_bounds__(256) void k_ld_vstats(const uint32_t* __restrict__ D, int64_t wn,
                                                    int64_t m, int64_t nv, int64_t rows_pad, int cap,
-                                                   int64_t row_bytes, uint32_t* __restrict__ lists,
+                                                   uint32_t* __restrict__ lists,
                                                    int4* __restrict__ vst) {
   const int lane = threadIdx.x & 63;
   const int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -87,7 +89,7 @@ __global__ __launch_bounds__(256) void k_ld_vstats(const uint32_t* __restrict__ 
       while (miss) {
         const int bit = __ffs(miss) - 1;
         const int64_t smp = 16 * w + (bit >> 1);
-        if (pos < cap) list[pos] = kWide ? (uint32_t)smp : (uint32_t)(smp * row_bytes);
+        if (pos < cap) list[pos] = (uint32_t)smp;
         ++pos;
         miss &= miss - 1;
       }
@@ -140,25 +142,23 @@ __global__ __launch_bounds__(256) void k_ld_groups(const int4* __restrict__ vst,
 }
 
 constexpr int kSpS = 65;          // LDS row stride of the per-pair cells (words)
-constexpr int kSpBatch = 8;       // gathers per lane and batch
-constexpr int kSpFlush = 248;     // gathers between byte-counter flushes (< 256)
+constexpr int kSpBatch = 8;       // missing calls per lane and batch
+constexpr int kSpFlush = 248;     // missing calls between byte-counter flushes (< 256)
 
 __device__ __forceinline__ uint32_t gather_word(const uint32_t* p) { return *p; }
-__device__ __forceinline__ uint2 gather_word(const uint2* p) { return *p; }
 
 // Walks one lane's missing-call list (cnt entries; the wave's longest list
 // has cmax) in batches of kSpBatch and hands each batch of gathered words to
-// consume(); the word of entry x is at base + offset(x) + lane_bytes, with
-// offset(x) = x (byte offset) or x * row_bytes (kWide: x is the sample).
-// Lanes past their list get `idle`.  Two stages in flight: the entries of
-// batch j + 2 and the words of batch j + 1 load while batch j is counted.
-// List slots hold a multiple of kSpBatch entries and cmax does not exceed
-// the slot, so every list read stays inside the slot (entries past cnt are
-// read but not used).
-template <bool kWide, typename W, typename F>
+// consume(); the word of sample k is at base + 16 k + lane_bytes (one strip
+// of T).  Lanes past their list get `idle`.  Two stages in flight: the
+// entries of batch j + 2 and the words of batch j + 1 load while batch j is
+// counted.  List slots hold a multiple of kSpBatch entries and cmax does not
+// exceed the slot, so every list read stays inside the slot (entries past
+// cnt are read but not used).
+template <typename W, typename F>
 __device__ __forceinline__ void gather_list(const uint32_t* __restrict__ list, int cnt, int cmax,
-                                            const char* __restrict__ base, int64_t row_bytes,
-                                            uint32_t lane_bytes, W idle, F&& consume) {
+                                            const char* __restrict__ base, uint32_t lane_bytes,
+                                            W idle, F&& consume) {
   const int nb = (cmax + kSpBatch - 1) / kSpBatch;
   if (nb == 0) return;
   uint32_t ks[kSpBatch];
@@ -172,8 +172,7 @@ __device__ __forceinline__ void gather_list(const uint32_t* __restrict__ list, i
   auto load_w = [&](int j) {
 #pragma unroll
     for (int u = 0; u < kSpBatch; ++u) {
-      const char* p = kWide ? base + (int64_t)ks[u] * row_bytes + lane_bytes
-                            : base + (ks[u] + lane_bytes);
+      const char* p = base + (((uint64_t)ks[u] << 4) + lane_bytes);
       w[u] = j * kSpBatch + u < cnt ? gather_word(reinterpret_cast<const W*>(p)) : idle;
     }
   };
@@ -220,14 +219,13 @@ __device__ __forceinline__ void count_batch(const uint32_t (&words)[kSpBatch], u
   }
 }
 
-template <bool kWide>
 __global__ __launch_bounds__(256, 3) void k_ld_sparse(
-    const uint32_t* __restrict__ D, int64_t wn, const uint32_t* __restrict__ T, int64_t tw,
+    const uint32_t* __restrict__ D, int64_t wn, const uint32_t* __restrict__ T, int64_t t_rows,
     const uint32_t* __restrict__ lists, const int4* __restrict__ vst,
     const int64_t* __restrict__ gsum, const int* __restrict__ gmax,
     const uint32_t* __restrict__ groups_ok, uint32_t min_groups, int cap, int64_t budget,
-    int64_t m, int64_t nv, int64_t n_row_tiles, int64_t n_band, int32_t window, double r2_min,
-    LdScratch sc, pg_ld_pair* __restrict__ dbg, int64_t v0) {
+    int64_t m, int64_t nv, int64_t n_row_tiles, int64_t n_band, int32_t window,
+    double r2_min, LdScratch sc, pg_ld_pair* __restrict__ dbg, int64_t v0) {
   const int64_t blk = xcd_swizzle(blockIdx.x, gridDim.x);
   const int64_t I = blk / n_band;
   const int64_t J = I + blk % n_band;
@@ -235,13 +233,16 @@ __global__ __launch_bounds__(256, 3) void k_ld_sparse(
     return;
 
   // per-pair cells: first the Sxy partial sums, then the b-side corrections
+  // (row a, column b); the a-side corrections (row b, column a): homA1 |
+  // homA2 << 16 and the shared missing calls
   __shared__ uint32_t s_cell[kLdTile * kSpS];
+  __shared__ uint32_t s_acell[kLdTile * kSpS];
+  __shared__ uint32_t s_mcell[kLdTile * kSpS];
   const int t = threadIdx.x, lane = t & 63;
   const int wid = __builtin_amdgcn_readfirstlane(t >> 6);
   const int g = lane >> 5, rl = lane & 31;
   const int qi = wid >> 1, qj = wid & 1;   // this wave's 32 x 32 quadrant
-  const int64_t row_bytes = tw * 4;
-  for (int e = t; e < kLdTile * kSpS; e += 256) s_cell[e] = 0;
+  for (int e = t; e < kLdTile * kSpS; e += 256) s_cell[e] = s_acell[e] = s_mcell[e] = 0;
   __syncthreads();
 
   // ---- Sxy: each wave takes a quarter of the samples for the whole tile
@@ -311,12 +312,62 @@ __global__ __launch_bounds__(256, 3) void k_ld_sparse(
     xy[v] = (int)s_cell[(32 * qi + 8 * (v >> 2) + 4 * g + (v & 3)) * kSpS + bl];
   __syncthreads();
 
-  // ---- b-side corrections into the cells: lane (16 * wave + lane / 4,
-  // q = lane % 4) owns variant `own` of tile I and the 16 variants of word q
-  // of tile J, counted at the missing calls of `own`.  The first flush
-  // stores, so every cell is written even for an empty list.
+  // ---- corrections.  Lane (16 * wave + lane / 4, q = lane % 4) owns
+  // variant `own` of each tile side and the 16 variants of word q of the
+  // other side.  b-side: at the missing calls of variant own of tile I, the
+  // codes of word q of tile J, into s_cell; the first flush stores, so every
+  // cell is written even for an empty list.  a-side: at the missing calls of
+  // variant own of tile J, the codes of word q of tile I, into s_acell and
+  // s_mcell.  The four lanes of one variant read one 16-byte piece.
+  const int own = 16 * wid + (lane >> 2), q = lane & 3;
+  uint32_t bh1[4] = {0, 0, 0, 0}, bh2[4] = {0, 0, 0, 0}, bms[4];
+  uint32_t ah1[4] = {0, 0, 0, 0}, ah2[4] = {0, 0, 0, 0}, ams[4] = {0, 0, 0, 0};
+  bool first = true;
+  int since_b = 0, since_a = 0;
+  auto flush_b = [&]() {
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int idx = own * kSpS + 16 * q + 4 * e + d;
+        const uint32_t val = ((bh1[d] >> (8 * e)) & 0xFFu) | (((bh2[d] >> (8 * e)) & 0xFFu) << 16);
+        s_cell[idx] = first ? val : s_cell[idx] + val;
+      }
+      bh1[d] = bh2[d] = 0;
+    }
+    first = false;
+  };
+  auto flush_a = [&]() {
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int idx = own * kSpS + 16 * q + 4 * e + d;
+        s_acell[idx] += ((ah1[d] >> (8 * e)) & 0xFFu) | (((ah2[d] >> (8 * e)) & 0xFFu) << 16);
+        s_mcell[idx] += (ams[d] >> (8 * e)) & 0xFFu;
+      }
+      ah1[d] = ah2[d] = ams[d] = 0;
+    }
+  };
+  auto count_b = [&](const uint32_t (&w)[kSpBatch]) {
+    count_batch<false>(w, bh1, bh2, bms);
+    since_b += kSpBatch;
+    if (since_b == kSpFlush) {
+      flush_b();
+      since_b = 0;
+    }
+  };
+  auto count_a = [&](const uint32_t (&w)[kSpBatch]) {
+    count_batch<true>(w, ah1, ah2, ams);
+    since_a += kSpBatch;
+    if (since_a == kSpFlush) {
+      flush_a();
+      since_a = 0;
+    }
+  };
+  const uint32_t* stripI = T + I * t_rows * 4;
+  const uint32_t* stripJ = T + J * t_rows * 4;
   {
-    const int own = 16 * wid + (lane >> 2), q = lane & 3;
     const int cnt = vst[I * kLdTile + own].x;
     int cmax = cnt;
     for (int d = 32; d > 0; d >>= 1) {
@@ -324,83 +375,22 @@ __global__ __launch_bounds__(256, 3) void k_ld_sparse(
       cmax = o > cmax ? o : cmax;
     }
     cmax = __builtin_amdgcn_readfirstlane(cmax);
-    uint32_t h1[4] = {0, 0, 0, 0}, h2[4] = {0, 0, 0, 0}, ms[4];
-    bool first = true;
-    int since = 0;
-    auto flush = [&]() {
-#pragma unroll
-      for (int d = 0; d < 4; ++d) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int idx = own * kSpS + 16 * q + 4 * e + d;
-          const uint32_t val = ((h1[d] >> (8 * e)) & 0xFFu) | (((h2[d] >> (8 * e)) & 0xFFu) << 16);
-          s_cell[idx] = first ? val : s_cell[idx] + val;
-        }
-        h1[d] = h2[d] = 0;
-      }
-      first = false;
-    };
-    gather_list<kWide>(lists + (I * kLdTile + own) * (int64_t)cap, cnt, cmax,
-                       reinterpret_cast<const char*>(T + 4 * J), row_bytes, 4u * q, 0xAAAAAAAAu,
-                       [&](const uint32_t (&w)[kSpBatch]) {
-                         count_batch<false>(w, h1, h2, ms);
-                         since += kSpBatch;
-                         if (since == kSpFlush) {
-                           flush();
-                           since = 0;
-                         }
-                       });
-    if (since || first) flush();
+    gather_list(lists + (I * kLdTile + own) * (int64_t)cap, cnt, cmax,
+                reinterpret_cast<const char*>(stripJ), 4u * q, 0xAAAAAAAAu, count_b);
   }
-
-  // ---- a-side corrections in registers, in the accumulator layout: at the
-  // missing calls of b = bl, the codes of this lane's 16 rows (bytes g and
-  // g + 2 of the quadrant's two T words) are counted per row v.
-  uint32_t wa03[16], wam[8];   // homA1 | homA2 << 16 per v; missing, two v per word
-#pragma unroll
-  for (int v = 0; v < 16; ++v) wa03[v] = 0;
-#pragma unroll
-  for (int v = 0; v < 8; ++v) wam[v] = 0;
   {
-    const int64_t b = J * kLdTile + bl;
-    const int cnt = vst[b].x;
+    const int cnt = vst[J * kLdTile + own].x;
     int cmax = cnt;
     for (int d = 32; d > 0; d >>= 1) {
       const int o = __shfl_xor(cmax, d, 64);
       cmax = o > cmax ? o : cmax;
     }
     cmax = __builtin_amdgcn_readfirstlane(cmax);
-    const uint32_t sel = g ? 0x07050301u : 0x06040200u;
-    uint32_t h1[4] = {0, 0, 0, 0}, h2[4] = {0, 0, 0, 0}, ms[4] = {0, 0, 0, 0};
-    int since = 0;
-    auto flush = [&]() {
-#pragma unroll
-      for (int d = 0; d < 4; ++d) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int v = 4 * e + d;
-          wa03[v] += ((h1[d] >> (8 * e)) & 0xFFu) | (((h2[d] >> (8 * e)) & 0xFFu) << 16);
-          wam[v >> 1] += ((ms[d] >> (8 * e)) & 0xFFu) << (16 * (v & 1));
-        }
-        h1[d] = h2[d] = ms[d] = 0;
-      }
-    };
-    gather_list<kWide>(lists + b * (int64_t)cap, cnt, cmax,
-                       reinterpret_cast<const char*>(T + 4 * I + 2 * qi), row_bytes, 0u,
-                       make_uint2(0xAAAAAAAAu, 0xAAAAAAAAu), [&](const uint2 (&w)[kSpBatch]) {
-                         uint32_t p[kSpBatch];
-#pragma unroll
-                         for (int u = 0; u < kSpBatch; ++u)
-                           p[u] = __builtin_amdgcn_perm(w[u].y, w[u].x, sel);
-                         count_batch<true>(p, h1, h2, ms);
-                         since += kSpBatch;
-                         if (since == kSpFlush) {
-                           flush();
-                           since = 0;
-                         }
-                       });
-    flush();
+    gather_list(lists + (J * kLdTile + own) * (int64_t)cap, cnt, cmax,
+                reinterpret_cast<const char*>(stripI), 4u * q, 0xAAAAAAAAu, count_a);
   }
+  if (since_b || first) flush_b();
+  if (since_a) flush_a();
   __syncthreads();
 
   // ---- pairs
@@ -413,10 +403,10 @@ __global__ __launch_bounds__(256, 3) void k_ld_sparse(
     const int64_t a = I * kLdTile + al;
     if (!(a < b && b - a <= window)) continue;
     const int4 sa = vst[a];
-    const uint32_t pb = s_cell[al * kSpS + bl];
-    const int64_t a1 = wa03[v] & 0xFFFFu, a2 = wa03[v] >> 16;
+    const uint32_t pb = s_cell[al * kSpS + bl], pa = s_acell[bl * kSpS + al];
+    const int64_t a1 = pa & 0xFFFFu, a2 = pa >> 16;
     const int64_t b1 = pb & 0xFFFFu, b2 = pb >> 16;
-    const int64_t both = (wam[v >> 1] >> (16 * (v & 1))) & 0xFFFFu;
+    const int64_t both = s_mcell[bl * kSpS + al];
     const int64_t n = m - sa.x - sb.x + both;
     const int64_t sx = sa.y - (a2 - a1), sy = sb.y - (b2 - b1);
     const int64_t sxx = sa.z - (a2 + a1), syy = sb.z - (b2 + b1), sxy = xy[v];
@@ -436,12 +426,14 @@ __global__ __launch_bounds__(256, 3) void k_ld_sparse(
 constexpr int kTrW = 32;            // words per block side: 512 variants x 512 samples
 constexpr int kTrS = kTrW + 1;      // LDS row stride (words)
 
-// Sample-major operand T (t_rows x tw words) from the variant-major D
-// (rows_pad x wn words): T[k][a] holds the codes of variants 16a..16a+15 at
-// sample k.  A block takes 32 words of each side; lanes read consecutive
-// words of a D row (full lines), the 16x16 transposes land in LDS, and the
-// block writes whole 128-byte runs of T rows.  Variants past rows_pad read
-// as missing.  Does nothing while *gate < gate_min.
+// Sample-major operand T in strips of 64 variants from the variant-major D
+// (rows_pad x wn words): word a (the codes of variants 16a..16a+15) at sample
+// k is T[((a / 4) * t_rows + k) * 4 + a % 4].  A block takes 32 words of each
+// side; lanes read consecutive words of a D row (full lines), the 16x16
+// transposes land in LDS, and each half-wave writes one sample's 32 words as
+// eight 16-byte pieces of eight strips (consecutive samples of a strip are
+// adjacent, so a block fills whole lines).  Variants past rows_pad read as
+// missing.  Does nothing while *gate < gate_min.
 __global__ __launch_bounds__(256) void k_ld_transpose(const uint32_t* __restrict__ D,
                                                       int64_t rows_pad, int64_t wn,
                                                       uint32_t* __restrict__ T, int64_t t_rows,
@@ -473,19 +465,16 @@ __global__ __launch_bounds__(256) void k_ld_transpose(const uint32_t* __restrict
   for (int row = 2 * wave + (lane >> 5); row < 16 * kTrW; row += 8) {
     const int64_t k = 16 * g0 + row, a = a0 + (lane & 31);
     if (k < t_rows && a < tw)   // T row 16 gl + c is LDS row c * kTrW + gl
-      T[k * tw + a] = s_out[((row & 15) * kTrW + (row >> 4)) * kTrS + (lane & 31)];
+      T[((a >> 2) * t_rows + k) * 4 + (a & 3)] =
+          s_out[((row & 15) * kTrW + (row >> 4)) * kTrS + (lane & 31)];
   }
 }
 
-int launch_ld_sparse_stats(const uint32_t* D, int64_t wn, int64_t tw, int64_t m, int64_t nv,
+int launch_ld_sparse_stats(const uint32_t* D, int64_t wn, int64_t m, int64_t nv,
                            int64_t rows_pad, const LdSparse& sp, hipStream_t st) {
   const dim3 grid((unsigned)ceil_div(rows_pad, 4));
-  if (sp.wide)
-    hipLaunchKernelGGL(k_ld_vstats<true>, grid, dim3(256), 0, st, D, wn, m, nv, rows_pad, sp.cap,
-                       tw * 4, sp.lists, sp.vst);
-  else
-    hipLaunchKernelGGL(k_ld_vstats<false>, grid, dim3(256), 0, st, D, wn, m, nv, rows_pad, sp.cap,
-                       tw * 4, sp.lists, sp.vst);
+  hipLaunchKernelGGL(k_ld_vstats, grid, dim3(256), 0, st, D, wn, m, nv, rows_pad, sp.cap, sp.lists,
+                     sp.vst);
   int rc = check_launch("ld_vstats");
   if (rc == PG_OK) rc = fill_u32(sp.groups_ok, 1, 0u, st);
   if (rc != PG_OK) return rc;
@@ -504,7 +493,7 @@ int launch_ld_transpose(const uint32_t* D, int64_t rows_pad, int64_t wn, uint32_
   return check_launch("ld_transpose");
 }
 
-int launch_ld_sparse(const uint32_t* D, int64_t wn, const uint32_t* T, int64_t tw, int64_t m,
+int launch_ld_sparse(const uint32_t* D, int64_t wn, const uint32_t* T, int64_t t_rows, int64_t m,
                      int64_t nv, int64_t rows_pad, int32_t window, double r2_min,
                      const LdScratch& sc, const LdSparse& sp, hipStream_t st, pg_ld_pair* dbg,
                      int64_t v0) {
@@ -516,10 +505,10 @@ int launch_ld_sparse(const uint32_t* D, int64_t wn, const uint32_t* T, int64_t t
   }
   const int64_t n_row_tiles = rows_pad / kLdTile;
   const int64_t n_band = ((int64_t)window + kLdTile - 1) / kLdTile + 1;
-  auto kern = sp.wide ? k_ld_sparse<true> : k_ld_sparse<false>;
-  hipLaunchKernelGGL(kern, dim3((unsigned)(n_row_tiles * n_band)), dim3(256), 0, st, D, wn, T, tw,
-                     sp.lists, sp.vst, sp.gsum, sp.gmax, sp.groups_ok, sp.min_groups, sp.cap,
-                     sp.budget, m, nv, n_row_tiles, n_band, window, r2_min, sc, dbg, v0);
+  hipLaunchKernelGGL(k_ld_sparse, dim3((unsigned)(n_row_tiles * n_band)), dim3(256), 0, st, D, wn,
+                     T, t_rows, sp.lists, sp.vst, sp.gsum, sp.gmax, sp.groups_ok, sp.min_groups,
+                     sp.cap, sp.budget, m, nv, n_row_tiles, n_band, window, r2_min, sc,
+                     dbg, v0);
   rc = check_launch("ld_sparse");
   mark_stage(2, st);
   return rc;

@@ -270,7 +270,7 @@ constexpr int kLdPopcKWords = 16;     // 32-bit plane words per K chunk
 // {c, sum x, sum x^2, 0}, and per 64-variant group the total and largest
 // count.  A tile (I, J) takes the path when ld_tile_sparse holds.
 struct LdSparse {
-  uint32_t* lists;     // rows_pad x cap entries (T byte offsets or sample indices)
+  uint32_t* lists;     // rows_pad x cap entries (sample indices, increasing)
   int4* vst;           // rows_pad
   int64_t* gsum;       // rows_pad / 64
   int* gmax;           // rows_pad / 64
@@ -278,7 +278,6 @@ struct LdSparse {
   uint32_t min_groups; // the path is on when groups_ok reaches this
   int cap;
   int64_t budget;      // largest missing-call total of a tile's two groups
-  bool wide;           // list entries are sample indices (64-bit gather addresses)
 };
 __device__ inline bool ld_tile_sparse(const int64_t* gsum, const int* gmax,
                                       const uint32_t* groups_ok, uint32_t min_groups, int64_t I,
@@ -308,19 +307,21 @@ constexpr int kLdVariantFp4 = 0;
 constexpr int kLdVariantInt8 = 1;
 // Correction path, first part: lists, counts and totals from D
 // (variant-major, wn words), the group statistics and groups_ok.
-int launch_ld_sparse_stats(const uint32_t* D, int64_t wn, int64_t tw, int64_t m, int64_t nv,
+int launch_ld_sparse_stats(const uint32_t* D, int64_t wn, int64_t m, int64_t nv,
                            int64_t rows_pad, const LdSparse& sp, hipStream_t st);
-// The sample-major operand of the gathers, transposed from D (t_rows =
-// round_up(m, 128) rows of tw words); nothing when the path is off.
+// The sample-major operand of the corrections, transposed from D in strips
+// of 64 variants: word w (0-3) of strip s at sample k is T[(s * t_rows + k) *
+// 4 + w] (t_rows = round_up(m, 128); tw words of 16 variants per sample, a
+// multiple of 4); nothing when the path is off.
 int launch_ld_transpose(const uint32_t* D, int64_t rows_pad, int64_t wn, uint32_t* T,
                         int64_t t_rows, int64_t tw, const LdSparse& sp, hipStream_t st);
 // Second part: the dense kernel on the tiles this path leaves, then the
-// correction kernel with D for the Gram and T (sample-major, round_up(m, 128)
-// rows of tw words, built after the first part) for the gathers.  With `dbg`,
+// correction kernel with D for the Gram and T (the strips above, built after
+// the first part) for the corrections.  With `dbg`,
 // the dense kernel is not run and each pair of a correction tile writes its
 // record to dbg[a * window + (b - a - 1)] (a, b local; the record holds
 // v0 + a, v0 + b) instead of the emission test.
-int launch_ld_sparse(const uint32_t* D, int64_t wn, const uint32_t* T, int64_t tw, int64_t m,
+int launch_ld_sparse(const uint32_t* D, int64_t wn, const uint32_t* T, int64_t t_rows, int64_t m,
                      int64_t nv, int64_t rows_pad, int32_t window, double r2_min,
                      const LdScratch& sc, const LdSparse& sp, hipStream_t st,
                      pg_ld_pair* dbg = nullptr, int64_t v0 = 0);

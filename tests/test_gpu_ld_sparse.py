@@ -18,7 +18,6 @@ pg = pytest.importorskip("paper_1410_4803_amd")
 from ldcheck import compare_records as _compare
 
 SPARSE, FORCE, DIAG = 3, 3 | (1 << 8), 3 | (2 << 8)
-WIDE = 4 << 8     # 64-bit gather addressing (what operands above 4 GiB use)
 FIELDS = ("n", "sx", "sy", "sxx", "syy", "sxy")
 
 
@@ -48,10 +47,10 @@ def _r2(s):
     return r2
 
 
-def _diag(c, W, nv, sample_idx=None, v_range=None, wide=False):
+def _diag(c, W, nv, sample_idx=None, v_range=None):
     slots = nv * W
     out = torch.full((slots, 64), 0xFF, dtype=torch.uint8, device="cuda")
-    out, n_out = pg.ld_window(c, W, 0.0, capacity=slots, path=DIAG | (WIDE if wide else 0),
+    out, n_out = pg.ld_window(c, W, 0.0, capacity=slots, path=DIAG,
                               out=out, sample_idx=sample_idx, v_range=v_range)
     assert int(n_out.item()) == slots
     return pg.records_to_numpy(out, slots)
@@ -86,20 +85,18 @@ def _check_diag(rec, codes, W, v0=0):
     return int(taken.sum())
 
 
-@pytest.mark.parametrize("wide", [False, True])
 @pytest.mark.parametrize("n,V,W,miss", [(1, 5, 3, 0.05), (2, 40, 7, 0.05), (17, 65, 64, 0.05),
                                         (63, 130, 65, 0.0), (64, 300, 1, 0.05),
                                         (129, 257, 100, 0.02), (300, 700, 257, 0.01),
                                         (1000, 400, 1000, 0.05)])
-def test_sparse_diag_all_pairs(n, V, W, miss, wide):
+def test_sparse_diag_all_pairs(n, V, W, miss):
     bed = synth.mosaic(n, V, switch=0.02, miss=miss, seed=n + V + W, garbage_pad=True)
     codes = oracle.unpack(bed, n, V)
-    rec = _diag(pg.Cohort.from_numpy(bed, n), W, V, wide=wide)
+    rec = _diag(pg.Cohort.from_numpy(bed, n), W, V)
     assert _check_diag(rec, codes, W) > 0
 
 
-@pytest.mark.parametrize("wide", [False, True])
-def test_sparse_diag_counter_flush(wide):
+def test_sparse_diag_counter_flush():
     """More than 248 missing calls per variant: the byte counters are flushed
     into the per-pair cells more than once."""
     n, V, W = 8192, 200, 64
@@ -107,7 +104,33 @@ def test_sparse_diag_counter_flush(wide):
     codes = oracle.unpack(bed, n, V)
     miss = (codes == 1).sum(axis=1)
     assert miss.max() > 248 and miss.max() <= _cap(n)
-    rec = _diag(pg.Cohort.from_numpy(bed, n), W, V, wide=wide)
+    rec = _diag(pg.Cohort.from_numpy(bed, n), W, V)
+    assert _check_diag(rec, codes, W) == sum(min(W, V - 1 - a) for a in range(V))
+
+
+def test_sparse_diag_long_lists():
+    """Lists of mixed length in one tile: 20 variants with 300 missing calls
+    each (byte-counter flushes), one whose 200 missing calls are consecutive
+    samples (adjacent rows of the strip), one missing only the first and last
+    sample, and light variants."""
+    n, V, W = 8192, 200, 150
+    codes = oracle.unpack(synth.mosaic(n, V, switch=0.02, miss=0.002, seed=71), n, V).copy()
+    rng = np.random.default_rng(72)
+    for v in list(range(0, 10)) + list(range(64, 74)):
+        codes[v, rng.choice(n, 300, replace=False)] = 1
+    codes[130, 4000:4200] = 1
+    codes[131, [0, n - 1]] = 1
+    rec = _diag(pg.Cohort.from_numpy(_pack(codes), n), W, V)
+    assert _check_diag(rec, codes, W) == sum(min(W, V - 1 - a) for a in range(V))
+
+
+def test_sparse_diag_many_samples():
+    """66,000 selected samples: strip offsets past 2^20 bytes, list slots of
+    4,128 entries; the sums stay exact."""
+    n, V, W = 66000, 100, 40
+    bed = synth.mosaic(n, V, switch=0.02, miss=0.002, seed=73)
+    codes = oracle.unpack(bed, n, V)
+    rec = _diag(pg.Cohort.from_numpy(bed, n), W, V)
     assert _check_diag(rec, codes, W) == sum(min(W, V - 1 - a) for a in range(V))
 
 
@@ -133,8 +156,7 @@ def test_sparse_diag_list_slot_boundary():
     _compare(got, ref, -np.inf)
 
 
-@pytest.mark.parametrize("wide", [False, True])
-def test_sparse_diag_mask_selection_range(wide):
+def test_sparse_diag_mask_selection_range():
     n, V, W = 400, 1000, 150
     bed = synth.mosaic(n, V, switch=0.01, miss=0.01, seed=8, garbage_pad=True)
     mask = synth.missing_mask(n, V, 0.03, seed=9)
@@ -144,11 +166,11 @@ def test_sparse_diag_mask_selection_range(wide):
     codes = oracle.select(oracle.unpack(bed, n, V, mask), idx, vb, ve)
     c = pg.Cohort.from_numpy(bed, n, mask)
     rec = _diag(c, W, ve - vb, sample_idx=torch.from_numpy(idx).cuda(), v_range=(vb, ve),
-                wide=wide)
+                )
     assert _check_diag(rec, codes, W, v0=vb) > 0
 
 
-@pytest.mark.parametrize("path", [SPARSE, FORCE, FORCE | WIDE])
+@pytest.mark.parametrize("path", [SPARSE, FORCE])
 def test_sparse_mixed_tiles_emission(path):
     """Variants 600-700 miss 40% of their calls, so their tiles exceed the
     budget (and the list slots); the dense kernel takes those, the correction
