@@ -453,7 +453,10 @@ int pg_peak_rates(void* workspace, size_t workspace_bytes, double* out);
  * kind of tile body (IBS; LD matrix-core; LD popcount).  Each
  * problem's arguments mean exactly what they mean for pg_ibs_matrix /
  * pg_ld_window, and its outputs are identical to a separate call with the
- * same path.  Usage:
+ * same path.  Kernel variants in a batch: IBS matrix-core problems run the
+ * pipelined fp4 tile (the default) or the pipelined int8 tile (variant 7),
+ * any other IBS variant runs the default; LD matrix-core problems run the
+ * fp4 tile (the default) or the int8 tile (variant 1).  Usage:
  *   pg_batch_plan -> pg_batch_workspace_bytes -> (allocate) -> pg_batch_upload
  *   -> pg_batch_launch (any number of times; or pg_batch_capture once and
  *   pg_graph_launch many times) -> pg_plan_free.

@@ -211,11 +211,12 @@ int pg_batch_plan(const pg_problem* probs, int n_probs, pg_plan** out) {
     int rc;
     if (q.p.kind == PG_KIND_IBS) {
       rc = batch_validate_ibs(q.p, q.s, q.path, q.variant, q.rows_pad, q.words);
-      // the persistent kernel hosts the default matrix-core body (pipelined
-      // fp4, or pipelined int8 where fp4 sums could reach 2^24): every
-      // matrix-core variant gives the same counts, and hosting more bodies
-      // would raise the kernel's register and LDS budget for every tile
-      if (rc == PG_OK && q.path == PG_PATH_MFMA) {
+      // the persistent kernel hosts the two pipelined matrix-core bodies
+      // (fp4, the default; int8, variant 7, also the default where fp4 sums
+      // could reach 2^24); every other matrix-core variant gives the same
+      // counts and runs the default body, since hosting more bodies would
+      // raise the kernel's register and LDS budget for every tile
+      if (rc == PG_OK && q.path == PG_PATH_MFMA && q.variant != kIbsVariantPipe) {
         IbsPlan dflt;
         rc = plan_ibs_default(q.s, dflt);
         q.variant = dflt.variant;

@@ -255,8 +255,9 @@ __global__ __launch_bounds__(256, 3) void k_ld_sparse(
     const int64_t ngroups = wn / 8;
     const int64_t q0 = ngroups * wid / 4, q1 = ngroups * (wid + 1) / 4;
     v16i acc00 = (v16i){0}, acc01 = (v16i){0}, acc10 = (v16i){0}, acc11 = (v16i){0};
-    // two register sets, alternating, so the prefetch needs no copies
-    uint4 r0[4], r1[4];
+    // three register sets, rotating, so the prefetch (two groups ahead)
+    // needs no copies
+    uint4 r0[4], r1[4], r2[4];
     auto load = [&](uint4 (&r)[4], int64_t q) {
       r[0] = *reinterpret_cast<const uint4*>(pa + 8 * q);
       r[1] = *reinterpret_cast<const uint4*>(pa + off1 + 8 * q);
@@ -286,11 +287,14 @@ __global__ __launch_bounds__(256, 3) void k_ld_sparse(
       }
     };
     if (q0 < q1) load(r0, q0);
-    for (int64_t q = q0; q < q1; q += 2) {
-      if (q + 1 < q1) load(r1, q + 1);
+    if (q0 + 1 < q1) load(r1, q0 + 1);
+    for (int64_t q = q0; q < q1; q += 3) {
+      if (q + 2 < q1) load(r2, q + 2);
       step(r0);
-      if (q + 2 < q1) load(r0, q + 2);
+      if (q + 3 < q1) load(r0, q + 3);
       if (q + 1 < q1) step(r1);
+      if (q + 4 < q1) load(r1, q + 4);
+      if (q + 2 < q1) step(r2);
     }
     // 32x32 accumulator layout: register v of lane l holds row
     // 8*(v/4) + 4*(l/32) + v%4 and column l%32.

@@ -21,12 +21,15 @@ from . import api
 IBS_CANDIDATES = {"mfma": N.PG_PATH_MFMA, "mfma_int8": N.PG_PATH_MFMA | (7 << 8),
                   "mfma_fp4": N.PG_PATH_MFMA | (3 << 8), "mfma_fp4rep": N.PG_PATH_MFMA | (4 << 8),
                   "mfma_w8": N.PG_PATH_MFMA | (5 << 8), "popc": N.PG_PATH_POPC}
-# inside a batch every matrix-core problem runs the default body, so only the
-# path is worth choosing there
-IBS_BATCH_CANDIDATES = {"mfma": N.PG_PATH_MFMA, "popc": N.PG_PATH_POPC}
-# batches run the matrix-core and popcount LD tiles; one-problem calls (the
-# serving loop) also have the missing-call correction path
-LD_BATCH_CANDIDATES = {"mfma": N.PG_PATH_MFMA, "popc": N.PG_PATH_POPC}
+# a batch hosts the pipelined fp4 and int8 matrix-core tiles and the popcount
+# tile, so the tile and the path are chosen per problem there
+IBS_BATCH_CANDIDATES = {"mfma": N.PG_PATH_MFMA, "mfma_int8": N.PG_PATH_MFMA | (7 << 8),
+                        "popc": N.PG_PATH_POPC}
+# batches run the fp4 and int8 matrix-core and the popcount LD tiles;
+# one-problem calls (the serving loop) also have the missing-call correction
+# path
+LD_BATCH_CANDIDATES = {"mfma": N.PG_PATH_MFMA, "mfma_int8": N.PG_PATH_MFMA | (1 << 8),
+                       "popc": N.PG_PATH_POPC}
 LD_CANDIDATES = {"mfma": N.PG_PATH_MFMA, "mfma_int8": N.PG_PATH_MFMA | (1 << 8),
                  "popc": N.PG_PATH_POPC, "sparse": N.PG_PATH_SPARSE}
 

@@ -39,6 +39,9 @@ def _problems(seed=0):
         pg.IbsProblem(c[6], layout="tri", path="auto"),
         pg.IbsProblem(c[2], layout="full", path=2 | (4 << 8)),
         pg.IbsProblem(c[0], sample_idx=idx[:90], layout="tri", path=2 | (3 << 8)),
+        # the int8 tiles the batch hosts beside the fp4 ones
+        pg.IbsProblem(c[6], layout="full", path=2 | (7 << 8)),
+        pg.LdProblem(c[3], window=200, r2_min=0.0, capacity=200000, path=2 | (1 << 8)),
     ]
     return specs, probs, idx
 
