@@ -746,6 +746,8 @@ def main():
                                        "traffic": traffic_from_profile("k_ld_popc")}
                 else:
                     rec["vs_mfma"] = round(extras[f"{key}_mfma"]["ms_per_step"] / msl, 3)
+                    if lpath == LD_SPARSE_ALL:
+                        rec["traffic_bytes_per_launch"] = traffic_from_profile("k_ld_sparse")
                 rec["path"] = lpath if isinstance(lpath, str) else LD_PATH_NAMES[lpath]
                 extras[f"{key}_{rec['path']}"] = rec
                 del wkl
