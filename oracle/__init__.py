@@ -81,6 +81,8 @@ def _load():
         lib.oracle_genome_terms.restype = None
         lib.oracle_genome.argtypes = [p, i64, i64, p, p, p, i64, p, p, p, p]
         lib.oracle_genome.restype = None
+        lib.oracle_genome_means.argtypes = [p, i64, i64, p, p]
+        lib.oracle_genome_means.restype = None
         lib.oracle_cluster_complete.argtypes = [p, i64, p]
         lib.oracle_cluster_complete.restype = i32
         lib.oracle_threads.argtypes = []
@@ -266,6 +268,17 @@ def genome_terms(x: int, y: int) -> np.ndarray:
     t = np.zeros(5, dtype=np.float64)
     _load().oracle_genome_terms(int(x), int(y), t.ctypes.data)
     return t
+
+
+def genome_means(codes_vm: np.ndarray):
+    """((E00, E10, E20, E11, E21), K): the means of the five terms over the
+    markers of codes_vm with at least 4 observed alleles, and their count."""
+    V, n = codes_vm.shape
+    codes_vm = _c(codes_vm, np.int8)
+    e = np.zeros(5, dtype=np.float64)
+    k = np.zeros(1, dtype=np.int64)
+    _load().oracle_genome_means(codes_vm.ctypes.data, n, V, e.ctypes.data, k.ctypes.data)
+    return e, int(k[0])
 
 
 def genome(codes_vm: np.ndarray, ibs0, ibs1, nonmiss):

@@ -503,11 +503,47 @@ void oracle_genome_terms(int64_t x, int64_t y, double t[5]) {
 }
 
 /*
- * The IBD report for IBS counts over the samples and variants of codes_vm
- * (variant-major, V rows of n codes): per marker with at least 4 observed
- * alleles among these samples, the five terms above, summed in increasing
- * marker order and divided by the number K of such markers (E00, E10, E20,
- * E11, E21).  For each of `count` pairs with jointly non-missing count N:
+ * The means of the five terms above over the markers of codes_vm
+ * (variant-major, V rows of n codes) with at least 4 observed alleles among
+ * these samples: E = {E00, E10, E20, E11, E21} and the number K of such
+ * markers.  Each sum is formed in two levels: the terms of each run of
+ * GENOME_RUN consecutive markers are added in increasing marker order,
+ * starting from 0, then the runs' sums in increasing run order, starting
+ * from 0; each mean is its sum divided by K.
+ */
+#define GENOME_RUN 1024
+void oracle_genome_means(const int8_t* codes_vm, int64_t n, int64_t V, double E[5], int64_t* Kout) {
+  double S[5] = {0, 0, 0, 0, 0}, R[5] = {0, 0, 0, 0, 0};
+  int64_t K = 0;
+  for (int64_t v = 0; v < V; ++v) {
+    int64_t calls = 0, a2 = 0;
+    for (int64_t k = 0; k < n; ++k) {
+      const int8_t c = codes_vm[v * n + k];
+      if (c == MISSING) continue;
+      calls += 1;
+      a2 += dosage(c);
+    }
+    if (2 * calls >= 4) {
+      double t[5];
+      oracle_genome_terms(a2, 2 * calls - a2, t);
+      for (int q = 0; q < 5; ++q) R[q] += t[q];
+      K += 1;
+    }
+    if ((v + 1) % GENOME_RUN == 0 || v == V - 1) {   /* the run ends */
+      for (int q = 0; q < 5; ++q) {
+        S[q] += R[q];
+        R[q] = 0.0;
+      }
+    }
+  }
+  for (int q = 0; q < 5; ++q) E[q] = S[q] / (double)K;
+  *Kout = K;
+}
+
+/*
+ * The IBD report for IBS counts over the samples and variants of codes_vm:
+ * the means E00, E10, E11 and K of oracle_genome_means, then for each of
+ * `count` pairs with jointly non-missing count N:
  *   P0 = IBS0 / N,  P1 = IBS1 / N,
  *   Z0 = min(P0 / E00, 1),
  *   Z1 = (P1 - Z0 E10) / E11, clamped to [0, 1 - Z0],
@@ -518,24 +554,11 @@ void oracle_genome_terms(int64_t x, int64_t y, double t[5]) {
 void oracle_genome(const int8_t* codes_vm, int64_t n, int64_t V, const uint32_t* ibs0,
                    const uint32_t* ibs1, const uint32_t* nonmiss, int64_t count, double* z0,
                    double* z1, double* z2, double* pi_hat) {
-  double S[5] = {0, 0, 0, 0, 0};
+  double E[5];
   int64_t K = 0;
-  for (int64_t v = 0; v < V; ++v) {
-    int64_t calls = 0, a2 = 0;
-    for (int64_t k = 0; k < n; ++k) {
-      const int8_t c = codes_vm[v * n + k];
-      if (c == MISSING) continue;
-      calls += 1;
-      a2 += dosage(c);
-    }
-    if (2 * calls < 4) continue;
-    double t[5];
-    oracle_genome_terms(a2, 2 * calls - a2, t);
-    for (int q = 0; q < 5; ++q) S[q] += t[q];
-    K += 1;
-  }
-  const double E00 = S[0] / (double)K, E10 = S[1] / (double)K;
-  const double E11 = S[3] / (double)K;
+  oracle_genome_means(codes_vm, n, V, E, &K);
+  const double E00 = E[0], E10 = E[1];
+  const double E11 = E[3];
   const int ok = K > 0 && E00 != 0.0 && E11 != 0.0;
 #pragma omp parallel for schedule(static)
   for (int64_t e = 0; e < count; ++e) {

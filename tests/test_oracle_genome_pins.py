@@ -145,3 +145,33 @@ def test_similarity_is_the_rounded_rational():
             continue
         assert s[k] == float(Fraction(2 * int(i2[k]) + int(i1[k]), 2 * int(nm[k])))
         assert abs(s[k] + d[k] - 1.0) <= 2.3e-16
+
+
+def test_means_within_rounding_bound_of_exact_mean():
+    """The five means over 2,500 markers (two full runs of 1,024 and a ragged
+    third): within the rounding bound of the exact rational mean of the same
+    per-marker terms (each term pinned above), and K equals the markers with
+    at least 4 observed alleles, counted directly.  Includes markers with no
+    call, one call and two calls."""
+    rng = np.random.default_rng(21)
+    V, n = 2500, 40
+    codes = rng.choice(np.array([0, 1, 2, 3], dtype=np.int8), size=(V, n),
+                       p=[0.3, 0.05, 0.4, 0.25])
+    codes[7] = 1
+    codes[1500] = 1
+    codes[1500, 3] = 2
+    codes[2100] = 1
+    codes[2100, [0, 9]] = 3
+    E, K = oracle.genome_means(codes)
+    called = (codes != 1).sum(axis=1)
+    use = 2 * called >= 4
+    assert K == int(use.sum()) and K == V - 2 and not use[7] and not use[1500] and use[2100]
+    exact = [Fraction(0)] * 5
+    for v in np.nonzero(use)[0]:
+        a2 = int(np.where(codes[v] == 3, 2, np.where(codes[v] == 2, 1, 0)).sum())
+        t = oracle.genome_terms(a2, 2 * int(called[v]) - a2)
+        exact = [e + Fraction(float(x)) for e, x in zip(exact, t)]
+    for q in range(5):
+        mean = exact[q] / K
+        bound = Fraction(V + 2, 2 ** 53) * mean
+        assert abs(Fraction(float(E[q])) - mean) <= bound, q
