@@ -722,7 +722,8 @@ int pg_ibs_similarity(const uint32_t* ibs1, const uint32_t* ibs2, const uint32_t
 
 namespace {
 // Variant-major operand of the selection (rows_pad x wn words), the five
-// per-marker term columns, the per-marker flags and the six sums.
+// per-marker term columns, the per-marker flags, the six sums and the runs'
+// partial sums.
 struct GenomePlan {
   int64_t rows_pad, wn, off_D, off_terms, off_used, off_sums, bytes;
 };
@@ -733,7 +734,7 @@ void plan_genome(const Sel& s, GenomePlan& p) {
   p.off_D = c.take(p.rows_pad * p.wn * 4);
   p.off_terms = c.take(5 * p.rows_pad * 8);
   p.off_used = c.take(p.rows_pad * 4);
-  p.off_sums = c.take(8 * 8);
+  p.off_sums = c.take(8 * genome_sums_doubles(s.nv));
   p.bytes = c.off;
 }
 }  // namespace

@@ -142,60 +142,67 @@ __global__ __launch_bounds__(256) void k_genome_terms(const uint32_t* __restrict
   used[v] = ok ? 1u : 0u;
 }
 
-// The five sums in increasing marker order and the count K of markers that
-// count; out = {S00, S10, S20, S11, S21, K}.  One block: all threads stage a
-// chunk of the five term columns in LDS (coalesced loads, many in flight),
-// then threads 0..4 each add their column's chunk in order; a marker that
-// does not count, and the padding past the last marker, add +0.0, which
-// leaves a non-negative sum unchanged.  K is an integer count, summed in any
-// order.
-constexpr int kSumChunk = 1024;
-constexpr int kSumPer = 5 * kSumChunk / 256;      // staged values per thread
-__global__ __launch_bounds__(256) void k_genome_sums(const double* __restrict__ terms,
-                                                    const uint32_t* __restrict__ used, int64_t nv,
-                                                    int64_t rows_pad, double* __restrict__ out) {
-  __shared__ double buf[5][kSumChunk + 1];
-  __shared__ unsigned long long kcount;
+// The five sums and the count K of markers that count, in two levels: each
+// run of kSumRun consecutive markers is summed in increasing marker order
+// from 0, then the runs' sums are added in increasing run order from 0.
+// k_genome_run_sums: one block per run; all threads stage the run's five
+// term columns in LDS (coalesced loads), then threads 0..4 each add their
+// column in order; a marker that does not count, and the padding past the
+// last marker, add +0.0, which leaves a non-negative sum unchanged.  It
+// writes part[q * n_runs + r] (q < 5) and the run's count at q = 5.
+constexpr int kSumRun = 1024;
+constexpr int kSumPer = 5 * kSumRun / 256;      // staged values per thread
+__global__ __launch_bounds__(256) void k_genome_run_sums(const double* __restrict__ terms,
+                                                         const uint32_t* __restrict__ used,
+                                                         int64_t nv, int64_t rows_pad,
+                                                         int64_t n_runs,
+                                                         double* __restrict__ part) {
+  __shared__ double buf[5][kSumRun + 1];
+  __shared__ unsigned int kcount;
   const int t = threadIdx.x;
+  const int64_t r = blockIdx.x, c0 = r * kSumRun;
+  const int64_t len = nv - c0 < kSumRun ? nv - c0 : kSumRun;
   if (t == 0) kcount = 0;
-  double S = 0.0;
-  unsigned long long K = 0;
-  // the next chunk is loaded into registers while the current one is summed
-  double nxt[kSumPer];
-  auto fetch = [&](int64_t c0) {
+  double v[kSumPer];
 #pragma unroll
-    for (int r = 0; r < kSumPer; ++r) {
-      const int i = t + 256 * r, q = i / kSumChunk, j = i % kSumChunk;
-      nxt[r] = c0 + j < nv ? terms[q * rows_pad + c0 + j] : 0.0;
-    }
-  };
-  fetch(0);
-  for (int64_t c0 = 0; c0 < nv; c0 += kSumChunk) {
-    const int64_t len = nv - c0 < kSumChunk ? nv - c0 : kSumChunk;
-#pragma unroll
-    for (int r = 0; r < kSumPer; ++r) {
-      const int i = t + 256 * r;
-      buf[i / kSumChunk][i % kSumChunk] = nxt[r];
-    }
-    for (int64_t j = t; j < len; j += 256) K += used[c0 + j];
-    __syncthreads();
-    if (c0 + kSumChunk < nv) fetch(c0 + kSumChunk);
-    if (t < 5) {
-      const double* col = buf[t];
-      for (int j = 0; j < len; j += 32) {
-        double b[32];
-#pragma unroll
-        for (int u = 0; u < 32; ++u) b[u] = col[j + u];
-#pragma unroll
-        for (int u = 0; u < 32; ++u) S = __dadd_rn(S, b[u]);
-      }
-    }
-    __syncthreads();
+  for (int u = 0; u < kSumPer; ++u) {
+    const int i = t + 256 * u, q = i / kSumRun, j = i % kSumRun;
+    v[u] = j < len ? terms[q * rows_pad + c0 + j] : 0.0;
   }
-  atomicAdd(&kcount, K);
+  unsigned int K = 0;
+  for (int64_t j = t; j < len; j += 256) K += used[c0 + j];
+#pragma unroll
+  for (int u = 0; u < kSumPer; ++u) {
+    const int i = t + 256 * u;
+    buf[i / kSumRun][i % kSumRun] = v[u];
+  }
   __syncthreads();
-  if (t < 5) out[t] = S;
-  if (t == 5) out[5] = (double)kcount;
+  if (K) atomicAdd(&kcount, K);
+  if (t < 5) {
+    const double* col = buf[t];
+    double S = 0.0;
+    for (int j = 0; j < len; j += 32) {
+      double b[32];
+#pragma unroll
+      for (int u = 0; u < 32; ++u) b[u] = col[j + u];
+#pragma unroll
+      for (int u = 0; u < 32; ++u) S = __dadd_rn(S, b[u]);
+    }
+    part[t * n_runs + r] = S;
+  }
+  __syncthreads();
+  if (t == 0) part[5 * n_runs + r] = (double)kcount;
+}
+
+// out = {S00, S10, S20, S11, S21, K}: threads 0..4 add the runs' sums of
+// their column in run order; thread 5 adds the counts (integers, exact).
+__global__ __launch_bounds__(64) void k_genome_total(const double* __restrict__ part,
+                                                     int64_t n_runs, double* __restrict__ out) {
+  const int t = threadIdx.x;
+  if (t > 5) return;
+  double S = 0.0;
+  for (int64_t r = 0; r < n_runs; ++r) S = __dadd_rn(S, part[t * n_runs + r]);
+  out[t] = S;
 }
 
 __global__ __launch_bounds__(256) void k_genome_pairs(const double* __restrict__ sums,
@@ -240,8 +247,14 @@ int launch_genome(const uint32_t* D, int64_t wn, int64_t nv, int64_t rows_pad, d
                      rows_pad, terms, used);
   int rc = check_launch("genome_terms");
   if (rc != PG_OK) return rc;
-  hipLaunchKernelGGL(k_genome_sums, dim3(1), dim3(256), 0, st, terms, used, nv, rows_pad, sums);
-  rc = check_launch("genome_sums");
+  const int64_t n_runs = genome_runs(nv);
+  double* part = sums + 8;
+  hipLaunchKernelGGL(k_genome_run_sums, dim3((unsigned)n_runs), dim3(256), 0, st, terms, used, nv,
+                     rows_pad, n_runs, part);
+  rc = check_launch("genome_run_sums");
+  if (rc != PG_OK) return rc;
+  hipLaunchKernelGGL(k_genome_total, dim3(1), dim3(64), 0, st, part, n_runs, sums);
+  rc = check_launch("genome_total");
   mark_stage(1, st);
   if (rc != PG_OK || count <= 0) return rc;
   const int64_t blocks = ceil_div(count, 256) < 65536 ? ceil_div(count, 256) : 65536;

@@ -384,9 +384,12 @@ int launch_ibs_distance(const uint32_t* i0, const uint32_t* i1, const uint32_t* 
 int launch_ibs_similarity(const uint32_t* i1, const uint32_t* i2, const uint32_t* nm,
                           int64_t count, double* s, hipStream_t st);
 // IBD report from the variant-major operand D of the selection (rows_pad x
-// wn words): terms 5 x rows_pad doubles, used rows_pad words, sums 6 doubles
-// of workspace; then `count` pairs of IBS counts.  Stage 1 ends after the
-// per-marker averages.
+// wn words): terms 5 x rows_pad doubles, used rows_pad words, sums
+// genome_sums_doubles(nv) doubles of workspace (the six totals, padded to 8,
+// then six per run of 1,024 markers); then `count` pairs of IBS counts.
+// Stage 1 ends after the per-marker averages.
+inline int64_t genome_runs(int64_t nv) { return nv > 0 ? (nv + 1023) / 1024 : 1; }
+inline int64_t genome_sums_doubles(int64_t nv) { return 8 + 6 * genome_runs(nv); }
 int launch_genome(const uint32_t* D, int64_t wn, int64_t nv, int64_t rows_pad, double* terms,
                   uint32_t* used, double* sums, const uint32_t* i0, const uint32_t* i1,
                   const uint32_t* nm, int64_t count, double* z0, double* z1, double* z2,
