@@ -783,7 +783,7 @@ int pg_ibs_genome(const pg_genotypes* g, const int32_t* sample_idx, int64_t n_se
 
 namespace {
 struct ClusterPlan {
-  int64_t off_D, off_nnd, off_nnj, bytes;
+  int64_t off_D, off_nnd, off_nnj, off_ctl, off_rows, bytes;
 };
 int plan_cluster(int64_t m, ClusterPlan& p) {
   if (m < 1 || m >= kMaxIndex) return fail(PG_EINVAL, "m %lld outside [1, 2^31)", (long long)m);
@@ -791,6 +791,8 @@ int plan_cluster(int64_t m, ClusterPlan& p) {
   p.off_D = c.take(m * m * 8);
   p.off_nnd = c.take(m * 8);
   p.off_nnj = c.take(m * 4);
+  p.off_ctl = c.take(16);
+  p.off_rows = c.take(m * 4);
   p.bytes = c.off;
   return PG_OK;
 }
@@ -822,7 +824,8 @@ int pg_ibs_cluster(const uint32_t* ibs0, const uint32_t* ibs1, const uint32_t* n
   hipStream_t st = (hipStream_t)stream;
   mark_stage(0, st);
   return launch_ibs_cluster(ibs0, ibs1, nonmiss, m, (double*)(ws + p.off_D),
-                            (double*)(ws + p.off_nnd), (int*)(ws + p.off_nnj), merges, st);
+                            (double*)(ws + p.off_nnd), (int*)(ws + p.off_nnj),
+                            (int*)(ws + p.off_ctl), (int*)(ws + p.off_rows), merges, st);
 }
 
 }  // extern "C"

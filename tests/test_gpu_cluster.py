@@ -70,6 +70,28 @@ def test_cluster_ties_and_empty_samples():
     assert np.array_equal(got["height"], ref["height"])
 
 
+def test_cluster_per_merge_launches_ties_and_empty_samples():
+    """From 3,200 samples each merge runs as three launches over the chip:
+    3,300 samples over 60 markers (coarse distances, many ties), 300
+    duplicated samples (distance-0 ties) and two samples without any call
+    (+inf to everyone); the merge sequence equals the oracle's."""
+    n0, V = 3000, 60
+    codes = oracle.unpack(synth.hwe(n0, V, (0.2, 0.5), 0.0, seed=57), n0, V)
+    codes = np.concatenate([codes, codes[:, :300]], axis=1)
+    codes[:, 17] = 1
+    codes[:, 2999] = 1
+    m = codes.shape[1]
+    bed = np.zeros((V, (m + 3) // 4), dtype=np.uint8)
+    for k in range(m):
+        bed[:, k // 4] |= codes[:, k].astype(np.uint8) << (2 * (k % 4))
+    i0, i1, _, nm = oracle.ibs_matrix(codes, full=True)
+    ref = oracle.cluster_complete(oracle.ibs_distance(i0, i1, nm))
+    assert np.isinf(ref["height"][-1]) and (ref["height"] == 0).sum() >= 299
+    got = _cluster(_ibs(bed, m), m)
+    assert np.array_equal(got["a"], ref["a"]) and np.array_equal(got["b"], ref["b"])
+    assert np.array_equal(got["height"], ref["height"])
+
+
 def test_cluster_full_size_small_workload():
     """Complete linkage of the 1,000-sample relationship-matrix panel (the
     paper's clustering timings use the same two panel sizes)."""
