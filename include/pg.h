@@ -377,8 +377,8 @@ int pg_cluster_workspace_bytes(int64_t m, size_t* bytes);
  * with the smallest a, then the smallest b.  merges (device, m - 1 records)
  * receives the merge sequence in order; the result is exactly determined by
  * the counts.  Below 3,200 samples one block runs the merge loop; from
- * 3,200 on, each merge is three kernel launches over the chip (the stream
- * receives 3 (m - 1) launches).  Stages for pg_profile_events: 1 =
+ * 3,200 on, each merge is two kernel launches over the chip (the stream
+ * receives 2 (m - 1) launches).  Stages for pg_profile_events: 1 =
  * distances and nearest neighbours, 2 = the merge loop.
  */
 int pg_ibs_cluster(const uint32_t* ibs0, const uint32_t* ibs1, const uint32_t* nonmiss,

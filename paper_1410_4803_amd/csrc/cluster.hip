@@ -436,34 +436,38 @@ __global__ __launch_bounds__(kCT) void k_cluster(double* __restrict__ D, int64_t
   }
 }
 
-// ---- the merge loop as three launches per merge (large cohorts) -------------
-// The same steps as k_cluster, each spread over the chip: k_cl_pick (one
-// block) finds the pair and records the merge, k_cl_fold (one thread per
-// sample) folds j into i, retires j and lists the rows whose neighbour may
-// have moved, and k_cl_rescan (a block per listed row) rescans them.  The
-// pair and the list live in the workspace (ctl = {i, j, listed rows}), so
-// the host only enqueues; every kernel returns early once no pair is left.
-constexpr int kClPickT = 1024;
-constexpr int kClScanT = 1024;
+// ---- the merge loop as two launches per merge (large cohorts) ---------------
+// The same steps as k_cluster, each spread over the chip.  k_cl_fold: every
+// block finds the pair itself (the argmin over the cached neighbours, the
+// same in every block; a block that already sees j retired by another block
+// still finds i, since i != j), block 0 records the merge, and each thread
+// folds sample k = its global index: j into i, j retired, and k appended to
+// the list of rows to rescan when its neighbour may have moved.  k_cl_rescan
+// (a block per listed row) rescans them.  The list's length for merge t is
+// cnt[t % 2]; merge t clears cnt[(t + 1) % 2], whose last reader was merge
+// t - 1's rescan, so the host only enqueues.
+constexpr int kClT = 1024;
 constexpr int kClScanBlocks = 64;
 
-__global__ __launch_bounds__(kClPickT) void k_cl_pick(int64_t m, const double* __restrict__ nn_d,
-                                                      const int* __restrict__ nn_j, int64_t t,
-                                                      pg_merge* __restrict__ merges,
-                                                      int* __restrict__ ctl) {
-  __shared__ double s_v[kClPickT / 64];
-  __shared__ int s_i[kClPickT / 64];
+__global__ __launch_bounds__(kClT) void k_cl_fold(double* __restrict__ D, int64_t m,
+                                                 double* __restrict__ nn_d,
+                                                 const int* __restrict__ nn_j, int64_t t,
+                                                 pg_merge* __restrict__ merges,
+                                                 int* __restrict__ cnt, int* __restrict__ rows) {
+  __shared__ double s_v[kClT / 64];
+  __shared__ int s_i[kClT / 64];
+  __shared__ int s_pair[2];
   const double inf = __longlong_as_double(0x7ff0000000000000ll);
   const double nan = __longlong_as_double(kNaN);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double bv = inf;
   int bi = -1;
-  for (int64_t k0 = tid; k0 < m; k0 += kClPickT * kCU) {
+  for (int64_t k0 = tid; k0 < m; k0 += kClT * kCU) {
     double v[kCU];
 #pragma unroll
-    for (int u = 0; u < kCU; ++u) v[u] = k0 + u * kClPickT < m ? nn_d[k0 + u * kClPickT] : nan;
+    for (int u = 0; u < kCU; ++u) v[u] = k0 + u * kClT < m ? nn_d[k0 + u * kClT] : nan;
 #pragma unroll
-    for (int u = 0; u < kCU; ++u) take_min(bv, bi, v[u], (int)(k0 + u * kClPickT));
+    for (int u = 0; u < kCU; ++u) take_min(bv, bi, v[u], (int)(k0 + u * kClT));
   }
   wave_min(bv, bi);
   if (lane == 0) {
@@ -473,28 +477,24 @@ __global__ __launch_bounds__(kClPickT) void k_cl_pick(int64_t m, const double* _
   __syncthreads();
   if (tid == 0) {
     double hv = s_v[0];
-    int i = s_i[0];
-    for (int w = 1; w < kClPickT / 64; ++w) take_min(hv, i, s_v[w], s_i[w]);
-    const int j = i >= 0 ? nn_j[i] : -1;
-    if (i >= 0) {   // always: two active clusters always pair
-      merges[t].a = i;
-      merges[t].b = j;
-      merges[t].height = hv;
+    int pi = s_i[0];
+    for (int w = 1; w < kClT / 64; ++w) take_min(hv, pi, s_v[w], s_i[w]);
+    const int pj = pi >= 0 ? nn_j[pi] : -1;
+    s_pair[0] = pi;
+    s_pair[1] = pj;
+    if (blockIdx.x == 0) {
+      if (pi >= 0) {   // always: two active clusters always pair
+        merges[t].a = pi;
+        merges[t].b = pj;
+        merges[t].height = hv;
+      }
+      cnt[(t + 1) & 1] = 0;
     }
-    ctl[0] = i;
-    ctl[1] = j;
-    ctl[2] = 0;
   }
-}
-
-__global__ __launch_bounds__(256) void k_cl_fold(double* __restrict__ D, int64_t m,
-                                                 double* __restrict__ nn_d,
-                                                 const int* __restrict__ nn_j,
-                                                 int* __restrict__ ctl, int* __restrict__ rows) {
-  const int i = ctl[0], j = ctl[1];
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  __syncthreads();
+  const int i = s_pair[0], j = s_pair[1];
+  const int64_t k = (int64_t)blockIdx.x * kClT + tid;
   if (i < 0 || k >= m) return;
-  const double nan = __longlong_as_double(kNaN);
   // fold: D[i][k] = D[k][i] = max(D[i][k], D[j][k]) for the active k (a
   // retired k has NaN in row i); retire j: its column becomes NaN
   const double a = D[(int64_t)i * m + k];
@@ -514,19 +514,18 @@ __global__ __launch_bounds__(256) void k_cl_fold(double* __restrict__ D, int64_t
     const double dk = nn_d[k];
     const int nk = nn_j[k];
     if (dk == dk && (k == i || (k < i && (nk == i || nk == j)) || (k > i && nk == j)))
-      rows[atomicAdd(&ctl[2], 1)] = (int)k;
+      rows[atomicAdd(&cnt[t & 1], 1)] = (int)k;
   }
 }
 
-__global__ __launch_bounds__(kClScanT) void k_cl_rescan(const double* __restrict__ D, int64_t m,
-                                                        double* __restrict__ nn_d,
-                                                        int* __restrict__ nn_j,
-                                                        const int* __restrict__ ctl,
-                                                        const int* __restrict__ rows) {
-  __shared__ double s_v[kClScanT / 64];
-  __shared__ int s_i[kClScanT / 64];
-  if (ctl[0] < 0) return;
-  const int nrows = ctl[2];
+__global__ __launch_bounds__(kClT) void k_cl_rescan(const double* __restrict__ D, int64_t m,
+                                                    double* __restrict__ nn_d,
+                                                    int* __restrict__ nn_j, int64_t t,
+                                                    const int* __restrict__ cnt,
+                                                    const int* __restrict__ rows) {
+  __shared__ double s_v[kClT / 64];
+  __shared__ int s_i[kClT / 64];
+  const int nrows = cnt[t & 1];
   const double inf = __longlong_as_double(0x7ff0000000000000ll);
   const double nan = __longlong_as_double(kNaN);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -535,15 +534,15 @@ __global__ __launch_bounds__(kClScanT) void k_cl_rescan(const double* __restrict
     const double* row = D + k * m;
     double v = inf;
     int l = -1;
-    for (int64_t c0 = k + 1 + tid; c0 < m; c0 += (int64_t)kClScanT * kCR) {
+    for (int64_t c0 = k + 1 + tid; c0 < m; c0 += (int64_t)kClT * kCR) {
       double x[kCR];
 #pragma unroll
       for (int u = 0; u < kCR; ++u) {
-        const int64_t c = c0 + (int64_t)u * kClScanT;
+        const int64_t c = c0 + (int64_t)u * kClT;
         x[u] = c < m ? row[c] : nan;
       }
 #pragma unroll
-      for (int u = 0; u < kCR; ++u) take_min(v, l, x[u], (int)(c0 + (int64_t)u * kClScanT));
+      for (int u = 0; u < kCR; ++u) take_min(v, l, x[u], (int)(c0 + (int64_t)u * kClT));
     }
     wave_min(v, l);
     __syncthreads();   // s_v / s_i free (the previous row's reader is done)
@@ -555,7 +554,7 @@ __global__ __launch_bounds__(kClScanT) void k_cl_rescan(const double* __restrict
     if (tid == 0) {
       double rv = s_v[0];
       int rl = s_i[0];
-      for (int w = 1; w < kClScanT / 64; ++w) take_min(rv, rl, s_v[w], s_i[w]);
+      for (int w = 1; w < kClT / 64; ++w) take_min(rv, rl, s_v[w], s_i[w]);
       nn_d[k] = rl >= 0 ? rv : nan;
       nn_j[k] = rl;
     }
@@ -576,12 +575,12 @@ int launch_ibs_cluster(const uint32_t* i0, const uint32_t* i1, const uint32_t* n
     hipLaunchKernelGGL(k_cluster, dim3(1), dim3(kCT), 0, st, D, m, nn_d, nn_j, merges);
     rc = check_launch("cluster");
   } else {
-    const unsigned fold_blocks = (unsigned)ceil_div(m, 256);
+    const unsigned fold_blocks = (unsigned)ceil_div(m, kClT);
+    rc = fill_u32(reinterpret_cast<uint32_t*>(ctl), 2, 0u, st);   // the two list lengths
     for (int64_t t = 0; t + 1 < m && rc == PG_OK; ++t) {
-      hipLaunchKernelGGL(k_cl_pick, dim3(1), dim3(kClPickT), 0, st, m, nn_d, nn_j, t, merges, ctl);
-      hipLaunchKernelGGL(k_cl_fold, dim3(fold_blocks), dim3(256), 0, st, D, m, nn_d, nn_j, ctl,
-                         rows);
-      hipLaunchKernelGGL(k_cl_rescan, dim3(kClScanBlocks), dim3(kClScanT), 0, st, D, m, nn_d, nn_j,
+      hipLaunchKernelGGL(k_cl_fold, dim3(fold_blocks), dim3(kClT), 0, st, D, m, nn_d, nn_j, t,
+                         merges, ctl, rows);
+      hipLaunchKernelGGL(k_cl_rescan, dim3(kClScanBlocks), dim3(kClT), 0, st, D, m, nn_d, nn_j, t,
                          ctl, rows);
       rc = check_launch("cluster_step");
     }

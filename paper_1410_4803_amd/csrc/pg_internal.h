@@ -394,9 +394,10 @@ int launch_genome(const uint32_t* D, int64_t wn, int64_t nv, int64_t rows_pad, d
                   uint32_t* used, double* sums, const uint32_t* i0, const uint32_t* i1,
                   const uint32_t* nm, int64_t count, double* z0, double* z1, double* z2,
                   double* pi, hipStream_t st);
-// D: m x m doubles; nn_d: m doubles; nn_j: m ints; ctl: 4 ints; rows: m ints.
-// From kClusterSplitMin samples on, each merge runs as three launches over
-// the chip (the pair, the fold, the rescans) instead of one block's loop.
+// D: m x m doubles; nn_d: m doubles; nn_j: m ints; ctl: 4 ints (the first two
+// count the rows to rescan); rows: m ints.  From kClusterSplitMin samples on,
+// each merge runs as two launches over the chip (the pair and the fold; the
+// rescans) instead of one block's loop.
 constexpr int64_t kClusterSplitMin = 3200;
 int launch_ibs_cluster(const uint32_t* i0, const uint32_t* i1, const uint32_t* nm, int64_t m,
                        double* D, double* nn_d, int* nn_j, int* ctl, int* rows,
