@@ -701,8 +701,9 @@ def main():
         ol = torch.empty((cap, 64), dtype=torch.uint8, device=dev)
         nl = torch.empty(1, dtype=torch.int64, device=dev)
         for wl, key, lpaths in ((synth.ld_large(), "ld_large",
-                                 ("mfma", "sparse", LD_SPARSE_ALL, "popc", LD_INT8)),
-                                (synth.ld_large_nomiss(), "ld_large_nomiss", ("mfma", "sparse"))):
+                                 ("mfma", "auto", "sparse", LD_SPARSE_ALL, "popc", LD_INT8)),
+                                (synth.ld_large_nomiss(), "ld_large_nomiss",
+                                 ("mfma", "auto", "sparse"))):
             log(f"timing LD windows on {wl['name']}")
             cl = pg.Cohort.from_numpy(wl["bed"], wl["n"], device=dev)
             W = wl["window"]

@@ -114,7 +114,16 @@ enum pg_layout {
  * 8-15 select a kernel variant of that path (0 = the library's default; the
  * tuner tries the others).  Unknown variants fall back to the default. */
 enum pg_path {
-  PG_PATH_AUTO = 0, /* library picks per shape (pg_resolve_path) */
+  PG_PATH_AUTO = 0, /* library picks per shape (pg_resolve_path): the
+                       matrix-core path (variant 0), except for LD windows
+                       of at least 500 over at least 5,000 samples outside
+                       batches, where it is PG_PATH_SPARSE with the sampled
+                       gate (variant bit 8): the correction path runs only
+                       if the missing calls counted over about 4,096
+                       sampled variants average at most its tile budget,
+                       and the matrix-core kernel takes every tile
+                       otherwise.  Batches resolve AUTO to the matrix-core
+                       path. */
   PG_PATH_POPC = 1, /* bit planes + popcount on the vector ALUs */
   PG_PATH_MFMA = 2, /* 2-bit codes expanded to indicator features (values
                        0, +-1) and contracted on the matrix cores.  Default
@@ -142,7 +151,8 @@ enum pg_path {
                        64-variant groups pass these tests on their own
                        (then the extra sample-major operand pays).  Exact
                        like the other paths; not available in batches.
-                       Variant bits: 1 drops the last two rules; 2
+                       Variant bits: 1 drops the last two rules; 8 adds
+                       the sampled gate of PG_PATH_AUTO; 2
                        (pg_ld_window only) is a
                        diagnostic that implies 1: no
                        emission; every pair (a, b) of a tile the path takes

@@ -121,11 +121,13 @@ int make_sel(const pg_genotypes* g, bool list, const int32_t* idx, int64_t n_sel
 // PG_PATH_AUTO.  Measured whole-call times (the sweep mode of bench.py):
 // the pipelined fp4 matrix-core kernel wins every IBS shape of 64 to 10,000
 // samples x 5,000 to 100,000 variants, the popcount kernel coming closest
-// at 64 samples (0.087 vs 0.081 ms), and every LD shape of 500 to 20,000
-// samples x windows of 50 to 1,000 at 0.5% and 1% missing calls.  The
-// missing-call correction path wins only on data without missing calls
-// (5,000 samples and up, windows of 500 and up), which the plan cannot see,
-// so it stays a caller's choice.
+// at 64 samples (0.087 vs 0.081 ms).  For LD the missing-call correction
+// path wins on data with few missing calls from 5,000 samples and windows
+// of 500 (up to 1.52x at 20,000 samples, window 1,000) and the dense fp4
+// kernel everywhere else, so the missing rate decides: there AUTO takes the
+// correction path behind a sampled gate (kLdGated) that counts the missing
+// calls of about 4,096 variants and leaves the path off, for the cost of
+// that count, unless a tile would hold few enough of them on average.
 int ibs_auto_path(int64_t m, int64_t nv) {
   (void)m;
   (void)nv;
@@ -133,11 +135,14 @@ int ibs_auto_path(int64_t m, int64_t nv) {
 }
 
 int ld_auto_path(int64_t m, int64_t nv, int32_t window) {
-  (void)m;
   (void)nv;
-  (void)window;
-  return PG_PATH_MFMA;
+  return m >= 5000 && window >= 500 ? PG_PATH_SPARSE : PG_PATH_MFMA;
 }
+
+// Variant bits of the correction path: every tile whose lists fit (1), the
+// diagnostic records (2, implies 1), the sampled gate (8; what AUTO sets).
+constexpr int kLdAllTiles = 1, kLdDiag = 2, kLdGated = 8;
+constexpr int64_t kLdGateSamples = 4096;   // variants the gate samples (about)
 
 // Resolves the kernel variant: 0 (or an undefined code) is the default, the
 // pipelined fp4 kernel; fp4 variants fall back to the pipelined int8 kernel
@@ -199,7 +204,10 @@ int plan_ld(const Sel& s, int32_t window, int path_arg, LdPlan& p) {
   if (path_arg < 0 || (path_arg >> 16) != 0) return fail(PG_EINVAL, "bad path argument %d", path_arg);
   int path = path_arg & 0xFF;
   p.variant = (path_arg >> 8) & 0xFF;
-  if (path == PG_PATH_AUTO) path = ld_auto_path(s.m, s.nv, window);
+  if (path == PG_PATH_AUTO) {
+    path = ld_auto_path(s.m, s.nv, window);
+    if (path == PG_PATH_SPARSE) p.variant |= kLdGated;
+  }
   if (path != PG_PATH_MFMA && path != PG_PATH_POPC && path != PG_PATH_SPARSE)
     return fail(PG_EINVAL, "unknown path %d", path);
   p.path = path;
@@ -234,15 +242,12 @@ int plan_ld(const Sel& s, int32_t window, int path_arg, LdPlan& p) {
     p.off_vst = c.take(p.rows_pad * 16);
     p.off_gsum = c.take(p.rows_pad / kLdTile * 8);
     p.off_gmax = c.take(p.rows_pad / kLdTile * 4);
-    p.off_any = c.take(4);
+    p.off_any = c.take(16);   // groups_ok, then the gate's 64-bit count at +8
   }
   p.bytes = c.off;
   return PG_OK;
 }
 
-// Variant bits of the correction path: every tile whose lists fit (1), the
-// diagnostic records (2, implies 1).
-constexpr int kLdAllTiles = 1, kLdDiag = 2;
 
 // Band tiles take the correction path when their two 64-variant groups hold
 // at most 3m/8 missing calls (m selected samples), and only once a quarter
@@ -285,7 +290,18 @@ int ld_pairs(const Sel& s, const LdPlan& p, char* ws, int32_t window, double r2_
   }
   LdSparse sp{(uint32_t*)(ws + p.off_lists), (int4*)(ws + p.off_vst), (int64_t*)(ws + p.off_gsum),
               (int*)(ws + p.off_gmax), (uint32_t*)(ws + p.off_any), ld_sparse_min_groups(p),
-              p.cap, ld_sparse_budget(p, s.m)};
+              p.cap, ld_sparse_budget(p, s.m), nullptr, 0, 1};
+  if (p.variant & kLdGated) {
+    // on when the sampled variants' mean, times the 128 variants of a tile,
+    // is within the tile budget: count <= budget * n_samp / 128
+    sp.gate = (uint64_t*)(ws + p.off_any + 8);
+    sp.gate_stride = s.nv > kLdGateSamples ? s.nv / kLdGateSamples : 1;
+    const int64_t n_samp = ceil_div(s.nv, sp.gate_stride);
+    sp.gate_max = sp.budget == INT64_MAX
+                      ? UINT64_MAX
+                      : (uint64_t)(sp.budget / (2 * kLdTile) * n_samp +
+                                   sp.budget % (2 * kLdTile) * n_samp / (2 * kLdTile));
+  }
   uint32_t* T = (uint32_t*)(ws + p.off_T);
   if (rc == PG_OK) rc = launch_ld_sparse_stats(D, p.words, s.m, s.nv, p.rows_pad, sp, st);
   // the sample-major operand only when the path is on
@@ -381,7 +397,9 @@ int batch_validate_ld(const pg_problem& q, Sel& s, int& path, int& variant, int6
   if (q.capacity < 0) return fail(PG_EINVAL, "capacity < 0");
   if (q.capacity > 0 && !q.out) return fail(PG_EINVAL, "out is NULL with capacity > 0");
   LdPlan p;
-  rc = plan_ld(s, q.window, q.path, p);
+  // AUTO in a batch: the matrix-core path (the correction path is not hosted)
+  const int path_arg = (q.path & 0xFF) == PG_PATH_AUTO ? (q.path & ~0xFF) | PG_PATH_MFMA : q.path;
+  rc = plan_ld(s, q.window, path_arg, p);
   if (rc != PG_OK) return rc;
   if (p.path == PG_PATH_SPARSE)
     return fail(PG_EUNSUPPORTED, "the missing-call correction path is not available in batches");

@@ -37,14 +37,39 @@
 
 namespace pg {
 
+// Missing calls of every stride-th variant row of D (the first m samples),
+// added to *gate: one wave per sampled row.
+__global__ __launch_bounds__(256) void k_ld_miss_sample(const uint32_t* __restrict__ D, int64_t wn,
+                                                        int64_t m, int64_t nv, int64_t stride,
+                                                        unsigned long long* __restrict__ gate) {
+  const int lane = threadIdx.x & 63;
+  const int64_t v = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * stride;
+  if (v >= nv) return;
+  const uint32_t* row = D + v * wn;
+  unsigned int c = 0;
+  for (int64_t w = lane; w < wn; w += 64) {
+    const uint32_t x = row[w];
+    uint32_t miss = x & ~(x >> 1) & 0x55555555u;   // code 01
+    const int64_t valid = m - 16 * w;              // selected samples in this word
+    if (valid < 16) miss &= valid <= 0 ? 0u : ((1u << (2 * valid)) - 1u);
+    c += __popc(miss);
+  }
+  for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, 64);
+  if (lane == 0 && c) atomicAdd(gate, (unsigned long long)c);
+}
+
 // Per-variant missing-call list, count and totals: one wave per variant row
 // of the variant-major operand D (padding samples are missing calls and are
 // not listed; padding variants get zero counts and empty lists).  A list
-// entry is the sample index.
+// entry is the sample index.  Does nothing when a gate is given and the
+// sampled count exceeds gate_max (the path stays off).
 __global__ __launch_bounds__(256) void k_ld_vstats(const uint32_t* __restrict__ D, int64_t wn,
                                                    int64_t m, int64_t nv, int64_t rows_pad, int cap,
                                                    uint32_t* __restrict__ lists,
-                                                   int4* __restrict__ vst) {
+                                                   int4* __restrict__ vst,
+                                                   const unsigned long long* __restrict__ gate,
+                                                   unsigned long long gate_max) {
+  if (gate && *gate > gate_max) return;
   const int lane = threadIdx.x & 63;
   const int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   if (v >= rows_pad) return;
@@ -113,8 +138,11 @@ __global__ __launch_bounds__(256) void k_ld_groups(const int4* __restrict__ vst,
                                                    int cap, int64_t budget,
                                                    int64_t* __restrict__ gsum,
                                                    int* __restrict__ gmax,
-                                                   uint32_t* __restrict__ groups_ok) {
+                                                   uint32_t* __restrict__ groups_ok,
+                                                   const unsigned long long* __restrict__ gate,
+                                                   unsigned long long gate_max) {
   __shared__ uint32_t s_ok;
+  if (gate && *gate > gate_max) return;   // groups_ok stays 0: the path is off
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (threadIdx.x == 0) s_ok = 0;
   __syncthreads();
@@ -476,16 +504,28 @@ __global__ __launch_bounds__(256) void k_ld_transpose(const uint32_t* __restrict
 
 int launch_ld_sparse_stats(const uint32_t* D, int64_t wn, int64_t m, int64_t nv,
                            int64_t rows_pad, const LdSparse& sp, hipStream_t st) {
+  int rc = PG_OK;
+  unsigned long long* gate = reinterpret_cast<unsigned long long*>(sp.gate);
+  if (gate) {
+    rc = fill_u32(reinterpret_cast<uint32_t*>(gate), 2, 0u, st);
+    if (rc != PG_OK) return rc;
+    const int64_t n_samp = ceil_div(nv, sp.gate_stride);
+    hipLaunchKernelGGL(k_ld_miss_sample, dim3((unsigned)ceil_div(n_samp, 4)), dim3(256), 0, st, D,
+                       wn, m, nv, sp.gate_stride, gate);
+    rc = check_launch("ld_miss_sample");
+    if (rc != PG_OK) return rc;
+  }
   const dim3 grid((unsigned)ceil_div(rows_pad, 4));
   hipLaunchKernelGGL(k_ld_vstats, grid, dim3(256), 0, st, D, wn, m, nv, rows_pad, sp.cap, sp.lists,
-                     sp.vst);
-  int rc = check_launch("ld_vstats");
+                     sp.vst, gate, (unsigned long long)sp.gate_max);
+  rc = check_launch("ld_vstats");
   if (rc == PG_OK) rc = fill_u32(sp.groups_ok, 1, 0u, st);
   if (rc != PG_OK) return rc;
   const int64_t n_groups = rows_pad / kLdTile;
   hipLaunchKernelGGL(k_ld_groups, dim3((unsigned)ceil_div(n_groups, kGrpPerBlock)), dim3(256), 0,
                      st, sp.vst,
-                     n_groups, sp.cap, sp.budget, sp.gsum, sp.gmax, sp.groups_ok);
+                     n_groups, sp.cap, sp.budget, sp.gsum, sp.gmax, sp.groups_ok, gate,
+                     (unsigned long long)sp.gate_max);
   return check_launch("ld_groups");
 }
 

@@ -278,6 +278,12 @@ struct LdSparse {
   uint32_t min_groups; // the path is on when groups_ok reaches this
   int cap;
   int64_t budget;      // largest missing-call total of a tile's two groups
+  // optional sampled gate: the statistics pass (and with it the path) runs
+  // only while *gate, the missing calls counted over a sample of the
+  // variants, is at most gate_max
+  uint64_t* gate;
+  uint64_t gate_max;
+  int64_t gate_stride; // every gate_stride-th variant is sampled
 };
 __device__ inline bool ld_tile_sparse(const int64_t* gsum, const int* gmax,
                                       const uint32_t* groups_ok, uint32_t min_groups, int64_t I,

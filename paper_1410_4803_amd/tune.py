@@ -47,8 +47,9 @@ def shape_key(kind: str, m: int, nv: int, window: int | None = None) -> str:
 
 def rule_of_thumb(kind: str, m: int, nv: int, window: int | None = None) -> int:
     """Default without a measurement: what the library's PG_PATH_AUTO resolves
-    to for the shape (pg_resolve_path; the matrix-core path at every shape
-    measured)."""
+    to for the shape (pg_resolve_path): the matrix-core path, except LD
+    windows of 500 and up over 5,000 samples and up, where it is the
+    correction path behind its sampled missing-call gate."""
     return api.resolve_path(kind, m, nv, window or 0, "auto")
 
 

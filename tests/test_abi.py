@@ -69,13 +69,16 @@ def test_workspace_sizes():
     assert rc == 0 and b == 512 * 320 * 4 + 10 * 10 * 192 * 256 * 4
     rc, b = _ibs_ws(_g(500, 5000), path=N.PG_PATH_MFMA | (1 << 8))   # variant 1: no split
     assert rc == 0 and b == 512 * 320 * 4
-    rc, b = _ld_ws(_g(5000, 500000), 1000)
+    rc, b = _ld_ws(_g(5000, 500000), 1000, path=N.PG_PATH_MFMA)
     assert rc == 0 and b > 500000 * 320 * 4
     # correction path: + sample-major operand (5120 x 31264 words), lists of
     # 320 entries per variant, 16 bytes of totals per variant
     rc, bs = _ld_ws(_g(5000, 500000), 1000, path=N.PG_PATH_SPARSE)
     assert rc == 0 and bs >= b + 5120 * 31264 * 4 + 500032 * 320 * 4 + 500032 * 16
     assert bs < b + 5120 * 31264 * 4 + 500032 * 320 * 4 + 500032 * 16 + (1 << 20)
+    # AUTO at this shape is the correction path behind its sampled gate
+    rc, ba = _ld_ws(_g(5000, 500000), 1000)
+    assert rc == 0 and ba == bs
     # list slots: max(64, ceil(m/16) rounded up to 8), at most 65528
     for m, cap in [(1, 64), (1000, 64), (1040, 72), (5000, 320), (2000000, 65528)]:
         rc, b0 = _ld_ws(_g(m, 64), 1, path=N.PG_PATH_MFMA)
@@ -338,11 +341,13 @@ def test_resolve_path_ibs(m, nv):
 
 
 @pytest.mark.parametrize("m,nv,w", [(1, 2, 1), (500, 20000, 50), (5000, 500000, 1000),
-                                    (20000, 20000, 1000)])
+                                    (20000, 20000, 1000), (4999, 20000, 1000), (5000, 20000, 499),
+                                    (20000, 20000, 50)])
 def test_resolve_path_ld(m, nv, w):
     """LD: PG_PATH_AUTO resolves to the matrix-core path (variant 0, the
-    pipelined fp4 tile); variant 1 is the int8 tile; the correction and
-    popcount paths pass through."""
+    pipelined fp4 tile), or from 5,000 samples and windows of 500 to the
+    correction path with its sampled gate (variant bit 8); variant 1 is the
+    int8 tile; the correction and popcount paths pass through."""
     lib = N.load()
     out = ctypes.c_int(-1)
 
@@ -350,7 +355,8 @@ def test_resolve_path_ld(m, nv, w):
         assert lib.pg_resolve_path(N.PG_KIND_LD, m, nv, w, path, ctypes.byref(out)) == 0
         return out.value
 
-    assert res(N.PG_PATH_AUTO) == N.PG_PATH_MFMA
+    gated = m >= 5000 and w >= 500
+    assert res(N.PG_PATH_AUTO) == (N.PG_PATH_SPARSE | (8 << 8) if gated else N.PG_PATH_MFMA)
     assert res(N.PG_PATH_MFMA | (1 << 8)) == N.PG_PATH_MFMA | (1 << 8)
     assert res(N.PG_PATH_SPARSE) == N.PG_PATH_SPARSE
     assert res(N.PG_PATH_POPC) == N.PG_PATH_POPC

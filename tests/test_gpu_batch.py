@@ -222,3 +222,16 @@ def test_batch_full_workload():
             sel = got[k][(got[k]["a"] >= a0) & (got[k]["a"] < a0 + 60)]
             compare_records(sel, ref, d["r2_min"])
     b.close()
+
+
+def test_batch_auto_ld_is_the_matrix_core_path():
+    """A shape where one-problem calls resolve AUTO to the gated correction
+    path: in a batch AUTO is the matrix-core path, with the same records."""
+    n, V = 5000, 1200
+    c = pg.Cohort.from_numpy(synth.mosaic(n, V, switch=0.01, miss=0.0, seed=61), n)
+    b = pg.Batch([pg.LdProblem(c, window=500, r2_min=0.1, capacity=400000, path="auto")])
+    b.launch()
+    got = b.results()[0]
+    assert got.tobytes() == pg.ld_records(c, 500, 0.1, path="mfma").tobytes()
+    assert got.tobytes() == pg.ld_records(c, 500, 0.1, path="auto").tobytes()
+    b.close()

@@ -200,3 +200,20 @@ def test_sparse_no_missing_calls():
     assert _compare(got, ref, 0.3) > 0
     rec = _diag(c, 64, V)
     assert _check_diag(rec, codes, 64) == sum(min(64, V - 1 - a) for a in range(V))
+
+
+@pytest.mark.parametrize("miss", [0.0, 0.003, 0.01])
+def test_auto_gate_follows_missing_rate(miss):
+    """PG_PATH_AUTO from 5,000 samples and windows of 500 is the correction
+    path behind a sampled missing-call gate: without missing calls the path
+    runs, at 1% the gate leaves every tile to the dense kernel, and in
+    between the tiles decide; the records equal the dense path's in every
+    case."""
+    n, V, W = 5000, 3000, 500
+    bed = synth.mosaic(n, V, switch=0.005, miss=miss, seed=81)
+    c = pg.Cohort.from_numpy(bed, n)
+    assert pg.api.resolve_path("ld", n, V, W, "auto") == SPARSE | (8 << 8)
+    for r2_min in (0.2, -np.inf):
+        got = pg.ld_records(c, W, r2_min, path="auto")
+        ref = pg.ld_records(c, W, r2_min, path="mfma")
+        assert len(got) > 0 and got.tobytes() == ref.tobytes()
